@@ -1,0 +1,376 @@
+"""Pins of the oracle against what the paper and the mathematics fix.
+
+Every test here runs on the CPU.  Each checks the oracle against something
+other than itself: a library routine (numpy's Philox), a closed form (test
+particle, leapfrog cold-plasma dispersion), an invariant (Gauss's law, pair
+bookkeeping), brute force on a tiny case, or the paper's analytic results
+(growth rate of section 3, screening density of Eq. 5, energy balance of
+section 4 and Eq. 10, oscillation frequency of section 5).
+"""
+import math
+from decimal import Decimal, getcontext
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import analytic as A
+from tests import brute_tree
+
+
+def _np_philox(ctr, key):
+    return np.array(brute_tree.philox(ctr, key), dtype=np.uint64)
+
+
+# --------------------------------------------------------------------------- RNG
+@pytest.mark.parametrize("ctr,key", [
+    ((0, 0, 0, 0), (0, 0)),
+    ((1, 0, 0, 0), (0, 0)),
+    ((7, 3, 2, 0), (12345, 2012055870)),
+    ((2**64 - 1, 2**64 - 1, 5, 0), (2**63 + 5, 77)),
+    ((123456789, 63, 2, 0), (0xFFFFFFFFFFFFFFFE, 2012055875)),
+])
+def test_philox_matches_numpy(ctr, key):
+    """Philox4x64-10 (SC'11) bit for bit against numpy.random.Philox."""
+    assert (oracle.philox4x64_10(ctr, key) == _np_philox(ctr, key)).all()
+
+
+# ----------------------------------------------------------------- photon path
+def test_conversion_table_is_floor_of_geometric_tail():
+    """T_k = floor(q^k 2^32), q = exp(-dt/(l_gamma dx)), checked with 40-digit
+    decimal arithmetic instead of libm."""
+    dt, dx, lg = 0.45, 1.0, 20.0
+    t = oracle.conv_table(dt, dx, lg)
+    getcontext().prec = 40
+    r = Decimal(dt) / (Decimal(lg) * Decimal(dx))
+    assert t[-1] == 0 and t[-2] > 0
+    mismatches = 0
+    for k in range(len(t)):
+        exact = (-(Decimal(k) * r)).exp() * (Decimal(2) ** 32)
+        fl = int(exact)  # floor for positive values
+        if k == 0:
+            assert t[0] == 0xFFFFFFFF
+            continue
+        if t[k] != min(fl, 0xFFFFFFFF):
+            # libm rounding may only matter within a hair of an integer
+            assert abs(exact - Decimal(t[k] + 1)) < Decimal("1e-6") or \
+                abs(exact - Decimal(t[k])) < Decimal("1e-6")
+            mismatches += 1
+    assert mismatches <= 1
+    # length: q^k 2^32 < 1  <=>  k > 32 ln2 / r
+    assert abs(len(t) - 1 - math.ceil(32 * math.log(2) / (dt / lg))) <= 1
+
+
+def test_conversion_steps_follow_discretised_exponential():
+    """n_conv = min{k>=1 : u >= T_k} has P(n_conv > k) = q^k: its mean is
+    1/(1-q), i.e. ceil(S/(c dt)) for an exponential path S of mean l_gamma."""
+    dt, dx, lg = 0.45, 1.0, 20.0
+    t = oracle.conv_table(dt, dx, lg).astype(np.int64)
+    rng = np.random.default_rng(5)
+    u = rng.integers(0, 2**32, size=200_000, dtype=np.int64)
+    # first k >= 1 with u >= T_k; T is decreasing so use searchsorted on -T
+    k = np.searchsorted(-t[1:], -u, side="left") + 1
+    q = math.exp(-dt / (lg * dx))
+    mean = 1.0 / (1.0 - q)
+    sd = math.sqrt(q) / (1.0 - q)
+    assert abs(k.mean() - mean) < 5 * sd / math.sqrt(len(u))
+    for kk in (1, 10, 50, 200):
+        emp = (k > kk).mean()
+        assert abs(emp - q**kk) < 5 * math.sqrt(q**kk * (1 - q**kk) / len(u)) + 1e-9
+
+
+# ------------------------------------------------------------- test particle
+def _test_particle(e0, dt, n_steps, p0=0.0, species=1, precision=oracle.FP64):
+    g = oracle.OracleGap(n_cells=64, dx=1.0, dt=dt, boundary=oracle.PERIODIC, e0=e0,
+                         gamma_thr=1e300, f=0.5, l_gamma=0.0, weight=0.0, seed=1,
+                         precision=precision)
+    g.seed_explicit(species, [3], [0.25], [p0], [9])
+    ps, xs = [], []
+    for _ in range(n_steps):
+        assert g.step(1) == oracle.OK
+        P = g.particles(species)
+        ps.append(P["p"][0])
+        xs.append(P["cell"][0] + P["off"][0])
+    return np.array(ps), np.array(xs)
+
+
+def test_test_particle_momentum_closed_form():
+    """Weight 0 (no current) in a uniform field: p^{n+1/2} = p0 + (n+1) q E0 dt,
+    to within one rounding per step."""
+    e0, dt, p0 = 3.0, 0.3, -2.5
+    for species, q in ((0, -1.0), (1, 1.0)):
+        ps, _ = _test_particle(e0, dt, 400, p0=p0, species=species)
+        n = np.arange(400)
+        exact = p0 + (n + 1) * q * e0 * dt
+        ulp = np.spacing(np.abs(exact) + 1.0)
+        assert np.all(np.abs(ps - exact) <= (n + 2) * ulp)
+
+
+def test_test_particle_position_second_order():
+    """x(t) = x0 + (gamma(t) - gamma(t0)) / (q E0) for hyperbolic motion; the
+    leapfrog error at fixed time falls by ~4 when dt is halved."""
+    e0 = 0.5
+    T = 12.0
+    errs = []
+    for dt in (0.2, 0.1, 0.05):
+        n = int(round(T / dt))
+        ps, xs = _test_particle(e0, dt, n, p0=0.0, species=1)
+        # exact: p(t) = E0 (t + dt/2) from p(-dt/2) = 0; position at t = n dt
+        t_end = n * dt
+        p_exact0 = e0 * dt / 2
+        g0 = math.sqrt(1 + p_exact0**2)
+        g1 = math.sqrt(1 + (e0 * (t_end + dt / 2)) ** 2)
+        # the particle drifts across the periodic box: unwrap by cell count
+        x_exact = 3.25 + (g1 - g0) / e0
+        x_num = xs[-1]
+        wraps = round((x_exact - x_num) / 64.0)
+        errs.append(abs(x_num + 64.0 * wraps - x_exact))
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 3.5 < r1 < 4.5 and 3.5 < r2 < 4.5, errs
+
+
+# ------------------------------------------------------------------- Gauss
+@pytest.mark.parametrize("boundary", [oracle.ABSORBING, oracle.PERIODIC])
+@pytest.mark.parametrize("precision", [oracle.FP64, oracle.MIXED])
+def test_gauss_residual_at_roundoff(boundary, precision):
+    """The charge-conserving deposit keeps E_c - E_{c-1} = rho_c at every
+    (interior) node, to round-off accumulated by the field update."""
+    g = oracle.OracleGap(n_cells=128, dx=1.0, dt=0.45, boundary=boundary, e0=20.0,
+                         gamma_thr=60.0, f=0.5, l_gamma=8.0, weight=0.5, seed=11,
+                         precision=precision)
+    g.seed(oracle.SEED_RANDOM, 256, 1)
+    steps = 300
+    assert g.step(steps) == oracle.OK
+    F = g.fields()
+    E, rho = F["E"], F["rho"]
+    if boundary == oracle.PERIODIC:
+        r = (E - np.roll(E, 1)) - rho[:-1]
+    else:
+        r = (E[1:] - E[:-1]) - rho[1:-1]
+    bound = 10 * np.finfo(float).eps * steps * np.abs(E).max()
+    assert np.abs(r).max() <= bound
+    assert g.history()["pairs_created"][-1] > 256  # the cascade did run
+
+
+# ----------------------------------------------------------- uniform drift
+def test_uniform_lattice_drift_flux_is_uniform_and_exact():
+    """A lattice of one species drifting at one velocity in zero field puts the
+    same integer flux m * dq through every cell (m macros per cell)."""
+    m, nc = 4, 32
+    dt, dx, p = 0.45, 1.0, 3.7
+    g = oracle.OracleGap(n_cells=nc, dx=dx, dt=dt, boundary=oracle.PERIODIC, e0=0.0,
+                         gamma_thr=1e300, f=0.5, l_gamma=0.0, weight=0.0, seed=1)
+    N = m * nc
+    x = np.floor((np.arange(N) + 0.5) * (nc / N) * 2**24).astype(np.int64)
+    g.seed_explicit(0, x >> 24, (x & 0xFFFFFF) / 2**24, np.full(N, p), np.arange(N) * 2)
+    K = g.offset_bits
+    for _ in range(5):
+        assert g.step(1) == oracle.OK
+        flux = g.fields()["flux"]
+        v = p / math.sqrt(1 + p * p)
+        dq = round(v * (dt / dx) * 2**K)
+        assert np.all(flux == -m * dq)
+
+
+# ------------------------------------------------------------- cold plasma
+def test_cold_plasma_frequency_matches_leapfrog_dispersion():
+    """Uniform co-located pairs (n per species) in a small uniform field
+    oscillate at sin(omega dt/2) = omega_p dt/2, omega_p^2 = 2n."""
+    from scipy.optimize import curve_fit
+    nc, dx, dt, e0 = 8, 1.0, 0.45, 1e-3
+    g = oracle.OracleGap(n_cells=nc, dx=dx, dt=dt, boundary=oracle.PERIODIC, e0=e0,
+                         gamma_thr=1e300, f=0.5, l_gamma=0.0, weight=1.0, seed=1)
+    g.seed(oracle.SEED_LATTICE, nc, 1)
+    n_per_species = 1.0 * 1 / dx
+    omega = A.leapfrog_cold_frequency(n_per_species, dt)
+    periods = 24
+    steps = int(periods * 2 * math.pi / omega / dt)
+    assert g.step(steps) == oracle.OK
+    Em = g.history()["e_mean"]
+    t = np.arange(1, steps + 1) * dt
+
+    def model(t, a, w, ph, b):
+        return a * np.cos(w * t + ph) + b
+
+    p0 = (e0, omega * (1 + 1e-4), 0.0, 0.0)
+    # initial phase from the first sample
+    popt, _ = curve_fit(model, t, Em, p0=p0, maxfev=20000)
+    assert abs(popt[1] / omega - 1.0) < 1e-6
+    # and the continuum frequency sqrt(2n) is measurably different
+    assert abs(popt[1] / math.sqrt(2 * n_per_species) - 1.0) > 1e-2
+
+
+# ------------------------------------------------------------ brute force
+@pytest.mark.parametrize("l_gamma,absorbing", [(0.0, True), (6.0, True), (6.0, False)])
+def test_frozen_field_tree_matches_brute_force(l_gamma, absorbing):
+    """Zero weight freezes E at E0; per-step lepton, photon, conversion, escape
+    and absorption counts and every final lepton agree exactly with an
+    independent lineage-by-lineage simulation using numpy's Philox."""
+    prm = dict(n_cells=48, dx=1.0, dt=0.45,
+               boundary=oracle.ABSORBING if absorbing else oracle.PERIODIC,
+               e0=50.0, gamma_thr=100.0, f=0.5, l_gamma=l_gamma, weight=0.0, seed=2012055870)
+    steps = 32 if l_gamma == 0.0 else 60
+    g = oracle.OracleGap(**prm)
+    g.seed(oracle.SEED_RANDOM, 3, 1)
+    seeds = []
+    for s in (0, 1):
+        P = g.particles(s)
+        for c, o, p, i in zip(P["cell"], P["off"], P["p"], P["id"]):
+            seeds.append((s, int(c), int(round(o * 2**40)), float(p), int(i)))
+    assert g.step(steps) == oracle.OK
+    ref = brute_tree.run(prm["n_cells"], prm["dx"], prm["dt"], absorbing, prm["e0"],
+                         prm["gamma_thr"], prm["f"], l_gamma, seeds, steps, prm["seed"])
+    h = g.history()
+    for key in ("n_minus", "n_plus", "n_photons", "photons_emitted", "photons_escaped",
+                "pairs_created", "absorbed_minus", "absorbed_plus"):
+        assert np.array_equal(h[key], ref[key]), key
+    final = {}
+    for s in (0, 1):
+        P = g.particles(s)
+        for c, o, p, i in zip(P["cell"], P["off"], P["p"], P["id"]):
+            final[int(i)] = (s, int(c), int(round(o * 2**40)), float(p))
+    assert final == ref["final"]
+    assert h["pairs_created"][-1] > 20
+
+
+# ------------------------------------------------------------ bookkeeping
+def test_pair_and_photon_bookkeeping_invariants():
+    """N- - N+ changes only by absorption; every emitted photon is in flight,
+    converted or escaped; lost energy only grows."""
+    g = oracle.OracleGap(n_cells=512, dx=1.0, dt=0.45, boundary=oracle.ABSORBING, e0=50.0,
+                         gamma_thr=100.0, f=0.5, l_gamma=20.0, weight=1.0, seed=2012055870)
+    g.seed(oracle.SEED_RANDOM, 64, 16)
+    assert g.step(400) == oracle.OK
+    h = g.history()
+    assert np.all((h["n_minus"] - h["n_plus"]) == -(h["absorbed_minus"] - h["absorbed_plus"]))
+    assert np.all(h["photons_emitted"] == h["n_photons"] + h["pairs_created"] + h["photons_escaped"])
+    assert np.all(np.diff(h["lost_energy"]) >= 0)
+    assert np.all(np.diff(h["pairs_created"]) >= 0)
+
+
+def test_emission_conserves_energy_in_frozen_field():
+    """In a frozen field the only energy source is the work q E0 v dt; emission
+    itself moves gamma_pair from the emitter to the pair exactly (in-place)."""
+    e0, dt = 50.0, 0.45
+    g = oracle.OracleGap(n_cells=4096, dx=1.0, dt=dt, boundary=oracle.PERIODIC, e0=e0,
+                         gamma_thr=100.0, f=0.5, l_gamma=0.0, weight=1e-300, seed=3)
+    g.seed(oracle.SEED_RANDOM, 2, 1)
+    prev = None
+    for _ in range(30):
+        before = {s: g.particles(s) for s in (0, 1)}
+        assert g.step(1) == oracle.OK
+        after = {s: g.particles(s) for s in (0, 1)}
+        # energy before emission of each pushed lepton = gamma(p_old + q E0 dt)
+        e_pushed = 0.0
+        for s, q in ((0, -1.0), (1, 1.0)):
+            pn = before[s]["p"] + q * e0 * dt
+            e_pushed += np.sum(np.sqrt(1 + pn * pn))
+        e_after = sum(np.sum(np.sqrt(1 + after[s]["p"] ** 2)) for s in (0, 1))
+        tot = e_after
+        assert abs(tot - e_pushed) <= 1e-9 * e_pushed
+        prev = tot
+    assert prev is not None and g.count(0) > 2
+
+
+def test_invalid_parameters_rejected():
+    base = dict(n_cells=16, dx=1.0, dt=0.45, boundary=0, e0=1.0, gamma_thr=100.0, f=0.5,
+                l_gamma=0.0, weight=1.0, seed=1)
+    assert oracle.validate(**base) == oracle.OK
+    for k, v in [("dt", 1.0), ("dt", 1.5), ("f", 0.01), ("f", 1.0), ("gamma_thr", 1.0),
+                 ("n_cells", 1), ("boundary", 7), ("l_gamma", -1.0), ("weight", -1.0),
+                 ("e0", float("nan"))]:
+        assert oracle.validate(**{**base, k: v}) == oracle.ERR_ARG, k
+
+
+# -------------------------------------------------------- analytic physics
+@pytest.mark.parametrize("f,steps", [(0.1, 560), (0.01, 2300)])
+def test_frozen_field_growth_rate_matches_population_model(f, steps):
+    """Section 3: in a uniform field the cascade grows as exp(Gamma t) with
+    Gamma the root of Eqs. 1-2 (Gamma t_a -> W(2/f) for small f)."""
+    gthr, e0 = 500.0, 1.0
+    ta = gthr / e0
+    dt = 0.1 * f * ta          # t_p / dt = 10
+    g = oracle.OracleGap(n_cells=4, dx=2 * dt, dt=dt, boundary=oracle.PERIODIC, e0=e0,
+                         gamma_thr=gthr, f=f, l_gamma=0.0, weight=0.0, seed=1)
+    g.seed(oracle.SEED_RANDOM, 1, 1)
+    assert g.step(steps) == oracle.OK
+    h = g.history()
+    n = h["n_minus"].astype(float)
+    t = (h["step"] + 1) * dt
+    sel = t > 1.5 * ta
+    G = np.polyfit(t[sel], np.log(n[sel]), 1)[0]
+    exact = A.growth_rate_exact(f, ta)
+    assert abs(G / exact - 1.0) < 0.10, (G, exact)
+    # the Lambert form of Eq. 3 is the small-f limit of the same root
+    assert abs(A.growth_rate_lambert(f, ta) / exact - 1.0) < 0.05
+
+
+@pytest.fixture(scope="module")
+def screening_run():
+    """Self-consistent, resolved screening run: periodic, in-place pairs,
+    f = 0.1, t_p/dt = 10, ~300 macros per cell per species at n_s."""
+    f, e0, gthr, dt, dx, nc = 0.1, 100.0, 100.0, 0.01, 0.1, 40
+    ns = A.screening_density(e0, gthr, f)
+    w = ns * dx / 300.0
+    g = oracle.OracleGap(n_cells=nc, dx=dx, dt=dt, boundary=oracle.PERIODIC, e0=e0,
+                         gamma_thr=gthr, f=f, l_gamma=0.0, weight=w, seed=7)
+    g.seed(oracle.SEED_RANDOM, nc, 1)
+    snaps = []
+    for _ in range(240):
+        assert g.step(5) == oracle.OK
+        P = np.concatenate([g.particles(0)["p"], g.particles(1)["p"]])
+        gam = np.sqrt(1 + P * P)
+        snaps.append((g.steps_done - 1, gam.mean(), np.mean(gam ** -3.0)))
+    return dict(g=g, h=g.history(), snaps=np.array(snaps), f=f, e0=e0, gthr=gthr, dt=dt,
+                dx=dx, nc=nc, w=w, ns=ns)
+
+
+def test_screening_density_eq5(screening_run):
+    """Eq. 5 overestimates the density at screening by a factor 1.5-2."""
+    r = screening_run
+    h = r["h"]
+    i_s = int(np.argmax(h["e_mean"] < 0))
+    assert i_s > 0
+    n_at_s = h["n_minus"][i_s] * r["w"] / (r["nc"] * r["dx"])
+    ratio = n_at_s / r["ns"]
+    assert 0.35 <= ratio <= 1.0, ratio
+
+
+def test_energy_balance_and_mean_gamma(screening_run):
+    """Section 4: at screening the field energy E0^2/8pi has gone to the
+    leptons, n_s <gamma> m c^2 = E0^2/8pi, with <gamma> ~ gamma_thr/ln(2/f)."""
+    r = screening_run
+    h = r["h"]
+    i_s = int(np.argmax(h["e_mean"] < 0))
+    field0 = r["e0"] ** 2 / 2 * r["nc"] * r["dx"]
+    assert abs(h["kinetic"][i_s] / field0 - 1.0) < 0.25
+    snaps = r["snaps"]
+    j = int(np.argmin(np.abs(snaps[:, 0] - i_s)))
+    assert abs(snaps[j, 1] / A.mean_gamma(r["gthr"], r["f"]) - 1.0) < 0.25
+
+
+def test_oscillation_frequency_relativistic(screening_run):
+    """Section 5: after screening <E> oscillates at omega_0 = sqrt(2 n <1/gamma^3>)
+    (normalised), with n and <1/gamma^3> measured from the particles."""
+    r = screening_run
+    h = r["h"]
+    Em = h["e_mean"]
+    zc = np.where(np.diff(np.sign(Em)) != 0)[0]
+    assert len(zc) >= 5
+    # two full periods after the first reversal
+    a, b = zc[0], zc[4]
+    omega_meas = 2 * 2 * math.pi / ((b - a) * r["dt"])
+    snaps = r["snaps"]
+    sel = (snaps[:, 0] >= a) & (snaps[:, 0] < b)
+    inv_g3 = snaps[sel, 2].mean()
+    n = h["n_minus"][a:b].mean() * r["w"] / (r["nc"] * r["dx"])
+    omega_th = A.relativistic_plasma_frequency(n, inv_g3)
+    assert abs(omega_meas / omega_th - 1.0) < 0.15, (omega_meas, omega_th)
+
+
+def test_energy_conserved_in_resolved_run(screening_run):
+    """Total energy (leptons, field, photons, losses) drifts by well under 1%
+    in the resolved run (leapfrog error only)."""
+    h = screening_run["h"]
+    tot = h["kinetic"] + h["field"] + h["photon_energy"] + h["lost_energy"]
+    assert np.max(np.abs(tot / tot[0] - 1.0)) < 1e-2
