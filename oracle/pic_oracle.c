@@ -383,7 +383,7 @@ static int step_once(orc_gap* g) {
       double p = R(g, S->p[i] + R(g, qdt * Epart));
       double gam = R(g, sqrt(R(g, 1.0 + R(g, p * p))));
       double v = R(g, p / gam);
-      if (!isfinite(p)) nonfinite = 1;
+      if (!isfinite(p) || !isfinite(gam)) nonfinite = 1;
       /* move: displacement in cells, rounded to the 2^-K grid */
       double d = R(g, v * dtdx);
       int64_t dq = (int64_t)rint(d * scale);
@@ -421,6 +421,11 @@ static int step_once(orc_gap* g) {
         g->lost_energy += P->weight * sqrt(1.0 + p * p);
       }
     }
+  }
+
+  if (nonfinite) {
+    for (int s = 0; s < 2; ++s) { free(alive[s]); free(gam_new[s]); }
+    return ORC_ERR_NONFINITE;
   }
 
   /* 4. Ampere: E^{n+1} = E^n - J dt, with J dt = w * F * 2^-K. */
@@ -463,7 +468,7 @@ static int step_once(orc_gap* g) {
         if (absorbing) {
           if (X < 0 || X >= domain) {
             g->photons_escaped++;
-            g->lost_energy += P->weight * gpair;
+            g->lost_energy += P->weight * (P->f * P->gamma_thr);
             continue;
           }
         } else {
@@ -508,7 +513,6 @@ static int step_once(orc_gap* g) {
   /* 7. Capacity: the step that overflows is not completed. */
   if (P->capacity > 0 && (g->sp[0].n > P->capacity || g->sp[1].n > P->capacity))
     return ORC_ERR_CAPACITY;
-  if (nonfinite) return ORC_ERR_NONFINITE;
 
   /* 8. Diagnostics of the completed step. */
   record_history(g);
