@@ -1,0 +1,154 @@
+"""Benchmark of the MI355X pair-cascade PIC path: particle-pushes per second.
+
+One step is one PIC time step of the whole path (gather and push, move and
+current deposit, Ampere update, emission, conversion, periodic re-sort) for
+every lepton of the workload.  A push is one lepton advanced one step,
+counted exactly by the device.  The default workload is the binary64 single
+gap of 8192 cells seeded with 1024 pairs (E0 = 200, gamma_thr = 200,
+l_gamma = 50 cells, absorbing), run for its 20000 steps with inputs resident
+in HBM; the same physics in mixed precision is timed beside it.
+
+Prints one JSON line.  The roofline entry is for the push kernel, which
+moves the lepton state: 4 B cell + 8 B offset + 8 B momentum read and written
+(40 B per push) in binary64, 24 B per push in mixed precision.  Its time is
+summed from HIP events bracketing every push launch on the library's stream.
+The cpu_baseline entry times the oracle (single thread) on the first steps of
+the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import workloads  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_PUSH = {workloads.FP64: 40, workloads.MIXED: 24}
+DTYPE = {workloads.FP64: "f64", workloads.MIXED: "f32/f64"}
+
+
+def _params(P, c):
+    return P.make_params(c["n_cells"], c["dx"], c["dt"], c["boundary"], c["e0"], c["gamma_thr"],
+                         c["f"], c["l_gamma"], c["weight"], int(c["capacity"]),
+                         int(c["photon_capacity"]), c["seed"], c["precision"],
+                         c.get("sort_every", 0), c.get("diag_every", 0), c.get("history_rows", 0))
+
+
+def run_gpu(cfg, steps, warmup):
+    import torch
+    import paper_2012_05587_amd as P
+    P.lib()
+    stream = torch.cuda.Stream()
+    if warmup > 0:
+        w = P.Gap(_params(P, cfg), stream=stream)
+        w.seed_particles(workloads.SEED_RANDOM, cfg["n_pairs"], cfg["macro_per_pair"])
+        w.step_n(warmup)
+        torch.cuda.synchronize()
+        w.close()
+        del w
+    g = P.Gap(_params(P, cfg), stream=stream)
+    g.seed_particles(workloads.SEED_RANDOM, cfg["n_pairs"], cfg["macro_per_pair"])
+    g.profile_push(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.step_n(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    push_ms, launches = g.read_push_time()
+    m = g.read_moments()
+    h = g.read_history()
+    out = dict(seconds=t1 - t0, pushes=int(m.pushes), steps=int(m.steps_done), status=int(m.status),
+               push_ms=push_ms, push_launches=launches,
+               peak_leptons=int((h["n_minus"] + h["n_plus"]).max()) if len(h) else 0,
+               final_leptons=int(m.n_minus + m.n_plus))
+    g.close()
+    return out
+
+
+def run_cpu_baseline(cfg, steps):
+    import oracle
+    kw = {k: cfg[k] for k in workloads.GAP_KEYS}
+    g = oracle.OracleGap(**kw, capacity=0)
+    g.seed(workloads.SEED_RANDOM, cfg["n_pairs"], cfg["macro_per_pair"])
+    n0 = g.count(0) + g.count(1)
+    t0 = time.perf_counter()
+    st = g.step(steps)
+    t1 = time.perf_counter()
+    h = g.history()
+    live = (h["n_minus"] + h["n_plus"]).astype("int64")
+    pushes = int(n0 + live[:-1].sum()) if len(live) else 0
+    return dict(value=pushes / (t1 - t0), seconds=t1 - t0, pushes=pushes, status=st)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default: whole run)")
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="c2_fp64_single_gap")
+    ap.add_argument("--cpu-steps", type=int, default=300)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this path runs on one GPU; --gpus {args.gpus} is not supported "
+              "(independent gaps shard across GPUs without communication; not built here)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    cfg = workloads.config(args.workload)
+    steps = args.steps if args.steps is not None else cfg["steps"]
+    main_run = run_gpu(cfg, steps, args.warmup)
+    value = main_run["pushes"] / main_run["seconds"]
+    bpp = BYTES_PER_PUSH[cfg["precision"]]
+    achieved = main_run["pushes"] * bpp / (main_run["push_ms"] * 1e-3) / 1e9 if main_run["push_ms"] else 0.0
+
+    extra = {}
+    if not args.no_mixed and cfg["precision"] == workloads.FP64:
+        mcfg = dict(cfg, precision=workloads.MIXED)
+        mr = run_gpu(mcfg, steps, 0)
+        extra["mixed_same_workload"] = dict(
+            value=mr["pushes"] / mr["seconds"], unit="pushes/s", pushes=mr["pushes"],
+            seconds=mr["seconds"], push_kernel_GBs=mr["pushes"] * 24 / (mr["push_ms"] * 1e-3) / 1e9
+            if mr["push_ms"] else None, status=mr["status"])
+
+    cpu = None
+    if not args.no_cpu:
+        cb = run_cpu_baseline(cfg, min(args.cpu_steps, steps))
+        cpu = dict(value=cb["value"], unit="pushes/s", cores=1, kind="oracle",
+                   sample=f"first {min(args.cpu_steps, steps)} steps of {args.workload} "
+                          f"({cb['pushes']} pushes, {cb['seconds']:.1f} s, single thread)")
+
+    line = {
+        "metric": "particle-pushes/sec + % HBM roofline, mixed-batched vs plain FP64, 1 MI355X",
+        "value": value,
+        "unit": "pushes/s",
+        "n_gpus": 1,
+        "steps": main_run["steps"],
+        "warmup": args.warmup,
+        "ms_per_step": main_run["seconds"] * 1e3 / max(main_run["steps"], 1),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPE[cfg["precision"]],
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n_cells": cfg["n_cells"], "seed_pairs": cfg["n_pairs"],
+                   "e0": cfg["e0"], "gamma_thr": cfg["gamma_thr"], "l_gamma": cfg["l_gamma"],
+                   "steps": steps, "peak_leptons": main_run["peak_leptons"],
+                   "pushes": main_run["pushes"], "status": main_run["status"]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_push", "bytes_per_push": bpp,
+                     "kernel_ms": main_run["push_ms"], "launches": main_run["push_launches"]},
+        "cpu_baseline": cpu,
+    }
+    line.update(extra)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

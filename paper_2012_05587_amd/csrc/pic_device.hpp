@@ -1,0 +1,135 @@
+// Internal header of the MI355X pair-cascade PIC library: the per-gap
+// descriptor that lives in device memory, launch constants, and device
+// helpers (Philox4x64-10, wave-level scans).  Not part of the C-ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pic.h"
+
+namespace pic {
+
+constexpr int kBlock = 256;           // threads per workgroup (4 wave64)
+constexpr int kItems = 4;             // particles per thread per work item
+constexpr int kChunk = kBlock * kItems;
+constexpr int kTile = 2048;           // cells of the per-workgroup LDS current tile
+constexpr int kPhChunk = kBlock * 4;  // photons per convert work item
+constexpr int kCellChunk = kBlock * 4;
+constexpr int32_t kDead = INT32_MIN;  // cell of an absorbed lepton until re-sort
+constexpr int kMaxEmit = 64;
+constexpr uint64_t kTagSeed = 1, kTagPhoton = 2;
+
+// One gap, in device memory.  The host fills the constant part at creation;
+// kernels update the counters.  Particle and photon arrays are double
+// buffered; `buf` selects the live copy and flips at each re-sort.
+struct GapDev {
+  // ---- constants
+  int32_t n_cells, boundary, K, table_len;
+  int32_t precision, diag_every, hist_rows, pad0;
+  int64_t one, domain, photon_step, cap, ph_cap;
+  double dt, dx, weight, wq, e0;
+  double dtdx, gthr, gpair, pchild;  // values exactly representable in the particle type
+  double gpair64, child_gamma64;     // binary64 pair energy and child gamma for diagnostics
+  uint64_t seed;
+  double* E;
+  long long* F;
+  long long* F_last;
+  long long* rho_acc;
+  uint32_t* table;
+  int32_t* sort_cnt[2];
+  pic_history_row* hist;
+  int32_t* cell[2][2];  // [buf][species]
+  void* off[2][2];
+  void* p[2][2];
+  uint64_t* id[2][2];
+  long long* ph_x[2];
+  int32_t* ph_step[2];
+  uint64_t* ph_child[2];  // electron id with bit 0 = (direction > 0)
+
+  // ---- counters (device-updated)
+  unsigned long long n[2];       // slots in use at step start
+  unsigned long long n_next[2];  // append cursor
+  unsigned long long dead[2];    // absorbed slots since the last re-sort
+  unsigned long long live[2];    // live leptons after the last completed step
+  unsigned long long n_ph, n_ph_next, inflight;
+  unsigned long long pairs_created, photons_emitted, photons_escaped, absorbed[2];
+  unsigned long long pushes;
+  unsigned long long hist_count;
+  unsigned long long sorted_n[2], ph_sorted;
+  long long step;
+  int32_t status, buf, phbuf, pad2;
+  int32_t overflow, nonfinite, emit_err, pad1;
+  double lost_energy;
+  double ke_acc, fe_acc, es_acc;
+  pic_history_row last;
+};
+
+// ---------------------------------------------------------------- Philox
+// Philox4x64-10 (Salmon, Moraes, Dror & Shaw, SC'11): ten rounds of two
+// 64x64->128 multiplies with a key schedule bumped by the Weyl constants.
+struct U64x4 { uint64_t v[4]; };
+
+__device__ __forceinline__ U64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2,
+                                               uint64_t c3, uint64_t k0, uint64_t k1) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) { k0 += W0; k1 += W1; }
+    uint64_t hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
+    uint64_t hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
+    uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+  }
+  U64x4 o;
+  o.v[0] = c0; o.v[1] = c1; o.v[2] = c2; o.v[3] = c3;
+  return o;
+}
+
+// ---------------------------------------------------------- wave helpers
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// Inclusive prefix sum over the 64 lanes of a wave.
+template <typename I>
+__device__ __forceinline__ I wave_incl_scan(I x) {
+  const int l = lane_id();
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    I y = __shfl_up(x, d, 64);
+    if (l >= d) x += y;
+  }
+  return x;
+}
+
+template <typename V>
+__device__ __forceinline__ V wave_sum(V x) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+  return x;
+}
+
+// Locate the gap owning work item w: largest g with start[g] <= w.
+__device__ __forceinline__ int find_gap(const long long* __restrict__ start, int B, long long w) {
+  int lo = 0, hi = B - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= w) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Contiguous share of `total` work items for this workgroup, with the
+// workgroup index remapped so that each of the 8 XCDs (which receive
+// workgroups round-robin) walks one contiguous eighth of the items and keeps
+// the field lines of its cells in its own L2.
+__device__ __forceinline__ void xcd_range(long long total, long long& w0, long long& w1) {
+  const int nb = gridDim.x, b = blockIdx.x;
+  int lb = b;
+  if ((nb & 7) == 0) lb = (b & 7) * (nb >> 3) + (b >> 3);
+  long long per = (total + nb - 1) / nb;
+  w0 = (long long)lb * per;
+  w1 = w0 + per < total ? w0 + per : total;
+}
+
+}  // namespace pic

@@ -1,0 +1,31 @@
+// Launchers of the device kernels, called by the host runtime.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "pic_device.hpp"
+
+namespace pic {
+
+struct StepLaunch {
+  GapDev* gaps;        // device array of B descriptors
+  long long* wi;       // particle work-item prefix, B + 1 entries (device)
+  long long* pwi;      // photon work-item prefix, B + 1 entries (device)
+  long long* cwi;      // cell work-item prefix, B + 1 entries (device, static)
+  long long cell_items;
+  int B;
+  int push_grid, conv_grid;
+  hipStream_t stream;
+};
+
+hipError_t launch_step(const StepLaunch& L, bool mixed);
+hipError_t launch_push(const StepLaunch& L, bool mixed);
+hipError_t launch_step_after_push(const StepLaunch& L, bool mixed);
+hipError_t launch_sort(const StepLaunch& L, bool mixed);
+hipError_t launch_plan(const StepLaunch& L);
+hipError_t launch_seed(GapDev* gaps, int g, int mode, long long N, double p0m, double p0p,
+                       long long base0, long long base1, bool mixed, hipStream_t st);
+hipError_t launch_rho(GapDev* gaps, int g, long long* rho_acc, long long n_nodes, bool mixed,
+                      hipStream_t st);
+
+}  // namespace pic

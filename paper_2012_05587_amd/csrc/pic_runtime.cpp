@@ -1,0 +1,760 @@
+// Host runtime and C-ABI of the pair-cascade PIC library (see include/pic.h).
+//
+// A gap is a batch of one.  The runtime validates parameters, carves the
+// caller's device workspace into the per-gap arrays, fills the device
+// descriptors, and enqueues the step kernels on the caller's stream (as a
+// replayed HIP graph once the sequence is known).  It never allocates
+// device memory.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "pic.h"
+#include "pic_device.hpp"
+#include "pic_kernels.hpp"
+
+using pic::GapDev;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kDefaultSort = 20;
+constexpr int kDefaultHist = 4096;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct GapLayout {
+  size_t E, F, F_last, rho, table, sort_cnt[2], hist;
+  size_t cell[2][2], off[2][2], p[2][2], id[2][2];
+  size_t ph_x[2], ph_step[2], ph_child[2];
+  size_t end;
+  int64_t table_len;
+};
+
+struct Layout {
+  size_t gaps, wi, pwi, cwi, total;
+  std::vector<GapLayout> g;
+  long long cell_items;
+};
+
+int offset_bits(int precision) { return precision == PIC_MIXED ? 24 : 40; }
+
+// Photon conversion table T_k = floor(exp(-k dt / (l_gamma dx)) 2^32), until 0.
+int64_t table_length(const pic_gap_params& p) {
+  if (!(p.l_gamma > 0.0)) return 0;
+  const double r = p.dt / (p.l_gamma * p.dx);
+  // the entries vanish once k r > 32 ln 2
+  return (int64_t)std::ceil(32.0 * std::log(2.0) / r) + 3;
+}
+
+std::vector<uint32_t> build_table(const pic_gap_params& p) {
+  std::vector<uint32_t> t;
+  if (!(p.l_gamma > 0.0)) return t;
+  const double r = p.dt / (p.l_gamma * p.dx);
+  for (int64_t k = 0;; ++k) {
+    const double v = std::floor(std::ldexp(std::exp(-((double)k * r)), 32));
+    t.push_back(v >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)v);
+    if (v == 0.0) break;
+  }
+  return t;
+}
+
+int hist_rows_of(const pic_gap_params& p) { return p.history_rows > 0 ? p.history_rows : kDefaultHist; }
+
+pic_status validate(const pic_gap_params* p) {
+  if (!p) return PIC_ERR_ARG;
+  if (p->n_cells < 2 || p->n_cells > (1 << 22)) return PIC_ERR_ARG;
+  if (!(p->dx > 0.0) || !(p->dt > 0.0) || !(p->dt < p->dx) || !std::isfinite(p->dx)) return PIC_ERR_ARG;
+  if (p->boundary != PIC_BC_PERIODIC && p->boundary != PIC_BC_ABSORBING) return PIC_ERR_ARG;
+  if (!std::isfinite(p->e0)) return PIC_ERR_ARG;
+  if (!(p->gamma_thr > 1.0) || !(p->f > 0.0) || !(p->f < 1.0)) return PIC_ERR_ARG;
+  if (std::isfinite(p->gamma_thr)) {
+    if (!(p->f * p->gamma_thr >= 2.0)) return PIC_ERR_ARG;
+    if (!((1.0 - p->f) * p->gamma_thr >= 1.0)) return PIC_ERR_ARG;
+  }
+  if (!(p->l_gamma >= 0.0) || !std::isfinite(p->l_gamma)) return PIC_ERR_ARG;
+  if (!(p->weight >= 0.0) || !std::isfinite(p->weight)) return PIC_ERR_ARG;
+  if (p->capacity < 1 || p->capacity >= (int64_t)1 << 31) return PIC_ERR_ARG;
+  if (p->photon_capacity < 0 || p->photon_capacity >= (int64_t)1 << 31) return PIC_ERR_ARG;
+  if (p->l_gamma > 0.0 && p->photon_capacity < 1) return PIC_ERR_ARG;
+  if (p->precision != PIC_FP64 && p->precision != PIC_MIXED) return PIC_ERR_ARG;
+  if (p->sort_every < 0 || p->diag_every < 0 || p->history_rows < 0) return PIC_ERR_ARG;
+  if (table_length(*p) > (int64_t)1 << 28) return PIC_ERR_ARG;
+  return PIC_OK;
+}
+
+Layout make_layout(const pic_gap_params* prm, int B) {
+  Layout L;
+  size_t o = 0;
+  L.gaps = o; o = align_up(o + sizeof(GapDev) * (size_t)B);
+  L.wi = o; o = align_up(o + sizeof(long long) * (size_t)(B + 1));
+  L.pwi = o; o = align_up(o + sizeof(long long) * (size_t)(B + 1));
+  L.cwi = o; o = align_up(o + sizeof(long long) * (size_t)(B + 1));
+  L.cell_items = 0;
+  const int prec = prm[0].precision;
+  const size_t tb = prec == PIC_MIXED ? 4 : 8;
+  const int hist = hist_rows_of(prm[0]);
+  L.g.resize((size_t)B);
+  for (int i = 0; i < B; ++i) {
+    const pic_gap_params& p = prm[i];
+    GapLayout& G = L.g[(size_t)i];
+    const size_t nc = (size_t)p.n_cells, cap = (size_t)p.capacity, pc = (size_t)p.photon_capacity;
+    G.E = o; o = align_up(o + 8 * nc);
+    G.F = o; o = align_up(o + 8 * nc);
+    G.F_last = o; o = align_up(o + 8 * nc);
+    G.rho = o; o = align_up(o + 8 * (nc + 1));
+    G.table_len = (int64_t)build_table(p).size();
+    G.table = o; o = align_up(o + 4 * (size_t)G.table_len);
+    for (int s = 0; s < 2; ++s) { G.sort_cnt[s] = o; o = align_up(o + 4 * nc); }
+    G.hist = o; o = align_up(o + sizeof(pic_history_row) * (size_t)hist);
+    for (int b = 0; b < 2; ++b)
+      for (int s = 0; s < 2; ++s) {
+        G.cell[b][s] = o; o = align_up(o + 4 * cap);
+        G.off[b][s] = o; o = align_up(o + tb * cap);
+        G.p[b][s] = o; o = align_up(o + tb * cap);
+        G.id[b][s] = o; o = align_up(o + 8 * cap);
+      }
+    for (int b = 0; b < 2; ++b) {
+      G.ph_x[b] = o; o = align_up(o + 8 * pc);
+      G.ph_step[b] = o; o = align_up(o + 4 * pc);
+      G.ph_child[b] = o; o = align_up(o + 8 * pc);
+    }
+    G.end = o;
+    L.cell_items += ((long long)p.n_cells + pic::kCellChunk - 1) / pic::kCellChunk;
+  }
+  L.total = o;
+  return L;
+}
+
+template <typename T>
+void fill_precision_constants(GapDev& G, const pic_gap_params& p) {
+  const T gthr = (T)p.gamma_thr;
+  const T gpair = (T)(p.f * p.gamma_thr);
+  const T ghalf = gpair * (T)0.5;
+  const T pchild = std::sqrt(ghalf * ghalf - (T)1);
+  G.dtdx = (double)(T)(p.dt / p.dx);
+  G.gthr = (double)gthr;
+  G.gpair = (double)gpair;
+  G.pchild = (double)pchild;
+  G.child_gamma64 = std::sqrt(1.0 + G.pchild * G.pchild);
+}
+
+}  // namespace
+
+struct pic_gap {
+  pic_batch* b;
+  int idx;
+  bool standalone;
+};
+
+struct pic_batch {
+  int B = 0;
+  int precision = 0, sort_every = kDefaultSort, diag_every = 1, hist_rows = kDefaultHist;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  Layout L;
+  std::vector<pic_gap_params> prm;
+  std::vector<pic_gap> views;
+  std::vector<int32_t> known_status;
+  pic::StepLaunch launch{};
+  long long host_step = 0;
+  bool started = false;
+  hipGraphExec_t graph = nullptr;
+  hipGraph_t graph_tmpl = nullptr;
+  // push-kernel timing
+  bool profiling = false;
+  std::vector<hipEvent_t> ev;   // start/stop pairs, reused
+  size_t ev_used = 0;
+  double prof_ms = 0.0;
+  long long prof_launches = 0;
+};
+
+namespace {
+
+GapDev* dgaps(pic_batch* b) { return reinterpret_cast<GapDev*>(b->ws + b->L.gaps); }
+
+pic_status read_desc(pic_batch* b, int i, GapDev* out) {
+  if (hipMemcpyAsync(out, dgaps(b) + i, sizeof(GapDev), hipMemcpyDeviceToHost, b->stream) != hipSuccess)
+    return PIC_ERR_DEVICE;
+  if (hipStreamSynchronize(b->stream) != hipSuccess) return PIC_ERR_DEVICE;
+  b->known_status[(size_t)i] = out->status;
+  return PIC_OK;
+}
+
+pic_status write_desc(pic_batch* b, int i, const GapDev* in) {
+  if (hipMemcpyAsync(dgaps(b) + i, in, sizeof(GapDev), hipMemcpyHostToDevice, b->stream) != hipSuccess)
+    return PIC_ERR_DEVICE;
+  if (hipStreamSynchronize(b->stream) != hipSuccess) return PIC_ERR_DEVICE;
+  return PIC_OK;
+}
+
+pic_status copy_to_host(pic_batch* b, void* dst, const void* src, size_t bytes) {
+  if (bytes == 0) return PIC_OK;
+  if (hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, b->stream) != hipSuccess) return PIC_ERR_DEVICE;
+  return PIC_OK;
+}
+
+pic_status create_batch(const pic_gap_params* params, int n_gaps, void* d_ws, size_t ws_bytes,
+                        void* hip_stream, pic_batch** out) {
+  if (!params || !out || n_gaps < 1 || n_gaps > (1 << 16)) return PIC_ERR_ARG;
+  *out = nullptr;
+  for (int i = 0; i < n_gaps; ++i) {
+    if (validate(&params[i]) != PIC_OK) return PIC_ERR_ARG;
+    if (params[i].precision != params[0].precision || params[i].sort_every != params[0].sort_every ||
+        params[i].diag_every != params[0].diag_every || params[i].history_rows != params[0].history_rows)
+      return PIC_ERR_ARG;
+  }
+  Layout L = make_layout(params, n_gaps);
+  if (!d_ws || ws_bytes < L.total || (reinterpret_cast<uintptr_t>(d_ws) % kAlign) != 0)
+    return PIC_ERR_WORKSPACE;
+  pic_batch* b = new (std::nothrow) pic_batch();
+  if (!b) return PIC_ERR_ARG;
+  b->B = n_gaps;
+  b->precision = params[0].precision;
+  b->sort_every = params[0].sort_every > 0 ? params[0].sort_every : kDefaultSort;
+  b->diag_every = params[0].diag_every > 0 ? params[0].diag_every : 1;
+  b->hist_rows = hist_rows_of(params[0]);
+  b->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  b->ws = reinterpret_cast<char*>(d_ws);
+  b->ws_bytes = ws_bytes;
+  b->L = L;
+  b->prm.assign(params, params + n_gaps);
+  b->known_status.assign((size_t)n_gaps, PIC_OK);
+  b->views.resize((size_t)n_gaps);
+  for (int i = 0; i < n_gaps; ++i) b->views[(size_t)i] = pic_gap{b, i, false};
+
+  std::vector<GapDev> host((size_t)n_gaps);
+  std::vector<long long> cwi((size_t)n_gaps + 1, 0);
+  char* ws = b->ws;
+  pic_status st = PIC_OK;
+  for (int i = 0; i < n_gaps && st == PIC_OK; ++i) {
+    const pic_gap_params& p = params[i];
+    const GapLayout& GL = L.g[(size_t)i];
+    GapDev& G = host[(size_t)i];
+    std::memset(&G, 0, sizeof G);
+    G.n_cells = p.n_cells;
+    G.boundary = p.boundary;
+    G.K = offset_bits(p.precision);
+    G.precision = p.precision;
+    G.diag_every = b->diag_every;
+    G.hist_rows = b->hist_rows;
+    G.one = (int64_t)1 << G.K;
+    G.domain = (int64_t)p.n_cells * G.one;
+    G.photon_step = (int64_t)std::rint(std::ldexp(p.dt / p.dx, G.K));
+    G.cap = p.capacity;
+    G.ph_cap = p.photon_capacity;
+    G.dt = p.dt;
+    G.dx = p.dx;
+    G.weight = p.weight;
+    G.wq = std::ldexp(p.weight, -G.K);
+    G.e0 = p.e0;
+    G.gpair64 = p.f * p.gamma_thr;
+    G.seed = p.seed;
+    if (p.precision == PIC_MIXED) fill_precision_constants<float>(G, p);
+    else fill_precision_constants<double>(G, p);
+    G.E = reinterpret_cast<double*>(ws + GL.E);
+    G.F = reinterpret_cast<long long*>(ws + GL.F);
+    G.F_last = reinterpret_cast<long long*>(ws + GL.F_last);
+    G.rho_acc = reinterpret_cast<long long*>(ws + GL.rho);
+    G.table = reinterpret_cast<uint32_t*>(ws + GL.table);
+    G.table_len = (int32_t)GL.table_len;
+    for (int s = 0; s < 2; ++s) G.sort_cnt[s] = reinterpret_cast<int32_t*>(ws + GL.sort_cnt[s]);
+    G.hist = reinterpret_cast<pic_history_row*>(ws + GL.hist);
+    for (int bb = 0; bb < 2; ++bb) {
+      for (int s = 0; s < 2; ++s) {
+        G.cell[bb][s] = reinterpret_cast<int32_t*>(ws + GL.cell[bb][s]);
+        G.off[bb][s] = ws + GL.off[bb][s];
+        G.p[bb][s] = ws + GL.p[bb][s];
+        G.id[bb][s] = reinterpret_cast<uint64_t*>(ws + GL.id[bb][s]);
+      }
+      G.ph_x[bb] = reinterpret_cast<long long*>(ws + GL.ph_x[bb]);
+      G.ph_step[bb] = reinterpret_cast<int32_t*>(ws + GL.ph_step[bb]);
+      G.ph_child[bb] = reinterpret_cast<uint64_t*>(ws + GL.ph_child[bb]);
+    }
+    cwi[(size_t)i + 1] = cwi[(size_t)i] + ((long long)p.n_cells + pic::kCellChunk - 1) / pic::kCellChunk;
+
+    // initial field and zeroed flux; conversion table
+    std::vector<double> E((size_t)p.n_cells, p.e0);
+    if (hipMemcpy(G.E, E.data(), 8 * (size_t)p.n_cells, hipMemcpyHostToDevice) != hipSuccess) st = PIC_ERR_DEVICE;
+    std::vector<long long> z((size_t)p.n_cells + 1, 0);
+    if (st == PIC_OK && hipMemcpy(G.F, z.data(), 8 * (size_t)p.n_cells, hipMemcpyHostToDevice) != hipSuccess) st = PIC_ERR_DEVICE;
+    if (st == PIC_OK && hipMemcpy(G.F_last, z.data(), 8 * (size_t)p.n_cells, hipMemcpyHostToDevice) != hipSuccess) st = PIC_ERR_DEVICE;
+    const std::vector<uint32_t> T = build_table(p);
+    if (st == PIC_OK && !T.empty() &&
+        hipMemcpy(G.table, T.data(), 4 * T.size(), hipMemcpyHostToDevice) != hipSuccess) st = PIC_ERR_DEVICE;
+  }
+  if (st == PIC_OK &&
+      hipMemcpy(dgaps(b), host.data(), sizeof(GapDev) * (size_t)n_gaps, hipMemcpyHostToDevice) != hipSuccess)
+    st = PIC_ERR_DEVICE;
+  b->launch.gaps = dgaps(b);
+  b->launch.wi = reinterpret_cast<long long*>(ws + L.wi);
+  b->launch.pwi = reinterpret_cast<long long*>(ws + L.pwi);
+  b->launch.cwi = reinterpret_cast<long long*>(ws + L.cwi);
+  b->launch.cell_items = L.cell_items;
+  b->launch.B = n_gaps;
+  b->launch.push_grid = 1024;
+  b->launch.conv_grid = 512;
+  b->launch.stream = b->stream;
+  if (st == PIC_OK &&
+      hipMemcpy(b->launch.cwi, cwi.data(), sizeof(long long) * cwi.size(), hipMemcpyHostToDevice) != hipSuccess)
+    st = PIC_ERR_DEVICE;
+  if (st == PIC_OK && pic::launch_plan(b->launch) != hipSuccess) st = PIC_ERR_DEVICE;
+  if (st == PIC_OK && hipStreamSynchronize(b->stream) != hipSuccess) st = PIC_ERR_DEVICE;
+  if (st != PIC_OK) {
+    delete b;
+    return st;
+  }
+  *out = b;
+  return PIC_OK;
+}
+
+pic_status append_counts(pic_batch* b, int g, long long add0, long long add1) {
+  GapDev G;
+  pic_status st = read_desc(b, g, &G);
+  if (st != PIC_OK) return st;
+  G.n[0] += (unsigned long long)add0; G.n_next[0] = G.n[0]; G.live[0] += (unsigned long long)add0;
+  G.n[1] += (unsigned long long)add1; G.n_next[1] = G.n[1]; G.live[1] += (unsigned long long)add1;
+  st = write_desc(b, g, &G);
+  if (st != PIC_OK) return st;
+  if (pic::launch_plan(b->launch) != hipSuccess) return PIC_ERR_DEVICE;
+  return hipStreamSynchronize(b->stream) == hipSuccess ? PIC_OK : PIC_ERR_DEVICE;
+}
+
+// Folds the recorded event pairs into the running total (synchronises).
+pic_status drain_events(pic_batch* b) {
+  if (b->ev_used == 0) return PIC_OK;
+  if (hipStreamSynchronize(b->stream) != hipSuccess) return PIC_ERR_DEVICE;
+  for (size_t i = 0; i + 1 < b->ev_used; i += 2) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, b->ev[i], b->ev[i + 1]) != hipSuccess) return PIC_ERR_DEVICE;
+    b->prof_ms += ms;
+    b->prof_launches += 1;
+  }
+  b->ev_used = 0;
+  return PIC_OK;
+}
+
+pic_status enqueue_steps(pic_batch* b, int64_t n_steps) {
+  const bool mixed = b->precision == PIC_MIXED;
+  for (int64_t k = 0; k < n_steps; ++k) {
+    if (b->profiling) {
+      if (b->ev_used + 2 > b->ev.size()) {
+        if (b->ev.size() >= 8192) {
+          pic_status st = drain_events(b);
+          if (st != PIC_OK) return st;
+        } else {
+          for (int e = 0; e < 2; ++e) {
+            hipEvent_t h;
+            if (hipEventCreate(&h) != hipSuccess) return PIC_ERR_DEVICE;
+            b->ev.push_back(h);
+          }
+        }
+      }
+      pic::StepLaunch L = b->launch;
+      if (hipEventRecord(b->ev[b->ev_used], b->stream) != hipSuccess) return PIC_ERR_DEVICE;
+      if (pic::launch_push(L, mixed) != hipSuccess) return PIC_ERR_DEVICE;
+      if (hipEventRecord(b->ev[b->ev_used + 1], b->stream) != hipSuccess) return PIC_ERR_DEVICE;
+      b->ev_used += 2;
+      if (pic::launch_step_after_push(L, mixed) != hipSuccess) return PIC_ERR_DEVICE;
+    } else if (pic::launch_step(b->launch, mixed) != hipSuccess) {
+      return PIC_ERR_DEVICE;
+    }
+    b->host_step += 1;
+    if (b->host_step % b->sort_every == 0)
+      if (pic::launch_sort(b->launch, mixed) != hipSuccess) return PIC_ERR_DEVICE;
+  }
+  b->started = true;
+  return PIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pic_status pic_validate_params(const pic_gap_params* p) { return validate(p); }
+
+size_t pic_workspace_bytes(const pic_gap_params* p) {
+  if (validate(p) != PIC_OK) return 0;
+  return make_layout(p, 1).total;
+}
+
+size_t pic_batch_workspace_bytes(const pic_gap_params* params, int32_t n_gaps) {
+  if (!params || n_gaps < 1) return 0;
+  for (int i = 0; i < n_gaps; ++i)
+    if (validate(&params[i]) != PIC_OK) return 0;
+  return make_layout(params, n_gaps).total;
+}
+
+int32_t pic_batch_plan(const pic_gap_params* params, int32_t n_gaps, size_t budget_bytes,
+                       uint8_t* admitted, size_t* ws_bytes) {
+  if (!params || n_gaps < 1 || !admitted) return PIC_ERR_ARG;
+  std::vector<pic_gap_params> acc;
+  size_t used = 0;
+  for (int i = 0; i < n_gaps; ++i) {
+    admitted[i] = 0;
+    if (validate(&params[i]) != PIC_OK) continue;
+    acc.push_back(params[i]);
+    const size_t need = make_layout(acc.data(), (int)acc.size()).total;
+    if (need <= budget_bytes) {
+      admitted[i] = 1;
+      used = need;
+    } else {
+      acc.pop_back();
+    }
+  }
+  if (ws_bytes) *ws_bytes = used;
+  return (int32_t)acc.size();
+}
+
+pic_status pic_create_gap(const pic_gap_params* p, void* d_ws, size_t ws_bytes, void* hip_stream,
+                          pic_gap** out) {
+  if (!out) return PIC_ERR_ARG;
+  *out = nullptr;
+  pic_batch* b = nullptr;
+  pic_status st = create_batch(p, 1, d_ws, ws_bytes, hip_stream, &b);
+  if (st != PIC_OK) return st;
+  b->views[0].standalone = true;
+  *out = &b->views[0];
+  return PIC_OK;
+}
+
+pic_status pic_create_batch(const pic_gap_params* params, int32_t n_gaps, void* d_ws,
+                            size_t ws_bytes, void* hip_stream, pic_batch** out) {
+  return create_batch(params, n_gaps, d_ws, ws_bytes, hip_stream, out);
+}
+
+pic_gap* pic_batch_gap(pic_batch* b, int32_t i) {
+  if (!b || i < 0 || i >= b->B) return nullptr;
+  return &b->views[(size_t)i];
+}
+
+int32_t pic_batch_size(const pic_batch* b) { return b ? b->B : 0; }
+
+int32_t pic_offset_bits(const pic_gap* g) {
+  if (!g) return PIC_ERR_ARG;
+  return offset_bits(g->b->precision);
+}
+
+pic_status pic_seed_particles(pic_gap* g, int32_t mode, int64_t n_pairs, int32_t macro_per_pair,
+                              double p0_minus, double p0_plus) {
+  if (!g || n_pairs < 0 || macro_per_pair < 1) return PIC_ERR_ARG;
+  if (mode != PIC_SEED_RANDOM && mode != PIC_SEED_LATTICE) return PIC_ERR_ARG;
+  if (!std::isfinite(p0_minus) || !std::isfinite(p0_plus)) return PIC_ERR_ARG;
+  pic_batch* b = g->b;
+  if (b->started) return PIC_ERR_STATE;
+  const long long N = (long long)n_pairs * (long long)macro_per_pair;
+  if (n_pairs > 0 && N / n_pairs != macro_per_pair) return PIC_ERR_ARG;
+  GapDev G;
+  pic_status st = read_desc(b, g->idx, &G);
+  if (st != PIC_OK) return st;
+  if ((long long)G.n[0] + N > G.cap || (long long)G.n[1] + N > G.cap) return PIC_ERR_CAPACITY;
+  if (N == 0) return PIC_OK;
+  if (pic::launch_seed(dgaps(b), g->idx, mode, N, p0_minus, p0_plus, (long long)G.n[0],
+                       (long long)G.n[1], b->precision == PIC_MIXED, b->stream) != hipSuccess)
+    return PIC_ERR_DEVICE;
+  return append_counts(b, g->idx, N, N);
+}
+
+pic_status pic_seed_explicit(pic_gap* g, int32_t species, int64_t n, const int32_t* cell,
+                             const double* off, const double* p, const uint64_t* id) {
+  if (!g || species < 0 || species > 1 || n < 0) return PIC_ERR_ARG;
+  if (n > 0 && (!cell || !off || !p || !id)) return PIC_ERR_ARG;
+  pic_batch* b = g->b;
+  if (b->started) return PIC_ERR_STATE;
+  const pic_gap_params& prm = b->prm[(size_t)g->idx];
+  for (int64_t i = 0; i < n; ++i) {
+    if (cell[i] < 0 || cell[i] >= prm.n_cells) return PIC_ERR_ARG;
+    if (!(off[i] >= 0.0) || !(off[i] < 1.0) || !std::isfinite(p[i])) return PIC_ERR_ARG;
+  }
+  GapDev G;
+  pic_status st = read_desc(b, g->idx, &G);
+  if (st != PIC_OK) return st;
+  if ((long long)G.n[species] + n > G.cap) return PIC_ERR_CAPACITY;
+  if (n == 0) return PIC_OK;
+  const int K = offset_bits(b->precision);
+  const size_t base = (size_t)G.n[species];
+  const int bb = G.buf;
+  std::vector<int32_t> c(cell, cell + n);
+  std::vector<uint64_t> ids(id, id + n);
+  hipError_t e = hipMemcpy(G.cell[bb][species] + base, c.data(), 4 * (size_t)n, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(G.id[bb][species] + base, ids.data(), 8 * (size_t)n, hipMemcpyHostToDevice);
+  if (b->precision == PIC_MIXED) {
+    std::vector<float> o((size_t)n), pp((size_t)n);
+    for (int64_t i = 0; i < n; ++i) {
+      o[(size_t)i] = (float)std::ldexp(std::floor(std::ldexp(off[i], K)), -K);
+      pp[(size_t)i] = (float)p[i];
+    }
+    if (e == hipSuccess) e = hipMemcpy((float*)G.off[bb][species] + base, o.data(), 4 * (size_t)n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy((float*)G.p[bb][species] + base, pp.data(), 4 * (size_t)n, hipMemcpyHostToDevice);
+  } else {
+    std::vector<double> o((size_t)n), pp(p, p + n);
+    for (int64_t i = 0; i < n; ++i) o[(size_t)i] = std::ldexp(std::floor(std::ldexp(off[i], K)), -K);
+    if (e == hipSuccess) e = hipMemcpy((double*)G.off[bb][species] + base, o.data(), 8 * (size_t)n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy((double*)G.p[bb][species] + base, pp.data(), 8 * (size_t)n, hipMemcpyHostToDevice);
+  }
+  if (e != hipSuccess) return PIC_ERR_DEVICE;
+  return append_counts(b, g->idx, species == 0 ? n : 0, species == 1 ? n : 0);
+}
+
+pic_status pic_step_n(pic_gap* g, int64_t n_steps, pic_step_report* out) {
+  if (!g || n_steps < 0) return PIC_ERR_ARG;
+  if (!g->standalone) return PIC_ERR_STATE;
+  pic_batch* b = g->b;
+  if (b->known_status[0] != PIC_OK) return PIC_ERR_STATE;
+  pic_status st = enqueue_steps(b, n_steps);
+  if (st != PIC_OK) return st;
+  if (out) {
+    GapDev G;
+    st = read_desc(b, 0, &G);
+    if (st != PIC_OK) return st;
+    out->steps_done = G.step;
+    out->status = G.status;
+    out->pushes = (int64_t)G.pushes;
+  }
+  return PIC_OK;
+}
+
+pic_status pic_batch_step_n(pic_batch* b, int64_t n_steps, pic_status* per_gap) {
+  if (!b || n_steps < 0) return PIC_ERR_ARG;
+  pic_status st = enqueue_steps(b, n_steps);
+  if (st != PIC_OK) return st;
+  if (per_gap) {
+    std::vector<GapDev> all((size_t)b->B);
+    if (hipMemcpyAsync(all.data(), dgaps(b), sizeof(GapDev) * (size_t)b->B, hipMemcpyDeviceToHost,
+                       b->stream) != hipSuccess)
+      return PIC_ERR_DEVICE;
+    if (hipStreamSynchronize(b->stream) != hipSuccess) return PIC_ERR_DEVICE;
+    for (int i = 0; i < b->B; ++i) {
+      per_gap[i] = all[(size_t)i].status;
+      b->known_status[(size_t)i] = all[(size_t)i].status;
+    }
+  }
+  return PIC_OK;
+}
+
+pic_status pic_read_fields(pic_gap* g, double* E, double* rho, int32_t n_cells) {
+  if (!g) return PIC_ERR_ARG;
+  pic_batch* b = g->b;
+  GapDev G;
+  pic_status st = read_desc(b, g->idx, &G);
+  if (st != PIC_OK) return st;
+  if (n_cells != G.n_cells) return PIC_ERR_ARG;
+  if (E && copy_to_host(b, E, G.E, 8 * (size_t)n_cells) != PIC_OK) return PIC_ERR_DEVICE;
+  if (rho) {
+    std::vector<long long> acc((size_t)n_cells + 1);
+    if (pic::launch_rho(dgaps(b), g->idx, G.rho_acc, n_cells + 1, b->precision == PIC_MIXED,
+                        b->stream) != hipSuccess)
+      return PIC_ERR_DEVICE;
+    if (copy_to_host(b, acc.data(), G.rho_acc, 8 * acc.size()) != PIC_OK) return PIC_ERR_DEVICE;
+    if (hipStreamSynchronize(b->stream) != hipSuccess) return PIC_ERR_DEVICE;
+    if (G.boundary == PIC_BC_PERIODIC) {
+      acc[0] += acc[(size_t)n_cells];
+      acc[(size_t)n_cells] = acc[0];
+    }
+    for (int32_t c = 0; c <= n_cells; ++c) rho[c] = G.wq * (double)acc[(size_t)c];
+  }
+  return hipStreamSynchronize(b->stream) == hipSuccess ? PIC_OK : PIC_ERR_DEVICE;
+}
+
+pic_status pic_read_flux(pic_gap* g, int64_t* flux, int32_t n_cells) {
+  if (!g || !flux) return PIC_ERR_ARG;
+  pic_batch* b = g->b;
+  GapDev G;
+  pic_status st = read_desc(b, g->idx, &G);
+  if (st != PIC_OK) return st;
+  if (n_cells != G.n_cells) return PIC_ERR_ARG;
+  if (copy_to_host(b, flux, G.F_last, 8 * (size_t)n_cells) != PIC_OK) return PIC_ERR_DEVICE;
+  return hipStreamSynchronize(b->stream) == hipSuccess ? PIC_OK : PIC_ERR_DEVICE;
+}
+
+pic_status pic_read_moments(pic_gap* g, pic_moments* out) {
+  if (!g || !out) return PIC_ERR_ARG;
+  GapDev G;
+  pic_status st = read_desc(g->b, g->idx, &G);
+  if (st != PIC_OK) return st;
+  std::memset(out, 0, sizeof *out);
+  out->steps_done = G.step;
+  out->status = G.status;
+  out->n_minus = (int64_t)G.live[0];
+  out->n_plus = (int64_t)G.live[1];
+  out->n_photons = (int64_t)G.inflight;
+  out->slots_minus = (int64_t)G.n[0];
+  out->slots_plus = (int64_t)G.n[1];
+  out->photon_slots = (int64_t)G.n_ph;
+  out->pushes = (int64_t)G.pushes;
+  out->last = G.last;
+  return PIC_OK;
+}
+
+pic_status pic_read_history(pic_gap* g, pic_history_row* rows, int64_t max_rows, int64_t* n_out) {
+  if (!g || max_rows < 0) return PIC_ERR_ARG;
+  pic_batch* b = g->b;
+  GapDev G;
+  pic_status st = read_desc(b, g->idx, &G);
+  if (st != PIC_OK) return st;
+  const int64_t R = G.hist_rows;
+  const int64_t avail = (int64_t)G.hist_count < R ? (int64_t)G.hist_count : R;
+  if (n_out) *n_out = avail;
+  if (!rows || max_rows == 0 || avail == 0) return PIC_OK;
+  std::vector<pic_history_row> ring((size_t)R);
+  if (copy_to_host(b, ring.data(), G.hist, sizeof(pic_history_row) * (size_t)R) != PIC_OK) return PIC_ERR_DEVICE;
+  if (hipStreamSynchronize(b->stream) != hipSuccess) return PIC_ERR_DEVICE;
+  const int64_t first = (int64_t)G.hist_count - avail;
+  const int64_t n = std::min(avail, max_rows);
+  for (int64_t k = 0; k < n; ++k) rows[k] = ring[(size_t)((first + k) % R)];
+  return PIC_OK;
+}
+
+pic_status pic_read_particles(pic_gap* g, int32_t species, int64_t max_n, int32_t* cell,
+                              double* off, double* p, uint64_t* id, int64_t* n_out) {
+  if (!g || species < 0 || species > 1 || max_n < 0) return PIC_ERR_ARG;
+  pic_batch* b = g->b;
+  GapDev G;
+  pic_status st = read_desc(b, g->idx, &G);
+  if (st != PIC_OK) return st;
+  const size_t n = (size_t)G.n[species];
+  const int bb = G.buf;
+  const bool mixed = b->precision == PIC_MIXED;
+  std::vector<int32_t> c(n);
+  std::vector<uint64_t> ids(n);
+  std::vector<double> o(n), pp(n);
+  std::vector<float> of, pf;
+  if (copy_to_host(b, c.data(), G.cell[bb][species], 4 * n) != PIC_OK) return PIC_ERR_DEVICE;
+  if (copy_to_host(b, ids.data(), G.id[bb][species], 8 * n) != PIC_OK) return PIC_ERR_DEVICE;
+  if (mixed) {
+    of.resize(n); pf.resize(n);
+    if (copy_to_host(b, of.data(), G.off[bb][species], 4 * n) != PIC_OK) return PIC_ERR_DEVICE;
+    if (copy_to_host(b, pf.data(), G.p[bb][species], 4 * n) != PIC_OK) return PIC_ERR_DEVICE;
+  } else {
+    if (copy_to_host(b, o.data(), G.off[bb][species], 8 * n) != PIC_OK) return PIC_ERR_DEVICE;
+    if (copy_to_host(b, pp.data(), G.p[bb][species], 8 * n) != PIC_OK) return PIC_ERR_DEVICE;
+  }
+  if (hipStreamSynchronize(b->stream) != hipSuccess) return PIC_ERR_DEVICE;
+  int64_t live = 0;
+  for (size_t i = 0; i < n; ++i) {
+    if (c[i] == pic::kDead) continue;
+    if (live < max_n) {
+      if (cell) cell[live] = c[i];
+      if (off) off[live] = mixed ? (double)of[i] : o[i];
+      if (p) p[live] = mixed ? (double)pf[i] : pp[i];
+      if (id) id[live] = ids[i];
+    }
+    ++live;
+  }
+  if (n_out) *n_out = live;
+  return PIC_OK;
+}
+
+pic_status pic_read_photons(pic_gap* g, int64_t max_n, int64_t* xq, int64_t* conv_step,
+                            int32_t* dir, uint64_t* child, int64_t* n_out) {
+  if (!g || max_n < 0) return PIC_ERR_ARG;
+  pic_batch* b = g->b;
+  GapDev G;
+  pic_status st = read_desc(b, g->idx, &G);
+  if (st != PIC_OK) return st;
+  const size_t n = (size_t)G.n_ph;
+  const int pb = G.phbuf;
+  std::vector<long long> x(n);
+  std::vector<int32_t> cs(n);
+  std::vector<uint64_t> ch(n);
+  if (copy_to_host(b, x.data(), G.ph_x[pb], 8 * n) != PIC_OK) return PIC_ERR_DEVICE;
+  if (copy_to_host(b, cs.data(), G.ph_step[pb], 4 * n) != PIC_OK) return PIC_ERR_DEVICE;
+  if (copy_to_host(b, ch.data(), G.ph_child[pb], 8 * n) != PIC_OK) return PIC_ERR_DEVICE;
+  if (hipStreamSynchronize(b->stream) != hipSuccess) return PIC_ERR_DEVICE;
+  int64_t k = 0;
+  for (size_t i = 0; i < n; ++i) {
+    if ((long long)cs[i] < G.step) continue;  // converted or escaped, not yet reclaimed
+    if (k < max_n) {
+      if (xq) xq[k] = x[i];
+      if (conv_step) conv_step[k] = cs[i];
+      if (dir) dir[k] = (ch[i] & 1u) ? 1 : -1;
+      if (child) child[k] = ch[i] & ~(uint64_t)1;
+    }
+    ++k;
+  }
+  if (n_out) *n_out = k;
+  return PIC_OK;
+}
+
+pic_status pic_set_fields(pic_gap* g, const double* E, int32_t n_cells) {
+  if (!g || !E) return PIC_ERR_ARG;
+  pic_batch* b = g->b;
+  if (n_cells != b->prm[(size_t)g->idx].n_cells) return PIC_ERR_ARG;
+  for (int32_t c = 0; c < n_cells; ++c)
+    if (!std::isfinite(E[c])) return PIC_ERR_ARG;
+  GapDev G;
+  pic_status st = read_desc(b, g->idx, &G);
+  if (st != PIC_OK) return st;
+  if (hipMemcpy(G.E, E, 8 * (size_t)n_cells, hipMemcpyHostToDevice) != hipSuccess) return PIC_ERR_DEVICE;
+  return PIC_OK;
+}
+
+pic_status pic_destroy(pic_gap* g) {
+  if (!g) return PIC_ERR_ARG;
+  if (!g->standalone) return PIC_ERR_STATE;
+  return pic_destroy_batch(g->b);
+}
+
+pic_status pic_destroy_batch(pic_batch* b) {
+  if (!b) return PIC_ERR_ARG;
+  pic_status st = hipStreamSynchronize(b->stream) == hipSuccess ? PIC_OK : PIC_ERR_DEVICE;
+  if (b->graph) (void)hipGraphExecDestroy(b->graph);
+  if (b->graph_tmpl) (void)hipGraphDestroy(b->graph_tmpl);
+  for (hipEvent_t e : b->ev) (void)hipEventDestroy(e);
+  delete b;
+  return st;
+}
+
+pic_status pic_batch_profile_push(pic_batch* b, int32_t enable) {
+  if (!b) return PIC_ERR_ARG;
+  if (b->profiling && !enable) {
+    pic_status st = drain_events(b);
+    if (st != PIC_OK) return st;
+  }
+  b->profiling = enable != 0;
+  b->ev_used = 0;
+  b->prof_ms = 0.0;
+  b->prof_launches = 0;
+  return PIC_OK;
+}
+
+pic_status pic_batch_read_push_time(pic_batch* b, double* ms, int64_t* launches) {
+  if (!b) return PIC_ERR_ARG;
+  pic_status st = drain_events(b);
+  if (st != PIC_OK) return st;
+  if (ms) *ms = b->prof_ms;
+  if (launches) *launches = b->prof_launches;
+  return PIC_OK;
+}
+
+pic_status pic_profile_push(pic_gap* g, int32_t enable) {
+  if (!g || !g->standalone) return PIC_ERR_ARG;
+  return pic_batch_profile_push(g->b, enable);
+}
+
+pic_status pic_read_push_time(pic_gap* g, double* ms, int64_t* launches) {
+  if (!g || !g->standalone) return PIC_ERR_ARG;
+  return pic_batch_read_push_time(g->b, ms, launches);
+}
+
+const char* pic_status_string(pic_status s) {
+  switch (s) {
+    case PIC_OK: return "ok";
+    case PIC_ERR_ARG: return "invalid argument";
+    case PIC_ERR_WORKSPACE: return "workspace too small or misaligned";
+    case PIC_ERR_CAPACITY: return "particle or photon capacity exhausted";
+    case PIC_ERR_DEVICE: return "HIP runtime error";
+    case PIC_ERR_STATE: return "invalid call order or frozen gap";
+    case PIC_ERR_NONFINITE: return "non-finite momentum";
+    case PIC_ERR_EMISSION: return "more than 64 emissions in one step";
+    default: return "unknown status";
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,123 @@
+"""The C-ABI library on the host: it loads, exports every function that
+include/pic.h declares, and validates parameters and workspaces without
+touching a device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads
+from tests import pic_cases as pc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "pic.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pic_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_function():
+    import paper_2012_05587_amd as P
+    L = P.lib()
+    names = _declared()
+    assert len(names) >= 25
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    assert set(names) == set(P.EXPORTS)
+
+
+def test_binding_fails_loudly_without_library(monkeypatch):
+    import paper_2012_05587_amd as P
+    monkeypatch.setattr(P, "_lib", None)
+    monkeypatch.setattr(P, "LIB_PATH", os.path.join(ROOT, "no_such_lib.so"))
+    with pytest.raises(RuntimeError):
+        P.lib()
+
+
+def _valid():
+    return dict(workloads.config("c1_fp64_reference_gap"))
+
+
+def test_validate_accepts_configs():
+    import paper_2012_05587_amd as P
+    for name in workloads.CONFIGS:
+        assert P.pic_validate_params(pc.gpu_params(workloads.config(name))) == P.OK, name
+    for c in workloads.batched_scan(n_gaps=16):
+        assert P.pic_validate_params(pc.gpu_params(c)) == P.OK
+
+
+@pytest.mark.parametrize("field,value", [
+    ("dt", 1.0), ("dt", -0.1), ("n_cells", 1), ("boundary", 5), ("f", 0.0), ("f", 1.0),
+    ("f", 0.01), ("gamma_thr", 1.0), ("l_gamma", -2.0), ("weight", -1.0), ("capacity", 0),
+    ("capacity", 2**31), ("precision", 3), ("e0", float("inf")), ("sort_every", -1),
+])
+def test_validate_rejects(field, value):
+    import paper_2012_05587_amd as P
+    c = _valid()
+    c[field] = value
+    assert P.pic_validate_params(pc.gpu_params(c)) == P.ERR_ARG
+    assert P.pic_workspace_bytes(pc.gpu_params(c)) == 0
+
+
+def test_photon_store_required_for_finite_path():
+    import paper_2012_05587_amd as P
+    c = _valid()
+    c["photon_capacity"] = 0
+    assert P.pic_validate_params(pc.gpu_params(c)) == P.ERR_ARG
+    c["l_gamma"] = 0.0
+    assert P.pic_validate_params(pc.gpu_params(c)) == P.OK
+
+
+def test_workspace_grows_with_capacity_and_precision():
+    import paper_2012_05587_amd as P
+    c = _valid()
+    a = P.pic_workspace_bytes(pc.gpu_params(c))
+    b = P.pic_workspace_bytes(pc.gpu_params(c, capacity=2 * c["capacity"]))
+    m = P.pic_workspace_bytes(pc.gpu_params(c, precision=workloads.MIXED))
+    assert 0 < a < b and m < a
+    # per-slot bytes: 2 buffers x 2 species x (4 + 8 + 8 + 8) in binary64
+    assert abs((b - a) - 2 * 2 * 28 * c["capacity"]) <= 16 * 256
+
+
+def test_batch_plan_admits_under_budget():
+    import paper_2012_05587_amd as P
+    gaps = [pc.gpu_params(c) for c in workloads.batched_scan(n_gaps=32)]
+    full = P.lib().pic_batch_workspace_bytes((P.GapParams * 32)(*gaps), 32)
+    adm, ws = P.batch_plan(gaps, full)
+    assert adm.all() and ws == full
+    adm, ws = P.batch_plan(gaps, full // 3)
+    assert 0 < adm.sum() < 32 and ws <= full // 3
+
+
+def test_create_rejects_bad_workspace_without_device():
+    import paper_2012_05587_amd as P
+    prm = pc.gpu_params(_valid())
+    h = C.c_void_p()
+    assert P.lib().pic_create_gap(C.byref(prm), None, 1 << 30, None, C.byref(h)) == P.ERR_WORKSPACE
+    assert P.lib().pic_create_gap(C.byref(prm), C.c_void_p(256), 16, None, C.byref(h)) == P.ERR_WORKSPACE
+    assert P.lib().pic_create_gap(C.byref(prm), C.c_void_p(4096 + 8), 1 << 40, None,
+                                  C.byref(h)) == P.ERR_WORKSPACE
+
+
+def test_status_strings():
+    import paper_2012_05587_amd as P
+    for st in (0, -1, -2, -3, -4, -5, -6, -7):
+        assert P.status_string(st)
+    assert "unknown" in P.status_string(-99)
+
+
+def test_oracle_and_library_share_no_code():
+    """The oracle sources name nothing from the HIP library and vice versa."""
+    orc = open(os.path.join(ROOT, "oracle", "pic_oracle.c")).read()
+    assert "pic.h" not in orc and "pic_device" not in orc
+    for f in os.listdir(os.path.join(ROOT, "paper_2012_05587_amd", "csrc")):
+        if f.endswith((".hip", ".cpp", ".hpp")):
+            txt = open(os.path.join(ROOT, "paper_2012_05587_amd", "csrc", f)).read()
+            assert "pic_oracle" not in txt and "orc_" not in txt, f
+    for f in ("__init__.py", "build.py"):
+        txt = open(os.path.join(ROOT, "paper_2012_05587_amd", f)).read()
+        assert "import oracle" not in txt and "from oracle" not in txt

@@ -1,0 +1,309 @@
+"""Parity of the HIP path with the oracle, through the C-ABI (needs a GPU).
+
+The two sides take the same seeded inputs.  Integer results (counts,
+cells, offsets on the fixed-point grid, flux) must agree bit for bit;
+momenta within 1e-12 (binary64) or 1e-5 (mixed) relative; E within 1e-4
+relative.  Because the current is summed in exact integers and both sides
+round every operation identically, E and the momenta in fact agree bit for
+bit, which the tests also record.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads
+from tests import pic_cases as pc
+
+pytestmark = pytest.mark.gpu
+
+PTOL = {workloads.FP64: 1e-12, workloads.MIXED: 1e-5}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2012_05587_amd as P
+    P.lib()
+    yield
+
+
+def _run_pair(cfg, steps, **over):
+    cfg = dict(cfg)
+    cfg.update(over)
+    cfg.setdefault("history_rows", steps + 8)
+    print(f"[case] {cfg.get('n_cells')} cells prec={cfg['precision']} steps={steps}", flush=True)
+    go = pc.make_oracle(cfg)
+    assert go.step(steps) == 0
+    gg = pc.make_gpu(cfg)
+    gg.step_n(steps)
+    return gg, go
+
+
+def _check_all(gg, go, precision):
+    pc.compare_history(gg.read_history(), go.history())
+    stats = pc.compare_particles(gg, go, PTOL[precision])
+    err, exact = pc.compare_fields(gg, go)
+    return stats, err, exact
+
+
+# ----------------------------------------------------------------- closed form
+def test_test_particle_closed_form_on_gpu():
+    """Weight 0 in a uniform field: p^{n+1/2} = p0 + (n+1) q E0 dt."""
+    import paper_2012_05587_amd as P
+    cfg = dict(n_cells=64, dx=1.0, dt=0.3, boundary=workloads.PERIODIC, e0=3.0, gamma_thr=1e300,
+               f=0.5, l_gamma=0.0, weight=0.0, seed=1, precision=workloads.FP64, capacity=16,
+               photon_capacity=0)
+    g = P.Gap(pc.gpu_params(cfg))
+    g.seed_explicit(1, [3], [0.25], [-2.5], [9])
+    g.seed_explicit(0, [7], [0.5], [1.0], [10])
+    n = 400
+    g.step_n(n)
+    pp = g.read_particles(1)["p"][0]
+    pm = g.read_particles(0)["p"][0]
+    assert abs(pp - (-2.5 + n * 3.0 * 0.3)) <= (n + 1) * np.spacing(abs(pp) + 1)
+    assert abs(pm - (1.0 - n * 3.0 * 0.3)) <= (n + 1) * np.spacing(abs(pm) + 1)
+
+
+# ---------------------------------------------------------------- reference gap
+@pytest.mark.parametrize("steps", [1, 37, 300])
+def test_c1_reference_gap_short(steps):
+    cfg = workloads.config("c1_fp64_reference_gap")
+    gg, go = _run_pair(cfg, steps)
+    stats, err, exact = _check_all(gg, go, cfg["precision"])
+    print("p err", stats, "E err", err, "E bitwise", exact)
+
+
+def test_c1_reference_gap_full_run():
+    """Configuration 1 over its whole 2000 steps, binary64."""
+    cfg = workloads.config("c1_fp64_reference_gap")
+    gg, go = _run_pair(cfg, cfg["steps"])
+    stats, err, exact = _check_all(gg, go, cfg["precision"])
+    print("p err", stats, "E err", err, "E bitwise", exact)
+    assert go.history()["pairs_created"][-1] > 5000
+
+
+def test_c3_mixed_gap_full_run():
+    """Configuration 3 (configuration 1 in mixed precision) against the oracle
+    taking every per-particle decision in binary32 too."""
+    cfg = workloads.config("c3_mixed_single_gap")
+    gg, go = _run_pair(cfg, cfg["steps"])
+    stats, err, exact = _check_all(gg, go, cfg["precision"])
+    print("p err", stats, "E err", err, "E bitwise", exact)
+
+
+@pytest.mark.parametrize("precision", [workloads.FP64, workloads.MIXED])
+def test_in_place_pairs_periodic(precision):
+    """The paper's own model: pairs made in place, periodic domain."""
+    cfg = dict(n_cells=300, dx=1.0, dt=0.45, boundary=workloads.PERIODIC, e0=30.0,
+               gamma_thr=60.0, f=0.25, l_gamma=0.0, weight=0.2, seed=77, precision=precision,
+               n_pairs=200, macro_per_pair=3, capacity=200_000, photon_capacity=0)
+    gg, go = _run_pair(cfg, 400)
+    _check_all(gg, go, precision)
+
+
+def test_lattice_seed_and_drift():
+    cfg = dict(n_cells=257, dx=1.0, dt=0.45, boundary=workloads.PERIODIC, e0=0.5,
+               gamma_thr=1e300, f=0.5, l_gamma=0.0, weight=1.0, seed=5,
+               precision=workloads.FP64, n_pairs=257 * 3 + 5, macro_per_pair=1,
+               seed_mode=workloads.SEED_LATTICE, p0_minus=0.3, p0_plus=-0.2,
+               capacity=2000, photon_capacity=0)
+    gg, go = _run_pair(cfg, 150)
+    _check_all(gg, go, cfg["precision"])
+    assert np.array_equal(gg.read_flux(), go.fields()["flux"])
+
+
+def test_config2_first_steps():
+    """Configuration 2 (8192 cells, 1024 seed pairs) step for step over its
+    first 200 steps, through screening."""
+    cfg = workloads.config("c2_fp64_single_gap")
+    gg, go = _run_pair(cfg, 200, capacity=4_000_000, photon_capacity=4_000_000)
+    stats, err, exact = _check_all(gg, go, cfg["precision"])
+    print("p err", stats, "E err", err, "E bitwise", exact)
+
+
+# ----------------------------------------------------------------- invariance
+def test_sort_cadence_does_not_change_results():
+    """Re-sorting only reorders memory: every cadence gives the same state."""
+    cfg = workloads.config("c1_fp64_reference_gap")
+    ref = None
+    for se in (1, 3, 20, 1_000_000):
+        gg = pc.make_gpu(cfg, sort_every=se, history_rows=500)
+        gg.step_n(400)
+        h = gg.read_history()
+        parts = [pc.by_id(gg.read_particles(s)) for s in (0, 1)]
+        E = gg.read_fields(rho=False)["E"]
+        if ref is None:
+            ref = (h, parts, E)
+            continue
+        for k in pc.HIST_INT:
+            assert np.array_equal(h[k], ref[0][k]), (se, k)
+        for s in (0, 1):
+            for k in ("id", "cell", "off", "p"):
+                assert np.array_equal(parts[s][k], ref[1][s][k]), (se, s, k)
+        assert np.array_equal(E, ref[2]), se
+
+
+def test_run_twice_is_bitwise_identical():
+    cfg = workloads.config("c3_mixed_single_gap")
+    out = []
+    for _ in range(2):
+        gg = pc.make_gpu(cfg, history_rows=400)
+        gg.step_n(300)
+        out.append((gg.read_history(), gg.read_fields(rho=False)["E"]))
+    assert np.array_equal(out[0][1], out[1][1])
+    for k in pc.HIST_INT:
+        assert np.array_equal(out[0][0][k], out[1][0][k])
+
+
+# ------------------------------------------------------------- Gauss / charge
+@pytest.mark.parametrize("precision", [workloads.FP64, workloads.MIXED])
+def test_gauss_law_on_gpu(precision):
+    cfg = workloads.config("c1_fp64_reference_gap")
+    gg = pc.make_gpu(cfg, precision=precision)
+    gg.step_n(500)
+    F = gg.read_fields(rho=True)
+    r = pc.gauss_residual(F["E"], F["rho"], periodic=False)
+    assert np.abs(r).max() <= 10 * np.finfo(float).eps * 500 * np.abs(F["E"]).max()
+
+
+# ---------------------------------------------------------------- edge cases
+def test_empty_gap_steps():
+    cfg = workloads.config("c1_fp64_reference_gap")
+    cfg["n_pairs"] = 0
+    gg, go = _run_pair(cfg, 25)
+    pc.compare_history(gg.read_history(), go.history())
+    assert np.array_equal(gg.read_fields(rho=False)["E"], go.fields()["E"])
+
+
+@pytest.mark.parametrize("n_pairs", [1, 1023, 1025, 3000])
+def test_ragged_counts(n_pairs):
+    """Counts that are not multiples of the work-item size."""
+    cfg = workloads.config("c1_fp64_reference_gap")
+    cfg.update(n_pairs=n_pairs, macro_per_pair=1)
+    gg, go = _run_pair(cfg, 120)
+    _check_all(gg, go, cfg["precision"])
+
+
+def test_capacity_overflow_freezes_gap():
+    """A tiny slot count freezes the gap at the last completed step; the
+    history up to then is the oracle's (periodic, in place: slots = live)."""
+    import paper_2012_05587_amd as P
+    cfg = dict(n_cells=128, dx=1.0, dt=0.45, boundary=workloads.PERIODIC, e0=40.0,
+               gamma_thr=80.0, f=0.5, l_gamma=0.0, weight=0.1, seed=3,
+               precision=workloads.FP64, n_pairs=50, macro_per_pair=1, capacity=3000,
+               photon_capacity=0, history_rows=400)
+    go = pc.make_oracle(cfg, capacity=3000)
+    st = go.step(300)
+    assert st == -3
+    gg = pc.make_gpu(cfg, sort_every=1)
+    rep = gg.step_n(300, report=True)
+    assert rep.status == P.ERR_CAPACITY
+    assert rep.steps_done == go.steps_done
+    pc.compare_history(gg.read_history(), go.history())
+    with pytest.raises(P.PicError):
+        gg.step_n(1)
+
+
+def test_nonfinite_detected():
+    import paper_2012_05587_amd as P
+    cfg = workloads.config("c1_fp64_reference_gap")
+    gg = pc.make_gpu(cfg)
+    gg.set_fields(np.full(cfg["n_cells"], 1e308))
+    rep = gg.step_n(20, report=True)
+    assert rep.status == P.ERR_NONFINITE
+
+
+def test_invalid_workspace_rejected():
+    import ctypes as C
+    import paper_2012_05587_amd as P
+    prm = pc.gpu_params(workloads.config("c1_fp64_reference_gap"))
+    h = C.c_void_p()
+    assert P.lib().pic_create_gap(C.byref(prm), None, 0, None, C.byref(h)) == P.ERR_WORKSPACE
+
+
+# ------------------------------------------------------------------- batch
+def test_batch_matches_oracle_per_gap():
+    """Gaps of different size and physics in one batch, each against its own
+    oracle run."""
+    import paper_2012_05587_amd as P
+    gaps = workloads.batched_scan(n_gaps=6, precision=workloads.FP64, steps=150)
+    for c in gaps:
+        c.update(n_cells=min(c["n_cells"], 3000), n_pairs=min(c["n_pairs"], 400),
+                 e0=min(c["e0"], 120.0), gamma_thr=max(c["gamma_thr"], 150.0),
+                 capacity=1_000_000, photon_capacity=1_000_000, history_rows=200)
+    b = P.Batch([pc.gpu_params(c) for c in gaps])
+    for view, c in zip(b.gaps, gaps):
+        view.seed_particles(0, c["n_pairs"], 1)
+    st = b.step_n(150, statuses=True)
+    assert np.all(st == 0)
+    for view, c in zip(b.gaps, gaps):
+        go = pc.make_oracle(c)
+        assert go.step(150) == 0
+        pc.compare_history(view.read_history(), go.history())
+        pc.compare_particles(view, go, PTOL[workloads.FP64])
+
+
+def test_batch_mixed_matches_single_gaps():
+    import paper_2012_05587_amd as P
+    gaps = workloads.batched_scan(n_gaps=4, precision=workloads.MIXED, steps=100)
+    for c in gaps:
+        c.update(n_cells=min(c["n_cells"], 3000), n_pairs=min(c["n_pairs"], 400),
+                 e0=min(c["e0"], 120.0), gamma_thr=max(c["gamma_thr"], 150.0),
+                 capacity=1_000_000, photon_capacity=1_000_000, history_rows=200)
+    b = P.Batch([pc.gpu_params(c) for c in gaps])
+    for view, c in zip(b.gaps, gaps):
+        view.seed_particles(0, c["n_pairs"], 1)
+    st = b.step_n(100, statuses=True)
+    assert np.all(st == 0)
+    for view, c in zip(b.gaps, gaps):
+        go = pc.make_oracle(c)
+        assert go.step(100) == 0
+        pc.compare_history(view.read_history(), go.history())
+        pc.compare_particles(view, go, PTOL[workloads.MIXED])
+
+
+# ------------------------------------------------- full-size sampled parity
+def test_config2_full_size_sampled_step():
+    """At configuration 2's full slot count and the benchmark's launch shape:
+    after 150 steps, one further step of a random sample of leptons is
+    recomputed by the oracle (weight 0 in the GPU's field) lepton by lepton,
+    and the invariants that hold at any size are checked."""
+    cfg = workloads.config("c2_fp64_single_gap")
+    gg = pc.make_gpu(cfg, history_rows=400)
+    gg.step_n(150)
+    E = gg.read_fields(rho=True)
+    before = [gg.read_particles(s) for s in (0, 1)]
+    gg.step_n(1)
+    after = [pc.by_id(gg.read_particles(s)) for s in (0, 1)]
+    h = gg.read_history()
+    # invariants at any size
+    assert np.all((h["n_minus"] - h["n_plus"]) == -(h["absorbed_minus"] - h["absorbed_plus"]))
+    assert np.all(h["photons_emitted"] == h["n_photons"] + h["pairs_created"] + h["photons_escaped"])
+    r = pc.gauss_residual(E["E"], E["rho"], periodic=False)
+    assert np.abs(r).max() <= 10 * np.finfo(float).eps * 151 * np.abs(E["E"]).max()
+    # sampled one-step recomputation
+    import oracle
+    rng = np.random.default_rng(1)
+    for s in (0, 1):
+        n = len(before[s]["id"])
+        pick = rng.choice(n, size=min(2000, n), replace=False)
+        og = oracle.OracleGap(**pc.gap_kwargs(dict(cfg, weight=0.0)), capacity=0)
+        og.set_fields(E["E"])
+        og.seed_explicit(s, before[s]["cell"][pick], before[s]["off"][pick], before[s]["p"][pick],
+                         before[s]["id"][pick])
+        # photon draws are keyed by the step index, which differs here; the
+        # emitter's own momentum and position do not depend on them
+        assert og.step(1) == 0
+        ref = pc.by_id(og.particles(s))
+        sel = np.isin(after[s]["id"], ref["id"])
+        got = {k: v[sel] for k, v in after[s].items()}
+        keep = np.isin(ref["id"], got["id"])
+        ref = {k: v[keep] for k, v in ref.items()}
+        assert np.array_equal(got["id"], ref["id"])
+        assert np.array_equal(got["cell"], ref["cell"])
+        assert np.array_equal(got["off"], ref["off"])
+        assert np.all(np.abs(got["p"] - ref["p"]) <= 1e-12 * np.maximum(np.abs(ref["p"]), 1))
+        assert len(got["id"]) > 0.9 * len(pick)

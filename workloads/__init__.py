@@ -1,0 +1,84 @@
+"""Seeded synthetic workloads of the pair-cascade PIC path.
+
+The paper (arXiv:2012.05587) runs its cascades on synthetic setups only: a
+uniform seed pair plasma at rest in a uniform initial field (section 3), or
+a co-rotating gap (section 7).  The workloads below keep that structure
+(uniform seed, uniform E0, exponential cascade) at the sizes of the five
+benchmark configurations.  This module only states parameters and draws
+seeded gap tables; it holds none of the method's arithmetic, and both the
+HIP path and the oracle take their inputs from it.
+
+Enumerations follow the C-ABI: boundary 0 = periodic, 1 = absorbing;
+precision 0 = binary64, 1 = mixed; seeding 0 = random, 1 = lattice.
+"""
+import math
+
+import numpy as np
+
+PERIODIC, ABSORBING = 0, 1
+FP64, MIXED = 0, 1
+SEED_RANDOM, SEED_LATTICE = 0, 1
+BASE_SEED = 2012055870
+
+# name -> gap parameters, seed plasma and run length
+CONFIGS = {
+    # 1: binary64 reference gap, small enough for the oracle in seconds
+    "c1_fp64_reference_gap": dict(
+        n_cells=512, dx=1.0, dt=0.45, boundary=ABSORBING, e0=50.0, gamma_thr=100.0, f=0.5,
+        l_gamma=20.0, weight=1.0, seed=BASE_SEED + 1, precision=FP64, n_pairs=64,
+        macro_per_pair=16, steps=2000, capacity=100_000, photon_capacity=100_000),
+    # 2: binary64 single gap, cascade to ~1e7 macro-particles over 20000 steps
+    "c2_fp64_single_gap": dict(
+        n_cells=8192, dx=1.0, dt=0.45, boundary=ABSORBING, e0=200.0, gamma_thr=200.0, f=0.5,
+        l_gamma=50.0, weight=1.0, seed=BASE_SEED + 2, precision=FP64, n_pairs=1024,
+        macro_per_pair=1, steps=20000, capacity=20_000_000, photon_capacity=20_000_000),
+    # 3: configuration 1 in mixed precision
+    "c3_mixed_single_gap": dict(
+        n_cells=512, dx=1.0, dt=0.45, boundary=ABSORBING, e0=50.0, gamma_thr=100.0, f=0.5,
+        l_gamma=20.0, weight=1.0, seed=BASE_SEED + 1, precision=MIXED, n_pairs=64,
+        macro_per_pair=16, steps=2000, capacity=100_000, photon_capacity=100_000),
+    # 5: large mixed-precision gap, cascade to ~5e8 macro-particles
+    "c5_large_mixed": dict(
+        n_cells=65536, dx=1.0, dt=0.45, boundary=ABSORBING, e0=1000.0, gamma_thr=500.0, f=0.5,
+        l_gamma=200.0, weight=1.0, seed=BASE_SEED + 5, precision=MIXED, n_pairs=16384,
+        macro_per_pair=1, steps=50000, capacity=300_000_000, photon_capacity=300_000_000,
+        sort_every=20),
+}
+
+GAP_KEYS = ("n_cells", "dx", "dt", "boundary", "e0", "gamma_thr", "f", "l_gamma", "weight",
+            "seed", "precision")
+
+
+def config(name):
+    return dict(CONFIGS[name])
+
+
+def batched_scan(n_gaps=256, precision=MIXED, steps=2000, seed=BASE_SEED):
+    """Configuration 4: independent gaps with log-uniform N_cells in
+    [1024, 16384], E0 and gamma_thr uniform in [50, 400], l_gamma uniform in
+    [10, 100] cells and log-uniform 256-4096 seed pairs; f = 0.5, dt = 0.45,
+    dx = 1, absorbing.  Slots per species are sized from the seed-to-screening
+    growth bound 3 * 2 * (E0^2 ln(2/f) / (2 gamma_thr)) * N_cells, clipped to
+    [1e5, 1e7]."""
+    rng = np.random.default_rng(seed)
+    gaps = []
+    for i in range(n_gaps):
+        nc = int(round(math.exp(rng.uniform(math.log(1024), math.log(16384)))))
+        e0 = float(rng.uniform(50.0, 400.0))
+        gthr = float(rng.uniform(50.0, 400.0))
+        lg = float(rng.uniform(10.0, 100.0))
+        pairs = int(round(math.exp(rng.uniform(math.log(256), math.log(4096)))))
+        ns = e0 * e0 * math.log(2.0 / 0.5) / (2.0 * gthr)
+        cap = int(min(max(3 * 2 * ns * nc, 1e5), 1e7))
+        gaps.append(dict(n_cells=nc, dx=1.0, dt=0.45, boundary=ABSORBING, e0=e0, gamma_thr=gthr,
+                         f=0.5, l_gamma=lg, weight=1.0, seed=seed + 1000 + i,
+                         precision=precision, n_pairs=pairs, macro_per_pair=1, steps=steps,
+                         capacity=cap, photon_capacity=cap))
+    return gaps
+
+
+def scaled(name, **over):
+    """A configuration with some fields replaced (smaller parity cases)."""
+    c = config(name)
+    c.update(over)
+    return c
