@@ -18,6 +18,8 @@ constexpr int kPhChunk = kBlock * 4;  // photons per convert work item
 constexpr int kCellChunk = kBlock * 4;
 constexpr int32_t kDead = INT32_MIN;  // cell of an absorbed lepton until re-sort
 constexpr int kMaxEmit = 64;
+constexpr int kStripes = 32;          // striped per-gap accumulators of the push kernel
+constexpr int kStripeStride = 16;     // doubles between stripes (one 128-byte line each)
 constexpr uint64_t kTagSeed = 1, kTagPhoton = 2;
 
 // One gap, in device memory.  The host fills the constant part at creation;
@@ -46,6 +48,9 @@ struct GapDev {
   long long* ph_x[2];
   int32_t* ph_step[2];
   uint64_t* ph_child[2];  // electron id with bit 0 = (direction > 0)
+  int32_t* ph_bucket;     // photon store sorted by conversion step: end of each bucket
+  float inv_lnq;          // 1 / ln q of the photon path, q = exp(-dt / (l_gamma dx))
+  int32_t pad3;
 
   // ---- counters (device-updated)
   unsigned long long n[2];       // slots in use at step start
@@ -57,6 +62,8 @@ struct GapDev {
   unsigned long long pushes;
   unsigned long long hist_count;
   unsigned long long sorted_n[2], ph_sorted;
+  unsigned long long ph_body_n;  // photons in the sorted body of the store
+  long long ph_base;             // conversion step of bucket 0 of the sorted body
   long long step;
   int32_t status, buf, phbuf, pad2;
   int32_t overflow, nonfinite, emit_err, pad1;
@@ -64,6 +71,29 @@ struct GapDev {
   double ke_acc, fe_acc, es_acc;
   pic_history_row last;
 };
+
+// Pointers loaded from a descriptor are generic to the compiler; casting
+// them to the global address space lets it emit global (not flat) memory
+// instructions.
+template <class T>
+using gptr = __attribute__((address_space(1))) T*;
+template <class T>
+__device__ __forceinline__ gptr<T> glb(T* p) { return (gptr<T>)p; }
+template <class T>
+__device__ __forceinline__ gptr<T> glb(void* p) { return (gptr<T>)(T*)p; }
+
+__device__ __forceinline__ void gadd(gptr<unsigned long long> p, unsigned long long v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Fixed-point offset arithmetic: 2^-24 offsets fit 32-bit integers, 2^-40
+// offsets need 64 bits.
+template <typename T>
+struct Fixed;
+template <>
+struct Fixed<float> { using I = int; };
+template <>
+struct Fixed<double> { using I = long long; };
 
 // ---------------------------------------------------------------- Philox
 // Philox4x64-10 (Salmon, Moraes, Dror & Shaw, SC'11): ten rounds of two
@@ -85,6 +115,13 @@ __device__ __forceinline__ U64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_
   U64x4 o;
   o.v[0] = c0; o.v[1] = c1; o.v[2] = c2; o.v[3] = c3;
   return o;
+}
+
+// Accumulator a (0 kinetic energy, 1 lost energy, 2-3 absorbed electrons /
+// positrons) of gap g, stripe st: each stripe on its own cache line, so the
+// workgroups of the push kernel do not all hit one address.
+__device__ __forceinline__ double* stripe_slot(double* stripes, int g, int a, int st) {
+  return stripes + (((size_t)g * 4 + a) * kStripes + st) * kStripeStride;
 }
 
 // ---------------------------------------------------------- wave helpers
@@ -123,13 +160,17 @@ __device__ __forceinline__ int find_gap(const long long* __restrict__ start, int
 // workgroup index remapped so that each of the 8 XCDs (which receive
 // workgroups round-robin) walks one contiguous eighth of the items and keeps
 // the field lines of its cells in its own L2.
-__device__ __forceinline__ void xcd_range(long long total, long long& w0, long long& w1) {
-  const int nb = gridDim.x, b = blockIdx.x;
+__device__ __forceinline__ void xcd_range(long long total, long long& w0, long long& w1,
+                                          int b, int nb) {
   int lb = b;
   if ((nb & 7) == 0) lb = (b & 7) * (nb >> 3) + (b >> 3);
   long long per = (total + nb - 1) / nb;
   w0 = (long long)lb * per;
   w1 = w0 + per < total ? w0 + per : total;
+}
+
+__device__ __forceinline__ void xcd_range(long long total, long long& w0, long long& w1) {
+  xcd_range(total, w0, w1, (int)blockIdx.x, (int)gridDim.x);
 }
 
 }  // namespace pic

@@ -32,12 +32,14 @@ struct GapLayout {
   size_t E, F, F_last, rho, table, sort_cnt[2], hist;
   size_t cell[2][2], off[2][2], p[2][2], id[2][2];
   size_t ph_x[2], ph_step[2], ph_child[2];
+  size_t ph_bucket;
   size_t end;
   int64_t table_len;
 };
 
 struct Layout {
-  size_t gaps, wi, pwi, cwi, total;
+  size_t gaps, wi, pwi, cwi, emit_cnt, emit_ent, stripes, total;
+  long long max_chunks;
   std::vector<GapLayout> g;
   long long cell_items;
 };
@@ -96,6 +98,12 @@ Layout make_layout(const pic_gap_params* prm, int B) {
   L.pwi = o; o = align_up(o + sizeof(long long) * (size_t)(B + 1));
   L.cwi = o; o = align_up(o + sizeof(long long) * (size_t)(B + 1));
   L.cell_items = 0;
+  // one emission slice per particle chunk the plan can hold
+  L.max_chunks = 0;
+  for (int i = 0; i < B; ++i) L.max_chunks += 2 * ((prm[i].capacity + pic::kChunk - 1) / pic::kChunk);
+  L.emit_cnt = o; o = align_up(o + sizeof(int32_t) * (size_t)L.max_chunks);
+  L.emit_ent = o; o = align_up(o + sizeof(uint32_t) * (size_t)L.max_chunks * pic::kChunk);
+  L.stripes = o; o = align_up(o + sizeof(double) * (size_t)B * 4 * pic::kStripes * pic::kStripeStride);
   const int prec = prm[0].precision;
   const size_t tb = prec == PIC_MIXED ? 4 : 8;
   const int hist = hist_rows_of(prm[0]);
@@ -124,6 +132,7 @@ Layout make_layout(const pic_gap_params* prm, int B) {
       G.ph_step[b] = o; o = align_up(o + 4 * pc);
       G.ph_child[b] = o; o = align_up(o + 8 * pc);
     }
+    G.ph_bucket = o; o = align_up(o + 4 * ((size_t)G.table_len + 1));
     G.end = o;
     L.cell_items += ((long long)p.n_cells + pic::kCellChunk - 1) / pic::kCellChunk;
   }
@@ -277,6 +286,8 @@ pic_status create_batch(const pic_gap_params* params, int n_gaps, void* d_ws, si
       G.ph_step[bb] = reinterpret_cast<int32_t*>(ws + GL.ph_step[bb]);
       G.ph_child[bb] = reinterpret_cast<uint64_t*>(ws + GL.ph_child[bb]);
     }
+    G.ph_bucket = reinterpret_cast<int32_t*>(ws + GL.ph_bucket);
+    G.inv_lnq = p.l_gamma > 0.0 ? (float)(-p.l_gamma * p.dx / p.dt) : 0.0f;
     cwi[(size_t)i + 1] = cwi[(size_t)i] + ((long long)p.n_cells + pic::kCellChunk - 1) / pic::kCellChunk;
 
     // initial field and zeroed flux; conversion table
@@ -288,6 +299,9 @@ pic_status create_batch(const pic_gap_params* params, int n_gaps, void* d_ws, si
     const std::vector<uint32_t> T = build_table(p);
     if (st == PIC_OK && !T.empty() &&
         hipMemcpy(G.table, T.data(), 4 * T.size(), hipMemcpyHostToDevice) != hipSuccess) st = PIC_ERR_DEVICE;
+    const std::vector<int32_t> zb(T.size() + 1, 0);
+    if (st == PIC_OK &&
+        hipMemcpy(G.ph_bucket, zb.data(), 4 * zb.size(), hipMemcpyHostToDevice) != hipSuccess) st = PIC_ERR_DEVICE;
   }
   if (st == PIC_OK &&
       hipMemcpy(dgaps(b), host.data(), sizeof(GapDev) * (size_t)n_gaps, hipMemcpyHostToDevice) != hipSuccess)
@@ -298,11 +312,19 @@ pic_status create_batch(const pic_gap_params* params, int n_gaps, void* d_ws, si
   b->launch.cwi = reinterpret_cast<long long*>(ws + L.cwi);
   b->launch.cell_items = L.cell_items;
   b->launch.B = n_gaps;
-  b->launch.push_grid = 1024;
-  b->launch.conv_grid = 512;
+  b->launch.push_grid = 4096;
+  b->launch.conv_grid = 128;
+  b->launch.emit_grid = 128;
+  b->launch.emit_cnt = reinterpret_cast<int32_t*>(ws + L.emit_cnt);
+  b->launch.emit_ent = reinterpret_cast<uint32_t*>(ws + L.emit_ent);
+  b->launch.stripes = reinterpret_cast<double*>(ws + L.stripes);
   b->launch.stream = b->stream;
   if (st == PIC_OK &&
       hipMemcpy(b->launch.cwi, cwi.data(), sizeof(long long) * cwi.size(), hipMemcpyHostToDevice) != hipSuccess)
+    st = PIC_ERR_DEVICE;
+  const std::vector<double> zs((size_t)n_gaps * 4 * pic::kStripes * pic::kStripeStride, 0.0);
+  if (st == PIC_OK && hipMemcpy(b->launch.stripes, zs.data(), sizeof(double) * zs.size(),
+                                hipMemcpyHostToDevice) != hipSuccess)
     st = PIC_ERR_DEVICE;
   if (st == PIC_OK && pic::launch_plan(b->launch) != hipSuccess) st = PIC_ERR_DEVICE;
   if (st == PIC_OK && hipStreamSynchronize(b->stream) != hipSuccess) st = PIC_ERR_DEVICE;

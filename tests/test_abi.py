@@ -79,8 +79,9 @@ def test_workspace_grows_with_capacity_and_precision():
     b = P.pic_workspace_bytes(pc.gpu_params(c, capacity=2 * c["capacity"]))
     m = P.pic_workspace_bytes(pc.gpu_params(c, precision=workloads.MIXED))
     assert 0 < a < b and m < a
-    # per-slot bytes: 2 buffers x 2 species x (4 + 8 + 8 + 8) in binary64
-    assert abs((b - a) - 2 * 2 * 28 * c["capacity"]) <= 16 * 256
+    # per-slot bytes: 2 buffers x 2 species x (4 + 8 + 8 + 8) in binary64, plus a
+    # 4-byte emission-list entry per species
+    assert abs((b - a) - (2 * 2 * 28 + 8) * c["capacity"]) <= 16 * 1024
 
 
 def test_batch_plan_admits_under_budget():

@@ -31,7 +31,7 @@ CONFIGS = {
     "c2_fp64_single_gap": dict(
         n_cells=8192, dx=1.0, dt=0.45, boundary=ABSORBING, e0=200.0, gamma_thr=200.0, f=0.5,
         l_gamma=50.0, weight=1.0, seed=BASE_SEED + 2, precision=FP64, n_pairs=1024,
-        macro_per_pair=1, steps=20000, capacity=20_000_000, photon_capacity=20_000_000),
+        macro_per_pair=1, steps=20000, capacity=30_000_000, photon_capacity=60_000_000),
     # 3: configuration 1 in mixed precision
     "c3_mixed_single_gap": dict(
         n_cells=512, dx=1.0, dt=0.45, boundary=ABSORBING, e0=50.0, gamma_thr=100.0, f=0.5,
