@@ -152,6 +152,12 @@ static int64_t conv_steps(const orc_gap* g, uint32_t u) {
 /* ------------------------------------------------------------------------ */
 static double R(const orc_gap* g, double x) { return g->mixed ? (double)(float)x : x; }
 
+/* Lorentz factor of momentum p as the push computes it, in the particle
+ * precision; energies are summed from it in binary64. */
+static double gamma_of(const orc_gap* g, double p) {
+  return R(g, sqrt(R(g, 1.0 + R(g, p * p))));
+}
+
 int orc_validate(const orc_params* p) {
   if (!p) return ORC_ERR_ARG;
   if (p->n_cells < 2) return ORC_ERR_ARG;
@@ -324,7 +330,7 @@ static void record_history(orc_gap* g) {
   double w = g->prm.weight;
   double ke = 0.0;
   for (int s = 0; s < 2; ++s)
-    for (int64_t i = 0; i < g->sp[s].n; ++i) ke += w * sqrt(1.0 + g->sp[s].p[i] * g->sp[s].p[i]);
+    for (int64_t i = 0; i < g->sp[s].n; ++i) ke += w * gamma_of(g, g->sp[s].p[i]);
   r.kinetic = ke;
   double fe = 0.0, es = 0.0;
   for (int32_t c = 0; c < g->prm.n_cells; ++c) {
@@ -418,7 +424,7 @@ static int step_once(orc_gap* g) {
         S->offq[i] = nq;
       } else {
         g->absorbed[s]++;
-        g->lost_energy += P->weight * sqrt(1.0 + p * p);
+        g->lost_energy += P->weight * gamma_of(g, p);
       }
     }
   }
