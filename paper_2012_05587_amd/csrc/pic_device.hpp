@@ -32,7 +32,7 @@ struct GapDev {
   int64_t one, domain, photon_step, cap, ph_cap;
   double dt, dx, weight, wq, e0;
   double dtdx, gthr, gpair, pchild;  // values exactly representable in the particle type
-  double gpair64, child_gamma64;     // binary64 pair energy and child gamma for diagnostics
+  double gpair64, child_gamma64;     // binary64 pair energy; child gamma in the particle precision
   uint64_t seed;
   double* E;
   long long* F;

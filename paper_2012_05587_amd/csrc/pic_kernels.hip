@@ -295,22 +295,21 @@ __global__ __launch_bounds__(kBlock) void k_push(GapDev* __restrict__ gaps,
           ++k;
         }
         if (k > kMaxEmit) { emit_bad = true; k = 0; }
+        T gnew = gam;
         if (k > 0) {
           const T mag = sqrt(gm * gm - one_t);
           pn = pn > (T)0 ? mag : -mag;
+          gnew = sqrt(one_t + pn * pn);
           const int pos = atomicAdd(&s_emit_n, 1);
           s_emit[pos] = ((uint32_t)(i - i0) << 8) | (uint32_t)k;
         }
         pA[i] = pn;
         offA[i] = (T)nq * inv_scale;
         if (c2 != c) cellA[i] = c2;
-        if (cur_diag) {
-          const double pd = (double)pn;
-          tally.ke += w_d * sqrt(1.0 + pd * pd);
-        }
+        // energy: the Lorentz factor in the particle precision, summed in binary64
+        if (cur_diag) tally.ke += w_d * (double)gnew;
       } else {
-        const double pd = (double)pn;
-        tally.lost += w_d * sqrt(1.0 + pd * pd);
+        tally.lost += w_d * (double)gam;
         tally.absorbed[s] += 1;
         pA[i] = pn;
         cellA[i] = kDead;
@@ -691,19 +690,55 @@ __global__ __launch_bounds__(1024) void k_plan(GapDev* __restrict__ gaps, int B,
 
 // Ends a step for every gap: freeze on error, roll the counters, write the
 // history row, and plan the next step.
+constexpr int kFoldMax = 1024;  // gaps whose stripes finalize folds with the whole block
+
 __device__ void finalize_body(GapDev* __restrict__ gaps, int B, long long* __restrict__ wi,
                               long long* __restrict__ pwi, double* __restrict__ stripes) {
+  __shared__ unsigned long long s_fold[kFoldMax * 4];
+  // fold the striped push tallies: 32 lanes sum the stripes of one
+  // (gap, accumulator) pair; accumulators 2 and 3 hold integer counts
+  const bool wide = B <= kFoldMax;
+  if (wide) {
+    const int lane = lane_id();
+    const int pairs = B * 4;
+    for (int base = (threadIdx.x >> 6) * 2; base < pairs; base += (blockDim.x >> 6) * 2) {
+      const int pair = base + (lane >> 5);
+      const int st = lane & 31;
+      unsigned long long bits = 0;
+      if (pair < pairs) {
+        unsigned long long* slot = (unsigned long long*)stripe_slot(stripes, pair >> 2, pair & 3, st);
+        bits = *slot;
+        *slot = 0ull;
+      }
+      double dv = __longlong_as_double((long long)bits);
+      unsigned long long uv = bits;
+#pragma unroll
+      for (int d = 16; d >= 1; d >>= 1) {
+        dv += __shfl_xor(dv, d, 64);
+        uv += __shfl_xor(uv, d, 64);
+      }
+      if (st == 0 && pair < pairs)
+        s_fold[pair] = (pair & 3) < 2 ? (unsigned long long)__double_as_longlong(dv) : uv;
+    }
+    __syncthreads();
+  }
   for (int g = threadIdx.x; g < B; g += blockDim.x) {
     GapDev* G = gaps + g;
-    // fold the striped push tallies of this step
     double ke = 0.0, lost = 0.0;
     unsigned long long ab[2] = {0, 0};
-    for (int st = 0; st < kStripes; ++st) {
-      ke += *stripe_slot(stripes, g, 0, st);
-      lost += *stripe_slot(stripes, g, 1, st);
-      ab[0] += *(unsigned long long*)stripe_slot(stripes, g, 2, st);
-      ab[1] += *(unsigned long long*)stripe_slot(stripes, g, 3, st);
-      for (int a = 0; a < 4; ++a) *(unsigned long long*)stripe_slot(stripes, g, a, st) = 0ull;
+    if (wide) {
+      ke = __longlong_as_double((long long)s_fold[g * 4 + 0]);
+      lost = __longlong_as_double((long long)s_fold[g * 4 + 1]);
+      ab[0] = s_fold[g * 4 + 2];
+      ab[1] = s_fold[g * 4 + 3];
+    } else {
+      for (int st = 0; st < kStripes; ++st) {
+        ke += *stripe_slot(stripes, g, 0, st);
+        lost += *stripe_slot(stripes, g, 1, st);
+        ab[0] += *(unsigned long long*)stripe_slot(stripes, g, 2, st);
+        ab[1] += *(unsigned long long*)stripe_slot(stripes, g, 3, st);
+        for (int a = 0; a < 4; ++a) *(unsigned long long*)stripe_slot(stripes, g, a, st) = 0ull;
+      }
     }
     G->ke_acc += ke;
     G->lost_energy += lost;
@@ -836,41 +871,53 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(GapDev* __restrict__ gaps,
     gptr<int32_t> cnt = glb(G->sort_cnt[s]);
     const int nb = buf ^ 1;
     gptr<const int32_t> cin = glb<const int32_t>((void*)G->cell[buf][s]);
-    gptr<int32_t> cout = glb(G->cell[nb][s]);
-    gptr<const uint64_t> iin = glb<const uint64_t>((void*)G->id[buf][s]);
-    gptr<uint64_t> iout = glb(G->id[nb][s]);
     int cvs[kItems];
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
       const long long i = i0 + threadIdx.x + (long long)j * kBlock;
       cvs[j] = i < i1 ? cin[i] : kDead;
     }
+    if (PASS == 0) {
+#pragma unroll
+      for (int j = 0; j < kItems; ++j) {
+        const int cv = cvs[j];
+        int head_lane, run_len;
+        wave_runs(cv, head_lane, run_len);
+        if (run_len > 0 && cv != kDead)
+          __hip_atomic_fetch_add(cnt + cv, run_len, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      continue;
+    }
+    // destinations of all items first (one returning atomic per run), then the moves
+    long long dst[kItems];
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+      const int cv = cvs[j];
+      int head_lane, run_len;
+      wave_runs(cv, head_lane, run_len);
+      int b = 0;
+      if (run_len > 0 && cv != kDead)
+        b = __hip_atomic_fetch_add(cnt + cv, run_len, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      b = __shfl(b, head_lane, 64);
+      dst[j] = (long long)b + (lane - head_lane);
+    }
+    gptr<int32_t> cout = glb(G->cell[nb][s]);
+    gptr<const uint64_t> iin = glb<const uint64_t>((void*)G->id[buf][s]);
+    gptr<uint64_t> iout = glb(G->id[nb][s]);
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
       const long long i = i0 + threadIdx.x + (long long)j * kBlock;
       const int cv = cvs[j];
-      int head_lane, run_len;
-      wave_runs(cv, head_lane, run_len);
-      if (PASS == 0) {
-        if (run_len > 0 && cv != kDead)
-          __hip_atomic_fetch_add(cnt + cv, run_len, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (cv == kDead) continue;
+      const long long d = dst[j];
+      cout[d] = cv;
+      iout[d] = iin[i];
+      if (elem_bytes == 8) {
+        glb<double>(G->off[nb][s])[d] = glb<const double>(G->off[buf][s])[i];
+        glb<double>(G->p[nb][s])[d] = glb<const double>(G->p[buf][s])[i];
       } else {
-        int b = 0;
-        if (run_len > 0 && cv != kDead)
-          b = __hip_atomic_fetch_add(cnt + cv, run_len, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        b = __shfl(b, head_lane, 64);
-        if (cv != kDead) {
-          const long long dst = (long long)b + (lane - head_lane);
-          cout[dst] = cv;
-          iout[dst] = iin[i];
-          if (elem_bytes == 8) {
-            glb<double>(G->off[nb][s])[dst] = glb<const double>(G->off[buf][s])[i];
-            glb<double>(G->p[nb][s])[dst] = glb<const double>(G->p[buf][s])[i];
-          } else {
-            glb<float>(G->off[nb][s])[dst] = glb<const float>(G->off[buf][s])[i];
-            glb<float>(G->p[nb][s])[dst] = glb<const float>(G->p[buf][s])[i];
-          }
-        }
+        glb<float>(G->off[nb][s])[d] = glb<const float>(G->off[buf][s])[i];
+        glb<float>(G->p[nb][s])[d] = glb<const float>(G->p[buf][s])[i];
       }
     }
   }

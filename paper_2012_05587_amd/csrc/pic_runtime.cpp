@@ -150,7 +150,7 @@ void fill_precision_constants(GapDev& G, const pic_gap_params& p) {
   G.gthr = (double)gthr;
   G.gpair = (double)gpair;
   G.pchild = (double)pchild;
-  G.child_gamma64 = std::sqrt(1.0 + G.pchild * G.pchild);
+  G.child_gamma64 = (double)std::sqrt((T)1 + pchild * pchild);
 }
 
 }  // namespace
@@ -176,6 +176,7 @@ struct pic_batch {
   bool started = false;
   hipGraphExec_t graph = nullptr;
   hipGraph_t graph_tmpl = nullptr;
+  bool graph_failed = false;
   // push-kernel timing
   bool profiling = false;
   std::vector<hipEvent_t> ev;   // start/stop pairs, reused
@@ -362,34 +363,81 @@ pic_status drain_events(pic_batch* b) {
   return PIC_OK;
 }
 
-pic_status enqueue_steps(pic_batch* b, int64_t n_steps) {
+// One step launched directly, with the push bracketed by events when
+// profiling; the re-sort follows every sort_every steps.
+pic_status eager_step(pic_batch* b) {
   const bool mixed = b->precision == PIC_MIXED;
-  for (int64_t k = 0; k < n_steps; ++k) {
-    if (b->profiling) {
-      if (b->ev_used + 2 > b->ev.size()) {
-        if (b->ev.size() >= 8192) {
-          pic_status st = drain_events(b);
-          if (st != PIC_OK) return st;
-        } else {
-          for (int e = 0; e < 2; ++e) {
-            hipEvent_t h;
-            if (hipEventCreate(&h) != hipSuccess) return PIC_ERR_DEVICE;
-            b->ev.push_back(h);
-          }
+  if (b->profiling) {
+    if (b->ev_used + 2 > b->ev.size()) {
+      if (b->ev.size() >= 8192) {
+        pic_status st = drain_events(b);
+        if (st != PIC_OK) return st;
+      } else {
+        for (int e = 0; e < 2; ++e) {
+          hipEvent_t h;
+          if (hipEventCreate(&h) != hipSuccess) return PIC_ERR_DEVICE;
+          b->ev.push_back(h);
         }
       }
-      pic::StepLaunch L = b->launch;
-      if (hipEventRecord(b->ev[b->ev_used], b->stream) != hipSuccess) return PIC_ERR_DEVICE;
-      if (pic::launch_push(L, mixed) != hipSuccess) return PIC_ERR_DEVICE;
-      if (hipEventRecord(b->ev[b->ev_used + 1], b->stream) != hipSuccess) return PIC_ERR_DEVICE;
-      b->ev_used += 2;
-      if (pic::launch_step_after_push(L, mixed) != hipSuccess) return PIC_ERR_DEVICE;
-    } else if (pic::launch_step(b->launch, mixed) != hipSuccess) {
-      return PIC_ERR_DEVICE;
     }
-    b->host_step += 1;
-    if (b->host_step % b->sort_every == 0)
-      if (pic::launch_sort(b->launch, mixed) != hipSuccess) return PIC_ERR_DEVICE;
+    if (hipEventRecord(b->ev[b->ev_used], b->stream) != hipSuccess) return PIC_ERR_DEVICE;
+    if (pic::launch_push(b->launch, mixed) != hipSuccess) return PIC_ERR_DEVICE;
+    if (hipEventRecord(b->ev[b->ev_used + 1], b->stream) != hipSuccess) return PIC_ERR_DEVICE;
+    b->ev_used += 2;
+    if (pic::launch_step_after_push(b->launch, mixed) != hipSuccess) return PIC_ERR_DEVICE;
+  } else if (pic::launch_step(b->launch, mixed) != hipSuccess) {
+    return PIC_ERR_DEVICE;
+  }
+  b->host_step += 1;
+  if (b->host_step % b->sort_every == 0)
+    if (pic::launch_sort(b->launch, mixed) != hipSuccess) return PIC_ERR_DEVICE;
+  return PIC_OK;
+}
+
+// Captures sort_every steps and the re-sort that ends them as one graph.
+// Every kernel reads its counts and plans from device memory, so the graph
+// can be replayed at any step that is a multiple of sort_every.
+bool build_graph(pic_batch* b) {
+  const bool mixed = b->precision == PIC_MIXED;
+  if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeRelaxed) != hipSuccess) return false;
+  bool ok = true;
+  for (int k = 0; k < b->sort_every && ok; ++k) ok = pic::launch_step(b->launch, mixed) == hipSuccess;
+  if (ok) ok = pic::launch_sort(b->launch, mixed) == hipSuccess;
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(b->stream, &g);
+  if (!ok || e != hipSuccess || !g) {
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    return false;
+  }
+  hipGraphExec_t x = nullptr;
+  if (hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    return false;
+  }
+  b->graph_tmpl = g;
+  b->graph = x;
+  return true;
+}
+
+pic_status enqueue_steps(pic_batch* b, int64_t n_steps) {
+  // graphs need a capturable (non-null) stream and no per-launch events
+  const bool graphs = b->stream != nullptr && !b->profiling && !b->graph_failed;
+  while (n_steps > 0) {
+    if (graphs && b->host_step % b->sort_every == 0 && n_steps >= b->sort_every) {
+      if (!b->graph && !build_graph(b)) {
+        b->graph_failed = true;
+        return enqueue_steps(b, n_steps);
+      }
+      if (hipGraphLaunch(b->graph, b->stream) != hipSuccess) return PIC_ERR_DEVICE;
+      b->host_step += b->sort_every;
+      n_steps -= b->sort_every;
+    } else {
+      pic_status st = eager_step(b);
+      if (st != PIC_OK) return st;
+      --n_steps;
+    }
   }
   b->started = true;
   return PIC_OK;

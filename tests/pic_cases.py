@@ -33,9 +33,9 @@ def gpu_params(cfg, **over):
         c.get("history_rows", 0))
 
 
-def make_gpu(cfg, **over):
+def make_gpu(cfg, stream=None, **over):
     import paper_2012_05587_amd as P
-    g = P.Gap(gpu_params(cfg, **over))
+    g = P.Gap(gpu_params(cfg, **over), stream=stream)
     if cfg.get("n_pairs", 0):
         g.seed_particles(cfg.get("seed_mode", workloads.SEED_RANDOM), cfg["n_pairs"],
                          cfg.get("macro_per_pair", 1), cfg.get("p0_minus", 0.0),

@@ -146,6 +146,34 @@ def test_sort_cadence_does_not_change_results():
         assert np.array_equal(E, ref[2]), se
 
 
+@pytest.mark.parametrize("precision", [workloads.FP64, workloads.MIXED])
+def test_graph_replay_matches_eager_and_oracle(precision):
+    """On a side stream the library replays captured graphs of sort_every
+    steps; mixed with direct launches and reads between the calls, every
+    state must equal a run launched directly and the oracle's."""
+    import torch
+    cfg = workloads.config("c1_fp64_reference_gap")
+    cfg.update(precision=precision, history_rows=500)
+    seq = [7, 40, 13, 60, 20, 100, 3]
+    side = torch.cuda.Stream()
+    gg = pc.make_gpu(cfg, stream=side)
+    ge = pc.make_gpu(cfg)
+    go = pc.make_oracle(cfg)
+    done = 0
+    for n in seq:
+        gg.step_n(n)
+        ge.step_n(n)
+        assert go.step(n) == 0
+        done += n
+        hg, he = gg.read_history(), ge.read_history()
+        for k in pc.HIST_INT:
+            assert np.array_equal(hg[k], he[k]), (done, k)
+        assert np.array_equal(gg.read_fields(rho=False)["E"], ge.read_fields(rho=False)["E"]), done
+    pc.compare_history(gg.read_history(), go.history())
+    pc.compare_particles(gg, go, PTOL[precision])
+    pc.compare_fields(gg, go)
+
+
 def test_run_twice_is_bitwise_identical():
     cfg = workloads.config("c3_mixed_single_gap")
     out = []
