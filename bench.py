@@ -1,19 +1,23 @@
 """Benchmark of the MI355X pair-cascade PIC path: particle-pushes per second.
 
-One step is one PIC time step of the whole path (gather and push, move and
+A step is one PIC time step of the whole path (gather and push, move and
 current deposit, Ampere update, emission, conversion, periodic re-sort) for
-every lepton of the workload.  A push is one lepton advanced one step,
-counted exactly by the device.  The default workload is the binary64 single
-gap of 8192 cells seeded with 1024 pairs (E0 = 200, gamma_thr = 200,
-l_gamma = 50 cells, absorbing), run for its 20000 steps with inputs resident
-in HBM; the same physics in mixed precision is timed beside it.
+every lepton of every gap.  A push is one lepton advanced one step, counted
+exactly by the device.  Inputs are resident in HBM before timing starts.
+
+Default workload ("mixed-batched vs plain FP64"): 256 independent gaps with
+N_cells log-uniform in [1024, 16384], E0 and gamma_thr uniform in [50, 400],
+l_gamma uniform in [10, 100] cells and 256-4096 seed pairs, advanced together
+for 2000 steps in mixed precision (value).  Beside it: the same batch in
+binary64, and the binary64 single gap of 8192 cells (E0 = gamma_thr = 200,
+l_gamma = 50, 1024 seed pairs) over its numerically stable first 10000 steps.
 
 Prints one JSON line.  The roofline entry is for the push kernel, which
-moves the lepton state: 4 B cell + 8 B offset + 8 B momentum read and written
-(40 B per push) in binary64, 24 B per push in mixed precision.  Its time is
-summed from HIP events bracketing every push launch on the library's stream.
-The cpu_baseline entry times the oracle (single thread) on the first steps of
-the same workload.
+moves the lepton state: 4 B cell + 4 B offset + 4 B momentum read and written
+(24 B per push) in mixed precision, 40 B per push in binary64.  Its time is
+summed from HIP events bracketing every push launch on the library's stream,
+in a second run identical to the timed one.  The cpu_baseline entry times the
+oracle on a bounded sample of the same workload, one gap per process.
 """
 import argparse
 import json
@@ -27,14 +31,19 @@ sys.path.insert(0, ROOT)
 import workloads  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
-# Timed steps when --steps is not given.  Configuration 2 at dt = 0.45 has a
-# non-relativistic omega_p dt far above the leapfrog limit of 2 once its
-# plasma cools; after ~10600 steps its field and photon counts grow
-# exponentially (a numerical instability that the oracle shows identically),
-# so its stable first 10000 steps are the job.
-DEFAULT_STEPS = {"c2_fp64_single_gap": 10000}
 BYTES_PER_PUSH = {workloads.FP64: 40, workloads.MIXED: 24}
 DTYPE = {workloads.FP64: "f64", workloads.MIXED: "f32/f64"}
+METRIC = "particle-pushes/sec + % HBM roofline, mixed-batched vs plain FP64, 1 MI355X"
+# Timed steps when --steps is not given.  The single gap of 8192 cells at
+# dt = 0.45 has a non-relativistic omega_p dt far above the leapfrog limit of
+# 2 once its plasma cools; after ~10600 steps its field and photon counts grow
+# exponentially (a numerical instability the oracle shows identically), so its
+# stable first 10000 steps are the job.
+DEFAULT_STEPS = {"c2_fp64_single_gap": 10000}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def _params(P, c):
@@ -44,89 +53,170 @@ def _params(P, c):
                          c.get("sort_every", 0), c.get("diag_every", 0), c.get("history_rows", 0))
 
 
-def log(msg):
-    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+def _workload(name, precision=None):
+    """List of gap configurations of a workload (one for single gaps)."""
+    if name == "c4_batched":
+        gaps = workloads.batched_scan(256, precision=workloads.MIXED if precision is None else precision)
+    else:
+        gaps = [workloads.config(name)]
+        if precision is not None:
+            gaps[0]["precision"] = precision
+    return gaps
 
 
-def run_gpu(cfg, steps, warmup, dump=None):
+def _make(P, gaps, stream):
+    """A Batch of the gaps (or a Gap for one), seeded."""
+    if len(gaps) == 1:
+        g = P.Gap(_params(P, gaps[0]), stream=stream)
+        views = [g]
+    else:
+        g = P.Batch([_params(P, c) for c in gaps], stream=stream)
+        views = g.gaps
+    for v, c in zip(views, gaps):
+        v.seed_particles(workloads.SEED_RANDOM, c["n_pairs"], c["macro_per_pair"])
+    return g, views
+
+
+def run_gpu(gaps, steps, profile=True, dump=None):
     """Times `steps` steps from the seeded start (graph replay on a side
-    stream), then repeats the same run launching every kernel directly with
-    the push kernel bracketed by HIP events, for that kernel's duration."""
+    stream); with profile, repeats the run launching every kernel directly
+    with the push kernel bracketed by HIP events, for that kernel's time."""
     import torch
     import paper_2012_05587_amd as P
     P.lib()
-    cfg = dict(cfg, history_rows=steps + 8)
+    gaps = [dict(c, history_rows=steps + 8) for c in gaps]
     stream = torch.cuda.Stream()
-    if warmup > 0:
-        w = P.Gap(_params(P, cfg), stream=stream)
-        w.seed_particles(workloads.SEED_RANDOM, cfg["n_pairs"], cfg["macro_per_pair"])
-        w.step_n(warmup)
-        torch.cuda.synchronize()
-        w.close()
-        del w
-    g = P.Gap(_params(P, cfg), stream=stream)
-    g.seed_particles(workloads.SEED_RANDOM, cfg["n_pairs"], cfg["macro_per_pair"])
+    g, views = _make(P, gaps, stream)
     torch.cuda.synchronize()
-    log(f"timing {steps} steps, precision {cfg['precision']}")
+    log(f"timing {steps} steps of {len(gaps)} gap(s), precision {gaps[0]['precision']}")
     t0 = time.perf_counter()
     g.step_n(steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     log(f"done in {t1 - t0:.2f} s")
-    m = g.read_moments()
-    h = g.read_history()
-    if dump:
+    pushes, peak, frozen, done = 0, 0, 0, 0
+    for v in views:
+        m = v.read_moments()
+        pushes += int(m.pushes)
+        frozen += int(m.status != 0)
+        done = max(done, int(m.steps_done))
+    if len(views) == 1:
+        h = views[0].read_history()
+        peak = int((h["n_minus"] + h["n_plus"]).max()) if len(h) else 0
+        if dump:
+            import numpy as np
+            np.save(dump, h)
+    elif dump:
+        # per step, summed over the gaps still running: live leptons, photons
+        # in flight, cumulative pairs and photons
         import numpy as np
-        np.save(dump, h)
-    out = dict(seconds=t1 - t0, pushes=int(m.pushes), steps=int(m.steps_done), status=int(m.status),
-               peak_leptons=int((h["n_minus"] + h["n_plus"]).max()) if len(h) else 0,
-               final_leptons=int(m.n_minus + m.n_plus))
+        cols = ("live", "n_photons", "pairs_created", "photons_emitted", "running")
+        out_h = np.zeros(steps, dtype=[(c, np.int64) for c in cols])
+        for v in views:
+            h = v.read_history()
+            k = h["step"]
+            out_h["live"][k] += h["n_minus"] + h["n_plus"]
+            out_h["n_photons"][k] += h["n_photons"]
+            # per-step increments of the cumulative counts
+            out_h["pairs_created"][k] += np.diff(h["pairs_created"], prepend=0)
+            out_h["photons_emitted"][k] += np.diff(h["photons_emitted"], prepend=0)
+            out_h["running"][k] += 1
+        np.save(dump, out_h)
+    out = dict(seconds=t1 - t0, pushes=pushes, steps=done, frozen=frozen, peak_leptons=peak,
+               push_ms=None, push_launches=None)
     g.close()
-    del g
-    # the same run again, with the push kernel timed by events
-    g = P.Gap(_params(P, cfg), stream=stream)
-    g.seed_particles(workloads.SEED_RANDOM, cfg["n_pairs"], cfg["macro_per_pair"])
-    g.profile_push(True)
-    log("timing the push kernel with events")
-    g.step_n(steps)
-    push_ms, launches = g.read_push_time()
-    m2 = g.read_moments()
-    if int(m2.pushes) != out["pushes"]:
-        raise RuntimeError("profiled run differs from the timed run")
-    out.update(push_ms=push_ms, push_launches=launches)
-    g.close()
+    del g, views, v
+    torch.cuda.empty_cache()
+    if profile:
+        g, views = _make(P, gaps, stream)
+        g.profile_push(True)
+        log("timing the push kernel with events")
+        g.step_n(steps)
+        push_ms, launches = g.read_push_time()
+        again = sum(int(x.read_moments().pushes) for x in views)
+        if again != pushes:
+            raise RuntimeError("profiled run differs from the timed run")
+        out.update(push_ms=push_ms, push_launches=launches)
+        g.close()
+        del g, views
+        torch.cuda.empty_cache()
     return out
 
 
-def run_cpu_baseline(cfg, steps):
+def warm_up(steps):
+    """Loads the code objects and builds a graph on a small batch."""
+    import torch
+    import paper_2012_05587_amd as P
+    if steps <= 0:
+        return
+    gaps = workloads.batched_scan(4, precision=workloads.MIXED, steps=steps)
+    for c in gaps:
+        c.update(capacity=200_000, photon_capacity=200_000)
+    for prec in (workloads.MIXED, workloads.FP64):
+        g, _ = _make(P, [dict(c, precision=prec) for c in gaps], torch.cuda.Stream())
+        g.step_n(steps)
+        torch.cuda.synchronize()
+        g.close()
+
+
+def _oracle_gap(args):
+    c, steps = args
+    sys.path.insert(0, ROOT)
     import oracle
-    kw = {k: cfg[k] for k in workloads.GAP_KEYS}
-    g = oracle.OracleGap(**kw, capacity=0)
-    g.seed(workloads.SEED_RANDOM, cfg["n_pairs"], cfg["macro_per_pair"])
-    n0 = g.count(0) + g.count(1)
-    log(f"oracle baseline: {steps} steps")
-    t0 = time.perf_counter()
-    st = g.step(steps)
-    t1 = time.perf_counter()
-    h = g.history()
+    o = oracle.OracleGap(**{k: c[k] for k in workloads.GAP_KEYS}, capacity=0)
+    o.seed(workloads.SEED_RANDOM, c["n_pairs"], c["macro_per_pair"])
+    n0 = o.count(0) + o.count(1)
+    o.step(steps)
+    h = o.history()
     live = (h["n_minus"] + h["n_plus"]).astype("int64")
-    pushes = int(n0 + live[:-1].sum()) if len(live) else 0
-    return dict(value=pushes / (t1 - t0), seconds=t1 - t0, pushes=pushes, status=st)
+    return int(n0 + (live[:-1].sum() if len(live) else 0))
+
+
+def run_cpu_baseline(gaps, steps, procs):
+    """The oracle on a bounded sample: the first `steps` steps of each gap,
+    one gap per process; pushes per second of wall time."""
+    import multiprocessing as mp
+    jobs = [(c, steps) for c in gaps]
+    log(f"oracle baseline: {len(jobs)} gap(s) x {steps} steps on {procs} process(es)")
+    t0 = time.perf_counter()
+    if procs > 1:
+        with mp.get_context("fork").Pool(procs) as pool:
+            pushes = sum(pool.map(_oracle_gap, jobs, chunksize=1))
+    else:
+        pushes = sum(_oracle_gap(j) for j in jobs)
+    t1 = time.perf_counter()
+    return dict(value=pushes / (t1 - t0), seconds=t1 - t0, pushes=pushes)
+
+
+def _leg(r, precision):
+    bpp = BYTES_PER_PUSH[precision]
+    leg = dict(value=r["pushes"] / r["seconds"], unit="pushes/s", pushes=r["pushes"],
+               seconds=r["seconds"], steps=r["steps"], frozen_gaps=r["frozen"])
+    if r["push_ms"]:
+        leg["push_kernel_GBs"] = r["pushes"] * bpp / (r["push_ms"] * 1e-3) / 1e9
+    return leg
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=None, help="timed steps (default: whole run)")
-    ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--workload", default="c2_fp64_single_gap")
-    ap.add_argument("--cpu-steps", type=int, default=300)
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default: whole job)")
+    ap.add_argument("--warmup", type=int, default=40)
+    ap.add_argument("--workload", default="c4_batched",
+                    choices=["c4_batched"] + sorted(workloads.CONFIGS))
+    ap.add_argument("--cpu-gaps", type=int, default=32)
+    ap.add_argument("--cpu-steps", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--dump-history", default=None, help="save the history rows (.npy)")
+    ap.add_argument("--no-compare", action="store_true", help="skip the comparison legs")
+    ap.add_argument("--dump-history", default=None, help="save the history rows (.npy, single gap)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy a 1 GiB device buffer 3 times (counter calibration)")
     args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this path runs on one GPU; --gpus {args.gpus} is not supported "
+              "(independent gaps would shard across GPUs without communication; not built here)",
+              file=sys.stderr)
+        sys.exit(2)
     if args.copy_probe:
         import torch
         a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
@@ -136,37 +226,54 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": 1 << 30, "copies": 3}))
         return
-    if args.gpus != 1:
-        print(f"bench.py: this path runs on one GPU; --gpus {args.gpus} is not supported "
-              "(independent gaps shard across GPUs without communication; not built here)",
-              file=sys.stderr)
-        sys.exit(2)
 
-    cfg = workloads.config(args.workload)
-    steps = args.steps if args.steps is not None else DEFAULT_STEPS.get(args.workload, cfg["steps"])
-    main_run = run_gpu(cfg, steps, args.warmup, args.dump_history)
-    value = main_run["pushes"] / main_run["seconds"]
-    bpp = BYTES_PER_PUSH[cfg["precision"]]
-    achieved = main_run["pushes"] * bpp / (main_run["push_ms"] * 1e-3) / 1e9 if main_run["push_ms"] else 0.0
+    gaps = _workload(args.workload)
+    prec = gaps[0]["precision"]
+    steps = args.steps if args.steps is not None else DEFAULT_STEPS.get(args.workload, gaps[0]["steps"])
 
-    extra = {}
-    if not args.no_mixed and cfg["precision"] == workloads.FP64:
-        mcfg = dict(cfg, precision=workloads.MIXED)
-        mr = run_gpu(mcfg, steps, 0)
-        extra["mixed_same_workload"] = dict(
-            value=mr["pushes"] / mr["seconds"], unit="pushes/s", pushes=mr["pushes"],
-            seconds=mr["seconds"], push_kernel_GBs=mr["pushes"] * 24 / (mr["push_ms"] * 1e-3) / 1e9
-            if mr["push_ms"] else None, status=mr["status"])
-
+    # the oracle's process pool forks before anything touches the GPU
     cpu = None
     if not args.no_cpu:
-        cb = run_cpu_baseline(cfg, min(args.cpu_steps, steps))
-        cpu = dict(value=cb["value"], unit="pushes/s", cores=1, kind="oracle",
-                   sample=f"first {min(args.cpu_steps, steps)} steps of {args.workload} "
-                          f"({cb['pushes']} pushes, {cb['seconds']:.1f} s, single thread)")
+        sample = gaps[:args.cpu_gaps]
+        procs = min(len(sample), os.cpu_count() or 1, 16)
+        cb = run_cpu_baseline(sample, min(args.cpu_steps, steps), procs)
+        cpu = dict(value=cb["value"], unit="pushes/s", cores=procs, kind="oracle",
+                   sample=f"first {min(args.cpu_steps, steps)} steps of {len(sample)} gap(s) of "
+                          f"{args.workload}, one gap per process ({cb['pushes']} pushes, "
+                          f"{cb['seconds']:.1f} s)")
 
+    warm_up(args.warmup)
+    main_run = run_gpu(gaps, steps, profile=True, dump=args.dump_history)
+    value = main_run["pushes"] / main_run["seconds"]
+    bpp = BYTES_PER_PUSH[prec]
+    achieved = main_run["pushes"] * bpp / (main_run["push_ms"] * 1e-3) / 1e9
+
+    extra = {}
+    if not args.no_compare:
+        if args.workload == "c4_batched":
+            r = run_gpu(_workload("c4_batched", workloads.FP64), steps, profile=False)
+            extra["fp64_batched_same_workload"] = _leg(r, workloads.FP64)
+            c2 = _workload("c2_fp64_single_gap")
+            r = run_gpu(c2, DEFAULT_STEPS["c2_fp64_single_gap"], profile=True)
+            leg = _leg(r, workloads.FP64)
+            leg["workload"] = "c2_fp64_single_gap (8192 cells, 1024 seed pairs, first 10000 steps)"
+            extra["plain_fp64_single_gap"] = leg
+        elif prec == workloads.FP64:
+            r = run_gpu(_workload(args.workload, workloads.MIXED), steps, profile=True)
+            extra["mixed_same_workload"] = _leg(r, workloads.MIXED)
+
+    cfg = {"workload": args.workload, "gaps": len(gaps), "steps": steps,
+           "pushes": main_run["pushes"], "frozen_gaps": main_run["frozen"]}
+    if len(gaps) == 1:
+        cfg.update(n_cells=gaps[0]["n_cells"], seed_pairs=gaps[0]["n_pairs"], e0=gaps[0]["e0"],
+                   gamma_thr=gaps[0]["gamma_thr"], l_gamma=gaps[0]["l_gamma"],
+                   peak_leptons=main_run["peak_leptons"])
+    else:
+        cfg.update(n_cells="log-uniform 1024-16384", e0="U[50,400]", gamma_thr="U[50,400]",
+                   l_gamma="U[10,100] cells", seed_pairs="log-uniform 256-4096",
+                   caps="1e5-1e7 per species")
     line = {
-        "metric": "particle-pushes/sec + % HBM roofline, mixed-batched vs plain FP64, 1 MI355X",
+        "metric": METRIC,
         "value": value,
         "unit": "pushes/s",
         "n_gpus": 1,
@@ -176,12 +283,9 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": DTYPE[cfg["precision"]],
+        "dtype": DTYPE[prec],
         "data": "synthetic",
-        "config": {"workload": args.workload, "n_cells": cfg["n_cells"], "seed_pairs": cfg["n_pairs"],
-                   "e0": cfg["e0"], "gamma_thr": cfg["gamma_thr"], "l_gamma": cfg["l_gamma"],
-                   "steps": steps, "peak_leptons": main_run["peak_leptons"],
-                   "pushes": main_run["pushes"], "status": main_run["status"]},
+        "config": cfg,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_push", "bytes_per_push": bpp,

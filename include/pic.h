@@ -231,6 +231,7 @@ pic_status pic_read_push_time(pic_gap* g, double* ms, int64_t* launches);
 /* ---- Batches: many independent gaps advanced by the same launches. ----
  * All gaps of a batch share precision, sort_every, diag_every and
  * history_rows (taken from params[0]); every other parameter is per gap.
+ * The lepton capacities of a batch, both species, sum to less than 2^32.
  *
  * pic_batch_plan admits gaps in order while the total workspace stays
  * within budget_bytes: admitted[i] = 1 or 0; *ws_bytes = workspace of the

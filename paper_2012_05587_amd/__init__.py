@@ -270,9 +270,11 @@ class Gap(_GapView):
         return ms.value, n.value
 
     def close(self):
+        """Frees the handle and drops this object's reference to the workspace."""
         if self._h:
             lib().pic_destroy(self._h)
             self._h = None
+        self.workspace = None
 
     def __del__(self):
         try:
@@ -316,9 +318,13 @@ class Batch:
         return ms.value, n.value
 
     def close(self):
+        """Frees the handle and drops this object's reference to the workspace;
+        the gap views of a closed batch must not be used."""
         if self._h:
             lib().pic_destroy_batch(self._h)
             self._h = None
+        self.workspace = None
+        self.gaps = []
 
     def __del__(self):
         try:

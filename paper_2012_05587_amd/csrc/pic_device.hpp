@@ -16,8 +16,15 @@ constexpr int kChunk = kBlock * kItems;
 constexpr int kTile = 2048;           // cells of the per-workgroup LDS current tile
 constexpr int kPhChunk = kBlock * 4;  // photons per convert work item
 constexpr int kCellChunk = kBlock * 4;
+constexpr int kSortTile = 8192;       // cells of the LDS histogram of the lepton sort
+constexpr int kPhBins = 8192;         // conversion steps of the LDS histogram of the photon sort
 constexpr int32_t kDead = INT32_MIN;  // cell of an absorbed lepton until re-sort
 constexpr int kMaxEmit = 64;
+// emit_cnt of a chunk packs its emitter count (at most kChunk) below bit
+// kEmitShift and its photon count (at most kChunk * kMaxEmit) above it.
+constexpr int kEmitShift = 11;
+constexpr uint32_t kEmitMask = (1u << kEmitShift) - 1u;
+constexpr int kPushGrid = 4096;       // workgroups of the push kernel
 constexpr int kStripes = 32;          // striped per-gap accumulators of the push kernel
 constexpr int kStripeStride = 16;     // doubles between stripes (one 128-byte line each)
 constexpr uint64_t kTagSeed = 1, kTagPhoton = 2;
@@ -54,10 +61,12 @@ struct GapDev {
 
   // ---- counters (device-updated)
   unsigned long long n[2];       // slots in use at step start
-  unsigned long long n_next[2];  // append cursor
+  unsigned long long pair_next;  // pairs appended this step: both species grow by the same
+                                 // count, electron j at n[0] + j and positron j at n[1] + j
+  unsigned long long esc_next;   // photons that left the domain this step
   unsigned long long dead[2];    // absorbed slots since the last re-sort
   unsigned long long live[2];    // live leptons after the last completed step
-  unsigned long long n_ph, n_ph_next, inflight;
+  unsigned long long n_ph, n_ph_next, inflight;  // photon slots at step start, append cursor
   unsigned long long pairs_created, photons_emitted, photons_escaped, absorbed[2];
   unsigned long long pushes;
   unsigned long long hist_count;
@@ -160,10 +169,13 @@ __device__ __forceinline__ int find_gap(const long long* __restrict__ start, int
 // workgroup index remapped so that each of the 8 XCDs (which receive
 // workgroups round-robin) walks one contiguous eighth of the items and keeps
 // the field lines of its cells in its own L2.
+__device__ __forceinline__ int xcd_logical(int b, int nb) {
+  return (nb & 7) == 0 ? (b & 7) * (nb >> 3) + (b >> 3) : b;
+}
+
 __device__ __forceinline__ void xcd_range(long long total, long long& w0, long long& w1,
                                           int b, int nb) {
-  int lb = b;
-  if ((nb & 7) == 0) lb = (b & 7) * (nb >> 3) + (b >> 3);
+  const int lb = xcd_logical(b, nb);
   long long per = (total + nb - 1) / nb;
   w0 = (long long)lb * per;
   w1 = w0 + per < total ? w0 + per : total;

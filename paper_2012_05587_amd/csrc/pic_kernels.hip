@@ -86,26 +86,6 @@ __device__ __forceinline__ void block_minmax(int& mn, int& mx, int* s_red) {
   mx = max(max(s_red[4], s_red[5]), max(s_red[6], s_red[7]));
 }
 
-// Block-wide exclusive prefix sum (256 threads); `total` gets the sum.
-__device__ __forceinline__ unsigned long long block_excl_scan(unsigned long long x,
-                                                              unsigned long long* s_tmp,
-                                                              unsigned long long& total) {
-  const unsigned long long incl = wave_incl_scan(x);
-  const int w = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane_id() == 63) s_tmp[w] = incl;
-  __syncthreads();
-  unsigned long long off = 0, t = 0;
-#pragma unroll
-  for (int k = 0; k < kBlock / 64; ++k) {
-    const unsigned long long v = s_tmp[k];
-    if (k < w) off += v;
-    t += v;
-  }
-  total = t;
-  return off + incl - x;
-}
-
 // ------------------------------------------------------------------ push
 // Sums of one workgroup over the work items of one gap, flushed with one
 // atomic each when the workgroup moves to another gap or finishes.
@@ -150,6 +130,7 @@ __global__ __launch_bounds__(kBlock) void k_push(GapDev* __restrict__ gaps,
                                                  const long long* __restrict__ wi, int B,
                                                  int32_t* __restrict__ emit_cnt,
                                                  uint32_t* __restrict__ emit_ent,
+                                                 uint32_t* __restrict__ wg_emit,
                                                  double* __restrict__ stripes) {
   using I = typename Fixed<T>::I;
   __shared__ long long s_flux[kTile];
@@ -157,7 +138,7 @@ __global__ __launch_bounds__(kBlock) void k_push(GapDev* __restrict__ gaps,
   __shared__ int s_red[8];
   __shared__ double s_d[8];
   __shared__ unsigned long long s_u[8];
-  __shared__ int s_emit_n;
+  __shared__ int s_emit_n, s_emit_k;
 
   const long long total = wi[B];
   long long w0, w1;
@@ -167,6 +148,7 @@ __global__ __launch_bounds__(kBlock) void k_push(GapDev* __restrict__ gaps,
   PushTally tally = {0.0, 0.0, {0, 0}};
   int cur_g = -1;
   bool cur_diag = false;
+  uint32_t my_emitters = 0;  // emitters listed by this workgroup (thread 0)
 
   for (long long w = w0; w < w1; ++w) {
     const int g = find_gap(wi, B, w);
@@ -218,7 +200,7 @@ __global__ __launch_bounds__(kBlock) void k_push(GapDev* __restrict__ gaps,
         mx = max(mx, cl[j]);
       }
     }
-    if (tid == 0) s_emit_n = 0;
+    if (tid == 0) { s_emit_n = 0; s_emit_k = 0; }
     block_minmax(mn, mx, s_red);
     if (mx < mn) continue;  // no live lepton in this chunk (uniform)
     const int base = mn - 1;
@@ -301,6 +283,7 @@ __global__ __launch_bounds__(kBlock) void k_push(GapDev* __restrict__ gaps,
           pn = pn > (T)0 ? mag : -mag;
           gnew = sqrt(one_t + pn * pn);
           const int pos = atomicAdd(&s_emit_n, 1);
+          atomicAdd(&s_emit_k, k);
           s_emit[pos] = ((uint32_t)(i - i0) << 8) | (uint32_t)k;
         }
         pA[i] = pn;
@@ -338,13 +321,18 @@ __global__ __launch_bounds__(kBlock) void k_push(GapDev* __restrict__ gaps,
     // ---- emitters of this chunk, in the chunk's own slice of the list
     const int ne = s_emit_n;
     if (ne > 0) {
-      if (tid == 0) emit_cnt[w] = ne;
+      if (tid == 0) {
+        emit_cnt[w] = ne | (s_emit_k << kEmitShift);
+        my_emitters += (uint32_t)ne;
+      }
       gptr<uint32_t> el = glb(emit_ent + w * (long long)kChunk);
       for (int k = tid; k < ne; k += kBlock) el[k] = s_emit[k];
     }
     __syncthreads();
   }
   if (cur_g >= 0) flush_tally(stripes, cur_g, tally, cur_diag, s_d, s_u);
+  // emitters of this workgroup's chunk range, indexed in chunk order
+  if (tid == 0) wg_emit[xcd_logical((int)blockIdx.x, (int)gridDim.x)] = my_emitters;
 }
 
 // ------------------------------------------------------------------ emit
@@ -357,149 +345,264 @@ __device__ __forceinline__ void chunk_origin(const GapDev* G, long long local, i
   i0 = (s == 0 ? local : local - chunks0) * kChunk;
 }
 
-// Sum over the block of x (256 threads); every thread gets it.
-__device__ __forceinline__ unsigned long long block_sum(unsigned long long x,
-                                                        unsigned long long* s_tmp) {
-  const unsigned long long v = wave_sum(x);
-  __syncthreads();
-  if (lane_id() == 0) s_tmp[threadIdx.x >> 6] = v;
-  __syncthreads();
-  return (s_tmp[0] + s_tmp[1]) + (s_tmp[2] + s_tmp[3]);
+// Per-wave shares of a workgroup's total: s_wave[v] holds wave v's count on
+// entry; returns the block total and sets `pre` to the counts of the waves
+// before this one.  Every thread must call it.
+__device__ __forceinline__ unsigned long long wave_shares(const unsigned long long* s_wave,
+                                                          unsigned long long& pre) {
+  const int v = threadIdx.x >> 6;
+  unsigned long long t = 0;
+  pre = 0;
+#pragma unroll
+  for (int k = 0; k < kBlock / 64; ++k) {
+    if (k < v) pre += s_wave[k];
+    t += s_wave[k];
+  }
+  return t;
 }
 
+// Lanes below this one in the wave.
+__device__ __forceinline__ unsigned long long lanes_below() {
+  return (1ull << lane_id()) - 1ull;
+}
+
+// Pairs of a step share one slot cursor: the workgroup reserves `tot` pairs
+// (electron slots from n[0], positron slots from n[1]).
+__device__ __forceinline__ unsigned long long reserve_pairs(GapDev* G, unsigned long long tot) {
+  const unsigned long long b = atomicAdd(&G->pair_next, tot);
+  const unsigned long long cap = (unsigned long long)G->cap;
+  if (G->n[0] + b + tot > cap || G->n[1] + b + tot > cap) G->overflow = 1;
+  return b;
+}
+
+// Block-wide exclusive prefix sum of ints (256 threads); `total` gets the sum.
+__device__ __forceinline__ int block_excl_scan(int x, int* s_tmp, int& total) {
+  const int incl = wave_incl_scan(x);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane_id() == 63) s_tmp[w] = incl;
+  __syncthreads();
+  int off = 0, t = 0;
+#pragma unroll
+  for (int k = 0; k < kBlock / 64; ++k) {
+    const int v = s_tmp[k];
+    if (k < w) off += v;
+    t += v;
+  }
+  total = t;
+  return off + incl - x;
+}
+
+// The k photons (or in-place pairs) of emitter i of species s, written at
+// photon slots slot0 .. slot0 + k - 1 (pair slots n[0] + slot, n[1] + slot).
+// Returns the number of photons that left the domain.
+template <typename T>
+__device__ __forceinline__ unsigned emit_one(GapDev* __restrict__ G, int s, long long i, int k,
+                                             unsigned long long slot0, bool in_place) {
+  const int buf = G->buf;
+  const long long ONE = G->one;
+  const T scale = (T)(double)ONE;
+  const int c = G->cell[buf][s][i];
+  const long long oq = (long long)(((const T*)G->off[buf][s])[i] * scale);
+  const T pv = ((const T*)G->p[buf][s])[i];
+  const uint64_t id = G->id[buf][s][i];
+  const uint64_t stepn = (uint64_t)G->step;
+  const uint64_t seed = G->seed;
+  const int dir = pv > (T)0 ? 1 : -1;
+  unsigned esc = 0;
+  if (in_place) {
+    // pair made in place (the paper's zero mean free path)
+    const T pchild = (T)G->pchild;
+    const T pc = dir > 0 ? pchild : -pchild;
+    const T offn = (T)oq * ((T)1 / scale);
+    const unsigned long long cap = (unsigned long long)G->cap;
+    const unsigned long long ne0 = G->n[0], ne1 = G->n[1];
+    for (int jj = 0; jj < k; ++jj) {
+      const U64x4 u = philox4x64_10(stepn, (uint64_t)jj, kTagPhoton, 0, id, seed);
+      const uint64_t child = u.v[1] & ~(uint64_t)1;
+      const unsigned long long se = ne0 + slot0 + jj, sp = ne1 + slot0 + jj;
+      if (se < cap) {
+        G->cell[buf][0][se] = c; ((T*)G->off[buf][0])[se] = offn;
+        ((T*)G->p[buf][0])[se] = pc; G->id[buf][0][se] = child;
+      }
+      if (sp < cap) {
+        G->cell[buf][1][sp] = c; ((T*)G->off[buf][1])[sp] = offn;
+        ((T*)G->p[buf][1])[sp] = pc; G->id[buf][1][sp] = child | 1u;
+      }
+    }
+  } else {
+    const bool absorbing = G->boundary == PIC_BC_ABSORBING;
+    const unsigned long long ph_cap = (unsigned long long)G->ph_cap;
+    const int pb = G->phbuf;
+    const long long X0 = (long long)c * ONE + oq;
+    for (int jj = 0; jj < k; ++jj) {
+      const U64x4 u = philox4x64_10(stepn, (uint64_t)jj, kTagPhoton, 0, id, seed);
+      const uint64_t child = u.v[1] & ~(uint64_t)1;
+      const int ncv = conv_steps(G->table, G->table_len, (uint32_t)(u.v[0] >> 32), G->inv_lnq);
+      long long X = X0 + (long long)dir * (long long)ncv * G->photon_step;
+      int cstep = (int)((long long)stepn + ncv);
+      if (absorbing) {
+        if (X < 0 || X >= G->domain) { cstep = INT32_MIN; ++esc; }
+      } else {
+        X %= G->domain;
+        if (X < 0) X += G->domain;
+      }
+      const unsigned long long slot = slot0 + jj;
+      if (slot < ph_cap) {
+        G->ph_x[pb][slot] = X;
+        G->ph_step[pb][slot] = cstep;
+        G->ph_child[pb][slot] = child | (dir > 0 ? 1u : 0u);
+      }
+    }
+  }
+  return esc;
+}
+
+// Walks the emitters with flattened indices [qa, qb) (chunk order, then list
+// order within a chunk) among chunks [x, xend) of gap G, whose first emitter
+// has flattened index Q.  Windows of kBlock chunks are scanned for their
+// emitter counts; each round hands one emitter to each thread.  With
+// `write` false it returns the photons of the walked emitters (every thread
+// gets the sum); with `write` true it emits them at slots base + running
+// offset.  On return x and Q point past the last window walked.
+template <typename T>
+__device__ unsigned long long emit_walk(GapDev* __restrict__ G, long long& x, long long xend,
+                                        unsigned long long& Q, unsigned long long qa,
+                                        unsigned long long qb, long long wg0, bool write,
+                                        unsigned long long base, unsigned& esc,
+                                        gptr<const uint32_t> cntA, gptr<const uint32_t> entA,
+                                        int* s_nb, int* s_tmp) {
+  const bool in_place = G->table_len == 0;
+  unsigned long long run = 0;
+  while (x < xend && Q < qb) {
+    const long long xc0 = x + threadIdx.x;
+    const int ne = xc0 < xend ? (int)(cntA[xc0] & kEmitMask) : 0;
+    int nwin;
+    const int nb = block_excl_scan(ne, s_tmp, nwin);
+    s_nb[threadIdx.x] = nb;
+    __syncthreads();
+    const unsigned long long lo = qa > Q ? qa : Q;
+    const unsigned long long hi = qb < Q + (unsigned long long)nwin ? qb : Q + (unsigned long long)nwin;
+    for (unsigned long long r = lo; r < hi; r += kBlock) {
+      const unsigned long long q = r + threadIdx.x;
+      int k = 0, s = 0;
+      long long i = 0;
+      if (q < hi) {
+        const int ql = (int)(q - Q);
+        // the chunk holding emitter ql of the window: last t with s_nb[t] <= ql
+        int a = 0, b = kBlock - 1;
+        while (a < b) {
+          const int mid = (a + b + 1) >> 1;
+          if (s_nb[mid] <= ql) a = mid; else b = mid - 1;
+        }
+        const long long xc = x + a;
+        const uint32_t en = entA[xc * kChunk + (ql - s_nb[a])];
+        k = (int)(en & 255u);
+        long long i0;
+        chunk_origin(G, xc - wg0, s, i0);
+        i = i0 + (long long)(en >> 8);
+      }
+      int kt;
+      const int ex = block_excl_scan(k, s_tmp, kt);
+      if (write && k > 0) esc += emit_one<T>(G, s, i, k, base + run + (unsigned long long)ex, in_place);
+      run += (unsigned long long)kt;
+    }
+    x = x + kBlock < xend ? x + kBlock : xend;
+    Q += (unsigned long long)nwin;
+    __syncthreads();  // s_nb is rewritten by the next window
+  }
+  return run;
+}
+
+// Emission is balanced by emitters, not by chunks: the push left the number
+// of emitters of each of its workgroups (in chunk order), so every
+// workgroup here scans those counts, takes an equal share of the flattened
+// emitter list, and walks it gap by gap: one pass for the photon count of
+// the share, one slot reservation, one pass that writes.
 template <typename T>
 __device__ void emit_role(GapDev* __restrict__ gaps, const long long* __restrict__ wi, int B,
                           const int32_t* __restrict__ emit_cnt,
-                          const uint32_t* __restrict__ emit_ent, int vb, int nvb,
-                          unsigned long long* s_tmp, unsigned long long* s_base) {
-  const int lane = lane_id();
+                          const uint32_t* __restrict__ emit_ent,
+                          const uint32_t* __restrict__ wg_emit, int vb, int nvb,
+                          uint32_t* s_pre, unsigned long long* s_base, int* s_nb, int* s_tmp) {
+  constexpr int kPer = kPushGrid / kBlock;
   const long long total = wi[B];
-  long long w0, w1;
-  xcd_range(total, w0, w1, vb, nvb);
-  for (long long w = w0; w < w1;) {
-    const int g = find_gap(wi, B, w);
-    const long long wend = wi[g + 1] < w1 ? wi[g + 1] : w1;
+  if (total == 0) return;
+  // exclusive prefix of the push workgroups' emitter counts
+  uint32_t v[kPer];
+  uint32_t loc = 0;
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    v[j] = glb<const uint32_t>((void*)wg_emit)[threadIdx.x * kPer + j];
+    loc += v[j];
+  }
+  // block scan of the per-thread sums (a batch holds fewer than 2^32 lepton slots)
+  const uint32_t incl = wave_incl_scan(loc);
+  __syncthreads();
+  if (lane_id() == 63) s_tmp[threadIdx.x >> 6] = (int)incl;
+  __syncthreads();
+  uint32_t off = 0, E = 0;
+#pragma unroll
+  for (int k = 0; k < kBlock / 64; ++k) {
+    const uint32_t t = (uint32_t)s_tmp[k];
+    if (k < (int)(threadIdx.x >> 6)) off += t;
+    E += t;
+  }
+  off += incl - loc;
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    s_pre[threadIdx.x * kPer + j] = off;
+    off += v[j];
+  }
+  __syncthreads();
+  if (E == 0) return;
+  const unsigned long long share = ((unsigned long long)E + nvb - 1) / nvb;
+  const unsigned long long q0 = (unsigned long long)vb * share;
+  if (q0 >= E) return;
+  const unsigned long long q1 = q0 + share < E ? q0 + share : E;
+  // the push workgroup holding emitter q0: last lb with s_pre[lb] <= q0
+  int a = 0, b = kPushGrid - 1;
+  while (a < b) {
+    const int mid = (a + b + 1) >> 1;
+    if (s_pre[mid] <= q0) a = mid; else b = mid - 1;
+  }
+  const long long per = (total + kPushGrid - 1) / kPushGrid;
+  long long x = (long long)a * per;
+  unsigned long long Q = s_pre[a];
+  gptr<const uint32_t> cntA = glb<const uint32_t>((void*)emit_cnt);
+  gptr<const uint32_t> entA = glb<const uint32_t>((void*)emit_ent);
+  while (x < total && Q < q1) {
+    const int g = find_gap(wi, B, x);
     GapDev* __restrict__ G = gaps + g;
-    if (G->status != PIC_OK) { w = wend; continue; }
-    // pass 1: emissions of this workgroup's chunks of gap g, for one reservation
-    unsigned long long cnt = 0;
-    for (long long x = w; x < wend; ++x) {
-      const int ne = emit_cnt[x];
-      for (int e = threadIdx.x; e < ne; e += kBlock) cnt += emit_ent[x * kChunk + e] & 255u;
-    }
-    const unsigned long long tot = block_sum(cnt, s_tmp);
-    if (tot == 0) { w = wend; continue; }
-    const bool in_place = G->table_len == 0;
-    if (threadIdx.x == 0) {
-      atomicAdd(&G->photons_emitted, tot);
-      if (in_place) {
-        const unsigned long long be = atomicAdd(&G->n_next[0], tot);
-        const unsigned long long bp = atomicAdd(&G->n_next[1], tot);
-        atomicAdd(&G->pairs_created, tot);
-        if (be + tot > (unsigned long long)G->cap || bp + tot > (unsigned long long)G->cap)
-          G->overflow = 1;
-        s_base[0] = be;
-        s_base[1] = bp;
-      } else {
-        const unsigned long long b = atomicAdd(&G->n_ph_next, tot);
-        atomicAdd(&G->inflight, tot);
-        if (b + tot > (unsigned long long)G->ph_cap) G->overflow = 1;
-        s_base[0] = b;
-        s_base[1] = 0;
-      }
-    }
-    __syncthreads();
-    const unsigned long long base0 = s_base[0], base1 = s_base[1];
-    const int buf = G->buf;
-    const uint64_t stepn = (uint64_t)G->step;
-    const uint64_t seed = G->seed;
-    const bool absorbing = G->boundary == PIC_BC_ABSORBING;
-    const bool diag = (G->step % G->diag_every) == 0;
-    const long long ONE = G->one;
-    const T pchild = (T)G->pchild;
-    const T scale = (T)(double)ONE;
-    const unsigned long long cap = (unsigned long long)G->cap;
-    const unsigned long long ph_cap = (unsigned long long)G->ph_cap;
-    const int pb = G->phbuf;
-    unsigned long long run = 0, esc = 0;
-    double ke = 0.0;
-    // pass 2: write the photons (or pairs) at base + running offset
-    for (long long x = w; x < wend; ++x) {
-      const int ne = emit_cnt[x];
-      if (ne == 0) continue;
-      int s;
-      long long i0;
-      chunk_origin(G, x - wi[g], s, i0);
-      for (int r = 0; r < ne; r += kBlock) {
-        const int e = r + threadIdx.x;
-        int k = 0;
-        long long i = 0;
-        if (e < ne) {
-          const uint32_t en = emit_ent[x * kChunk + e];
-          k = (int)(en & 255u);
-          i = i0 + (long long)(en >> 8);
-        }
-        unsigned long long rt;
-        const unsigned long long ex = run + block_excl_scan((unsigned long long)k, s_tmp, rt);
-        run += rt;
-        if (k == 0) continue;
-        const int c = G->cell[buf][s][i];
-        const long long oq = (long long)(((const T*)G->off[buf][s])[i] * scale);
-        const T pv = ((const T*)G->p[buf][s])[i];
-        const uint64_t id = G->id[buf][s][i];
-        const int dir = pv > (T)0 ? 1 : -1;
-        if (in_place) {
-          // pair made in place (the paper's zero mean free path)
-          const T pc = dir > 0 ? pchild : -pchild;
-          const T offn = (T)oq * ((T)1 / scale);
-          for (int jj = 0; jj < k; ++jj) {
-            const U64x4 u = philox4x64_10(stepn, (uint64_t)jj, kTagPhoton, 0, id, seed);
-            const uint64_t child = u.v[1] & ~(uint64_t)1;
-            const unsigned long long se = base0 + ex + jj, sp = base1 + ex + jj;
-            if (se < cap) {
-              G->cell[buf][0][se] = c; ((T*)G->off[buf][0])[se] = offn;
-              ((T*)G->p[buf][0])[se] = pc; G->id[buf][0][se] = child;
-            }
-            if (sp < cap) {
-              G->cell[buf][1][sp] = c; ((T*)G->off[buf][1])[sp] = offn;
-              ((T*)G->p[buf][1])[sp] = pc; G->id[buf][1][sp] = child | 1u;
-            }
-          }
-          if (diag) ke += (double)k * 2.0 * G->weight * G->child_gamma64;
+    const long long xend = wi[g + 1];
+    const long long wg0 = wi[g];
+    // pass 1: photons of the share within this gap
+    long long x1 = x;
+    unsigned long long Q1 = Q;
+    unsigned esc = 0;
+    const unsigned long long tot =
+        emit_walk<T>(G, x1, xend, Q1, q0, q1, wg0, false, 0, esc, cntA, entA, s_nb, s_tmp);
+    if (tot > 0) {
+      if (threadIdx.x == 0) {
+        if (G->table_len == 0) {
+          s_base[0] = reserve_pairs(G, tot);
         } else {
-          const long long X0 = (long long)c * ONE + oq;
-          for (int jj = 0; jj < k; ++jj) {
-            const U64x4 u = philox4x64_10(stepn, (uint64_t)jj, kTagPhoton, 0, id, seed);
-            const uint64_t child = u.v[1] & ~(uint64_t)1;
-            const int ncv = conv_steps(G->table, G->table_len, (uint32_t)(u.v[0] >> 32), G->inv_lnq);
-            long long X = X0 + (long long)dir * (long long)ncv * G->photon_step;
-            int cstep = (int)((long long)stepn + ncv);
-            if (absorbing) {
-              if (X < 0 || X >= G->domain) { cstep = INT32_MIN; ++esc; }
-            } else {
-              X %= G->domain;
-              if (X < 0) X += G->domain;
-            }
-            const unsigned long long slot = base0 + ex + jj;
-            if (slot < ph_cap) {
-              G->ph_x[pb][slot] = X;
-              G->ph_step[pb][slot] = cstep;
-              G->ph_child[pb][slot] = child | (dir > 0 ? 1u : 0u);
-            }
-          }
+          const unsigned long long b0 = atomicAdd(&G->n_ph_next, tot);
+          if (b0 + tot > (unsigned long long)G->ph_cap) G->overflow = 1;
+          s_base[0] = b0;
         }
       }
+      __syncthreads();
+      const unsigned long long base = s_base[0];
+      emit_walk<T>(G, x, xend, Q, q0, q1, wg0, true, base, esc, cntA, entA, s_nb, s_tmp);
+      __syncthreads();  // s_base is reused by the next gap
+      if (G->boundary == PIC_BC_ABSORBING) {
+        const unsigned long long esc_w = wave_sum((unsigned long long)esc);
+        if (lane_id() == 0 && esc_w > 0) atomicAdd(&G->esc_next, esc_w);
+      }
     }
-    const unsigned long long esc_b = block_sum(esc, s_tmp);
-    const double ke_w = wave_sum(ke);
-    if (lane == 0 && ke_w != 0.0) atomicAdd(&G->ke_acc, ke_w);
-    if (threadIdx.x == 0 && esc_b > 0) {
-      atomicAdd(&G->photons_escaped, esc_b);
-      atomicAdd(&G->inflight, (unsigned long long)(-(long long)esc_b));
-      atomicAdd(&G->lost_energy, (double)esc_b * G->weight * G->gpair64);
-    }
-    __syncthreads();  // s_base and s_tmp are reused by the next gap
-    w = wend;
+    x = x1;
+    Q = Q1;
   }
 }
 
@@ -573,8 +676,13 @@ __device__ __forceinline__ void convert_item(const GapDev* G, long long local, l
 
 template <typename T>
 __device__ void convert_role(GapDev* __restrict__ gaps, const long long* __restrict__ pwi, int B,
-                             int vb, int nvb, unsigned long long* s_tmp,
+                             int vb, int nvb, unsigned long long* s_wave,
                              unsigned long long* s_base) {
+  // An item holds kPhChunk = 16 runs of 64 photons; wave v takes runs v, v + 4, v + 8, v + 12.
+  constexpr int kWaves = kBlock / 64;
+  constexpr int kRuns = kPhChunk / 64 / kWaves;
+  const int lane = lane_id();
+  const int v = threadIdx.x >> 6;
   const long long total = pwi[B];
   long long w0, w1;
   xcd_range(total, w0, w1, vb, nvb);
@@ -586,43 +694,47 @@ __device__ void convert_role(GapDev* __restrict__ gaps, const long long* __restr
     const int pb = G->phbuf, buf = G->buf;
     const int stepn = (int)G->step;
     gptr<const int32_t> phs = glb<const int32_t>((void*)G->ph_step[pb]);
-    // pass 1: due photons of this workgroup's items, for one reservation
+    // pass 1: due photons of this wave's runs
     unsigned long long cnt = 0;
     for (long long x = w; x < wend; ++x) {
       long long i0, i1;
       convert_item(G, x - pwi[g], i0, i1);
-      for (long long i = i0 + threadIdx.x; i < i1; i += kBlock) cnt += phs[i] == stepn ? 1u : 0u;
+      int st[kRuns];
+#pragma unroll
+      for (int t = 0; t < kRuns; ++t) {
+        const long long i = i0 + (long long)(v + kWaves * t) * 64 + lane;
+        st[t] = i < i1 ? phs[i] : INT32_MIN;
+      }
+#pragma unroll
+      for (int t = 0; t < kRuns; ++t) cnt += st[t] == stepn ? 1u : 0u;
     }
-    const unsigned long long tot = block_sum(cnt, s_tmp);
-    if (tot == 0) { w = wend; continue; }
-    const bool diag = ((long long)stepn % G->diag_every) == 0;
-    const unsigned long long cap = (unsigned long long)G->cap;
-    if (threadIdx.x == 0) {
-      const unsigned long long be = atomicAdd(&G->n_next[0], tot);
-      const unsigned long long bp = atomicAdd(&G->n_next[1], tot);
-      atomicAdd(&G->pairs_created, tot);
-      atomicAdd(&G->inflight, (unsigned long long)(-(long long)tot));
-      if (be + tot > cap || bp + tot > cap) G->overflow = 1;
-      if (diag) atomicAdd(&G->ke_acc, (double)tot * 2.0 * G->weight * G->child_gamma64);
-      s_base[0] = be;
-      s_base[1] = bp;
-    }
+    cnt = wave_sum(cnt);
+    __syncthreads();  // s_wave and s_base of the previous gap are consumed
+    if (lane == 0) s_wave[v] = cnt;
     __syncthreads();
-    const unsigned long long be = s_base[0], bp = s_base[1];
+    unsigned long long pre;
+    const unsigned long long tot = wave_shares(s_wave, pre);
+    if (tot == 0) { w = wend; continue; }
+    if (threadIdx.x == 0) s_base[0] = reserve_pairs(G, tot);
+    __syncthreads();
+    const unsigned long long base = s_base[0] + pre;
+    const unsigned long long ne0 = G->n[0], ne1 = G->n[1];
+    const unsigned long long cap = (unsigned long long)G->cap;
     const long long ONE = G->one;
     const T inv_scale = (T)(1.0 / (double)ONE);
     const T pchild = (T)G->pchild;
     unsigned long long run = 0;
-    // pass 2: write the pairs at base + running offset
+    // pass 2: the same runs in the same order; ballots give the slots
     for (long long x = w; x < wend; ++x) {
       long long i0, i1;
       convert_item(G, x - pwi[g], i0, i1);
-      for (long long r = i0; r < i1; r += kBlock) {
-        const long long i = r + threadIdx.x;
+#pragma unroll
+      for (int t = 0; t < kRuns; ++t) {
+        const long long i = i0 + (long long)(v + kWaves * t) * 64 + lane;
         const bool due = i < i1 && phs[i] == stepn;
-        unsigned long long rt;
-        const unsigned long long ex = run + block_excl_scan(due ? 1ull : 0ull, s_tmp, rt);
-        run += rt;
+        const unsigned long long m = __ballot(due);
+        const unsigned long long ex = run + (unsigned long long)__popcll(m & lanes_below());
+        run += (unsigned long long)__popcll(m);
         if (!due) continue;
         const long long X = G->ph_x[pb][i];
         const uint64_t ch = G->ph_child[pb][i];
@@ -630,7 +742,7 @@ __device__ void convert_role(GapDev* __restrict__ gaps, const long long* __restr
         const T offn = (T)(X % ONE) * inv_scale;
         const T pc = (ch & 1u) ? pchild : -pchild;
         const uint64_t child = ch & ~(uint64_t)1;
-        const unsigned long long se = be + ex, sp = bp + ex;
+        const unsigned long long se = ne0 + base + ex, sp = ne1 + base + ex;
         if (se < cap) {
           G->cell[buf][0][se] = c; ((T*)G->off[buf][0])[se] = offn;
           ((T*)G->p[buf][0])[se] = pc; G->id[buf][0][se] = child;
@@ -641,51 +753,57 @@ __device__ void convert_role(GapDev* __restrict__ gaps, const long long* __restr
         }
       }
     }
-    __syncthreads();
     w = wend;
   }
 }
 
 // ------------------------------------------------------------ plans
 // Work-item prefixes of the next launches: particle chunks per gap (both
-// species) and due-photon chunks per gap; frozen gaps get none.
+// species), due-photon chunks per gap, and chunks of the whole photon store
+// (for its re-sort); frozen gaps get none.
+__device__ __forceinline__ void gap_items(const GapDev* G, long long& a, long long& b, long long& c) {
+  a = b = c = 0;
+  if (G->status != PIC_OK) return;
+  a = ((long long)G->n[0] + kChunk - 1) / kChunk + ((long long)G->n[1] + kChunk - 1) / kChunk;
+  b = convert_items(G);
+  if (G->table_len > 0) c = ((long long)G->n_ph + kPhChunk - 1) / kPhChunk;
+}
+
 __device__ void compute_plans(GapDev* __restrict__ gaps, int B, long long* __restrict__ wi,
-                              long long* __restrict__ pwi) {
-  __shared__ long long s_a[1024], s_b[1024];
+                              long long* __restrict__ pwi, long long* __restrict__ qwi) {
+  __shared__ long long s_a[1024], s_b[1024], s_c[1024];
   const int tid = threadIdx.x, nt = blockDim.x;
   const int per = (B + nt - 1) / nt;
-  long long sa = 0, sb = 0;
+  long long sa = 0, sb = 0, sc = 0;
   for (int g = tid * per; g < (tid + 1) * per && g < B; ++g) {
-    const GapDev* G = gaps + g;
-    if (G->status == PIC_OK) {
-      sa += ((long long)G->n[0] + kChunk - 1) / kChunk + ((long long)G->n[1] + kChunk - 1) / kChunk;
-      sb += convert_items(G);
-    }
+    long long a, b, c;
+    gap_items(gaps + g, a, b, c);
+    sa += a; sb += b; sc += c;
   }
-  s_a[tid] = sa; s_b[tid] = sb;
+  s_a[tid] = sa; s_b[tid] = sb; s_c[tid] = sc;
   __syncthreads();
   for (int d = 1; d < nt; d <<= 1) {
-    long long ya = tid >= d ? s_a[tid - d] : 0, yb = tid >= d ? s_b[tid - d] : 0;
+    const long long ya = tid >= d ? s_a[tid - d] : 0, yb = tid >= d ? s_b[tid - d] : 0;
+    const long long yc = tid >= d ? s_c[tid - d] : 0;
     __syncthreads();
-    s_a[tid] += ya; s_b[tid] += yb;
+    s_a[tid] += ya; s_b[tid] += yb; s_c[tid] += yc;
     __syncthreads();
   }
-  long long ra = s_a[tid] - sa, rb = s_b[tid] - sb;
+  long long ra = s_a[tid] - sa, rb = s_b[tid] - sb, rc = s_c[tid] - sc;
   for (int g = tid * per; g < (tid + 1) * per && g < B; ++g) {
-    const GapDev* G = gaps + g;
-    wi[g] = ra; pwi[g] = rb;
-    if (G->status == PIC_OK) {
-      ra += ((long long)G->n[0] + kChunk - 1) / kChunk + ((long long)G->n[1] + kChunk - 1) / kChunk;
-      rb += convert_items(G);
-    }
+    wi[g] = ra; pwi[g] = rb; qwi[g] = rc;
+    long long a, b, c;
+    gap_items(gaps + g, a, b, c);
+    ra += a; rb += b; rc += c;
   }
-  if (tid == nt - 1) { wi[B] = s_a[nt - 1]; pwi[B] = s_b[nt - 1]; }
+  if (tid == nt - 1) { wi[B] = s_a[nt - 1]; pwi[B] = s_b[nt - 1]; qwi[B] = s_c[nt - 1]; }
 }
 
 __global__ __launch_bounds__(1024) void k_plan(GapDev* __restrict__ gaps, int B,
                                                long long* __restrict__ wi,
-                                               long long* __restrict__ pwi) {
-  compute_plans(gaps, B, wi, pwi);
+                                               long long* __restrict__ pwi,
+                                               long long* __restrict__ qwi) {
+  compute_plans(gaps, B, wi, pwi, qwi);
 }
 
 // Ends a step for every gap: freeze on error, roll the counters, write the
@@ -693,7 +811,8 @@ __global__ __launch_bounds__(1024) void k_plan(GapDev* __restrict__ gaps, int B,
 constexpr int kFoldMax = 1024;  // gaps whose stripes finalize folds with the whole block
 
 __device__ void finalize_body(GapDev* __restrict__ gaps, int B, long long* __restrict__ wi,
-                              long long* __restrict__ pwi, double* __restrict__ stripes) {
+                              long long* __restrict__ pwi, long long* __restrict__ qwi,
+                              double* __restrict__ stripes) {
   __shared__ unsigned long long s_fold[kFoldMax * 4];
   // fold the striped push tallies: 32 lanes sum the stripes of one
   // (gap, accumulator) pair; accumulators 2 and 3 hold integer counts
@@ -754,13 +873,26 @@ __device__ void finalize_body(GapDev* __restrict__ gaps, int B, long long* __res
       if (st != PIC_OK) {
         G->status = st;
       } else {
+        // what this step appended: dp pairs (in place or converted), dph
+        // photons stored, de of which left the domain
+        const unsigned long long dp = G->pair_next, dph = G->n_ph_next - G->n_ph;
+        const unsigned long long de = G->esc_next;
+        const bool in_place = G->table_len == 0;
+        const long long done = G->step;
+        G->pairs_created += dp;
+        G->photons_emitted += in_place ? dp : dph;
+        G->photons_escaped += de;
+        if (!in_place) G->inflight = G->inflight + dph - de - dp;
+        if (de) G->lost_energy += (double)de * G->weight * G->gpair64;
+        if (done % G->diag_every == 0 && dp) G->ke_acc += (double)dp * 2.0 * G->weight * G->child_gamma64;
         G->pushes = G->pushes + G->live[0] + G->live[1];
         for (int s = 0; s < 2; ++s) {
-          G->n[s] = G->n_next[s];
+          G->n[s] += dp;
           G->live[s] = G->n[s] - G->dead[s];
         }
+        G->pair_next = 0;
+        G->esc_next = 0;
         G->n_ph = G->n_ph_next;
-        const long long done = G->step;
         G->step = done + 1;
         if (done % G->diag_every == 0) {
           pic_history_row r;
@@ -789,7 +921,7 @@ __device__ void finalize_body(GapDev* __restrict__ gaps, int B, long long* __res
     G->es_acc = 0.0;
   }
   __syncthreads();
-  compute_plans(gaps, B, wi, pwi);
+  compute_plans(gaps, B, wi, pwi, qwi);
 }
 
 // Everything of a step between the push and the finalize: the Ampere update
@@ -802,22 +934,28 @@ __global__ __launch_bounds__(kBlock) void k_post(GapDev* __restrict__ gaps,
                                                  const long long* __restrict__ pwi, int B,
                                                  int n_field, int n_emit, int n_conv,
                                                  const int32_t* __restrict__ emit_cnt,
-                                                 const uint32_t* __restrict__ emit_ent) {
+                                                 const uint32_t* __restrict__ emit_ent,
+                                                 const uint32_t* __restrict__ wg_emit) {
   __shared__ double s_red[8];
-  __shared__ unsigned long long s_tmp[kBlock / 64];
-  __shared__ unsigned long long s_base[2];
+  __shared__ unsigned long long s_wave[kBlock / 64];
+  __shared__ unsigned long long s_base[1];
+  __shared__ int s_nb[kBlock];
+  __shared__ int s_tmp[kBlock / 64];
+  __shared__ uint32_t s_pre[kPushGrid];
   const int b = blockIdx.x;
   if (b < n_field) field_role(gaps, cwi, B, b, s_red);
   else if (b < n_field + n_emit)
-    emit_role<T>(gaps, wi, B, emit_cnt, emit_ent, b - n_field, n_emit, s_tmp, s_base);
-  else convert_role<T>(gaps, pwi, B, b - n_field - n_emit, n_conv, s_tmp, s_base);
+    emit_role<T>(gaps, wi, B, emit_cnt, emit_ent, wg_emit, b - n_field, n_emit, s_pre, s_base, s_nb,
+                 s_tmp);
+  else convert_role<T>(gaps, pwi, B, b - n_field - n_emit, n_conv, s_wave, s_base);
 }
 
 __global__ __launch_bounds__(1024) void k_finalize(GapDev* __restrict__ gaps, int B,
                                                    long long* __restrict__ wi,
                                                    long long* __restrict__ pwi,
+                                                   long long* __restrict__ qwi,
                                                    double* __restrict__ stripes) {
-  finalize_body(gaps, B, wi, pwi, stripes);
+  finalize_body(gaps, B, wi, pwi, qwi, stripes);
 }
 
 // ------------------------------------------------------------------ sort
@@ -849,10 +987,17 @@ __global__ __launch_bounds__(kBlock) void k_sort_zero(GapDev* __restrict__ gaps,
   if (blockIdx.x == cwi[g] && threadIdx.x == 0) { G->sorted_n[0] = 0; G->sorted_n[1] = 0; }
 }
 
+// Counting sort of the leptons by cell.  PASS 0 counts, PASS 1 (after the
+// scan turned the counts into bucket starts) moves each live lepton to the
+// other buffer.  A chunk whose cells span at most kSortTile counts in an LDS
+// histogram first and touches each global bucket once; wider chunks (leptons
+// appended since the last sort) use one global atomic per run of equal cells.
 template <int PASS>
 __global__ __launch_bounds__(kBlock) void k_sort_pass(GapDev* __restrict__ gaps,
                                                       const long long* __restrict__ wi, int B,
                                                       int elem_bytes) {
+  __shared__ int32_t s_hist[kSortTile];
+  __shared__ int s_red[8];
   const long long total = wi[B];
   long long w0, w1;
   xcd_range(total, w0, w1);
@@ -869,38 +1014,57 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(GapDev* __restrict__ gaps,
     const long long nS = (long long)G->n[s];
     const long long i1 = i0 + kChunk < nS ? i0 + kChunk : nS;
     gptr<int32_t> cnt = glb(G->sort_cnt[s]);
-    const int nb = buf ^ 1;
     gptr<const int32_t> cin = glb<const int32_t>((void*)G->cell[buf][s]);
     int cvs[kItems];
+    int mn = INT32_MAX, mx = INT32_MIN;
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
       const long long i = i0 + threadIdx.x + (long long)j * kBlock;
       cvs[j] = i < i1 ? cin[i] : kDead;
+      if (cvs[j] != kDead) { mn = min(mn, cvs[j]); mx = max(mx, cvs[j]); }
     }
-    if (PASS == 0) {
+    block_minmax(mn, mx, s_red);
+    if (mx < mn) continue;  // no live lepton in this chunk (uniform)
+    long long dst[kItems];
+    if (mx - mn < kSortTile) {
+      const int span = mx - mn + 1;
+      for (int k = threadIdx.x; k < span; k += kBlock) s_hist[k] = 0;
+      __syncthreads();
+      int rank[kItems];
+#pragma unroll
+      for (int j = 0; j < kItems; ++j)
+        rank[j] = cvs[j] != kDead ? atomicAdd(&s_hist[cvs[j] - mn], 1) : 0;
+      __syncthreads();
+      for (int k = threadIdx.x; k < span; k += kBlock) {
+        const int c = s_hist[k];
+        if (c == 0) continue;
+        if (PASS == 0)
+          __hip_atomic_fetch_add(cnt + mn + k, c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        else
+          s_hist[k] = __hip_atomic_fetch_add(cnt + mn + k, c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      if (PASS == 0) continue;  // the next chunk's block_minmax orders the LDS reuse
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < kItems; ++j)
+        dst[j] = cvs[j] != kDead ? (long long)s_hist[cvs[j] - mn] + rank[j] : 0;
+    } else {
 #pragma unroll
       for (int j = 0; j < kItems; ++j) {
         const int cv = cvs[j];
         int head_lane, run_len;
         wave_runs(cv, head_lane, run_len);
+        int b = 0;
         if (run_len > 0 && cv != kDead)
-          __hip_atomic_fetch_add(cnt + cv, run_len, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          b = __hip_atomic_fetch_add(cnt + cv, run_len, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (PASS == 1) {
+          b = __shfl(b, head_lane, 64);
+          dst[j] = (long long)b + (lane - head_lane);
+        }
       }
-      continue;
+      if (PASS == 0) continue;
     }
-    // destinations of all items first (one returning atomic per run), then the moves
-    long long dst[kItems];
-#pragma unroll
-    for (int j = 0; j < kItems; ++j) {
-      const int cv = cvs[j];
-      int head_lane, run_len;
-      wave_runs(cv, head_lane, run_len);
-      int b = 0;
-      if (run_len > 0 && cv != kDead)
-        b = __hip_atomic_fetch_add(cnt + cv, run_len, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      b = __shfl(b, head_lane, 64);
-      dst[j] = (long long)b + (lane - head_lane);
-    }
+    const int nb = buf ^ 1;
     gptr<int32_t> cout = glb(G->cell[nb][s]);
     gptr<const uint64_t> iin = glb<const uint64_t>((void*)G->id[buf][s]);
     gptr<uint64_t> iout = glb(G->id[nb][s]);
@@ -964,36 +1128,79 @@ __global__ __launch_bounds__(kBlock) void k_ph_zero(GapDev* __restrict__ gaps, i
   if (threadIdx.x == 0) G->ph_sorted = 0;
 }
 
+// Counting sort of the photon store by conversion step (key = step - now),
+// dropping photons that converted or escaped (key < 0).  A workgroup takes a
+// contiguous range of one gap's store; with at most kPhBins keys it counts in
+// an LDS histogram and touches each global bucket once per range, otherwise
+// it uses one global atomic per run of equal keys.
 template <int PASS>
-__global__ __launch_bounds__(kBlock) void k_ph_pass(GapDev* __restrict__ gaps, int B) {
+__global__ __launch_bounds__(kBlock) void k_ph_pass(GapDev* __restrict__ gaps,
+                                                    const long long* __restrict__ qwi, int B) {
+  __shared__ int32_t s_hist[kPhBins];
   const int lane = lane_id();
-  for (int g = 0; g < B; ++g) {
+  const long long total = qwi[B];
+  long long w0, w1;
+  xcd_range(total, w0, w1);
+  for (long long w = w0; w < w1;) {
+    const int g = find_gap(qwi, B, w);
+    const long long wend = qwi[g + 1] < w1 ? qwi[g + 1] : w1;
     GapDev* __restrict__ G = gaps + g;
-    if (G->status != PIC_OK || G->table_len == 0) continue;
     const long long nP = (long long)G->n_ph;
-    if (nP == 0) continue;
-    long long i0, i1;
-    xcd_range(nP, i0, i1);
+    const long long p0 = (w - qwi[g]) * kPhChunk;
+    const long long p1 = (wend - qwi[g]) * kPhChunk < nP ? (wend - qwi[g]) * kPhChunk : nP;
+    w = wend;
+    if (G->status != PIC_OK || G->table_len == 0) continue;
     const int pb = G->phbuf;
     const long long stepn = G->step;
-    int32_t* __restrict__ bucket = G->ph_bucket;
-    for (long long r = i0; r < i1; r += kBlock) {
-      const long long i = r + threadIdx.x;
-      const long long cs = i < i1 ? (long long)G->ph_step[pb][i] : (long long)INT32_MIN;
-      const int key = cs >= stepn ? (int)(cs - stepn) : -1;
-      int head_lane, run_len;
-      wave_runs(key, head_lane, run_len);
-      if (PASS == 0) {
-        if (run_len > 0 && key >= 0) atomicAdd(&bucket[key], run_len);
-      } else {
-        int b = 0;
-        if (run_len > 0 && key >= 0) b = atomicAdd(&bucket[key], run_len);
-        b = __shfl(b, head_lane, 64);
-        if (key >= 0) {
-          const long long dst = (long long)b + (lane - head_lane);
+    const int L = G->table_len;
+    gptr<int32_t> bucket = glb(G->ph_bucket);
+    gptr<const int32_t> sin = glb<const int32_t>((void*)G->ph_step[pb]);
+    if (L <= kPhBins) {
+      for (int k = threadIdx.x; k < L; k += kBlock) s_hist[k] = 0;
+      __syncthreads();
+      for (long long i = p0 + threadIdx.x; i < p1; i += kBlock) {
+        const long long cs = sin[i];
+        if (cs >= stepn) atomicAdd(&s_hist[cs - stepn], 1);
+      }
+      __syncthreads();
+      for (int k = threadIdx.x; k < L; k += kBlock) {
+        const int c = s_hist[k];
+        if (c == 0) continue;
+        if (PASS == 0)
+          __hip_atomic_fetch_add(bucket + k, c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        else
+          s_hist[k] = __hip_atomic_fetch_add(bucket + k, c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      if (PASS == 1) {
+        __syncthreads();
+        for (long long i = p0 + threadIdx.x; i < p1; i += kBlock) {
+          const long long cs = sin[i];
+          if (cs < stepn) continue;
+          const long long dst = atomicAdd(&s_hist[cs - stepn], 1);
           G->ph_x[pb ^ 1][dst] = G->ph_x[pb][i];
           G->ph_step[pb ^ 1][dst] = (int32_t)cs;
           G->ph_child[pb ^ 1][dst] = G->ph_child[pb][i];
+        }
+      }
+      __syncthreads();  // s_hist is zeroed for the next range
+    } else {
+      for (long long r = p0; r < p1; r += kBlock) {
+        const long long i = r + threadIdx.x;
+        const long long cs = i < p1 ? (long long)sin[i] : (long long)INT32_MIN;
+        const int key = cs >= stepn ? (int)(cs - stepn) : -1;
+        int head_lane, run_len;
+        wave_runs(key, head_lane, run_len);
+        int b = 0;
+        if (run_len > 0 && key >= 0)
+          b = __hip_atomic_fetch_add(bucket + key, run_len, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (PASS == 1) {
+          b = __shfl(b, head_lane, 64);
+          if (key >= 0) {
+            const long long dst = (long long)b + (lane - head_lane);
+            G->ph_x[pb ^ 1][dst] = G->ph_x[pb][i];
+            G->ph_step[pb ^ 1][dst] = (int32_t)cs;
+            G->ph_child[pb ^ 1][dst] = G->ph_child[pb][i];
+          }
         }
       }
     }
@@ -1010,13 +1217,13 @@ __global__ __launch_bounds__(1024) void k_ph_scan(GapDev* __restrict__ gaps, int
 
 __global__ __launch_bounds__(1024) void k_sort_finish(GapDev* __restrict__ gaps, int B,
                                                       long long* __restrict__ wi,
-                                                      long long* __restrict__ pwi) {
+                                                      long long* __restrict__ pwi,
+                                                      long long* __restrict__ qwi) {
   for (int g = threadIdx.x; g < B; g += blockDim.x) {
     GapDev* G = gaps + g;
     if (G->status != PIC_OK) continue;
     for (int s = 0; s < 2; ++s) {
       G->n[s] = G->sorted_n[s];
-      G->n_next[s] = G->sorted_n[s];
       G->live[s] = G->sorted_n[s];
       G->dead[s] = 0;
     }
@@ -1030,7 +1237,7 @@ __global__ __launch_bounds__(1024) void k_sort_finish(GapDev* __restrict__ gaps,
     }
   }
   __syncthreads();
-  compute_plans(gaps, B, wi, pwi);
+  compute_plans(gaps, B, wi, pwi, qwi);
 }
 
 // ------------------------------------------------------------------ seed
@@ -1098,11 +1305,11 @@ static int grid_for(long long want, int cap) {
 
 hipError_t launch_push(const StepLaunch& L, bool mixed) {
   if (mixed)
-    hipLaunchKernelGGL(k_push<float>, dim3(L.push_grid), dim3(kBlock), 0, L.stream, L.gaps, L.wi, L.B,
-                       L.emit_cnt, L.emit_ent, L.stripes);
+    hipLaunchKernelGGL(k_push<float>, dim3(kPushGrid), dim3(kBlock), 0, L.stream, L.gaps, L.wi, L.B,
+                       L.emit_cnt, L.emit_ent, L.wg_emit, L.stripes);
   else
-    hipLaunchKernelGGL(k_push<double>, dim3(L.push_grid), dim3(kBlock), 0, L.stream, L.gaps, L.wi, L.B,
-                       L.emit_cnt, L.emit_ent, L.stripes);
+    hipLaunchKernelGGL(k_push<double>, dim3(kPushGrid), dim3(kBlock), 0, L.stream, L.gaps, L.wi, L.B,
+                       L.emit_cnt, L.emit_ent, L.wg_emit, L.stripes);
   return hipGetLastError();
 }
 
@@ -1111,11 +1318,12 @@ hipError_t launch_step_after_push(const StepLaunch& L, bool mixed) {
   const int grid = nf + L.emit_grid + L.conv_grid;
   if (mixed)
     hipLaunchKernelGGL(k_post<float>, dim3(grid), dim3(kBlock), 0, L.stream, L.gaps, L.cwi, L.wi,
-                       L.pwi, L.B, nf, L.emit_grid, L.conv_grid, L.emit_cnt, L.emit_ent);
+                       L.pwi, L.B, nf, L.emit_grid, L.conv_grid, L.emit_cnt, L.emit_ent, L.wg_emit);
   else
     hipLaunchKernelGGL(k_post<double>, dim3(grid), dim3(kBlock), 0, L.stream, L.gaps, L.cwi, L.wi,
-                       L.pwi, L.B, nf, L.emit_grid, L.conv_grid, L.emit_cnt, L.emit_ent);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, L.stream, L.gaps, L.B, L.wi, L.pwi, L.stripes);
+                       L.pwi, L.B, nf, L.emit_grid, L.conv_grid, L.emit_cnt, L.emit_ent, L.wg_emit);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, L.stream, L.gaps, L.B, L.wi, L.pwi, L.qwi,
+                     L.stripes);
   return hipGetLastError();
 }
 
@@ -1130,17 +1338,17 @@ hipError_t launch_sort(const StepLaunch& L, bool mixed) {
   hipLaunchKernelGGL(k_sort_zero, dim3(grid_for(L.cell_items, 1 << 30)), dim3(kBlock), 0, L.stream, L.gaps, L.cwi, L.B);
   hipLaunchKernelGGL(k_ph_zero, dim3(L.B), dim3(kBlock), 0, L.stream, L.gaps, L.B);
   hipLaunchKernelGGL(k_sort_pass<0>, dim3(L.push_grid), dim3(kBlock), 0, L.stream, L.gaps, L.wi, L.B, eb);
-  hipLaunchKernelGGL(k_ph_pass<0>, dim3(L.conv_grid), dim3(kBlock), 0, L.stream, L.gaps, L.B);
+  hipLaunchKernelGGL(k_ph_pass<0>, dim3(L.ph_sort_grid), dim3(kBlock), 0, L.stream, L.gaps, L.qwi, L.B);
   hipLaunchKernelGGL(k_sort_scan, dim3(2 * L.B), dim3(1024), 0, L.stream, L.gaps, L.B);
   hipLaunchKernelGGL(k_ph_scan, dim3(L.B), dim3(1024), 0, L.stream, L.gaps, L.B);
   hipLaunchKernelGGL(k_sort_pass<1>, dim3(L.push_grid), dim3(kBlock), 0, L.stream, L.gaps, L.wi, L.B, eb);
-  hipLaunchKernelGGL(k_ph_pass<1>, dim3(L.conv_grid), dim3(kBlock), 0, L.stream, L.gaps, L.B);
-  hipLaunchKernelGGL(k_sort_finish, dim3(1), dim3(1024), 0, L.stream, L.gaps, L.B, L.wi, L.pwi);
+  hipLaunchKernelGGL(k_ph_pass<1>, dim3(L.ph_sort_grid), dim3(kBlock), 0, L.stream, L.gaps, L.qwi, L.B);
+  hipLaunchKernelGGL(k_sort_finish, dim3(1), dim3(1024), 0, L.stream, L.gaps, L.B, L.wi, L.pwi, L.qwi);
   return hipGetLastError();
 }
 
 hipError_t launch_plan(const StepLaunch& L) {
-  hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, L.stream, L.gaps, L.B, L.wi, L.pwi);
+  hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, L.stream, L.gaps, L.B, L.wi, L.pwi, L.qwi);
   return hipGetLastError();
 }
 

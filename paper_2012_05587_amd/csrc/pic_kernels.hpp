@@ -10,13 +10,15 @@ namespace pic {
 struct StepLaunch {
   GapDev* gaps;        // device array of B descriptors
   long long* wi;       // particle work-item prefix, B + 1 entries (device)
-  long long* pwi;      // photon work-item prefix, B + 1 entries (device)
+  long long* pwi;      // due-photon work-item prefix, B + 1 entries (device)
+  long long* qwi;      // photon-store work-item prefix (re-sort), B + 1 entries (device)
   long long* cwi;      // cell work-item prefix, B + 1 entries (device, static)
   long long cell_items;
   int B;
-  int push_grid, conv_grid, emit_grid;
+  int push_grid, conv_grid, emit_grid, ph_sort_grid;
   int32_t* emit_cnt;   // emitters per chunk of the current plan (device)
   uint32_t* emit_ent;  // kChunk entries per chunk (device)
+  uint32_t* wg_emit;   // emitters listed by each push workgroup, kPushGrid entries (device)
   double* stripes;     // striped push tallies, B x 4 x kStripes x kStripeStride (device)
   hipStream_t stream;
 };

@@ -38,11 +38,16 @@ struct GapLayout {
 };
 
 struct Layout {
-  size_t gaps, wi, pwi, cwi, emit_cnt, emit_ent, stripes, total;
-  long long max_chunks;
+  size_t gaps, wi, pwi, qwi, cwi, emit_cnt, emit_ent, wg_emit, stripes, total;
+  long long max_chunks, max_ph_chunks;
   std::vector<GapLayout> g;
   long long cell_items;
 };
+
+int grid_for_items(long long want) {
+  const long long g = want < 64 ? 64 : (want > 2048 ? 2048 : want);
+  return (int)((g + 7) / 8 * 8);
+}
 
 int offset_bits(int precision) { return precision == PIC_MIXED ? 24 : 40; }
 
@@ -90,19 +95,33 @@ pic_status validate(const pic_gap_params* p) {
   return PIC_OK;
 }
 
+// Lepton slots of a batch, both species; the per-step emitter prefix is
+// 32-bit, so a batch holds fewer than 2^32.
+bool batch_slots_ok(const pic_gap_params* prm, int B) {
+  unsigned long long slots = 0;
+  for (int i = 0; i < B; ++i) slots += 2ull * (unsigned long long)prm[i].capacity;
+  return slots < (1ull << 32);
+}
+
 Layout make_layout(const pic_gap_params* prm, int B) {
   Layout L;
   size_t o = 0;
   L.gaps = o; o = align_up(o + sizeof(GapDev) * (size_t)B);
   L.wi = o; o = align_up(o + sizeof(long long) * (size_t)(B + 1));
   L.pwi = o; o = align_up(o + sizeof(long long) * (size_t)(B + 1));
+  L.qwi = o; o = align_up(o + sizeof(long long) * (size_t)(B + 1));
   L.cwi = o; o = align_up(o + sizeof(long long) * (size_t)(B + 1));
   L.cell_items = 0;
   // one emission slice per particle chunk the plan can hold
   L.max_chunks = 0;
-  for (int i = 0; i < B; ++i) L.max_chunks += 2 * ((prm[i].capacity + pic::kChunk - 1) / pic::kChunk);
+  L.max_ph_chunks = 0;
+  for (int i = 0; i < B; ++i) {
+    L.max_chunks += 2 * ((prm[i].capacity + pic::kChunk - 1) / pic::kChunk);
+    L.max_ph_chunks += (prm[i].photon_capacity + pic::kPhChunk - 1) / pic::kPhChunk;
+  }
   L.emit_cnt = o; o = align_up(o + sizeof(int32_t) * (size_t)L.max_chunks);
   L.emit_ent = o; o = align_up(o + sizeof(uint32_t) * (size_t)L.max_chunks * pic::kChunk);
+  L.wg_emit = o; o = align_up(o + sizeof(uint32_t) * (size_t)pic::kPushGrid);
   L.stripes = o; o = align_up(o + sizeof(double) * (size_t)B * 4 * pic::kStripes * pic::kStripeStride);
   const int prec = prm[0].precision;
   const size_t tb = prec == PIC_MIXED ? 4 : 8;
@@ -220,6 +239,7 @@ pic_status create_batch(const pic_gap_params* params, int n_gaps, void* d_ws, si
         params[i].diag_every != params[0].diag_every || params[i].history_rows != params[0].history_rows)
       return PIC_ERR_ARG;
   }
+  if (!batch_slots_ok(params, n_gaps)) return PIC_ERR_ARG;
   Layout L = make_layout(params, n_gaps);
   if (!d_ws || ws_bytes < L.total || (reinterpret_cast<uintptr_t>(d_ws) % kAlign) != 0)
     return PIC_ERR_WORKSPACE;
@@ -310,14 +330,20 @@ pic_status create_batch(const pic_gap_params* params, int n_gaps, void* d_ws, si
   b->launch.gaps = dgaps(b);
   b->launch.wi = reinterpret_cast<long long*>(ws + L.wi);
   b->launch.pwi = reinterpret_cast<long long*>(ws + L.pwi);
+  b->launch.qwi = reinterpret_cast<long long*>(ws + L.qwi);
   b->launch.cwi = reinterpret_cast<long long*>(ws + L.cwi);
   b->launch.cell_items = L.cell_items;
   b->launch.B = n_gaps;
-  b->launch.push_grid = 4096;
-  b->launch.conv_grid = 128;
-  b->launch.emit_grid = 128;
+  // Emission, conversion and the photon re-sort get grids sized to what the
+  // batch can hold (about 16 chunks per workgroup when full), in whole
+  // multiples of the 8 XCDs.
+  b->launch.push_grid = pic::kPushGrid;
+  b->launch.emit_grid = grid_for_items(L.max_chunks / 16);
+  b->launch.conv_grid = grid_for_items(L.max_ph_chunks / 16);
+  b->launch.ph_sort_grid = grid_for_items(L.max_ph_chunks / 16);
   b->launch.emit_cnt = reinterpret_cast<int32_t*>(ws + L.emit_cnt);
   b->launch.emit_ent = reinterpret_cast<uint32_t*>(ws + L.emit_ent);
+  b->launch.wg_emit = reinterpret_cast<uint32_t*>(ws + L.wg_emit);
   b->launch.stripes = reinterpret_cast<double*>(ws + L.stripes);
   b->launch.stream = b->stream;
   if (st == PIC_OK &&
@@ -341,8 +367,8 @@ pic_status append_counts(pic_batch* b, int g, long long add0, long long add1) {
   GapDev G;
   pic_status st = read_desc(b, g, &G);
   if (st != PIC_OK) return st;
-  G.n[0] += (unsigned long long)add0; G.n_next[0] = G.n[0]; G.live[0] += (unsigned long long)add0;
-  G.n[1] += (unsigned long long)add1; G.n_next[1] = G.n[1]; G.live[1] += (unsigned long long)add1;
+  G.n[0] += (unsigned long long)add0; G.live[0] += (unsigned long long)add0;
+  G.n[1] += (unsigned long long)add1; G.live[1] += (unsigned long long)add1;
   st = write_desc(b, g, &G);
   if (st != PIC_OK) return st;
   if (pic::launch_plan(b->launch) != hipSuccess) return PIC_ERR_DEVICE;
@@ -458,6 +484,7 @@ size_t pic_batch_workspace_bytes(const pic_gap_params* params, int32_t n_gaps) {
   if (!params || n_gaps < 1) return 0;
   for (int i = 0; i < n_gaps; ++i)
     if (validate(&params[i]) != PIC_OK) return 0;
+  if (!batch_slots_ok(params, n_gaps)) return 0;
   return make_layout(params, n_gaps).total;
 }
 
@@ -470,6 +497,10 @@ int32_t pic_batch_plan(const pic_gap_params* params, int32_t n_gaps, size_t budg
     admitted[i] = 0;
     if (validate(&params[i]) != PIC_OK) continue;
     acc.push_back(params[i]);
+    if (!batch_slots_ok(acc.data(), (int)acc.size())) {
+      acc.pop_back();
+      continue;
+    }
     const size_t need = make_layout(acc.data(), (int)acc.size()).total;
     if (need <= budget_bytes) {
       admitted[i] = 1;

@@ -94,6 +94,17 @@ def test_batch_plan_admits_under_budget():
     assert 0 < adm.sum() < 32 and ws <= full // 3
 
 
+def test_batch_slot_limit():
+    """A batch holds fewer than 2^32 lepton slots (both species)."""
+    import paper_2012_05587_amd as P
+    big = pc.gpu_params(_valid(), capacity=(1 << 31) - 1, photon_capacity=1)
+    two = (P.GapParams * 2)(big, big)
+    assert P.lib().pic_batch_workspace_bytes(two, 2) == 0
+    assert P.lib().pic_batch_workspace_bytes((P.GapParams * 1)(big), 1) > 0
+    adm, _ = P.batch_plan([big, big], 1 << 62)
+    assert list(adm) == [1, 0]
+
+
 def test_create_rejects_bad_workspace_without_device():
     import paper_2012_05587_amd as P
     prm = pc.gpu_params(_valid())
