@@ -188,6 +188,154 @@ def run_cpu_baseline(gaps, steps, procs):
     return dict(value=pushes / (t1 - t0), seconds=t1 - t0, pushes=pushes)
 
 
+# ----------------------------------------------------------- profiles
+PROFILE_DIR = os.path.join(ROOT, "profiles")
+KERNEL_SOURCES = ("paper_2012_05587_amd/csrc/pic_kernels.hip",
+                  "paper_2012_05587_amd/csrc/pic_device.hpp",
+                  "paper_2012_05587_amd/csrc/pic_kernels.hpp")
+
+
+def kernel_source_hash():
+    """sha256 over the kernel sources: a stored counter figure is only used
+    while the kernels it was taken from are unchanged."""
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def _profile_name(workload, precision):
+    return f"k_push_{workload}_{'mixed' if precision == workloads.MIXED else 'fp64'}"
+
+
+def stored_traffic(workload, precision, steps):
+    """HBM bytes per push launch from the committed counter summary of this
+    workload, or None when it is missing or stale."""
+    path = os.path.join(PROFILE_DIR, _profile_name(workload, precision) + ".json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        prof = json.load(f)
+    if (prof.get("source_sha256") != kernel_source_hash() or prof.get("workload") != workload
+            or prof.get("steps") != steps or not prof.get("pmc", {}).get("traffic_bytes_per_launch")):
+        return None
+    return prof["pmc"]
+
+
+def _db_rows(db, sql, args=()):
+    import sqlite3
+    con = sqlite3.connect(db)
+    try:
+        return con.execute(sql, args).fetchall()
+    finally:
+        con.close()
+
+
+def _pmc_per_dispatch(db, counter, match):
+    """Per-dispatch counter values (summed over instances) of kernels whose
+    name contains `match`, in dispatch order."""
+    rows = _db_rows(db, "select dispatch_id, kernel_name, value from counters_collection "
+                        "where counter_name = ? order by dispatch_id", (counter,))
+    acc = {}
+    for d, name, v in rows:
+        if match in name:
+            acc[d] = acc.get(d, 0.0) + float(v)
+    return [acc[d] for d in sorted(acc)]
+
+
+def summarize(args):
+    """Writes profiles/<kernel>_<workload>.{md,json} from rocprofv3 output of
+    the bench command (kernel trace, FETCH_SIZE and WRITE_SIZE passes) and of
+    the copy probe (the same two counters over a 1 GiB device copy)."""
+    import numpy as np
+    with open(args.bench_json) as f:
+        bench = json.loads(f.read().strip().splitlines()[-1])
+    workload = bench["config"]["workload"]
+    prec = workloads.MIXED if bench["dtype"] != "f64" else workloads.FP64
+    kname = "k_push<float>" if prec == workloads.MIXED else "k_push<double>"
+    n = 2 * bench["steps"]  # the timed graph run and the evented run of the same steps
+    rows = _db_rows(args.trace_db, "select name, start, end from kernels order by start")
+    per = {}
+    for name, t0, t1 in rows:
+        per.setdefault(name.split("(")[0], []).append((t1 - t0) / 1e3)
+    push = [d for name, d in ((r[0], (r[2] - r[1]) / 1e3) for r in rows) if kname in name][-n:]
+    total = sum(sum(v) for v in per.values())
+    table = sorted(((k, len(v), float(np.mean(v)), sum(v) / 1e3, 100 * sum(v) / total)
+                    for k, v in per.items()), key=lambda r: -r[3])
+    ev_avg_us = bench["roofline"]["kernel_ms"] * 1e3 / bench["roofline"]["launches"]
+    alg = bench["roofline"]["bytes_per_push"] * bench["config"]["pushes"] / bench["steps"]
+
+    def copy_factor(db, counter):
+        v = _pmc_per_dispatch(db, counter, "copyBuffer")
+        big = [x for x in v if x > 0.25 * (1 << 20)]  # KiB: the 1 GiB copies
+        return (1 << 20) / float(np.mean(big)), len(big)
+
+    # the counter passes run the graph-replayed steps only (--timed-only);
+    # a pass that did not complete leaves its half of the traffic unknown
+    ff, nf = copy_factor(args.copy_fetch_db, "FETCH_SIZE") if args.copy_fetch_db else (None, 0)
+    wf, nw = copy_factor(args.copy_write_db, "WRITE_SIZE") if args.copy_write_db else (None, 0)
+    fetch = _pmc_per_dispatch(args.fetch_db, "FETCH_SIZE", kname)[-bench["steps"]:] if args.fetch_db else []
+    write = _pmc_per_dispatch(args.write_db, "WRITE_SIZE", kname)[-bench["steps"]:] if args.write_db else []
+    fkib = float(np.mean(fetch)) if fetch and ff else None
+    wkib = float(np.mean(write)) if write and wf else None
+    traffic = (fkib * ff + wkib * wf) * 1024.0 if fkib is not None and wkib is not None else None
+    alg_read = alg / 2.0  # the push reads and writes the same lepton state
+    prof = {
+        "kernel": kname, "workload": workload, "steps": bench["steps"],
+        "source_sha256": kernel_source_hash(),
+        "commands": args.command,
+        "notes": args.note,
+        "trace": {"dispatches": len(push), "avg_us": float(np.mean(push)),
+                  "bench_event_avg_us": ev_avg_us,
+                  "kernels": [dict(name=k, n=c, mean_us=m, total_ms=t, pct=p) for k, c, m, t, p in table]},
+        "pmc": {"dispatches": [len(fetch), len(write)], "fetch_kib_per_dispatch": fkib,
+                "write_kib_per_dispatch": wkib, "fetch_factor": ff, "write_factor": wf,
+                "copy_dispatches": [nf, nw],
+                "fetch_bytes_per_launch": fkib * ff * 1024.0 if fkib is not None else None,
+                "alg_read_bytes_per_launch": alg_read,
+                "traffic_bytes_per_launch": traffic, "alg_bytes_per_launch": alg,
+                "traffic_over_alg": traffic / alg if traffic is not None else None},
+        "bench": {k: bench[k] for k in ("value", "ms_per_step", "steps")},
+    }
+    base = os.path.join(PROFILE_DIR, _profile_name(workload, prec))
+    os.makedirs(PROFILE_DIR, exist_ok=True)
+    with open(base + ".json", "w") as f:
+        json.dump(prof, f, indent=1)
+    lines = [f"# {kname} on {workload} ({bench['steps']} steps)", "",
+             "Commands (run from the repository root; rocprofv3 after `cd /tmp && export TMPDIR=/tmp`,",
+             "with the repository path for `$R`):", ""]
+    lines += [f"    {c}" for c in args.command]
+    lines += ["", f"Kernel sources sha256: `{prof['source_sha256']}`", "",
+              f"## Kernel trace ({len(push)} dispatches of {kname} in the two runs of the workload)", "",
+              f"- rocprofv3 average duration: {prof['trace']['avg_us']:.2f} us",
+              f"- bench HIP-event average over the evented run: {ev_avg_us:.2f} us", "",
+              "| kernel | dispatches | mean us | total ms | % |", "|---|---|---|---|---|"]
+    lines += [f"| {k} | {c} | {m:.2f} | {t:.1f} | {p:.1f} |" for k, c, m, t, p in table[:14]]
+    lines += ["", "## HBM traffic per launch (PMC, one counter per run, the graph-replayed "
+              f"steps: {len(fetch)} / {len(write)} dispatches)", ""]
+    if fkib is not None:
+        lines += [f"- FETCH_SIZE {fkib:.0f} KiB/dispatch x calibration {ff:.3f} = "
+                  f"{fkib * ff * 1024 / 1e9:.3f} GB read per launch vs algorithmic "
+                  f"{alg_read / 1e9:.3f} GB (ratio {fkib * ff * 1024 / alg_read:.3f})",
+                  f"- calibration: a 1 GiB device copy reads FETCH_SIZE {1024 * 1024 / ff:.0f} KiB per copy"]
+    else:
+        lines += ["- FETCH_SIZE: no completed pass"]
+    if wkib is not None:
+        lines += [f"- WRITE_SIZE {wkib:.0f} KiB/dispatch x calibration {wf:.3f}",
+                  f"- calibration: a 1 GiB device copy writes WRITE_SIZE {1024 * 1024 / wf:.0f} KiB per copy"]
+    else:
+        lines += ["- WRITE_SIZE: no completed pass, so the total traffic is not reported"]
+    if traffic is not None:
+        lines += [f"- traffic {traffic / 1e9:.3f} GB/launch vs algorithmic {alg / 1e9:.3f} GB/launch "
+                  f"(ratio {traffic / alg:.3f})"]
+    lines += [""] + [f"Note: {n}" for n in args.note] + ([""] if args.note else [])
+    with open(base + ".md", "w") as f:
+        f.write("\n".join(lines))
+    print(base + ".md")
+
+
 def _leg(r, precision):
     bpp = BYTES_PER_PUSH[precision]
     leg = dict(value=r["pushes"] / r["seconds"], unit="pushes/s", pushes=r["pushes"],
@@ -211,7 +359,22 @@ def main():
     ap.add_argument("--dump-history", default=None, help="save the history rows (.npy, single gap)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy a 1 GiB device buffer 3 times (counter calibration)")
+    ap.add_argument("--timed-only", action="store_true",
+                    help="skip the evented rerun (counter passes: same push dispatches, graph-replayed)")
+    ap.add_argument("--summarize", action="store_true",
+                    help="write the profiles/ summary from rocprofv3 databases (no GPU)")
+    ap.add_argument("--bench-json")
+    ap.add_argument("--trace-db")
+    ap.add_argument("--fetch-db")
+    ap.add_argument("--write-db")
+    ap.add_argument("--copy-fetch-db")
+    ap.add_argument("--copy-write-db")
+    ap.add_argument("--command", action="append", default=[])
+    ap.add_argument("--note", action="append", default=[])
     args = ap.parse_args()
+    if args.summarize:
+        summarize(args)
+        return
     if args.gpus != 1:
         print(f"bench.py: this path runs on one GPU; --gpus {args.gpus} is not supported "
               "(independent gaps would shard across GPUs without communication; not built here)",
@@ -243,9 +406,13 @@ def main():
                           f"{cb['seconds']:.1f} s)")
 
     warm_up(args.warmup)
-    main_run = run_gpu(gaps, steps, profile=True, dump=args.dump_history)
+    main_run = run_gpu(gaps, steps, profile=not args.timed_only, dump=args.dump_history)
     value = main_run["pushes"] / main_run["seconds"]
     bpp = BYTES_PER_PUSH[prec]
+    if args.timed_only:
+        print(json.dumps({"timed_only": True, "workload": args.workload, "steps": main_run["steps"],
+                          "pushes": main_run["pushes"], "value": value}), flush=True)
+        return
     achieved = main_run["pushes"] * bpp / (main_run["push_ms"] * 1e-3) / 1e9
 
     extra = {}
@@ -262,6 +429,7 @@ def main():
             r = run_gpu(_workload(args.workload, workloads.MIXED), steps, profile=True)
             extra["mixed_same_workload"] = _leg(r, workloads.MIXED)
 
+    pmc = stored_traffic(args.workload, prec, steps)
     cfg = {"workload": args.workload, "gaps": len(gaps), "steps": steps,
            "pushes": main_run["pushes"], "frozen_gaps": main_run["frozen"]}
     if len(gaps) == 1:
@@ -287,7 +455,10 @@ def main():
         "data": "synthetic",
         "config": cfg,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": pmc["traffic_bytes_per_launch"] if pmc else None,
+                     "traffic_unit": "B/launch",
+                     "alg_bytes_per_launch": main_run["pushes"] * bpp / max(main_run["push_launches"], 1),
                      "kernel": "k_push", "bytes_per_push": bpp,
                      "kernel_ms": main_run["push_ms"], "launches": main_run["push_launches"]},
         "cpu_baseline": cpu,
