@@ -8,6 +8,26 @@
 
 #include "pic.h"
 
+// Push pipelining defaults (overridable at build time for tuning sweeps).
+#ifndef PIC_PUSH_F_PREFETCH
+#define PIC_PUSH_F_PREFETCH 1
+#endif
+#ifndef PIC_PUSH_F_EGROUP
+#define PIC_PUSH_F_EGROUP 4
+#endif
+#ifndef PIC_PUSH_F_WAVES
+#define PIC_PUSH_F_WAVES 4
+#endif
+#ifndef PIC_PUSH_D_PREFETCH
+#define PIC_PUSH_D_PREFETCH 0
+#endif
+#ifndef PIC_PUSH_D_EGROUP
+#define PIC_PUSH_D_EGROUP 4
+#endif
+#ifndef PIC_PUSH_D_WAVES
+#define PIC_PUSH_D_WAVES 1
+#endif
+
 namespace pic {
 
 constexpr int kBlock = 256;           // threads per workgroup (4 wave64)
@@ -25,6 +45,23 @@ constexpr int kMaxEmit = 64;
 constexpr int kEmitShift = 11;
 constexpr uint32_t kEmitMask = (1u << kEmitShift) - 1u;
 constexpr int kPushGrid = 4096;       // workgroups of the push kernel
+// Push pipelining per particle type: whether the next chunk's lepton state
+// is prefetched, how many items' E values are requested together, and the
+// waves per SIMD asked of the compiler (4 means at most 128 VGPRs).
+template <typename T>
+struct PushCfg;
+template <>
+struct PushCfg<float> {
+  static constexpr bool prefetch = PIC_PUSH_F_PREFETCH;
+  static constexpr int e_group = PIC_PUSH_F_EGROUP;
+  static constexpr int waves = PIC_PUSH_F_WAVES;
+};
+template <>
+struct PushCfg<double> {
+  static constexpr bool prefetch = PIC_PUSH_D_PREFETCH;
+  static constexpr int e_group = PIC_PUSH_D_EGROUP;
+  static constexpr int waves = PIC_PUSH_D_WAVES;
+};
 constexpr int kStripes = 32;          // striped per-gap accumulators of the push kernel
 constexpr int kStripeStride = 16;     // doubles between stripes (one 128-byte line each)
 constexpr uint64_t kTagSeed = 1, kTagPhoton = 2;

@@ -119,14 +119,44 @@ __device__ __forceinline__ void flush_tally(double* __restrict__ stripes, int g,
   t.ke = 0.0; t.lost = 0.0; t.absorbed[0] = 0; t.absorbed[1] = 0;
 }
 
+// E at the cells left of, at and right of cell cl (a dead slot reads cell 0),
+// with the boundary ghosts of the gather.
+template <typename T>
+__device__ __forceinline__ void load_e3(gptr<const double> E, int cl, bool periodic, int nc, T& em,
+                                        T& ec, T& ep) {
+  const int c = cl == kDead ? 0 : cl;
+  int cm = c - 1, cp = c + 1;
+  if (periodic) { cm = cm < 0 ? nc - 1 : cm; cp = cp >= nc ? 0 : cp; }
+  else { cm = cm < 0 ? 0 : cm; cp = cp >= nc ? nc - 1 : cp; }
+  em = (T)E[cm];
+  ec = (T)E[c];
+  ep = (T)E[cp];
+}
+
+// Lepton range of work item w of gap G: species s, indices [i0, i1).
+__device__ __forceinline__ void push_item(long long local, long long chunks0, long long n0,
+                                          long long n1, int& s, long long& i0, long long& i1) {
+  s = local < chunks0 ? 0 : 1;
+  i0 = (s == 0 ? local : local - chunks0) * kChunk;
+  const long long nS = s == 0 ? n0 : n1;
+  i1 = i0 + kChunk < nS ? i0 + kChunk : nS;
+}
+
 // One work item is a chunk of kChunk leptons of one species of one gap.
 // Leptons are sorted by cell (between re-sorts they drift by a few cells),
 // so a chunk touches a short range of cells: its current is summed in a
 // per-workgroup LDS tile over that range and added to the grid with one
 // atomic per touched cell.  Chunks spread over more than kTile cells (the
 // sparse early cascade, unsorted appended leptons) add to the grid directly.
+//
+// Loads are issued in phases (all lepton state of a chunk, then all its E
+// values) so that each phase waits once.  In binary32 the loop is also
+// software-pipelined: the lepton state of the next chunk of the same gap is
+// loaded while the current one is pushed, and the E values of the current
+// chunk are requested before that prefetch, so waiting for them leaves the
+// prefetch in flight.  The gap's constants are read once per gap.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_push(GapDev* __restrict__ gaps,
+__global__ __launch_bounds__(kBlock, PushCfg<T>::waves) void k_push(GapDev* __restrict__ gaps,
                                                  const long long* __restrict__ wi, int B,
                                                  int32_t* __restrict__ emit_cnt,
                                                  uint32_t* __restrict__ emit_ent,
@@ -146,191 +176,253 @@ __global__ __launch_bounds__(kBlock) void k_push(GapDev* __restrict__ gaps,
   const int tid = threadIdx.x;
   const int lane = lane_id();
   PushTally tally = {0.0, 0.0, {0, 0}};
-  int cur_g = -1;
-  bool cur_diag = false;
   uint32_t my_emitters = 0;  // emitters listed by this workgroup (thread 0)
 
+  // constants of the current gap
+  int g = -1;
+  long long gbeg = 0, gend = -1, chunks0 = 0, n0 = 0, n1 = 0;
+  bool diag = false, periodic = false, gap_ok = false;
+  int nc = 0;
+  gptr<int32_t> cellS[2] = {nullptr, nullptr};
+  gptr<T> offS[2] = {nullptr, nullptr}, pS[2] = {nullptr, nullptr};
+  gptr<const double> E = nullptr;
+  gptr<unsigned long long> F = nullptr;
+  I ONE = 0;
+  T scale = 0, inv_scale = 0, dt_t = 0, dtdx = 0, gthr = 0, gpair = 0;
+  double w_d = 0.0;
+  GapDev* __restrict__ G = gaps;
+
+  // lepton state of the chunk about to be pushed (prefetched when `have`)
+  int cl[kItems];
+  T ov[kItems], pv[kItems];
+  bool have = false;
+
   for (long long w = w0; w < w1; ++w) {
-    const int g = find_gap(wi, B, w);
-    GapDev* __restrict__ G = gaps + g;
-    if (g != cur_g) {
-      if (cur_g >= 0) flush_tally(stripes, cur_g, tally, cur_diag, s_d, s_u);
-      cur_g = g;
-      cur_diag = (G->step % G->diag_every) == 0;
+    if (w >= gend) {  // uniform: the first chunk of another gap
+      if (g >= 0) flush_tally(stripes, g, tally, diag, s_d, s_u);
+      g = find_gap(wi, B, w);
+      G = gaps + g;
+      gbeg = wi[g];
+      gend = wi[g + 1];
+      gap_ok = G->status == PIC_OK;
+      diag = (G->step % G->diag_every) == 0;
+      const int buf = G->buf;
+      n0 = (long long)G->n[0];
+      n1 = (long long)G->n[1];
+      chunks0 = (n0 + kChunk - 1) / kChunk;
+      for (int sp = 0; sp < 2; ++sp) {
+        cellS[sp] = glb(G->cell[buf][sp]);
+        offS[sp] = glb<T>(G->off[buf][sp]);
+        pS[sp] = glb<T>(G->p[buf][sp]);
+      }
+      E = glb<const double>(G->E);
+      F = glb<unsigned long long>((void*)G->F);
+      nc = G->n_cells;
+      periodic = G->boundary == PIC_BC_PERIODIC;
+      ONE = (I)G->one;
+      scale = (T)(double)G->one;
+      inv_scale = (T)(1.0 / (double)G->one);
+      dt_t = (T)G->dt;
+      dtdx = (T)G->dtdx;
+      gthr = (T)G->gthr;
+      gpair = (T)G->gpair;
+      w_d = G->weight;
+      have = false;
     }
-    if (G->status != PIC_OK) continue;
-    const int buf = G->buf;
-    const long long chunks0 = ((long long)G->n[0] + kChunk - 1) / kChunk;
-    const long long local = w - wi[g];
-    const int s = local < chunks0 ? 0 : 1;
-    const long long i0 = (s == 0 ? local : local - chunks0) * kChunk;
-    const long long nS = (long long)G->n[s];
-    const long long i1 = i0 + kChunk < nS ? i0 + kChunk : nS;
     if (tid == 0) emit_cnt[w] = 0;
-
-    gptr<int32_t> cellA = glb(G->cell[buf][s]);
-    gptr<T> offA = glb<T>(G->off[buf][s]);
-    gptr<T> pA = glb<T>(G->p[buf][s]);
-    gptr<const double> E = glb<const double>(G->E);
-    gptr<unsigned long long> F = glb<unsigned long long>((void*)G->F);
-    const int nc = G->n_cells;
-    const bool periodic = G->boundary == PIC_BC_PERIODIC;
-    const I ONE = (I)G->one;
-    const T scale = (T)(double)G->one;
-    const T inv_scale = (T)(1.0 / (double)G->one);
-    const T qdt = s == 0 ? -(T)G->dt : (T)G->dt;
-    const T dtdx = (T)G->dtdx;
-    const T gthr = (T)G->gthr, gpair = (T)G->gpair;
-    const T one_t = (T)1, half_t = (T)0.5;
-    const double w_d = G->weight;
-
-    int cl[kItems];
-    T ov[kItems], pv[kItems];
+    if (!gap_ok) continue;
+    int s;
+    long long i0, i1;
+    push_item(w - gbeg, chunks0, n0, n1, s, i0, i1);
+    gptr<int32_t> cellA = cellS[s];
+    gptr<T> offA = offS[s];
+    gptr<T> pA = pS[s];
+    if (!have) {
+      // unconditional loads (slots past the end read slot 0 and are discarded),
+      // so that all of them are in flight at once
+#pragma unroll
+      for (int j = 0; j < kItems; ++j) {
+        const long long i = i0 + tid + (long long)j * kBlock;
+        const long long ii = i < i1 ? i : 0;
+        const int cv = cellA[ii];
+        const T ovv = offA[ii], pvv = pA[ii];
+        cl[j] = i < i1 ? cv : kDead;
+        ov[j] = i < i1 ? ovv : (T)0;
+        pv[j] = i < i1 ? pvv : (T)0;
+      }
+    }
     int mn = INT32_MAX, mx = INT32_MIN;
 #pragma unroll
-    for (int j = 0; j < kItems; ++j) {
-      const long long i = i0 + tid + (long long)j * kBlock;
-      cl[j] = i < i1 ? cellA[i] : kDead;
-      ov[j] = (T)0;
-      pv[j] = (T)0;
-      if (cl[j] != kDead) {
-        ov[j] = offA[i];
-        pv[j] = pA[i];
-        mn = min(mn, cl[j]);
-        mx = max(mx, cl[j]);
-      }
-    }
+    for (int j = 0; j < kItems; ++j)
+      if (cl[j] != kDead) { mn = min(mn, cl[j]); mx = max(mx, cl[j]); }
     if (tid == 0) { s_emit_n = 0; s_emit_k = 0; }
     block_minmax(mn, mx, s_red);
-    if (mx < mn) continue;  // no live lepton in this chunk (uniform)
-    const int base = mn - 1;
-    const int span = mx - mn + 3;
-    const bool lds = span <= kTile;
-    if (lds) {
-      for (int k = tid; k < span; k += kBlock) s_flux[k] = 0;
+    // E at the cells around each lepton (dead slots read cell 0), requested
+    // for the first group of items now and for later groups just before
+    // they are pushed
+    constexpr int kEG = PushCfg<T>::e_group;
+    T Em[kItems], Ec[kItems], Ep[kItems];
+#pragma unroll
+    for (int j = 0; j < kEG; ++j) load_e3(E, cl[j], periodic, nc, Em[j], Ec[j], Ep[j]);
+    // prefetch the next chunk of this gap; the loads are issued whether or
+    // not there is one (then they read slot 0 and are discarded), so the
+    // wait for the E values above never waits for them
+    const bool pre = PushCfg<T>::prefetch && w + 1 < w1 && w + 1 < gend;
+    int cln[kItems];
+    T ovn[kItems], pvn[kItems];
+    if constexpr (PushCfg<T>::prefetch) {
+      int s2 = s;
+      long long j0 = 0, j1 = 0;
+      if (pre) push_item(w + 1 - gbeg, chunks0, n0, n1, s2, j0, j1);
+      gptr<const int32_t> c2A = cellS[s2];
+      gptr<const T> o2A = offS[s2];
+      gptr<const T> p2A = pS[s2];
+#pragma unroll
+      for (int j = 0; j < kItems; ++j) {
+        const long long i = j0 + tid + (long long)j * kBlock;
+        const long long ii = i < j1 ? i : 0;
+        const int cv = c2A[ii];
+        const T ovv = o2A[ii], pvv = p2A[ii];
+        cln[j] = i < j1 ? cv : kDead;
+        ovn[j] = i < j1 ? ovv : (T)0;
+        pvn[j] = i < j1 ? pvv : (T)0;
+      }
+    }
+    if (mx >= mn) {  // uniform: some lepton of this chunk is alive
+      const int base = mn - 1;
+      const int span = mx - mn + 3;
+      const bool lds = span <= kTile;
+      if (lds) {
+        for (int k = tid; k < span; k += kBlock) s_flux[k] = 0;
+        __syncthreads();
+      }
+      const T qdt = s == 0 ? -dt_t : dt_t;
+      const T one_t = (T)1, half_t = (T)0.5;
+      bool bad = false, emit_bad = false;
+#pragma unroll
+      for (int j = 0; j < kItems; ++j) {
+        if (j > 0 && j % kEG == 0) {
+#pragma unroll
+          for (int jj = j; jj < j + kEG; ++jj) load_e3(E, cl[jj], periodic, nc, Em[jj], Ec[jj], Ep[jj]);
+        }
+        const long long i = i0 + tid + (long long)j * kBlock;
+        const int c = cl[j];
+        if (c == kDead) continue;
+        const T o = ov[j];
+        const I oq = (I)(o * scale);
+        // gather: node averages, then linear in the offset
+        const T el = half_t * (Em[j] + Ec[j]);
+        const T er = half_t * (Ec[j] + Ep[j]);
+        const T Epart = el + o * (er - el);
+        // push and move
+        T pn = pv[j] + qdt * Epart;
+        const T gam = sqrt(one_t + pn * pn);
+        const T v = pn / gam;
+        const T d = v * dtdx;
+        const I dq = (I)rint(d * scale);
+        I nq = oq + dq;
+        I a1, a2 = 0;   // flux of a positive charge through this cell and the next
+        int cross = 0;  // -1, 0, +1: node crossed to the left / none / right
+        int c2 = c;
+        bool keep = true;
+        if (nq >= ONE) {
+          a1 = ONE - oq;
+          cross = 1;
+          c2 = c + 1;
+          nq -= ONE;
+          a2 = nq;
+          if (c2 >= nc) { if (periodic) c2 = 0; else keep = false; }
+        } else if (nq < 0) {
+          a1 = -oq;
+          cross = -1;
+          c2 = c - 1;
+          nq += ONE;
+          a2 = nq - ONE;
+          if (c2 < 0) { if (periodic) c2 = nc - 1; else keep = false; }
+        } else {
+          a1 = dq;
+        }
+        const long long f1 = s == 0 ? -(long long)a1 : (long long)a1;
+        const long long f2 = s == 0 ? -(long long)a2 : (long long)a2;
+        const bool second = cross != 0 && keep;
+        if (lds) {
+          // tile indices are unwrapped: c - 1 .. c + 1 all lie in [base, base + span)
+          atomicAdd((unsigned long long*)&s_flux[c - base], as_u64(f1));
+          if (second) atomicAdd((unsigned long long*)&s_flux[c + cross - base], as_u64(f2));
+        } else {
+          gadd(F + c, as_u64(f1));
+          if (second) gadd(F + c2, as_u64(f2));
+        }
+        if (!isfinite(pn) || !isfinite(gam)) bad = true;
+        if (keep) {
+          // emission: repeated subtraction of gamma_pair while at or above threshold
+          int k = 0;
+          T gm = gam;
+          while (gm >= gthr && k <= kMaxEmit) {
+            gm = gm - gpair;
+            ++k;
+          }
+          if (k > kMaxEmit) { emit_bad = true; k = 0; }
+          T gnew = gam;
+          if (k > 0) {
+            const T mag = sqrt(gm * gm - one_t);
+            pn = pn > (T)0 ? mag : -mag;
+            gnew = sqrt(one_t + pn * pn);
+            const int pos = atomicAdd(&s_emit_n, 1);
+            atomicAdd(&s_emit_k, k);
+            s_emit[pos] = ((uint32_t)(i - i0) << 8) | (uint32_t)k;
+          }
+          pA[i] = pn;
+          offA[i] = (T)nq * inv_scale;
+          if (c2 != c) cellA[i] = c2;
+          // energy: the Lorentz factor in the particle precision, summed in binary64
+          if (diag) tally.ke += w_d * (double)gnew;
+        } else {
+          tally.lost += w_d * (double)gam;
+          tally.absorbed[s] += 1;
+          pA[i] = pn;
+          cellA[i] = kDead;
+        }
+      }
+
+      const unsigned long long bad_w = __ballot(bad);
+      const unsigned long long ebad_w = __ballot(emit_bad);
+      if (lane == 0) {
+        if (bad_w) G->nonfinite = 1;
+        if (ebad_w) G->emit_err = 1;
+      }
+
+      __syncthreads();
+      if (lds) {
+        for (int k = tid; k < span; k += kBlock) {
+          const long long f = s_flux[k];
+          if (f != 0) {
+            int cc = base + k;
+            if (cc < 0) cc += nc;
+            else if (cc >= nc) cc -= nc;
+            gadd(F + cc, as_u64(f));
+          }
+        }
+      }
+      // ---- emitters of this chunk, in the chunk's own slice of the list
+      const int ne = s_emit_n;
+      if (ne > 0) {
+        if (tid == 0) {
+          emit_cnt[w] = ne | (s_emit_k << kEmitShift);
+          my_emitters += (uint32_t)ne;
+        }
+        gptr<uint32_t> el = glb(emit_ent + w * (long long)kChunk);
+        for (int k = tid; k < ne; k += kBlock) el[k] = s_emit[k];
+      }
       __syncthreads();
     }
-
-    bool bad = false, emit_bad = false;
-
+    if constexpr (PushCfg<T>::prefetch) {
 #pragma unroll
-    for (int j = 0; j < kItems; ++j) {
-      const long long i = i0 + tid + (long long)j * kBlock;
-      const int c = cl[j];
-      if (c == kDead) continue;
-      int cm = c - 1, cp = c + 1;
-      if (periodic) { cm = cm < 0 ? nc - 1 : cm; cp = cp >= nc ? 0 : cp; }
-      else { cm = cm < 0 ? 0 : cm; cp = cp >= nc ? nc - 1 : cp; }
-      const T Em = (T)E[cm], Ec = (T)E[c], Ep = (T)E[cp];
-      const T o = ov[j];
-      const I oq = (I)(o * scale);
-      // gather: node averages, then linear in the offset
-      const T el = half_t * (Em + Ec);
-      const T er = half_t * (Ec + Ep);
-      const T Epart = el + o * (er - el);
-      // push and move
-      T pn = pv[j] + qdt * Epart;
-      const T gam = sqrt(one_t + pn * pn);
-      const T v = pn / gam;
-      const T d = v * dtdx;
-      const I dq = (I)rint(d * scale);
-      I nq = oq + dq;
-      I a1, a2 = 0;  // flux of a positive charge through this cell and the next
-      int cross = 0;  // -1, 0, +1: node crossed to the left / none / right
-      int c2 = c;
-      bool keep = true;
-      if (nq >= ONE) {
-        a1 = ONE - oq;
-        cross = 1;
-        c2 = c + 1;
-        nq -= ONE;
-        a2 = nq;
-        if (c2 >= nc) { if (periodic) c2 = 0; else keep = false; }
-      } else if (nq < 0) {
-        a1 = -oq;
-        cross = -1;
-        c2 = c - 1;
-        nq += ONE;
-        a2 = nq - ONE;
-        if (c2 < 0) { if (periodic) c2 = nc - 1; else keep = false; }
-      } else {
-        a1 = dq;
-      }
-      const long long f1 = s == 0 ? -(long long)a1 : (long long)a1;
-      const long long f2 = s == 0 ? -(long long)a2 : (long long)a2;
-      const bool second = cross != 0 && keep;
-      if (lds) {
-        // tile indices are unwrapped: c - 1 .. c + 1 all lie in [base, base + span)
-        atomicAdd((unsigned long long*)&s_flux[c - base], as_u64(f1));
-        if (second) atomicAdd((unsigned long long*)&s_flux[c + cross - base], as_u64(f2));
-      } else {
-        gadd(F + c, as_u64(f1));
-        if (second) gadd(F + c2, as_u64(f2));
-      }
-      if (!isfinite(pn) || !isfinite(gam)) bad = true;
-      if (keep) {
-        // emission: repeated subtraction of gamma_pair while at or above threshold
-        int k = 0;
-        T gm = gam;
-        while (gm >= gthr && k <= kMaxEmit) {
-          gm = gm - gpair;
-          ++k;
-        }
-        if (k > kMaxEmit) { emit_bad = true; k = 0; }
-        T gnew = gam;
-        if (k > 0) {
-          const T mag = sqrt(gm * gm - one_t);
-          pn = pn > (T)0 ? mag : -mag;
-          gnew = sqrt(one_t + pn * pn);
-          const int pos = atomicAdd(&s_emit_n, 1);
-          atomicAdd(&s_emit_k, k);
-          s_emit[pos] = ((uint32_t)(i - i0) << 8) | (uint32_t)k;
-        }
-        pA[i] = pn;
-        offA[i] = (T)nq * inv_scale;
-        if (c2 != c) cellA[i] = c2;
-        // energy: the Lorentz factor in the particle precision, summed in binary64
-        if (cur_diag) tally.ke += w_d * (double)gnew;
-      } else {
-        tally.lost += w_d * (double)gam;
-        tally.absorbed[s] += 1;
-        pA[i] = pn;
-        cellA[i] = kDead;
-      }
+      for (int j = 0; j < kItems; ++j) { cl[j] = cln[j]; ov[j] = ovn[j]; pv[j] = pvn[j]; }
     }
-
-    const unsigned long long bad_w = __ballot(bad);
-    const unsigned long long ebad_w = __ballot(emit_bad);
-    if (lane == 0) {
-      if (bad_w) G->nonfinite = 1;
-      if (ebad_w) G->emit_err = 1;
-    }
-
-    __syncthreads();
-    if (lds) {
-      for (int k = tid; k < span; k += kBlock) {
-        const long long f = s_flux[k];
-        if (f != 0) {
-          int cc = base + k;
-          if (cc < 0) cc += nc;
-          else if (cc >= nc) cc -= nc;
-          gadd(F + cc, as_u64(f));
-        }
-      }
-    }
-    // ---- emitters of this chunk, in the chunk's own slice of the list
-    const int ne = s_emit_n;
-    if (ne > 0) {
-      if (tid == 0) {
-        emit_cnt[w] = ne | (s_emit_k << kEmitShift);
-        my_emitters += (uint32_t)ne;
-      }
-      gptr<uint32_t> el = glb(emit_ent + w * (long long)kChunk);
-      for (int k = tid; k < ne; k += kBlock) el[k] = s_emit[k];
-    }
-    __syncthreads();
+    have = pre;
   }
-  if (cur_g >= 0) flush_tally(stripes, cur_g, tally, cur_diag, s_d, s_u);
+  if (g >= 0) flush_tally(stripes, g, tally, diag, s_d, s_u);
   // emitters of this workgroup's chunk range, indexed in chunk order
   if (tid == 0) wg_emit[xcd_logical((int)blockIdx.x, (int)gridDim.x)] = my_emitters;
 }
@@ -654,12 +746,6 @@ __device__ __forceinline__ void photon_ranges(const GapDev* G, long long& b0, lo
   t1 = (long long)G->n_ph;
 }
 
-__device__ __forceinline__ long long convert_items(const GapDev* G) {
-  long long b0, b1, t0, t1;
-  photon_ranges(G, b0, b1, t0, t1);
-  return (b1 - b0 + kPhChunk - 1) / kPhChunk + (t1 - t0 + kPhChunk - 1) / kPhChunk;
-}
-
 __device__ __forceinline__ void convert_item(const GapDev* G, long long local, long long& i0,
                                              long long& i1) {
   long long b0, b1, t0, t1;
@@ -761,42 +847,117 @@ __device__ void convert_role(GapDev* __restrict__ gaps, const long long* __restr
 // Work-item prefixes of the next launches: particle chunks per gap (both
 // species), due-photon chunks per gap, and chunks of the whole photon store
 // (for its re-sort); frozen gaps get none.
-__device__ __forceinline__ void gap_items(const GapDev* G, long long& a, long long& b, long long& c) {
+struct PlanIn {
+  bool ok;
+  int table_len;
+  unsigned long long n0, n1, n_ph, body_n;
+  long long step, ph_base;
+  const int32_t* bucket;
+};
+
+__device__ __forceinline__ PlanIn plan_in(const GapDev* G) {
+  PlanIn p;
+  p.ok = G->status == PIC_OK;
+  p.table_len = G->table_len;
+  p.n0 = G->n[0];
+  p.n1 = G->n[1];
+  p.n_ph = G->n_ph;
+  p.body_n = G->ph_body_n;
+  p.step = G->step;
+  p.ph_base = G->ph_base;
+  p.bucket = G->ph_bucket;
+  return p;
+}
+
+__device__ __forceinline__ void plan_items(const PlanIn& p, long long& a, long long& b, long long& c) {
   a = b = c = 0;
-  if (G->status != PIC_OK) return;
-  a = ((long long)G->n[0] + kChunk - 1) / kChunk + ((long long)G->n[1] + kChunk - 1) / kChunk;
-  b = convert_items(G);
-  if (G->table_len > 0) c = ((long long)G->n_ph + kPhChunk - 1) / kPhChunk;
+  if (!p.ok) return;
+  a = ((long long)p.n0 + kChunk - 1) / kChunk + ((long long)p.n1 + kChunk - 1) / kChunk;
+  long long b0 = 0, b1 = 0;
+  const long long k = p.step - p.ph_base;
+  if (p.table_len > 0 && k >= 0 && k < p.table_len) {
+    b0 = k == 0 ? 0 : (long long)p.bucket[k - 1];
+    b1 = (long long)p.bucket[k];
+  }
+  b = (b1 - b0 + kPhChunk - 1) / kPhChunk + ((long long)(p.n_ph - p.body_n) + kPhChunk - 1) / kPhChunk;
+  if (p.table_len > 0) c = ((long long)p.n_ph + kPhChunk - 1) / kPhChunk;
+}
+
+// Exclusive prefix sums of three values over a block of up to 1024 threads
+// (wave scans, then one pass over the wave totals); t* get the totals.
+__device__ __forceinline__ void block_scan3(long long& a, long long& b, long long& c, long long& ta,
+                                            long long& tb, long long& tc) {
+  __shared__ long long s_w[3 * 16];
+  const long long ia = wave_incl_scan(a), ib = wave_incl_scan(b), ic = wave_incl_scan(c);
+  const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  if (lane_id() == 63) { s_w[w] = ia; s_w[16 + w] = ib; s_w[32 + w] = ic; }
+  __syncthreads();
+  long long oa = 0, ob = 0, oc = 0;
+  ta = tb = tc = 0;
+  for (int k = 0; k < nw; ++k) {
+    if (k < w) { oa += s_w[k]; ob += s_w[16 + k]; oc += s_w[32 + k]; }
+    ta += s_w[k]; tb += s_w[16 + k]; tc += s_w[32 + k];
+  }
+  a = oa + ia - a;
+  b = ob + ib - b;
+  c = oc + ic - c;
+}
+
+constexpr int kPlanPer = 4;  // gaps per thread whose items a plan keeps in registers
+
+// Writes the prefixes from the items of this thread's gaps tid*per + k.
+__device__ __forceinline__ void plan_write(int B, int per, const long long (&a)[kPlanPer],
+                                           const long long (&b)[kPlanPer],
+                                           const long long (&c)[kPlanPer], long long* __restrict__ wi,
+                                           long long* __restrict__ pwi, long long* __restrict__ qwi) {
+  long long ra = 0, rb = 0, rc = 0;
+#pragma unroll
+  for (int k = 0; k < kPlanPer; ++k) { ra += a[k]; rb += b[k]; rc += c[k]; }
+  long long ta, tb, tc;
+  block_scan3(ra, rb, rc, ta, tb, tc);
+#pragma unroll
+  for (int k = 0; k < kPlanPer; ++k) {
+    const int g = threadIdx.x * per + k;
+    if (k < per && g < B) {
+      wi[g] = ra; pwi[g] = rb; qwi[g] = rc;
+      ra += a[k]; rb += b[k]; rc += c[k];
+    }
+  }
+  if (threadIdx.x == 0) { wi[B] = ta; pwi[B] = tb; qwi[B] = tc; }
 }
 
 __device__ void compute_plans(GapDev* __restrict__ gaps, int B, long long* __restrict__ wi,
                               long long* __restrict__ pwi, long long* __restrict__ qwi) {
-  __shared__ long long s_a[1024], s_b[1024], s_c[1024];
   const int tid = threadIdx.x, nt = blockDim.x;
   const int per = (B + nt - 1) / nt;
+  if (per <= kPlanPer) {
+    long long a[kPlanPer], b[kPlanPer], c[kPlanPer];
+#pragma unroll
+    for (int k = 0; k < kPlanPer; ++k) {
+      a[k] = b[k] = c[k] = 0;
+      const int g = tid * per + k;
+      if (k < per && g < B) plan_items(plan_in(gaps + g), a[k], b[k], c[k]);
+    }
+    plan_write(B, per, a, b, c, wi, pwi, qwi);
+    return;
+  }
+  // very large batches: two passes over the gaps
   long long sa = 0, sb = 0, sc = 0;
   for (int g = tid * per; g < (tid + 1) * per && g < B; ++g) {
     long long a, b, c;
-    gap_items(gaps + g, a, b, c);
+    plan_items(plan_in(gaps + g), a, b, c);
     sa += a; sb += b; sc += c;
   }
-  s_a[tid] = sa; s_b[tid] = sb; s_c[tid] = sc;
-  __syncthreads();
-  for (int d = 1; d < nt; d <<= 1) {
-    const long long ya = tid >= d ? s_a[tid - d] : 0, yb = tid >= d ? s_b[tid - d] : 0;
-    const long long yc = tid >= d ? s_c[tid - d] : 0;
-    __syncthreads();
-    s_a[tid] += ya; s_b[tid] += yb; s_c[tid] += yc;
-    __syncthreads();
-  }
-  long long ra = s_a[tid] - sa, rb = s_b[tid] - sb, rc = s_c[tid] - sc;
+  long long ta, tb, tc;
+  block_scan3(sa, sb, sc, ta, tb, tc);
   for (int g = tid * per; g < (tid + 1) * per && g < B; ++g) {
-    wi[g] = ra; pwi[g] = rb; qwi[g] = rc;
+    wi[g] = sa; pwi[g] = sb; qwi[g] = sc;
     long long a, b, c;
-    gap_items(gaps + g, a, b, c);
-    ra += a; rb += b; rc += c;
+    plan_items(plan_in(gaps + g), a, b, c);
+    sa += a; sb += b; sc += c;
   }
-  if (tid == nt - 1) { wi[B] = s_a[nt - 1]; pwi[B] = s_b[nt - 1]; qwi[B] = s_c[nt - 1]; }
+  if (tid == 0) { wi[B] = ta; pwi[B] = tb; qwi[B] = tc; }
 }
 
 __global__ __launch_bounds__(1024) void k_plan(GapDev* __restrict__ gaps, int B,
@@ -808,125 +969,159 @@ __global__ __launch_bounds__(1024) void k_plan(GapDev* __restrict__ gaps, int B,
 
 // Ends a step for every gap: freeze on error, roll the counters, write the
 // history row, and plan the next step.
-constexpr int kFoldMax = 1024;  // gaps whose stripes finalize folds with the whole block
+
+// One gap's end of step (the push tallies are already folded into the
+// descriptor).  Every field is read before any is written, so the reads go
+// out together.
+__device__ __forceinline__ PlanIn finalize_gap(GapDev* __restrict__ G) {
+  const int status = G->status, nonfinite = G->nonfinite, overflow = G->overflow;
+  const int emit_err = G->emit_err, table_len = G->table_len, diag_every = G->diag_every;
+  const int hist_rows = G->hist_rows, n_cells = G->n_cells;
+  const unsigned long long pair_next = G->pair_next, esc_next = G->esc_next;
+  const unsigned long long n_ph = G->n_ph, n_ph_next = G->n_ph_next;
+  const unsigned long long n0 = G->n[0], n1 = G->n[1], dead0 = G->dead[0], dead1 = G->dead[1];
+  const unsigned long long live0 = G->live[0], live1 = G->live[1], pushes = G->pushes;
+  const unsigned long long absorbed0 = G->absorbed[0], absorbed1 = G->absorbed[1];
+  const unsigned long long inflight0 = G->inflight, created0 = G->pairs_created;
+  const unsigned long long emitted0 = G->photons_emitted, escaped0 = G->photons_escaped;
+  const unsigned long long hist_count = G->hist_count, body_n = G->ph_body_n;
+  const long long done = G->step, ph_base = G->ph_base;
+  const int32_t* bucket = G->ph_bucket;
+  const double weight = G->weight, gpair64 = G->gpair64, child_gamma64 = G->child_gamma64;
+  double ke = G->ke_acc, lost = G->lost_energy;
+  const double fe = G->fe_acc, es = G->es_acc;
+
+  G->ke_acc = 0.0;
+  G->fe_acc = 0.0;
+  G->es_acc = 0.0;
+  PlanIn out;
+  out.ok = false;
+  out.table_len = table_len;
+  out.body_n = body_n;
+  out.ph_base = ph_base;
+  out.bucket = bucket;
+  if (status != PIC_OK) return out;
+  const int st = nonfinite ? PIC_ERR_NONFINITE
+               : overflow  ? PIC_ERR_CAPACITY
+               : emit_err  ? PIC_ERR_EMISSION : PIC_OK;
+  if (st != PIC_OK) {
+    G->status = st;
+    return out;
+  }
+  // what this step appended: dp pairs (in place or converted), dph photons
+  // stored, de of which left the domain
+  const unsigned long long dp = pair_next, dph = n_ph_next - n_ph, de = esc_next;
+  const bool in_place = table_len == 0;
+  const bool diag = done % diag_every == 0;
+  const unsigned long long created = created0 + dp;
+  const unsigned long long emitted = emitted0 + (in_place ? dp : dph);
+  const unsigned long long escaped = escaped0 + de;
+  const unsigned long long inflight = in_place ? inflight0 : inflight0 + dph - de - dp;
+  if (de) lost += (double)de * weight * gpair64;
+  if (diag && dp) ke += (double)dp * 2.0 * weight * child_gamma64;
+  const unsigned long long nn0 = n0 + dp, nn1 = n1 + dp;
+  const unsigned long long nl0 = nn0 - dead0, nl1 = nn1 - dead1;
+  G->pairs_created = created;
+  G->photons_emitted = emitted;
+  G->photons_escaped = escaped;
+  G->inflight = inflight;
+  G->lost_energy = lost;
+  G->pushes = pushes + live0 + live1;
+  G->n[0] = nn0;
+  G->n[1] = nn1;
+  G->live[0] = nl0;
+  G->live[1] = nl1;
+  G->pair_next = 0;
+  G->esc_next = 0;
+  G->n_ph = n_ph_next;
+  G->step = done + 1;
+  if (diag) {
+    pic_history_row r;
+    r.step = done;
+    r.n_minus = (int64_t)nl0;
+    r.n_plus = (int64_t)nl1;
+    r.n_photons = (int64_t)inflight;
+    r.pairs_created = (int64_t)created;
+    r.photons_emitted = (int64_t)emitted;
+    r.photons_escaped = (int64_t)escaped;
+    r.absorbed_minus = (int64_t)absorbed0;
+    r.absorbed_plus = (int64_t)absorbed1;
+    r.kinetic = ke;
+    r.field = fe;
+    r.photon_energy = (double)inflight * weight * gpair64;
+    r.lost_energy = lost;
+    r.e_mean = es / (double)n_cells;
+    G->hist[hist_count % (unsigned long long)hist_rows] = r;
+    G->hist_count = hist_count + 1;
+    G->last = r;
+  }
+  out.ok = true;
+  out.n0 = nn0;
+  out.n1 = nn1;
+  out.n_ph = n_ph_next;
+  out.step = done + 1;
+  return out;
+}
 
 __device__ void finalize_body(GapDev* __restrict__ gaps, int B, long long* __restrict__ wi,
-                              long long* __restrict__ pwi, long long* __restrict__ qwi,
-                              double* __restrict__ stripes) {
-  __shared__ unsigned long long s_fold[kFoldMax * 4];
-  // fold the striped push tallies: 32 lanes sum the stripes of one
-  // (gap, accumulator) pair; accumulators 2 and 3 hold integer counts
-  const bool wide = B <= kFoldMax;
-  if (wide) {
-    const int lane = lane_id();
-    const int pairs = B * 4;
-    for (int base = (threadIdx.x >> 6) * 2; base < pairs; base += (blockDim.x >> 6) * 2) {
-      const int pair = base + (lane >> 5);
-      const int st = lane & 31;
-      unsigned long long bits = 0;
-      if (pair < pairs) {
-        unsigned long long* slot = (unsigned long long*)stripe_slot(stripes, pair >> 2, pair & 3, st);
-        bits = *slot;
-        *slot = 0ull;
-      }
-      double dv = __longlong_as_double((long long)bits);
-      unsigned long long uv = bits;
+                              long long* __restrict__ pwi, long long* __restrict__ qwi) {
+  const int per = (B + (int)blockDim.x - 1) / (int)blockDim.x;
+  if (per <= kPlanPer) {
+    // each thread ends its own gaps and plans them from the values in hand
+    long long a[kPlanPer], b[kPlanPer], c[kPlanPer];
 #pragma unroll
-      for (int d = 16; d >= 1; d >>= 1) {
-        dv += __shfl_xor(dv, d, 64);
-        uv += __shfl_xor(uv, d, 64);
-      }
-      if (st == 0 && pair < pairs)
-        s_fold[pair] = (pair & 3) < 2 ? (unsigned long long)__double_as_longlong(dv) : uv;
+    for (int k = 0; k < kPlanPer; ++k) {
+      a[k] = b[k] = c[k] = 0;
+      const int g = threadIdx.x * per + k;
+      if (k < per && g < B) plan_items(finalize_gap(gaps + g), a[k], b[k], c[k]);
     }
-    __syncthreads();
+    plan_write(B, per, a, b, c, wi, pwi, qwi);
+    return;
   }
-  for (int g = threadIdx.x; g < B; g += blockDim.x) {
-    GapDev* G = gaps + g;
-    double ke = 0.0, lost = 0.0;
-    unsigned long long ab[2] = {0, 0};
-    if (wide) {
-      ke = __longlong_as_double((long long)s_fold[g * 4 + 0]);
-      lost = __longlong_as_double((long long)s_fold[g * 4 + 1]);
-      ab[0] = s_fold[g * 4 + 2];
-      ab[1] = s_fold[g * 4 + 3];
-    } else {
-      for (int st = 0; st < kStripes; ++st) {
-        ke += *stripe_slot(stripes, g, 0, st);
-        lost += *stripe_slot(stripes, g, 1, st);
-        ab[0] += *(unsigned long long*)stripe_slot(stripes, g, 2, st);
-        ab[1] += *(unsigned long long*)stripe_slot(stripes, g, 3, st);
-        for (int a = 0; a < 4; ++a) *(unsigned long long*)stripe_slot(stripes, g, a, st) = 0ull;
-      }
-    }
-    G->ke_acc += ke;
-    G->lost_energy += lost;
-    for (int s = 0; s < 2; ++s) {
-      G->absorbed[s] += ab[s];
-      G->dead[s] += ab[s];
-    }
-    if (G->status == PIC_OK) {
-      int st = PIC_OK;
-      if (G->nonfinite) st = PIC_ERR_NONFINITE;
-      else if (G->overflow) st = PIC_ERR_CAPACITY;
-      else if (G->emit_err) st = PIC_ERR_EMISSION;
-      if (st != PIC_OK) {
-        G->status = st;
-      } else {
-        // what this step appended: dp pairs (in place or converted), dph
-        // photons stored, de of which left the domain
-        const unsigned long long dp = G->pair_next, dph = G->n_ph_next - G->n_ph;
-        const unsigned long long de = G->esc_next;
-        const bool in_place = G->table_len == 0;
-        const long long done = G->step;
-        G->pairs_created += dp;
-        G->photons_emitted += in_place ? dp : dph;
-        G->photons_escaped += de;
-        if (!in_place) G->inflight = G->inflight + dph - de - dp;
-        if (de) G->lost_energy += (double)de * G->weight * G->gpair64;
-        if (done % G->diag_every == 0 && dp) G->ke_acc += (double)dp * 2.0 * G->weight * G->child_gamma64;
-        G->pushes = G->pushes + G->live[0] + G->live[1];
-        for (int s = 0; s < 2; ++s) {
-          G->n[s] += dp;
-          G->live[s] = G->n[s] - G->dead[s];
-        }
-        G->pair_next = 0;
-        G->esc_next = 0;
-        G->n_ph = G->n_ph_next;
-        G->step = done + 1;
-        if (done % G->diag_every == 0) {
-          pic_history_row r;
-          r.step = done;
-          r.n_minus = (int64_t)G->live[0];
-          r.n_plus = (int64_t)G->live[1];
-          r.n_photons = (int64_t)G->inflight;
-          r.pairs_created = (int64_t)G->pairs_created;
-          r.photons_emitted = (int64_t)G->photons_emitted;
-          r.photons_escaped = (int64_t)G->photons_escaped;
-          r.absorbed_minus = (int64_t)G->absorbed[0];
-          r.absorbed_plus = (int64_t)G->absorbed[1];
-          r.kinetic = G->ke_acc;
-          r.field = G->fe_acc;
-          r.photon_energy = (double)G->inflight * G->weight * G->gpair64;
-          r.lost_energy = G->lost_energy;
-          r.e_mean = G->es_acc / (double)G->n_cells;
-          G->hist[G->hist_count % (unsigned long long)G->hist_rows] = r;
-          G->hist_count = G->hist_count + 1;
-          G->last = r;
-        }
-      }
-    }
-    G->ke_acc = 0.0;
-    G->fe_acc = 0.0;
-    G->es_acc = 0.0;
-  }
+  for (int g = threadIdx.x; g < B; g += blockDim.x) finalize_gap(gaps + g);
   __syncthreads();
   compute_plans(gaps, B, wi, pwi, qwi);
 }
 
+// ------------------------------------------------------------------ fold
+// The striped push tallies of the step: 32 lanes sum the stripes of one
+// (gap, accumulator) pair, clear them, and add the sum to the descriptor
+// with one atomic (accumulators 0-1 are binary64 energies, 2-3 counts of
+// absorbed electrons and positrons).
+__device__ void fold_role(GapDev* __restrict__ gaps, int B, double* __restrict__ stripes, int vb) {
+  const int pair = vb * (kBlock / kStripes) + (int)threadIdx.x / kStripes;
+  const int st = (int)threadIdx.x % kStripes;
+  unsigned long long bits = 0;
+  if (pair < 4 * B) {
+    gptr<unsigned long long> slot = glb<unsigned long long>((void*)stripe_slot(stripes, pair >> 2, pair & 3, st));
+    bits = *slot;
+    *slot = 0ull;
+  }
+  double dv = __longlong_as_double((long long)bits);
+  unsigned long long uv = bits;
+#pragma unroll
+  for (int d = kStripes / 2; d >= 1; d >>= 1) {  // within each group of kStripes lanes
+    dv += __shfl_xor(dv, d, 64);
+    uv += __shfl_xor(uv, d, 64);
+  }
+  if (st != 0 || pair >= 4 * B) return;
+  GapDev* __restrict__ G = gaps + (pair >> 2);
+  switch (pair & 3) {
+    case 0: if (dv != 0.0) atomicAdd(&G->ke_acc, dv); break;
+    case 1: if (dv != 0.0) atomicAdd(&G->lost_energy, dv); break;
+    default:
+      if (uv) {
+        const int s = (pair & 3) - 2;
+        atomicAdd(&G->absorbed[s], uv);
+        atomicAdd(&G->dead[s], uv);
+      }
+  }
+}
+
 // Everything of a step between the push and the finalize: the Ampere update
-// (blocks [0, n_field)), the emission draws (next n_emit blocks) and the
-// conversions (last n_conv blocks) are independent of each other.
+// (blocks [0, n_field)), the emission draws (next n_emit blocks), the
+// conversions (next n_conv blocks) and the fold of the push tallies (the
+// rest) are independent of each other.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_post(GapDev* __restrict__ gaps,
                                                  const long long* __restrict__ cwi,
@@ -935,7 +1130,8 @@ __global__ __launch_bounds__(kBlock) void k_post(GapDev* __restrict__ gaps,
                                                  int n_field, int n_emit, int n_conv,
                                                  const int32_t* __restrict__ emit_cnt,
                                                  const uint32_t* __restrict__ emit_ent,
-                                                 const uint32_t* __restrict__ wg_emit) {
+                                                 const uint32_t* __restrict__ wg_emit,
+                                                 double* __restrict__ stripes) {
   __shared__ double s_red[8];
   __shared__ unsigned long long s_wave[kBlock / 64];
   __shared__ unsigned long long s_base[1];
@@ -947,15 +1143,16 @@ __global__ __launch_bounds__(kBlock) void k_post(GapDev* __restrict__ gaps,
   else if (b < n_field + n_emit)
     emit_role<T>(gaps, wi, B, emit_cnt, emit_ent, wg_emit, b - n_field, n_emit, s_pre, s_base, s_nb,
                  s_tmp);
-  else convert_role<T>(gaps, pwi, B, b - n_field - n_emit, n_conv, s_wave, s_base);
+  else if (b < n_field + n_emit + n_conv)
+    convert_role<T>(gaps, pwi, B, b - n_field - n_emit, n_conv, s_wave, s_base);
+  else fold_role(gaps, B, stripes, b - n_field - n_emit - n_conv);
 }
 
 __global__ __launch_bounds__(1024) void k_finalize(GapDev* __restrict__ gaps, int B,
                                                    long long* __restrict__ wi,
                                                    long long* __restrict__ pwi,
-                                                   long long* __restrict__ qwi,
-                                                   double* __restrict__ stripes) {
-  finalize_body(gaps, B, wi, pwi, qwi, stripes);
+                                                   long long* __restrict__ qwi) {
+  finalize_body(gaps, B, wi, pwi, qwi);
 }
 
 // ------------------------------------------------------------------ sort
@@ -1315,15 +1512,17 @@ hipError_t launch_push(const StepLaunch& L, bool mixed) {
 
 hipError_t launch_step_after_push(const StepLaunch& L, bool mixed) {
   const int nf = grid_for(L.cell_items, 1 << 30);
-  const int grid = nf + L.emit_grid + L.conv_grid;
+  const int nfold = (4 * L.B * kStripes + kBlock - 1) / kBlock;
+  const int grid = nf + L.emit_grid + L.conv_grid + nfold;
   if (mixed)
     hipLaunchKernelGGL(k_post<float>, dim3(grid), dim3(kBlock), 0, L.stream, L.gaps, L.cwi, L.wi,
-                       L.pwi, L.B, nf, L.emit_grid, L.conv_grid, L.emit_cnt, L.emit_ent, L.wg_emit);
+                       L.pwi, L.B, nf, L.emit_grid, L.conv_grid, L.emit_cnt, L.emit_ent, L.wg_emit,
+                       L.stripes);
   else
     hipLaunchKernelGGL(k_post<double>, dim3(grid), dim3(kBlock), 0, L.stream, L.gaps, L.cwi, L.wi,
-                       L.pwi, L.B, nf, L.emit_grid, L.conv_grid, L.emit_cnt, L.emit_ent, L.wg_emit);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, L.stream, L.gaps, L.B, L.wi, L.pwi, L.qwi,
-                     L.stripes);
+                       L.pwi, L.B, nf, L.emit_grid, L.conv_grid, L.emit_cnt, L.emit_ent, L.wg_emit,
+                       L.stripes);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, L.stream, L.gaps, L.B, L.wi, L.pwi, L.qwi);
   return hipGetLastError();
 }
 
