@@ -1189,10 +1189,9 @@ __global__ __launch_bounds__(kBlock) void k_sort_zero(GapDev* __restrict__ gaps,
 // other buffer.  A chunk whose cells span at most kSortTile counts in an LDS
 // histogram first and touches each global bucket once; wider chunks (leptons
 // appended since the last sort) use one global atomic per run of equal cells.
-template <int PASS>
+template <int PASS, typename T>
 __global__ __launch_bounds__(kBlock) void k_sort_pass(GapDev* __restrict__ gaps,
-                                                      const long long* __restrict__ wi, int B,
-                                                      int elem_bytes) {
+                                                      const long long* __restrict__ wi, int B) {
   __shared__ int32_t s_hist[kSortTile];
   __shared__ int s_red[8];
   const long long total = wi[B];
@@ -1212,14 +1211,27 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(GapDev* __restrict__ gaps,
     const long long i1 = i0 + kChunk < nS ? i0 + kChunk : nS;
     gptr<int32_t> cnt = glb(G->sort_cnt[s]);
     gptr<const int32_t> cin = glb<const int32_t>((void*)G->cell[buf][s]);
+    // the whole lepton state is requested at once (slots past the end read
+    // slot 0 and are discarded), before any store of this chunk
     int cvs[kItems];
-    int mn = INT32_MAX, mx = INT32_MIN;
+    T ov[kItems], pv[kItems];
+    uint64_t idv[kItems];
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
       const long long i = i0 + threadIdx.x + (long long)j * kBlock;
-      cvs[j] = i < i1 ? cin[i] : kDead;
-      if (cvs[j] != kDead) { mn = min(mn, cvs[j]); mx = max(mx, cvs[j]); }
+      const long long ii = i < i1 ? i : 0;
+      const int cv = cin[ii];
+      if (PASS == 1) {
+        ov[j] = glb<const T>(G->off[buf][s])[ii];
+        pv[j] = glb<const T>(G->p[buf][s])[ii];
+        idv[j] = glb<const uint64_t>((void*)G->id[buf][s])[ii];
+      }
+      cvs[j] = i < i1 ? cv : kDead;
     }
+    int mn = INT32_MAX, mx = INT32_MIN;
+#pragma unroll
+    for (int j = 0; j < kItems; ++j)
+      if (cvs[j] != kDead) { mn = min(mn, cvs[j]); mx = max(mx, cvs[j]); }
     block_minmax(mn, mx, s_red);
     if (mx < mn) continue;  // no live lepton in this chunk (uniform)
     long long dst[kItems];
@@ -1263,23 +1275,17 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(GapDev* __restrict__ gaps,
     }
     const int nb = buf ^ 1;
     gptr<int32_t> cout = glb(G->cell[nb][s]);
-    gptr<const uint64_t> iin = glb<const uint64_t>((void*)G->id[buf][s]);
+    gptr<T> oout = glb<T>(G->off[nb][s]);
+    gptr<T> pout = glb<T>(G->p[nb][s]);
     gptr<uint64_t> iout = glb(G->id[nb][s]);
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
-      const long long i = i0 + threadIdx.x + (long long)j * kBlock;
-      const int cv = cvs[j];
-      if (cv == kDead) continue;
+      if (cvs[j] == kDead) continue;
       const long long d = dst[j];
-      cout[d] = cv;
-      iout[d] = iin[i];
-      if (elem_bytes == 8) {
-        glb<double>(G->off[nb][s])[d] = glb<const double>(G->off[buf][s])[i];
-        glb<double>(G->p[nb][s])[d] = glb<const double>(G->p[buf][s])[i];
-      } else {
-        glb<float>(G->off[nb][s])[d] = glb<const float>(G->off[buf][s])[i];
-        glb<float>(G->p[nb][s])[d] = glb<const float>(G->p[buf][s])[i];
-      }
+      cout[d] = cvs[j];
+      oout[d] = ov[j];
+      pout[d] = pv[j];
+      iout[d] = idv[j];
     }
   }
 }
@@ -1533,14 +1539,15 @@ hipError_t launch_step(const StepLaunch& L, bool mixed) {
 }
 
 hipError_t launch_sort(const StepLaunch& L, bool mixed) {
-  const int eb = mixed ? 4 : 8;
   hipLaunchKernelGGL(k_sort_zero, dim3(grid_for(L.cell_items, 1 << 30)), dim3(kBlock), 0, L.stream, L.gaps, L.cwi, L.B);
   hipLaunchKernelGGL(k_ph_zero, dim3(L.B), dim3(kBlock), 0, L.stream, L.gaps, L.B);
-  hipLaunchKernelGGL(k_sort_pass<0>, dim3(L.push_grid), dim3(kBlock), 0, L.stream, L.gaps, L.wi, L.B, eb);
+  if (mixed) hipLaunchKernelGGL((k_sort_pass<0, float>), dim3(L.push_grid), dim3(kBlock), 0, L.stream, L.gaps, L.wi, L.B);
+  else hipLaunchKernelGGL((k_sort_pass<0, double>), dim3(L.push_grid), dim3(kBlock), 0, L.stream, L.gaps, L.wi, L.B);
   hipLaunchKernelGGL(k_ph_pass<0>, dim3(L.ph_sort_grid), dim3(kBlock), 0, L.stream, L.gaps, L.qwi, L.B);
   hipLaunchKernelGGL(k_sort_scan, dim3(2 * L.B), dim3(1024), 0, L.stream, L.gaps, L.B);
   hipLaunchKernelGGL(k_ph_scan, dim3(L.B), dim3(1024), 0, L.stream, L.gaps, L.B);
-  hipLaunchKernelGGL(k_sort_pass<1>, dim3(L.push_grid), dim3(kBlock), 0, L.stream, L.gaps, L.wi, L.B, eb);
+  if (mixed) hipLaunchKernelGGL((k_sort_pass<1, float>), dim3(L.push_grid), dim3(kBlock), 0, L.stream, L.gaps, L.wi, L.B);
+  else hipLaunchKernelGGL((k_sort_pass<1, double>), dim3(L.push_grid), dim3(kBlock), 0, L.stream, L.gaps, L.wi, L.B);
   hipLaunchKernelGGL(k_ph_pass<1>, dim3(L.ph_sort_grid), dim3(kBlock), 0, L.stream, L.gaps, L.qwi, L.B);
   hipLaunchKernelGGL(k_sort_finish, dim3(1), dim3(1024), 0, L.stream, L.gaps, L.B, L.wi, L.pwi, L.qwi);
   return hipGetLastError();
