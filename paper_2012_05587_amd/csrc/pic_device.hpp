@@ -79,6 +79,7 @@ struct GapDev {
   double gpair64, child_gamma64;     // binary64 pair energy; child gamma in the particle precision
   uint64_t seed;
   double* E;
+  float* Ef;  // E rounded to binary32 (read by the binary32 push; same values as (float)E)
   long long* F;
   long long* F_last;
   long long* rho_acc;

@@ -120,17 +120,29 @@ __device__ __forceinline__ void flush_tally(double* __restrict__ stripes, int g,
 }
 
 // E at the cells left of, at and right of cell cl (a dead slot reads cell 0),
-// with the boundary ghosts of the gather.
+// with the boundary ghosts of the gather.  The binary32 push reads the
+// binary32 copy of E (the same values as rounding E), binary64 reads E.
 template <typename T>
-__device__ __forceinline__ void load_e3(gptr<const double> E, int cl, bool periodic, int nc, T& em,
-                                        T& ec, T& ep) {
+struct ESrc;
+template <>
+struct ESrc<float> {
+  static __device__ __forceinline__ gptr<const float> of(const GapDev* G) { return glb<const float>((void*)G->Ef); }
+};
+template <>
+struct ESrc<double> {
+  static __device__ __forceinline__ gptr<const double> of(const GapDev* G) { return glb<const double>((void*)G->E); }
+};
+
+template <typename T>
+__device__ __forceinline__ void load_e3(gptr<const T> E, int cl, bool periodic, int nc, T& em, T& ec,
+                                        T& ep) {
   const int c = cl == kDead ? 0 : cl;
   int cm = c - 1, cp = c + 1;
   if (periodic) { cm = cm < 0 ? nc - 1 : cm; cp = cp >= nc ? 0 : cp; }
   else { cm = cm < 0 ? 0 : cm; cp = cp >= nc ? nc - 1 : cp; }
-  em = (T)E[cm];
-  ec = (T)E[c];
-  ep = (T)E[cp];
+  em = E[cm];
+  ec = E[c];
+  ep = E[cp];
 }
 
 // Lepton range of work item w of gap G: species s, indices [i0, i1).
@@ -185,7 +197,7 @@ __global__ __launch_bounds__(kBlock, PushCfg<T>::waves) void k_push(GapDev* __re
   int nc = 0;
   gptr<int32_t> cellS[2] = {nullptr, nullptr};
   gptr<T> offS[2] = {nullptr, nullptr}, pS[2] = {nullptr, nullptr};
-  gptr<const double> E = nullptr;
+  gptr<const T> E = nullptr;
   gptr<unsigned long long> F = nullptr;
   I ONE = 0;
   T scale = 0, inv_scale = 0, dt_t = 0, dtdx = 0, gthr = 0, gpair = 0;
@@ -215,7 +227,7 @@ __global__ __launch_bounds__(kBlock, PushCfg<T>::waves) void k_push(GapDev* __re
         offS[sp] = glb<T>(G->off[buf][sp]);
         pS[sp] = glb<T>(G->p[buf][sp]);
       }
-      E = glb<const double>(G->E);
+      E = ESrc<T>::of(G);
       F = glb<unsigned long long>((void*)G->F);
       nc = G->n_cells;
       periodic = G->boundary == PIC_BC_PERIODIC;
@@ -714,6 +726,7 @@ __device__ void field_role(GapDev* __restrict__ gaps, const long long* __restric
     const long long f = G->F[c];
     const double e = G->E[c] - wq * (double)f;
     G->E[c] = e;
+    G->Ef[c] = (float)e;
     G->F_last[c] = f;
     G->F[c] = 0;
     fe += e * e * dxh * 0.5;

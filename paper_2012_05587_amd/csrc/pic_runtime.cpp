@@ -29,7 +29,7 @@ constexpr int kDefaultHist = 4096;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct GapLayout {
-  size_t E, F, F_last, rho, table, sort_cnt[2], hist;
+  size_t E, Ef, F, F_last, rho, table, sort_cnt[2], hist;
   size_t cell[2][2], off[2][2], p[2][2], id[2][2];
   size_t ph_x[2], ph_step[2], ph_child[2];
   size_t ph_bucket;
@@ -132,6 +132,7 @@ Layout make_layout(const pic_gap_params* prm, int B) {
     GapLayout& G = L.g[(size_t)i];
     const size_t nc = (size_t)p.n_cells, cap = (size_t)p.capacity, pc = (size_t)p.photon_capacity;
     G.E = o; o = align_up(o + 8 * nc);
+    G.Ef = o; o = align_up(o + 4 * nc);
     G.F = o; o = align_up(o + 8 * nc);
     G.F_last = o; o = align_up(o + 8 * nc);
     G.rho = o; o = align_up(o + 8 * (nc + 1));
@@ -289,6 +290,7 @@ pic_status create_batch(const pic_gap_params* params, int n_gaps, void* d_ws, si
     if (p.precision == PIC_MIXED) fill_precision_constants<float>(G, p);
     else fill_precision_constants<double>(G, p);
     G.E = reinterpret_cast<double*>(ws + GL.E);
+    G.Ef = reinterpret_cast<float*>(ws + GL.Ef);
     G.F = reinterpret_cast<long long*>(ws + GL.F);
     G.F_last = reinterpret_cast<long long*>(ws + GL.F_last);
     G.rho_acc = reinterpret_cast<long long*>(ws + GL.rho);
@@ -314,6 +316,9 @@ pic_status create_batch(const pic_gap_params* params, int n_gaps, void* d_ws, si
     // initial field and zeroed flux; conversion table
     std::vector<double> E((size_t)p.n_cells, p.e0);
     if (hipMemcpy(G.E, E.data(), 8 * (size_t)p.n_cells, hipMemcpyHostToDevice) != hipSuccess) st = PIC_ERR_DEVICE;
+    const std::vector<float> Ef((size_t)p.n_cells, (float)p.e0);
+    if (st == PIC_OK && hipMemcpy(G.Ef, Ef.data(), 4 * (size_t)p.n_cells, hipMemcpyHostToDevice) != hipSuccess)
+      st = PIC_ERR_DEVICE;
     std::vector<long long> z((size_t)p.n_cells + 1, 0);
     if (st == PIC_OK && hipMemcpy(G.F, z.data(), 8 * (size_t)p.n_cells, hipMemcpyHostToDevice) != hipSuccess) st = PIC_ERR_DEVICE;
     if (st == PIC_OK && hipMemcpy(G.F_last, z.data(), 8 * (size_t)p.n_cells, hipMemcpyHostToDevice) != hipSuccess) st = PIC_ERR_DEVICE;
@@ -793,6 +798,9 @@ pic_status pic_set_fields(pic_gap* g, const double* E, int32_t n_cells) {
   pic_status st = read_desc(b, g->idx, &G);
   if (st != PIC_OK) return st;
   if (hipMemcpy(G.E, E, 8 * (size_t)n_cells, hipMemcpyHostToDevice) != hipSuccess) return PIC_ERR_DEVICE;
+  std::vector<float> Ef((size_t)n_cells);
+  for (int32_t c = 0; c < n_cells; ++c) Ef[(size_t)c] = (float)E[c];
+  if (hipMemcpy(G.Ef, Ef.data(), 4 * (size_t)n_cells, hipMemcpyHostToDevice) != hipSuccess) return PIC_ERR_DEVICE;
   return PIC_OK;
 }
 
