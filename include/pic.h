@@ -81,13 +81,21 @@ enum { PIC_ELECTRON = 0, PIC_POSITRON = 1 };
  *  l_gamma   mean photon path in cells before conversion; 0 makes the pair
  *            in place, as in the paper's model.
  *  weight    macro-particle weight w >= 0 (w = 0 gives test particles).
- *  capacity, photon_capacity  slots per species / in the photon store.
+ *  capacity, photon_capacity  slots per species / in the photon store.  A
+ *            step whose appends do not fit freezes the gap (the state of
+ *            the last completed step stays readable).  Slots of absorbed
+ *            leptons and converted photons are reused only after the next
+ *            re-sort, so with absorbing walls the step at which a gap
+ *            freezes can depend on sort_every.
  *  seed      key of the Philox4x64-10 streams of this gap.
  *  precision PIC_FP64: per-particle arithmetic in binary64, offsets on a
  *            2^-40 cell grid.  PIC_MIXED: binary32 push, offset (2^-24 grid)
  *            and momentum; the current, E and all diagnostics stay exact
  *            integer or binary64.
- *  sort_every   steps between particle re-sorts (0 = 20).
+ *  sort_every   steps between particle re-sorts; 0 lets the library choose
+ *               it while running (see pic_batch_tuning).  The cadence
+ *               changes cost only: results do not depend on it while no
+ *               gap runs out of slots.
  *  diag_every   steps between history rows (0 = 1).
  *  history_rows rows kept in the device history ring (0 = 4096).       */
 typedef struct {
@@ -252,6 +260,18 @@ pic_status pic_destroy_batch(pic_batch* b);
 /* Kernel timing of a batch, as pic_profile_push / pic_read_push_time. */
 pic_status pic_batch_profile_push(pic_batch* b, int32_t enable);
 pic_status pic_batch_read_push_time(pic_batch* b, double* ms, int64_t* launches);
+/* Re-sort cadence.  The sort is not part of the paper's method: it only
+ * reorders leptons for memory locality.  With sort_every = 0 the library times every
+ * replayed graph of S steps plus the sort, S in {5, 10, 20, 40, 80}, and
+ * every 16 replays probes half and twice the current S, switching when the
+ * challenger is more than 3% faster per step.  Synchronises the stream.
+ * Outputs (each may be NULL): the cadence in use, whether it is tuned, the
+ * number of timed replays and of switches so far. */
+pic_status pic_batch_tuning(pic_batch* b, int32_t* sort_every, int32_t* autotuned,
+                            int64_t* replays, int32_t* switches);
+/* The same for a single gap. */
+pic_status pic_tuning(pic_gap* g, int32_t* sort_every, int32_t* autotuned, int64_t* replays,
+                      int32_t* switches);
 
 #ifdef __cplusplus
 }

@@ -31,8 +31,15 @@ EXPORTS = [
     "pic_offset_bits", "pic_destroy", "pic_status_string", "pic_batch_plan",
     "pic_batch_workspace_bytes", "pic_create_batch", "pic_batch_step_n", "pic_batch_gap",
     "pic_batch_size", "pic_destroy_batch", "pic_profile_push", "pic_read_push_time",
-    "pic_batch_profile_push", "pic_batch_read_push_time",
+    "pic_batch_profile_push", "pic_batch_read_push_time", "pic_batch_tuning", "pic_tuning",
 ]
+
+
+def _tuning(name, h):
+    """Re-sort cadence in use: dict(sort_every, autotuned, replays, switches)."""
+    se, au, rp, sw = C.c_int32(), C.c_int32(), C.c_int64(), C.c_int32()
+    _check(name, getattr(lib(), name)(h, C.byref(se), C.byref(au), C.byref(rp), C.byref(sw)))
+    return dict(sort_every=se.value, autotuned=bool(au.value), replays=rp.value, switches=sw.value)
 
 
 class GapParams(C.Structure):
@@ -116,6 +123,8 @@ def lib():
         getattr(L, name).argtypes = [vp, i32]; getattr(L, name).restype = i32
     for name in ("pic_read_push_time", "pic_batch_read_push_time"):
         getattr(L, name).argtypes = [vp, P(dbl), P(i64)]; getattr(L, name).restype = i32
+    for name in ("pic_tuning", "pic_batch_tuning"):
+        getattr(L, name).argtypes = [vp, P(i32), P(i32), P(i64), P(i32)]; getattr(L, name).restype = i32
     _lib = L
     return L
 
@@ -269,6 +278,9 @@ class Gap(_GapView):
         _check("pic_read_push_time", lib().pic_read_push_time(self._h, C.byref(ms), C.byref(n)))
         return ms.value, n.value
 
+    def tuning(self):
+        return _tuning("pic_tuning", self._h)
+
     def close(self):
         """Frees the handle and drops this object's reference to the workspace."""
         if self._h:
@@ -316,6 +328,9 @@ class Batch:
         _check("pic_batch_read_push_time",
                lib().pic_batch_read_push_time(self._h, C.byref(ms), C.byref(n)))
         return ms.value, n.value
+
+    def tuning(self):
+        return _tuning("pic_batch_tuning", self._h)
 
     def close(self):
         """Frees the handle and drops this object's reference to the workspace;

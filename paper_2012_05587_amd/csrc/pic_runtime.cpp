@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <deque>
 #include <new>
 #include <vector>
 
@@ -181,9 +182,44 @@ struct pic_gap {
   bool standalone;
 };
 
+// Online choice of the re-sort cadence (sort_every = 0).  Sorting never
+// changes results, only cost: sorting often costs sort passes, sorting
+// rarely lets chunks spread over more cells and leaves appended leptons
+// unsorted longer.  Each candidate cadence S has its own captured graph (S
+// steps and the sort); every replay is timed with events that are read
+// without blocking.  Periods of kTunePeriod replays start with a probe
+// (current, challenger, current, challenger), the challenger alternating
+// between half and twice the current cadence; comparing it with the replays
+// beside it cancels the growth of the cascade, and a challenger faster per
+// step by more than kTuneGain becomes the cadence.
+constexpr int kTuneCand[] = {5, 10, 20, 40, 80};
+constexpr int kTuneN = 5;
+constexpr int kTuneStart = 2;  // 20 steps
+constexpr int kTunePeriod = 16;
+constexpr double kTuneGain = 0.03;
+
+struct Tuner {
+  bool on = false;
+  int cur = kTuneStart;
+  int round = 0;            // probe rounds opened
+  long long launches = 0;   // replays since tuning started
+  int probe_ch = -1;        // challenger of the open round (-1: none)
+  int got = 0;              // records of the open round read so far
+  bool closed = true;
+  double probe_cur = 0.0, probe_chal = 0.0;  // summed ms per step
+  int switches = 0;
+  struct Rec { hipEvent_t a, b; int ci; int round; };  // round -1: not a probe
+  std::deque<Rec> pending;
+  std::vector<hipEvent_t> spare;
+};
+
 struct pic_batch {
   int B = 0;
   int precision = 0, sort_every = kDefaultSort, diag_every = 1, hist_rows = kDefaultHist;
+  Tuner tune;
+  hipGraphExec_t tgraph[kTuneN] = {};
+  hipGraph_t ttmpl[kTuneN] = {};
+  long long since_sort = 0;  // steps enqueued since the last re-sort
   hipStream_t stream = nullptr;
   char* ws = nullptr;
   size_t ws_bytes = 0;
@@ -249,6 +285,7 @@ pic_status create_batch(const pic_gap_params* params, int n_gaps, void* d_ws, si
   b->B = n_gaps;
   b->precision = params[0].precision;
   b->sort_every = params[0].sort_every > 0 ? params[0].sort_every : kDefaultSort;
+  b->tune.on = params[0].sort_every == 0;
   b->diag_every = params[0].diag_every > 0 ? params[0].diag_every : 1;
   b->hist_rows = hist_rows_of(params[0]);
   b->stream = reinterpret_cast<hipStream_t>(hip_stream);
@@ -420,19 +457,22 @@ pic_status eager_step(pic_batch* b) {
     return PIC_ERR_DEVICE;
   }
   b->host_step += 1;
-  if (b->host_step % b->sort_every == 0)
+  b->since_sort += 1;
+  if (b->since_sort >= b->sort_every) {
     if (pic::launch_sort(b->launch, mixed) != hipSuccess) return PIC_ERR_DEVICE;
+    b->since_sort = 0;
+  }
   return PIC_OK;
 }
 
 // Captures sort_every steps and the re-sort that ends them as one graph.
 // Every kernel reads its counts and plans from device memory, so the graph
 // can be replayed at any step that is a multiple of sort_every.
-bool build_graph(pic_batch* b) {
+bool build_graph(pic_batch* b, int S, hipGraph_t* tmpl, hipGraphExec_t* exec) {
   const bool mixed = b->precision == PIC_MIXED;
   if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeRelaxed) != hipSuccess) return false;
   bool ok = true;
-  for (int k = 0; k < b->sort_every && ok; ++k) ok = pic::launch_step(b->launch, mixed) == hipSuccess;
+  for (int k = 0; k < S && ok; ++k) ok = pic::launch_step(b->launch, mixed) == hipSuccess;
   if (ok) ok = pic::launch_sort(b->launch, mixed) == hipSuccess;
   hipGraph_t g = nullptr;
   const hipError_t e = hipStreamEndCapture(b->stream, &g);
@@ -447,17 +487,103 @@ bool build_graph(pic_batch* b) {
     (void)hipGetLastError();
     return false;
   }
-  b->graph_tmpl = g;
-  b->graph = x;
+  *tmpl = g;
+  *exec = x;
   return true;
+}
+
+// ---- cadence tuner
+hipEvent_t tune_event(Tuner& t) {
+  if (!t.spare.empty()) {
+    hipEvent_t e = t.spare.back();
+    t.spare.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Reads the timed replays that have completed (never blocks); the open
+// round is decided once its four records are in (records of an earlier,
+// abandoned round are dropped).
+void tune_harvest(Tuner& t) {
+  while (!t.pending.empty()) {
+    Tuner::Rec r = t.pending.front();
+    if (hipEventQuery(r.b) != hipSuccess) break;
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, r.a, r.b);
+    t.pending.pop_front();
+    t.spare.push_back(r.a);
+    t.spare.push_back(r.b);
+    if (r.round != t.round || t.closed) continue;
+    const double per_step = (double)ms / (double)kTuneCand[r.ci];
+    if (r.ci == t.probe_ch) t.probe_chal += per_step;
+    else t.probe_cur += per_step;
+    if (++t.got == 4) {
+      if (t.probe_chal < (1.0 - kTuneGain) * t.probe_cur) {
+        t.cur = t.probe_ch;
+        t.switches += 1;
+      }
+      t.closed = true;
+    }
+  }
+}
+
+// Candidate for the next replay; `round` is the probe round it belongs to
+// (-1 outside probes).  A round opens at the start of every period.
+int tune_pick(Tuner& t, int& round) {
+  const long long pos = t.launches % kTunePeriod;
+  round = -1;
+  if (pos == 0) {
+    const int dir = (t.round & 1) ? 1 : -1;
+    int ch = t.cur + dir;
+    if (ch < 0 || ch >= kTuneN) ch = t.cur - dir;
+    t.round += 1;
+    t.probe_ch = (ch >= 0 && ch < kTuneN) ? ch : -1;
+    t.got = 0;
+    t.closed = t.probe_ch < 0;
+    t.probe_cur = t.probe_chal = 0.0;
+  }
+  if (!t.closed && pos < 4) {
+    round = t.round;
+    return (pos & 1) ? t.probe_ch : t.cur;
+  }
+  return t.cur;
 }
 
 pic_status enqueue_steps(pic_batch* b, int64_t n_steps) {
   // graphs need a capturable (non-null) stream and no per-launch events
   const bool graphs = b->stream != nullptr && !b->profiling && !b->graph_failed;
+  Tuner& t = b->tune;
   while (n_steps > 0) {
-    if (graphs && b->host_step % b->sort_every == 0 && n_steps >= b->sort_every) {
-      if (!b->graph && !build_graph(b)) {
+    if (graphs && t.on && b->since_sort == 0) {
+      tune_harvest(t);
+      int round = -1;
+      const int ci = tune_pick(t, round);
+      const int S = kTuneCand[ci];
+      if (n_steps >= S) {
+        if (!b->tgraph[ci] && !build_graph(b, S, &b->ttmpl[ci], &b->tgraph[ci])) {
+          b->graph_failed = true;
+          return enqueue_steps(b, n_steps);
+        }
+        hipEvent_t e0 = tune_event(t), e1 = tune_event(t);
+        if (!e0 || !e1) return PIC_ERR_DEVICE;
+        if (hipEventRecord(e0, b->stream) != hipSuccess) return PIC_ERR_DEVICE;
+        if (hipGraphLaunch(b->tgraph[ci], b->stream) != hipSuccess) return PIC_ERR_DEVICE;
+        if (hipEventRecord(e1, b->stream) != hipSuccess) return PIC_ERR_DEVICE;
+        t.pending.push_back(Tuner::Rec{e0, e1, ci, round});
+        t.launches += 1;
+        b->sort_every = S;  // eager steps that follow keep this cadence
+        b->host_step += S;
+        n_steps -= S;
+        continue;
+      }
+      // fewer steps left than the cadence: finish them eagerly at this cadence
+      b->sort_every = S;
+    }
+    if (graphs && !t.on && b->since_sort == 0 && n_steps >= b->sort_every) {
+      if (!b->graph && !build_graph(b, b->sort_every, &b->graph_tmpl, &b->graph)) {
         b->graph_failed = true;
         return enqueue_steps(b, n_steps);
       }
@@ -815,7 +941,13 @@ pic_status pic_destroy_batch(pic_batch* b) {
   pic_status st = hipStreamSynchronize(b->stream) == hipSuccess ? PIC_OK : PIC_ERR_DEVICE;
   if (b->graph) (void)hipGraphExecDestroy(b->graph);
   if (b->graph_tmpl) (void)hipGraphDestroy(b->graph_tmpl);
+  for (int i = 0; i < kTuneN; ++i) {
+    if (b->tgraph[i]) (void)hipGraphExecDestroy(b->tgraph[i]);
+    if (b->ttmpl[i]) (void)hipGraphDestroy(b->ttmpl[i]);
+  }
   for (hipEvent_t e : b->ev) (void)hipEventDestroy(e);
+  for (const Tuner::Rec& r : b->tune.pending) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+  for (hipEvent_t e : b->tune.spare) (void)hipEventDestroy(e);
   delete b;
   return st;
 }
@@ -831,6 +963,24 @@ pic_status pic_batch_profile_push(pic_batch* b, int32_t enable) {
   b->prof_ms = 0.0;
   b->prof_launches = 0;
   return PIC_OK;
+}
+
+pic_status pic_batch_tuning(pic_batch* b, int32_t* sort_every, int32_t* autotuned,
+                            int64_t* replays, int32_t* switches) {
+  if (!b) return PIC_ERR_ARG;
+  if (hipStreamSynchronize(b->stream) != hipSuccess) return PIC_ERR_DEVICE;
+  tune_harvest(b->tune);
+  if (sort_every) *sort_every = b->tune.on ? kTuneCand[b->tune.cur] : b->sort_every;
+  if (autotuned) *autotuned = b->tune.on ? 1 : 0;
+  if (replays) *replays = b->tune.launches;
+  if (switches) *switches = b->tune.switches;
+  return PIC_OK;
+}
+
+pic_status pic_tuning(pic_gap* g, int32_t* sort_every, int32_t* autotuned, int64_t* replays,
+                      int32_t* switches) {
+  if (!g) return PIC_ERR_ARG;
+  return pic_batch_tuning(g->b, sort_every, autotuned, replays, switches);
 }
 
 pic_status pic_batch_read_push_time(pic_batch* b, double* ms, int64_t* launches) {

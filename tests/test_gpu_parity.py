@@ -94,6 +94,17 @@ def test_c3_mixed_gap_full_run():
     print("p err", stats, "E err", err, "E bitwise", exact)
 
 
+def test_config5_physics_reduced():
+    """Configuration 5's physics (E0 = 1000, gamma_thr = 500, l_gamma = 200,
+    mixed precision) at its seed density on 512 cells, through screening
+    (about step 100) and 200 steps beyond, against the oracle."""
+    cfg = workloads.scaled("c5_large_mixed", n_cells=512, n_pairs=128, capacity=4_000_000,
+                           photon_capacity=4_000_000)
+    gg, go = _run_pair(cfg, 300)
+    stats, err, exact = _check_all(gg, go, cfg["precision"])
+    print("p err", stats, "E err", err, "E bitwise", exact)
+
+
 @pytest.mark.parametrize("precision", [workloads.FP64, workloads.MIXED])
 def test_in_place_pairs_periodic(precision):
     """The paper's own model: pairs made in place, periodic domain."""
@@ -172,6 +183,35 @@ def test_graph_replay_matches_eager_and_oracle(precision):
     pc.compare_history(gg.read_history(), go.history())
     pc.compare_particles(gg, go, PTOL[precision])
     pc.compare_fields(gg, go)
+
+
+@pytest.mark.parametrize("precision", [workloads.FP64, workloads.MIXED])
+def test_autotuned_sort_cadence_matches_fixed(precision):
+    """With sort_every = 0 the library times its graph replays and changes
+    the re-sort cadence as it runs; the state must stay exactly that of a
+    fixed cadence, and the tuner must report a cadence it can use."""
+    import torch
+    cfg = workloads.config("c1_fp64_reference_gap")
+    cfg.update(precision=precision, history_rows=1300)
+    side = torch.cuda.Stream()
+    gt = pc.make_gpu(cfg, stream=side, sort_every=0)
+    gf = pc.make_gpu(cfg, sort_every=20)
+    for n in (800, 37, 400):
+        gt.step_n(n)
+        gf.step_n(n)
+    ht, hf = gt.read_history(), gf.read_history()
+    for k in pc.HIST_INT:
+        assert np.array_equal(ht[k], hf[k]), k
+    for s in (0, 1):
+        a, b = pc.by_id(gt.read_particles(s)), pc.by_id(gf.read_particles(s))
+        for k in ("id", "cell", "off", "p"):
+            assert np.array_equal(a[k], b[k]), (s, k)
+    assert np.array_equal(gt.read_fields(rho=False)["E"], gf.read_fields(rho=False)["E"])
+    t = gt.tuning()
+    assert t["autotuned"] and t["sort_every"] in (5, 10, 20, 40, 80), t
+    assert t["replays"] >= 16, t
+    f = gf.tuning()
+    assert not f["autotuned"] and f["sort_every"] == 20, f
 
 
 def test_run_twice_is_bitwise_identical():
