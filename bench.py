@@ -362,6 +362,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--workload", default="c4_batched",
                     choices=["c4_batched"] + sorted(workloads.CONFIGS))
+    ap.add_argument("--sort-every", type=int, default=None,
+                    help="re-sort cadence for every gap (0 = tuned while running; default: the workload's)")
     ap.add_argument("--cpu-gaps", type=int, default=32)
     ap.add_argument("--cpu-steps", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true")
@@ -401,6 +403,8 @@ def main():
         return
 
     gaps = _workload(args.workload)
+    if args.sort_every is not None:
+        gaps = [dict(c, sort_every=args.sort_every) for c in gaps]
     prec = gaps[0]["precision"]
     steps = args.steps if args.steps is not None else DEFAULT_STEPS.get(args.workload, gaps[0]["steps"])
 

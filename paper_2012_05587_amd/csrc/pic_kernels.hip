@@ -161,6 +161,9 @@ __device__ __forceinline__ void push_item(long long local, long long chunks0, lo
 // atomic per touched cell.  Chunks spread over more than kTile cells (the
 // sparse early cascade, unsorted appended leptons) add to the grid directly.
 //
+// The lepton arrays are streamed once per step, so their loads and stores
+// are non-temporal and leave the caches to E and the grid.
+//
 // Loads are issued in phases (all lepton state of a chunk, then all its E
 // values) so that each phase waits once.  In binary32 the loop is also
 // software-pipelined: the lepton state of the next chunk of the same gap is
@@ -256,8 +259,8 @@ __global__ __launch_bounds__(kBlock, PushCfg<T>::waves) void k_push(GapDev* __re
       for (int j = 0; j < kItems; ++j) {
         const long long i = i0 + tid + (long long)j * kBlock;
         const long long ii = i < i1 ? i : 0;
-        const int cv = cellA[ii];
-        const T ovv = offA[ii], pvv = pA[ii];
+        const int cv = __builtin_nontemporal_load(&cellA[ii]);
+        const T ovv = __builtin_nontemporal_load(&offA[ii]), pvv = __builtin_nontemporal_load(&pA[ii]);
         cl[j] = i < i1 ? cv : kDead;
         ov[j] = i < i1 ? ovv : (T)0;
         pv[j] = i < i1 ? pvv : (T)0;
@@ -293,8 +296,8 @@ __global__ __launch_bounds__(kBlock, PushCfg<T>::waves) void k_push(GapDev* __re
       for (int j = 0; j < kItems; ++j) {
         const long long i = j0 + tid + (long long)j * kBlock;
         const long long ii = i < j1 ? i : 0;
-        const int cv = c2A[ii];
-        const T ovv = o2A[ii], pvv = p2A[ii];
+        const int cv = __builtin_nontemporal_load(&c2A[ii]);
+        const T ovv = __builtin_nontemporal_load(&o2A[ii]), pvv = __builtin_nontemporal_load(&p2A[ii]);
         cln[j] = i < j1 ? cv : kDead;
         ovn[j] = i < j1 ? ovv : (T)0;
         pvn[j] = i < j1 ? pvv : (T)0;
@@ -384,9 +387,9 @@ __global__ __launch_bounds__(kBlock, PushCfg<T>::waves) void k_push(GapDev* __re
             atomicAdd(&s_emit_k, k);
             s_emit[pos] = ((uint32_t)(i - i0) << 8) | (uint32_t)k;
           }
-          pA[i] = pn;
-          offA[i] = (T)nq * inv_scale;
-          if (c2 != c) cellA[i] = c2;
+          __builtin_nontemporal_store(pn, &pA[i]);
+          __builtin_nontemporal_store((T)nq * inv_scale, &offA[i]);
+          if (c2 != c) __builtin_nontemporal_store(c2, &cellA[i]);
           // energy: the Lorentz factor in the particle precision, summed in binary64
           if (diag) tally.ke += w_d * (double)gnew;
         } else {
