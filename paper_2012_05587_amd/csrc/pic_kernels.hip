@@ -86,6 +86,25 @@ __device__ __forceinline__ void block_minmax(int& mn, int& mx, int* s_red) {
   mx = max(max(s_red[4], s_red[5]), max(s_red[6], s_red[7]));
 }
 
+// Block-wide min and max of ints for a loop that calls it once per
+// iteration: the scratch is double-buffered by iteration parity, so only
+// one barrier is needed (the one between two uses of a buffer is the
+// barrier of the call in between).
+__device__ __forceinline__ void block_minmax_pp(int& mn, int& mx, int (*s_red)[8], int& parity) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    mn = min(mn, __shfl_xor(mn, d, 64));
+    mx = max(mx, __shfl_xor(mx, d, 64));
+  }
+  int* r = s_red[parity];
+  parity ^= 1;
+  const int w = threadIdx.x >> 6;
+  if (lane_id() == 0) { r[w] = mn; r[4 + w] = mx; }
+  __syncthreads();
+  mn = min(min(r[0], r[1]), min(r[2], r[3]));
+  mx = max(max(r[4], r[5]), max(r[6], r[7]));
+}
+
 // ------------------------------------------------------------------ push
 // Sums of one workgroup over the work items of one gap, flushed with one
 // atomic each when the workgroup moves to another gap or finishes.
@@ -180,10 +199,16 @@ __global__ __launch_bounds__(kBlock, PushCfg<T>::waves) void k_push(GapDev* __re
   using I = typename Fixed<T>::I;
   __shared__ long long s_flux[kTile];
   __shared__ uint32_t s_emit[kChunk];  // chunk-local index << 8 | k
-  __shared__ int s_red[8];
+  __shared__ int s_red[2][8];
   __shared__ double s_d[8];
   __shared__ unsigned long long s_u[8];
   __shared__ int s_emit_n, s_emit_k;
+
+  // the flux tile is kept zero between chunks (each flush clears what it
+  // read), so it is zeroed once here
+  for (int k = threadIdx.x; k < kTile; k += kBlock) s_flux[k] = 0;
+  __syncthreads();
+  int parity = 0;
 
   const long long total = wi[B];
   long long w0, w1;
@@ -271,7 +296,7 @@ __global__ __launch_bounds__(kBlock, PushCfg<T>::waves) void k_push(GapDev* __re
     for (int j = 0; j < kItems; ++j)
       if (cl[j] != kDead) { mn = min(mn, cl[j]); mx = max(mx, cl[j]); }
     if (tid == 0) { s_emit_n = 0; s_emit_k = 0; }
-    block_minmax(mn, mx, s_red);
+    block_minmax_pp(mn, mx, s_red, parity);
     // E at the cells around each lepton (dead slots read cell 0), requested
     // for the first group of items now and for later groups just before
     // they are pushed
@@ -307,10 +332,6 @@ __global__ __launch_bounds__(kBlock, PushCfg<T>::waves) void k_push(GapDev* __re
       const int base = mn - 1;
       const int span = mx - mn + 3;
       const bool lds = span <= kTile;
-      if (lds) {
-        for (int k = tid; k < span; k += kBlock) s_flux[k] = 0;
-        __syncthreads();
-      }
       const T qdt = s == 0 ? -dt_t : dt_t;
       const T one_t = (T)1, half_t = (T)0.5;
       bool bad = false, emit_bad = false;
@@ -412,6 +433,7 @@ __global__ __launch_bounds__(kBlock, PushCfg<T>::waves) void k_push(GapDev* __re
         for (int k = tid; k < span; k += kBlock) {
           const long long f = s_flux[k];
           if (f != 0) {
+            s_flux[k] = 0;
             int cc = base + k;
             if (cc < 0) cc += nc;
             else if (cc >= nc) cc -= nc;
