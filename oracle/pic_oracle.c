@@ -171,6 +171,7 @@ int orc_validate(const orc_params* p) {
   }
   if (!(p->l_gamma >= 0.0) || !isfinite(p->l_gamma)) return ORC_ERR_ARG;
   if (!(p->weight >= 0.0) || !isfinite(p->weight)) return ORC_ERR_ARG;
+  if (!isfinite(p->j_m)) return ORC_ERR_ARG;
   if (p->precision != ORC_FP64 && p->precision != ORC_MIXED) return ORC_ERR_ARG;
   if (p->capacity < 0) return ORC_ERR_ARG;
   return ORC_OK;
@@ -434,9 +435,15 @@ static int step_once(orc_gap* g) {
     return ORC_ERR_NONFINITE;
   }
 
-  /* 4. Ampere: E^{n+1} = E^n - J dt, with J dt = w * F * 2^-K. */
+  /* 4. Ampere: E^{n+1} = E^n - J dt, with J dt = w * F * 2^-K; in the
+   *    co-rotating frame (section 7) the imposed current adds j_m dt. */
   const double wq = ldexp(P->weight, -g->K);
-  for (int32_t c = 0; c < P->n_cells; ++c) g->E[c] = g->E[c] - wq * (double)g->F[c];
+  const double jmdt = P->j_m * P->dt;
+  for (int32_t c = 0; c < P->n_cells; ++c) {
+    double e = g->E[c] - wq * (double)g->F[c];
+    if (jmdt != 0.0) e = e + jmdt;
+    g->E[c] = e;
+  }
 
   /* 5. Emission by the leptons that were pushed and survived. */
   int err = ORC_OK;

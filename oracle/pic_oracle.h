@@ -10,8 +10,9 @@
  *
  * Units are normalised: c = m_e = e = omega_p0 = 1; x in c/omega_p0, t in
  * 1/omega_p0, E in m c omega_p0 / e, densities in n0.  In these units Gauss's
- * law is dE/dx = rho and Ampere's law (Eq. 4 of section 3, and Eq. 26 of
- * section 7 without the imposed current) is dE/dt = -J.
+ * law is dE/dx = rho and Ampere's law (Eq. 4 of section 3) is dE/dt = -J; in
+ * the frame co-rotating with the star (section 7) they read
+ * dE/dx = rho - rho_GJ and dE/dt = -(J - j_m), with the imposed current j_m.
  */
 #ifndef PIC_ORACLE_H
 #define PIC_ORACLE_H
@@ -40,6 +41,8 @@ typedef struct {
   uint64_t seed;
   int32_t  precision;   /* ORC_FP64 or ORC_MIXED (per-particle arithmetic in binary32) */
   int64_t  capacity;    /* max live leptons per species; 0 = unlimited */
+  double   j_m;         /* imposed current density (section 7, co-rotating frame):
+                           dE/dt = -(J - j_m); 0 outside that setup */
 } orc_params;
 
 typedef struct {

@@ -10,7 +10,10 @@ HIST_FLOAT = ("kinetic", "field", "photon_energy", "lost_energy")
 
 
 def gap_kwargs(cfg):
-    return {k: cfg[k] for k in workloads.GAP_KEYS}
+    kw = {k: cfg[k] for k in workloads.GAP_KEYS}
+    if cfg.get("j_m", 0.0):
+        kw["j_m"] = cfg["j_m"]
+    return kw
 
 
 def make_oracle(cfg, capacity=0):
@@ -19,6 +22,8 @@ def make_oracle(cfg, capacity=0):
     if cfg.get("n_pairs", 0):
         g.seed(cfg.get("seed_mode", workloads.SEED_RANDOM), cfg["n_pairs"],
                cfg.get("macro_per_pair", 1), cfg.get("p0_minus", 0.0), cfg.get("p0_plus", 0.0))
+    for sp, (cell, off, p, ids) in sorted(cfg.get("explicit", {}).items()):
+        g.seed_explicit(sp, cell, off, p, ids)
     return g
 
 
@@ -30,7 +35,7 @@ def gpu_params(cfg, **over):
         c["n_cells"], c["dx"], c["dt"], c["boundary"], c["e0"], c["gamma_thr"], c["f"],
         c["l_gamma"], c["weight"], int(c["capacity"]), int(c.get("photon_capacity", c["capacity"])),
         c["seed"], c["precision"], c.get("sort_every", 0), c.get("diag_every", 0),
-        c.get("history_rows", 0))
+        c.get("history_rows", 0), c.get("j_m", 0.0))
 
 
 def make_gpu(cfg, stream=None, **over):
@@ -40,6 +45,8 @@ def make_gpu(cfg, stream=None, **over):
         g.seed_particles(cfg.get("seed_mode", workloads.SEED_RANDOM), cfg["n_pairs"],
                          cfg.get("macro_per_pair", 1), cfg.get("p0_minus", 0.0),
                          cfg.get("p0_plus", 0.0))
+    for sp, (cell, off, p, ids) in sorted(cfg.get("explicit", {}).items()):
+        g.seed_explicit(sp, cell, off, p, ids)
     return g
 
 

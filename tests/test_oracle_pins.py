@@ -374,3 +374,59 @@ def test_energy_conserved_in_resolved_run(screening_run):
     h = screening_run["h"]
     tot = h["kinetic"] + h["field"] + h["photon_energy"] + h["lost_energy"]
     assert np.max(np.abs(tot / tot[0] - 1.0)) < 1e-2
+
+
+# ---------------------------------------------------------- co-rotating frame
+def _corot(n_cells, precision, boundary, dt=1e-2, ppc=8):
+    import workloads
+    from tests import pic_cases as pc
+    cfg = workloads.corotating_gap(n_cells=n_cells, dx=0.1, dt=dt, ppc_plus=ppc, gamma_thr=1e30,
+                                   f=0.5, precision=precision, capacity=0)
+    cfg["boundary"] = boundary
+    return cfg, pc.make_oracle(cfg)
+
+
+def test_imposed_current_closed_form():
+    """Section 7: with no plasma, Ampere's law dE/dt = -(J - j_m) gives
+    E(t) = E0 + j_m t in every cell (each step adds j_m dt once)."""
+    g = oracle.OracleGap(n_cells=16, dx=0.1, dt=1e-3, boundary=oracle.ABSORBING, e0=0.25,
+                         gamma_thr=1e30, f=0.5, l_gamma=0.0, weight=1.0, seed=3, j_m=1.5)
+    n = 1000
+    assert g.step(n) == 0
+    E = g.fields()["E"]
+    exact = 0.25 + n * (1.5 * 1e-3)
+    assert np.all(np.abs(E - exact) <= n * np.spacing(exact))
+    assert np.all(E == E[0])
+
+
+@pytest.mark.parametrize("precision,K,eps", [(oracle.FP64, 40, 2.0**-52), (oracle.MIXED, 24, 2.0**-23)])
+def test_corotating_loading_is_an_equilibrium(precision, K, eps):
+    """Section 7: electrons at -2 rho_GJ and positrons at rho_GJ satisfy Gauss's
+    law dE/dx = rho - rho_GJ with E = 0, and cold streams with J = j_m satisfy
+    Ampere's law, so in a periodic domain E stays zero up to the rounding of
+    the displacement (2^-K cell per step, against |v| dt/dx = 0.05 cell) and of
+    v = p / gamma; Gauss's law with the background holds exactly."""
+    n = 500
+    cfg, g = _corot(400, precision, oracle.PERIODIC)
+    assert g.step(n) == 0
+    F = g.fields()
+    E, rho = F["E"], F["rho"]
+    jmdt = 1.5 * cfg["dt"]
+    rel = 2.0**-K / (0.5 * cfg["dt"] / cfg["dx"]) + 8 * eps
+    assert np.max(np.abs(E)) <= n * jmdt * rel, (np.max(np.abs(E)), n * jmdt * rel)
+    resid = (E - np.roll(E, 1)) - (rho[:-1] - cfg["rho_gj"] * cfg["dx"])
+    assert np.max(np.abs(resid)) <= 16 * 2.0**-52 * max(np.max(np.abs(E)), 1.0)
+
+
+def test_corotating_gap_opens_at_the_walls():
+    """Section 7: with open walls the field stays zero everywhere except near
+    the walls, where streams leave the domain uncompensated and gaps open; the
+    interior keeps rho = rho_GJ and J = j_m."""
+    cfg, g = _corot(1000, oracle.FP64, oracle.ABSORBING)
+    assert g.step(300) == 0
+    F = g.fields()
+    E, rho = F["E"], F["rho"]
+    assert abs(E[0]) > 0.5 and abs(E[-1]) > 0.5
+    assert np.max(np.abs(E[300:700])) < 1e-9
+    resid = (E[1:] - E[:-1]) - (rho[1:-1] - cfg["rho_gj"] * cfg["dx"])
+    assert np.max(np.abs(resid)) <= 64 * 2.0**-52 * max(np.max(np.abs(E)), 1.0)

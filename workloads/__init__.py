@@ -77,6 +77,40 @@ def batched_scan(n_gaps=256, precision=MIXED, steps=2000, seed=BASE_SEED):
     return gaps
 
 
+def corotating_gap(n_cells=10000, dx=0.1, dt=1e-3, ppc_plus=10, gamma_thr=5000.0, f=0.01,
+                   l_gamma=0.0, precision=MIXED, steps=20000, capacity=20_000_000,
+                   photon_capacity=0, seed=BASE_SEED + 7):
+    """The co-rotating polar-cap gap of section 7: Goldreich-Julian density
+    n_GJ = |rho_GJ| / e is the density unit (rho_GJ = -1), the magnetosphere
+    imposes j_m = -1.5 rho_GJ c = 1.5, and the walls are open (leptons that
+    leave are removed).  Positrons at density 1 and electrons at density 2,
+    evenly spaced, make rho = rho_GJ with E = 0; cold velocities -0.5 c
+    (electrons) and +0.5 c (positrons), i.e. momenta -/+1/sqrt(3), make
+    J = 2 * 0.5 + 1 * 0.5 = j_m.  Defaults: the paper's L = 1000, dx = 0.1,
+    dt = 1e-3 (in units of c / omega_p,GJ and 1 / omega_p,GJ), gamma_thr =
+    5000 and f = 0.01 with pairs made in place.
+
+    Returns the gap configuration with the explicit seed in "explicit":
+    species -> (cell, offset, momentum, id), offsets on the 2^-24 grid."""
+    n_plus = ppc_plus * n_cells
+    n_minus = 2 * n_plus
+    weight = dx / ppc_plus  # one macro-positron per cell at density 1 gives w / dx
+    p_cold = 1.0 / math.sqrt(3.0)
+    explicit = {}
+    for sp, n, p0 in ((0, n_minus, -p_cold), (1, n_plus, p_cold)):
+        i = np.arange(n, dtype=np.int64)
+        X = ((2 * i + 1) * n_cells * (1 << 24)) // (2 * n)  # (i + 1/2) L / n on the 2^-24 grid
+        cell = (X >> 24).astype(np.int32)
+        off = (X & 0xFFFFFF).astype(np.float64) / float(1 << 24)
+        p = np.full(n, p0)
+        ids = 2 * i.astype(np.uint64) + np.uint64(sp)
+        explicit[sp] = (cell, off, p, ids)
+    return dict(n_cells=n_cells, dx=dx, dt=dt, boundary=ABSORBING, e0=0.0, gamma_thr=gamma_thr,
+                f=f, l_gamma=l_gamma, weight=weight, seed=seed, precision=precision, n_pairs=0,
+                macro_per_pair=1, steps=steps, capacity=capacity,
+                photon_capacity=photon_capacity, j_m=1.5, rho_gj=-1.0, explicit=explicit)
+
+
 def scaled(name, **over):
     """A configuration with some fields replaced (smaller parity cases)."""
     c = config(name)
