@@ -39,11 +39,14 @@ METRIC = "particle-pushes/sec + % HBM roofline, mixed-batched vs plain FP64, 1 M
 # 2 once its plasma cools; after ~10600 steps its field and photon counts grow
 # exponentially (a numerical instability the oracle shows identically), so its
 # stable first 10000 steps are the job.
-DEFAULT_STEPS = {"c2_fp64_single_gap": 10000, "c5_large_mixed": 500}
+DEFAULT_STEPS = {"c2_fp64_single_gap": 10000, "c5_large_mixed": 500, "n1_corotating": 300000}
 # The large gap of 65536 cells (E0 = 1000, 16384 seed pairs) screens within
 # ~100 steps; its dense plasma is then far from resolved by dt = 0.45 and the
 # scheme heats it (total energy +5% by step 500, +12% by step 600, then a
-# runaway of photons), so its first 500 steps are the job.
+# runaway of photons), so its first 500 steps are the job.  The co-rotating
+# gap (10000 cells, dt = 1e-3) opens gaps at its walls whose potential drop
+# grows roughly as t^2 / 8; leptons reach gamma_thr = 5000 near t = 200, so
+# its job is 300000 steps (t = 300).
 
 
 def log(msg):
@@ -54,13 +57,16 @@ def _params(P, c):
     return P.make_params(c["n_cells"], c["dx"], c["dt"], c["boundary"], c["e0"], c["gamma_thr"],
                          c["f"], c["l_gamma"], c["weight"], int(c["capacity"]),
                          int(c["photon_capacity"]), c["seed"], c["precision"],
-                         c.get("sort_every", 0), c.get("diag_every", 0), c.get("history_rows", 0))
+                         c.get("sort_every", 0), c.get("diag_every", 0), c.get("history_rows", 0),
+                         c.get("j_m", 0.0))
 
 
 def _workload(name, precision=None):
     """List of gap configurations of a workload (one for single gaps)."""
     if name == "c4_batched":
         gaps = workloads.batched_scan(256, precision=workloads.MIXED if precision is None else precision)
+    elif name == "n1_corotating":
+        gaps = [workloads.corotating_gap(precision=workloads.MIXED if precision is None else precision)]
     else:
         gaps = [workloads.config(name)]
         if precision is not None:
@@ -77,7 +83,10 @@ def _make(P, gaps, stream):
         g = P.Batch([_params(P, c) for c in gaps], stream=stream)
         views = g.gaps
     for v, c in zip(views, gaps):
-        v.seed_particles(workloads.SEED_RANDOM, c["n_pairs"], c["macro_per_pair"])
+        if c["n_pairs"]:
+            v.seed_particles(workloads.SEED_RANDOM, c["n_pairs"], c["macro_per_pair"])
+        for sp, (cell, off, p, ids) in sorted(c.get("explicit", {}).items()):
+            v.seed_explicit(sp, cell, off, p, ids)
     return g, views
 
 
@@ -361,7 +370,7 @@ def main():
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default: whole job)")
     ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--workload", default="c4_batched",
-                    choices=["c4_batched"] + sorted(workloads.CONFIGS))
+                    choices=["c4_batched", "n1_corotating"] + sorted(workloads.CONFIGS))
     ap.add_argument("--sort-every", type=int, default=None,
                     help="re-sort cadence for every gap (0 = tuned while running; default: the workload's)")
     ap.add_argument("--cpu-gaps", type=int, default=32)
@@ -453,6 +462,9 @@ def main():
         cfg.update(n_cells=gaps[0]["n_cells"], seed_pairs=gaps[0]["n_pairs"], e0=gaps[0]["e0"],
                    gamma_thr=gaps[0]["gamma_thr"], l_gamma=gaps[0]["l_gamma"],
                    peak_leptons=main_run["peak_leptons"])
+        if gaps[0].get("j_m"):
+            cfg.update(j_m=gaps[0]["j_m"], dt=gaps[0]["dt"], dx=gaps[0]["dx"], f=gaps[0]["f"],
+                       seed="cold streams: electrons at density 2, -0.5 c; positrons at 1, +0.5 c")
     else:
         cfg.update(n_cells="log-uniform 1024-16384", e0="U[50,400]", gamma_thr="U[50,400]",
                    l_gamma="U[10,100] cells", seed_pairs="log-uniform 256-4096",

@@ -97,7 +97,10 @@ enum { PIC_ELECTRON = 0, PIC_POSITRON = 1 };
  *               changes cost only: results do not depend on it while no
  *               gap runs out of slots.
  *  diag_every   steps between history rows (0 = 1).
- *  history_rows rows kept in the device history ring (0 = 4096).       */
+ *  history_rows rows kept in the device history ring (0 = 4096).
+ *  j_m       imposed current density of the frame co-rotating with the
+ *            star (section 7): Ampere's law becomes dE/dt = -(J - j_m);
+ *            0 everywhere else.                                          */
 typedef struct {
   int32_t  n_cells;
   double   dx, dt;
@@ -111,6 +114,7 @@ typedef struct {
   int32_t  precision;
   int32_t  sort_every, diag_every;
   int32_t  history_rows;
+  double   j_m;
 } pic_gap_params;
 
 /* One row per diagnosed step (the quantities of Figs. 1 and 3). */

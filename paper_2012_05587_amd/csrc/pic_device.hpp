@@ -75,6 +75,7 @@ struct GapDev {
   int32_t precision, diag_every, hist_rows, pad0;
   int64_t one, domain, photon_step, cap, ph_cap;
   double dt, dx, weight, wq, e0;
+  double jmdt;                       // imposed current times dt (section 7), 0 elsewhere
   double dtdx, gthr, gpair, pchild;  // values exactly representable in the particle type
   double gpair64, child_gamma64;     // binary64 pair energy; child gamma in the particle precision
   uint64_t seed;

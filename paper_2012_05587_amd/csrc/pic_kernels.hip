@@ -743,13 +743,14 @@ __device__ void field_role(GapDev* __restrict__ gaps, const long long* __restric
   if (G->status != PIC_OK) return;
   const long long c0 = (vb - cwi[g]) * (long long)kCellChunk;
   const int nc = G->n_cells;
-  const double wq = G->wq, dxh = G->dx;
+  const double wq = G->wq, dxh = G->dx, jmdt = G->jmdt;
   double fe = 0.0, es = 0.0;
   for (int k = threadIdx.x; k < kCellChunk; k += kBlock) {
     const long long c = c0 + k;
     if (c >= nc) break;
     const long long f = G->F[c];
-    const double e = G->E[c] - wq * (double)f;
+    double e = G->E[c] - wq * (double)f;
+    if (jmdt != 0.0) e = e + jmdt;  // imposed current of the co-rotating frame
     G->E[c] = e;
     G->Ef[c] = (float)e;
     G->F_last[c] = f;

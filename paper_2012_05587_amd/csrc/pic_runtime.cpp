@@ -87,6 +87,7 @@ pic_status validate(const pic_gap_params* p) {
   }
   if (!(p->l_gamma >= 0.0) || !std::isfinite(p->l_gamma)) return PIC_ERR_ARG;
   if (!(p->weight >= 0.0) || !std::isfinite(p->weight)) return PIC_ERR_ARG;
+  if (!std::isfinite(p->j_m)) return PIC_ERR_ARG;
   if (p->capacity < 1 || p->capacity >= (int64_t)1 << 31) return PIC_ERR_ARG;
   if (p->photon_capacity < 0 || p->photon_capacity >= (int64_t)1 << 31) return PIC_ERR_ARG;
   if (p->l_gamma > 0.0 && p->photon_capacity < 1) return PIC_ERR_ARG;
@@ -322,6 +323,7 @@ pic_status create_batch(const pic_gap_params* params, int n_gaps, void* d_ws, si
     G.weight = p.weight;
     G.wq = std::ldexp(p.weight, -G.K);
     G.e0 = p.e0;
+    G.jmdt = p.j_m * p.dt;
     G.gpair64 = p.f * p.gamma_thr;
     G.seed = p.seed;
     if (p.precision == PIC_MIXED) fill_precision_constants<float>(G, p);

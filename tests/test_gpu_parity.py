@@ -106,6 +106,27 @@ def test_config5_physics_reduced():
 
 
 @pytest.mark.parametrize("precision", [workloads.FP64, workloads.MIXED])
+def test_corotating_gap(precision):
+    """Section 7's co-rotating gap (imposed current j_m = 1.5, open walls,
+    electrons at twice the positron density in cold counter-streams), scaled
+    to 1000 cells with gamma_thr = 100 and f = 0.1 so that the gaps at the
+    walls accelerate leptons past threshold and make pairs within the run;
+    against the oracle, and Gauss's law with the background charge on the
+    GPU's own fields."""
+    cfg = workloads.corotating_gap(n_cells=1000, dx=0.1, dt=1e-2, ppc_plus=4, gamma_thr=100.0,
+                                   f=0.1, precision=precision, capacity=200_000)
+    gg, go = _run_pair(cfg, 6000)
+    stats, err, exact = _check_all(gg, go, precision)
+    h = gg.read_history()
+    assert h["pairs_created"][-1] > 1000 and h["absorbed_minus"][-1] > 0 and h["absorbed_plus"][-1] > 0
+    F = gg.read_fields(rho=True)
+    E, rho = F["E"], F["rho"]
+    resid = (E[1:] - E[:-1]) - (rho[1:-1] - cfg["rho_gj"] * cfg["dx"])
+    assert np.max(np.abs(resid)) <= 1e-12 * max(np.max(np.abs(E)), 1.0)
+    print("p err", stats, "E err", err, "E bitwise", exact)
+
+
+@pytest.mark.parametrize("precision", [workloads.FP64, workloads.MIXED])
 def test_in_place_pairs_periodic(precision):
     """The paper's own model: pairs made in place, periodic domain."""
     cfg = dict(n_cells=300, dx=1.0, dt=0.45, boundary=workloads.PERIODIC, e0=30.0,
