@@ -75,6 +75,8 @@ def lib():
     L.orc_set_fields.argtypes = [vp, vp]; L.orc_set_fields.restype = C.c_int
     L.orc_history.argtypes = [vp, vp, i64, P(i64)]; L.orc_history.restype = C.c_int
     L.orc_offset_bits.argtypes = [vp]; L.orc_offset_bits.restype = C.c_int
+    L.orc_event_map.argtypes = [vp, i32, i32, i32]; L.orc_event_map.restype = C.c_int
+    L.orc_read_event_map.argtypes = [vp, vp]; L.orc_read_event_map.restype = C.c_int
     L.orc_philox4x64_10.argtypes = [vp, vp, vp]; L.orc_philox4x64_10.restype = None
     L.orc_conv_table.argtypes = [dbl, dbl, dbl, vp, i64]; L.orc_conv_table.restype = i64
     _LIB = L
@@ -192,6 +194,21 @@ class OracleGap:
         F = np.zeros(self.n_cells, np.int64)
         self._L.orc_read_fields(self._h, _ptr(E), _ptr(rho), _ptr(F))
         return {"E": E, "rho": rho, "flux": F}
+
+    def event_map(self, x_bins, steps_per_row, rows):
+        """Starts counting pair events by (step row, cell bin)."""
+        st = self._L.orc_event_map(self._h, x_bins, steps_per_row, rows)
+        if st != OK:
+            raise RuntimeError(f"orc_event_map failed: {st}")
+        self._ev = (x_bins, rows)
+
+    def read_event_map(self):
+        x_bins, rows = self._ev
+        out = np.zeros((rows, x_bins), np.int64)
+        st = self._L.orc_read_event_map(self._h, _ptr(out))
+        if st != OK:
+            raise RuntimeError(f"orc_read_event_map failed: {st}")
+        return out
 
     def set_fields(self, E):
         E = np.ascontiguousarray(E, dtype=np.float64)

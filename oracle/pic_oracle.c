@@ -80,6 +80,10 @@ struct orc_gap {
   /* cumulative tallies */
   int64_t      pairs_created, photons_emitted, photons_escaped, absorbed[2];
   double       lost_energy;
+  /* pair-event map (the (x, t) map of section 7's figure): pairs made at step
+   * n in cell c count in row (n / ev_steps) % ev_rows, column c * ev_x / N_c */
+  int64_t*     ev_map;
+  int32_t      ev_x, ev_steps, ev_rows;
 };
 
 /* ------------------------------------------------------------------------ */
@@ -227,7 +231,7 @@ void orc_destroy(orc_gap* g) {
   for (int s = 0; s < 2; ++s) {
     free(g->sp[s].cell); free(g->sp[s].offq); free(g->sp[s].p); free(g->sp[s].id);
   }
-  free(g->ph); free(g->E); free(g->F); free(g->table); free(g->hist);
+  free(g->ph); free(g->E); free(g->F); free(g->table); free(g->hist); free(g->ev_map);
   free(g);
 }
 
@@ -308,12 +312,37 @@ static void append_photon(orc_gap* g, int64_t xq, int64_t conv_step, int32_t dir
   g->n_ph++;
 }
 
-static void append_pair(orc_gap* g, int32_t cell, int64_t offq, int32_t dir, uint64_t child,
-                        double pchild) {
+static void append_pair(orc_gap* g, int64_t n, int32_t cell, int64_t offq, int32_t dir,
+                        uint64_t child, double pchild) {
   double p = dir > 0 ? pchild : -pchild;
   species_push_back(&g->sp[0], cell, offq, p, child);
   species_push_back(&g->sp[1], cell, offq, p, child | 1u);
   g->pairs_created++;
+  if (g->ev_map) {
+    const int64_t row = (n / g->ev_steps) % g->ev_rows;
+    const int64_t col = (int64_t)cell * g->ev_x / g->prm.n_cells;
+    g->ev_map[row * g->ev_x + col] += 1;
+  }
+}
+
+int orc_event_map(orc_gap* g, int32_t x_bins, int32_t steps_per_row, int32_t rows) {
+  if (!g) return ORC_ERR_ARG;
+  free(g->ev_map);
+  g->ev_map = NULL;
+  if (x_bins == 0) return ORC_OK;
+  if (x_bins < 1 || steps_per_row < 1 || rows < 1) return ORC_ERR_ARG;
+  g->ev_map = (int64_t*)calloc((size_t)x_bins * (size_t)rows, sizeof(int64_t));
+  if (!g->ev_map) return ORC_ERR_ARG;
+  g->ev_x = x_bins;
+  g->ev_steps = steps_per_row;
+  g->ev_rows = rows;
+  return ORC_OK;
+}
+
+int orc_read_event_map(const orc_gap* g, int64_t* out) {
+  if (!g || !g->ev_map || !out) return ORC_ERR_ARG;
+  memcpy(out, g->ev_map, sizeof(int64_t) * (size_t)g->ev_x * (size_t)g->ev_rows);
+  return ORC_OK;
 }
 
 static void record_history(orc_gap* g) {
@@ -473,7 +502,7 @@ static int step_once(orc_gap* g) {
         g->photons_emitted++;
         if (g->table_len == 0) {
           /* in-place pair production (section 2) */
-          append_pair(g, c, oq, dir, child, pchild);
+          append_pair(g, n, c, oq, dir, child, pchild);
           continue;
         }
         int64_t nc = conv_steps(g, (uint32_t)(u[0] >> 32));
@@ -503,7 +532,7 @@ static int step_once(orc_gap* g) {
   for (int64_t i = 0; i < g->n_ph; ++i) {
     orc_photon ph = g->ph[i];
     if (ph.conv_step == n) {
-      append_pair(g, (int32_t)(ph.xq / ONE), ph.xq % ONE, ph.dir, ph.child, pchild);
+      append_pair(g, n, (int32_t)(ph.xq / ONE), ph.xq % ONE, ph.dir, ph.child, pchild);
     } else {
       g->ph[kept++] = ph;
     }

@@ -83,6 +83,11 @@ int      orc_read_fields(const orc_gap* g, double* E, double* rho, int64_t* last
 int      orc_set_fields(orc_gap* g, const double* E);
 int      orc_history(const orc_gap* g, orc_history_row* rows, int64_t max_rows, int64_t* n_out);
 int      orc_offset_bits(const orc_gap* g);
+/* Pair-event map: from now on every pair made at step n in cell c counts in
+ * row (n / steps_per_row) % rows, column c * x_bins / n_cells (x_bins = 0
+ * switches it off).  read copies rows x x_bins counts. */
+int      orc_event_map(orc_gap* g, int32_t x_bins, int32_t steps_per_row, int32_t rows);
+int      orc_read_event_map(const orc_gap* g, int64_t* out);
 
 /* Building blocks exposed for pinning against libraries and closed forms. */
 void     orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);

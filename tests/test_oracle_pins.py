@@ -430,3 +430,39 @@ def test_corotating_gap_opens_at_the_walls():
     assert np.max(np.abs(E[300:700])) < 1e-9
     resid = (E[1:] - E[:-1]) - (rho[1:-1] - cfg["rho_gj"] * cfg["dx"])
     assert np.max(np.abs(resid)) <= 64 * 2.0**-52 * max(np.max(np.abs(E)), 1.0)
+
+
+# ------------------------------------------------------------ pair-event map
+def test_event_map_single_emitter_closed_form():
+    """One positron with p = 1000 in zero field (w = 0, pairs in place): at step
+    0 it moves v dt / dx cells and, at or above gamma_thr = 100 with
+    gamma_pair = 50, makes k = floor((gamma - gamma_thr) / gamma_pair) + 1
+    pairs in the cell it reached; its children (gamma' = 25) and itself (now
+    below threshold) make none afterwards."""
+    g = oracle.OracleGap(n_cells=64, dx=1.0, dt=0.45, boundary=oracle.PERIODIC, e0=0.0,
+                         gamma_thr=100.0, f=0.5, l_gamma=0.0, weight=0.0, seed=11)
+    g.seed_explicit(1, [40], [0.75], [1000.0], [7])
+    g.event_map(16, 1, 10)
+    assert g.step(10) == 0
+    m = g.read_event_map()
+    gamma = math.sqrt(1.0 + 1000.0**2)
+    k = int((gamma - 100.0) // 50.0) + 1
+    x1 = 40 + 0.75 + 1000.0 / gamma * 0.45  # position after the move, cells
+    assert m.sum() == k
+    assert m[0, int(x1) * 16 // 64] == k
+    assert m[1:].sum() == 0
+
+
+def test_event_map_rows_match_history():
+    """Summed over cells, each row of the event map is the number of pairs the
+    history records for the steps of that row."""
+    g = oracle.OracleGap(n_cells=512, dx=1.0, dt=0.45, boundary=oracle.ABSORBING, e0=50.0,
+                         gamma_thr=100.0, f=0.5, l_gamma=20.0, weight=1.0, seed=2012055871)
+    g.seed(oracle.SEED_RANDOM, 256, 1)
+    g.event_map(32, 25, 20)
+    assert g.step(500) == 0
+    m = g.read_event_map()
+    h = g.history()
+    made = np.diff(np.concatenate([[0], h["pairs_created"]]))
+    assert made.sum() > 1000
+    assert np.array_equal(m.sum(axis=1), made.reshape(20, 25).sum(axis=1))
