@@ -227,6 +227,30 @@ pic_status pic_set_fields(pic_gap* g, const double* E, int32_t n_cells);
 /* Offset grid bits K of this gap (40 or 24). */
 int32_t pic_offset_bits(const pic_gap* g);
 
+/* ---- Diagnostics of the paper's figures, computed on the device. ----
+ * Phase-space histogram of species s (0 electrons, 1 positrons) of gap g:
+ * the momentum distributions of Fig. 2 (x_bins = 1) and the phase spaces
+ * of section 7's figure.  A live lepton in cell c with momentum p counts in
+ * d_counts[xb * p_bins + pb], xb = c * x_bins / n_cells (integer division),
+ * pb = floor((p - p_min) * (p_bins / (p_max - p_min))) in binary64,
+ * clamped to [0, p_bins).  d_counts is a caller-owned device array of
+ * x_bins * p_bins int64 that the counts are added to; the work is enqueued
+ * on the gap's stream (synchronise before reading).  Each count stands for
+ * weight leptons.  Errors: PIC_ERR_ARG for a bad species, bin counts or
+ * range. */
+pic_status pic_phase_space(pic_gap* g, int32_t species, int32_t x_bins, int32_t p_bins,
+                           double p_min, double p_max, int64_t* d_counts);
+/* Pair-event map of section 7's figure (pair production events in x and
+ * t).  From the next step on, every pair made at step n in cell c (in
+ * place, or by a photon converting there) adds 1 to
+ * d_map[row * x_bins + c * x_bins / n_cells], row = (n / steps_per_row) %
+ * rows.  d_map is a caller-owned device array of rows * x_bins int64, kept
+ * until the gap is destroyed or another call replaces it; the library
+ * zeroes it on the gap's stream.  d_map = NULL stops the counting.
+ * Synchronises the stream. */
+pic_status pic_event_map(pic_gap* g, int64_t* d_map, int32_t x_bins, int32_t steps_per_row,
+                         int32_t rows);
+
 /* Frees the handle (not the workspace).  Synchronises the stream. */
 pic_status pic_destroy(pic_gap* g);
 

@@ -32,6 +32,7 @@ EXPORTS = [
     "pic_batch_workspace_bytes", "pic_create_batch", "pic_batch_step_n", "pic_batch_gap",
     "pic_batch_size", "pic_destroy_batch", "pic_profile_push", "pic_read_push_time",
     "pic_batch_profile_push", "pic_batch_read_push_time", "pic_batch_tuning", "pic_tuning",
+    "pic_phase_space", "pic_event_map",
 ]
 
 
@@ -123,6 +124,8 @@ def lib():
         getattr(L, name).argtypes = [vp, i32]; getattr(L, name).restype = i32
     for name in ("pic_read_push_time", "pic_batch_read_push_time"):
         getattr(L, name).argtypes = [vp, P(dbl), P(i64)]; getattr(L, name).restype = i32
+    L.pic_phase_space.argtypes = [vp, i32, i32, i32, dbl, dbl, vp]; L.pic_phase_space.restype = i32
+    L.pic_event_map.argtypes = [vp, vp, i32, i32, i32]; L.pic_event_map.restype = i32
     for name in ("pic_tuning", "pic_batch_tuning"):
         getattr(L, name).argtypes = [vp, P(i32), P(i32), P(i64), P(i32)]; getattr(L, name).restype = i32
     _lib = L
@@ -200,6 +203,46 @@ class _GapView:
         p = np.ascontiguousarray(p, np.float64); ids = np.ascontiguousarray(ids, np.uint64)
         _check("pic_seed_explicit", lib().pic_seed_explicit(
             self._h, species, len(cell), _ptr(cell), _ptr(off), _ptr(p), _ptr(ids)))
+
+    def _owner(self):
+        return self if self._keep is None else self._keep
+
+    def _dev(self):
+        return self._owner().workspace.device
+
+    def _sync(self):
+        """Waits for the library's stream of this gap."""
+        import torch
+        st = self._owner().stream
+        if st is not None:
+            st.synchronize()
+        else:
+            torch.cuda.synchronize(self._dev())
+
+    def phase_space(self, species, x_bins, p_bins, p_min, p_max):
+        """Counts of live leptons of a species by (cell bin, momentum bin), as
+        an int64 array of shape (x_bins, p_bins) computed on the device."""
+        import torch
+        dev = self._dev()
+        out = torch.zeros(x_bins * p_bins, dtype=torch.int64, device=dev)
+        torch.cuda.current_stream(dev).synchronize()  # the zeros, before the library's stream
+        _check("pic_phase_space", lib().pic_phase_space(
+            self._h, species, x_bins, p_bins, float(p_min), float(p_max), C.c_void_p(out.data_ptr())))
+        self._sync()
+        return out.cpu().numpy().reshape(x_bins, p_bins)
+
+    def set_event_map(self, x_bins, steps_per_row, rows):
+        """Starts counting pair events by (step row, cell bin) on the device."""
+        import torch
+        m = torch.empty(rows * x_bins, dtype=torch.int64, device=self._dev())
+        _check("pic_event_map", lib().pic_event_map(self._h, C.c_void_p(m.data_ptr()), x_bins,
+                                                    steps_per_row, rows))
+        self._evmap = (m, rows, x_bins)
+
+    def read_event_map(self):
+        m, rows, x_bins = self._evmap
+        self._sync()
+        return m.cpu().numpy().reshape(rows, x_bins)
 
     def read_fields(self, rho=True):
         E = np.zeros(self.n_cells)

@@ -97,6 +97,8 @@ struct GapDev {
   int32_t* ph_bucket;     // photon store sorted by conversion step: end of each bucket
   float inv_lnq;          // 1 / ln q of the photon path, q = exp(-dt / (l_gamma dx))
   int32_t pad3;
+  unsigned long long* evmap;  // pair-event map (caller's device buffer), or null
+  int32_t ev_x, ev_steps, ev_rows, pad5;
 
   // ---- counters (device-updated)
   unsigned long long n[2];       // slots in use at step start
@@ -168,6 +170,14 @@ __device__ __forceinline__ U64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_
 // Accumulator a (0 kinetic energy, 1 lost energy, 2-3 absorbed electrons /
 // positrons) of gap g, stripe st: each stripe on its own cache line, so the
 // workgroups of the push kernel do not all hit one address.
+// Pair-event map: pairs made at step n in cell c count in row
+// (n / ev_steps) % ev_rows, column c * ev_x / n_cells.
+__device__ __forceinline__ void count_pairs(const GapDev* G, long long step, int c, unsigned long long k) {
+  const long long row = (step / G->ev_steps) % G->ev_rows;
+  const long long col = (long long)c * G->ev_x / G->n_cells;
+  atomicAdd(G->evmap + row * G->ev_x + col, k);
+}
+
 __device__ __forceinline__ double* stripe_slot(double* stripes, int g, int a, int st) {
   return stripes + (((size_t)g * 4 + a) * kStripes + st) * kStripeStride;
 }

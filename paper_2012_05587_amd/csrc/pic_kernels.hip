@@ -559,6 +559,7 @@ __device__ __forceinline__ unsigned emit_one(GapDev* __restrict__ G, int s, long
         ((T*)G->p[buf][1])[sp] = pc; G->id[buf][1][sp] = child | 1u;
       }
     }
+    if (G->evmap) count_pairs(G, (long long)stepn, c, (unsigned long long)k);
   } else {
     const bool absorbing = G->boundary == PIC_BC_ABSORBING;
     const unsigned long long ph_cap = (unsigned long long)G->ph_cap;
@@ -876,6 +877,7 @@ __device__ void convert_role(GapDev* __restrict__ gaps, const long long* __restr
           G->cell[buf][1][sp] = c; ((T*)G->off[buf][1])[sp] = offn;
           ((T*)G->p[buf][1])[sp] = pc; G->id[buf][1][sp] = child | 1u;
         }
+        if (G->evmap) count_pairs(G, (long long)stepn, c, 1ull);
       }
     }
     w = wend;
@@ -1534,6 +1536,46 @@ __global__ __launch_bounds__(kBlock) void k_rho(GapDev* __restrict__ gaps, int g
   }
 }
 
+// ------------------------------------------------------ phase space (diag)
+// Histogram of species s over (cell bin, momentum bin): cell c falls in bin
+// c * x_bins / n_cells, momentum p in floor((p - p_min) * inv_dp) clamped to
+// [0, p_bins), computed in binary64.  Counted in LDS when the bins fit.
+constexpr int kPhaseLds = 8192;
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_phase(GapDev* __restrict__ gaps, int g, int s, int x_bins,
+                                                  int p_bins, double p_min, double inv_dp,
+                                                  unsigned long long* __restrict__ out) {
+  __shared__ unsigned int h[kPhaseLds];
+  const GapDev* __restrict__ G = gaps + g;
+  const int nb = x_bins * p_bins;
+  const bool lds = nb <= kPhaseLds;
+  if (lds) {
+    for (int k = threadIdx.x; k < nb; k += kBlock) h[k] = 0u;
+    __syncthreads();
+  }
+  const int buf = G->buf, nc = G->n_cells;
+  const long long n = (long long)G->n[s];
+  const int32_t* __restrict__ cell = G->cell[buf][s];
+  const T* __restrict__ pp = (const T*)G->p[buf][s];
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock) {
+    const int c = cell[i];
+    if (c == kDead) continue;
+    const long long xb = (long long)c * x_bins / nc;
+    double q = floor(((double)pp[i] - p_min) * inv_dp);
+    q = q >= 0.0 ? q : 0.0;  // also a NaN momentum
+    q = q <= (double)(p_bins - 1) ? q : (double)(p_bins - 1);
+    const long long bin = xb * p_bins + (long long)q;
+    if (lds) atomicAdd(&h[bin], 1u);
+    else atomicAdd(out + bin, 1ull);
+  }
+  if (lds) {
+    __syncthreads();
+    for (int k = threadIdx.x; k < nb; k += kBlock)
+      if (h[k]) atomicAdd(out + k, (unsigned long long)h[k]);
+  }
+}
+
 __global__ void k_zero_ll(long long* __restrict__ a, long long n) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x)
@@ -1603,6 +1645,18 @@ hipError_t launch_seed(GapDev* gaps, int g, int mode, long long N, double p0m, d
   const int grid = (int)((N + kBlock - 1) / kBlock);
   if (mixed) hipLaunchKernelGGL(k_seed<float>, dim3(grid), dim3(kBlock), 0, st, gaps, g, mode, N, p0m, p0p, base0, base1);
   else hipLaunchKernelGGL(k_seed<double>, dim3(grid), dim3(kBlock), 0, st, gaps, g, mode, N, p0m, p0p, base0, base1);
+  return hipGetLastError();
+}
+
+hipError_t launch_phase(GapDev* gaps, int g, int s, int x_bins, int p_bins, double p_min, double inv_dp,
+                        unsigned long long* out, bool mixed, hipStream_t st) {
+  if (mixed) hipLaunchKernelGGL(k_phase<float>, dim3(1024), dim3(kBlock), 0, st, gaps, g, s, x_bins, p_bins, p_min, inv_dp, out);
+  else hipLaunchKernelGGL(k_phase<double>, dim3(1024), dim3(kBlock), 0, st, gaps, g, s, x_bins, p_bins, p_min, inv_dp, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(long long* a, long long n, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_ll, dim3(256), dim3(256), 0, st, a, n);
   return hipGetLastError();
 }
 

@@ -30,6 +30,9 @@ hipError_t launch_sort(const StepLaunch& L, bool mixed);
 hipError_t launch_plan(const StepLaunch& L);
 hipError_t launch_seed(GapDev* gaps, int g, int mode, long long N, double p0m, double p0p,
                        long long base0, long long base1, bool mixed, hipStream_t st);
+hipError_t launch_phase(GapDev* gaps, int g, int s, int x_bins, int p_bins, double p_min, double inv_dp,
+                        unsigned long long* out, bool mixed, hipStream_t st);
+hipError_t launch_zero(long long* a, long long n, hipStream_t st);
 hipError_t launch_rho(GapDev* gaps, int g, long long* rho_acc, long long n_nodes, bool mixed,
                       hipStream_t st);
 

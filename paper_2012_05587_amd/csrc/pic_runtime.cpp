@@ -796,6 +796,37 @@ pic_status pic_read_fields(pic_gap* g, double* E, double* rho, int32_t n_cells) 
   return hipStreamSynchronize(b->stream) == hipSuccess ? PIC_OK : PIC_ERR_DEVICE;
 }
 
+pic_status pic_phase_space(pic_gap* g, int32_t species, int32_t x_bins, int32_t p_bins, double p_min,
+                           double p_max, int64_t* d_counts) {
+  if (!g || !d_counts || species < 0 || species > 1 || x_bins < 1 || p_bins < 1) return PIC_ERR_ARG;
+  if ((int64_t)x_bins * p_bins > ((int64_t)1 << 30)) return PIC_ERR_ARG;
+  if (!std::isfinite(p_min) || !std::isfinite(p_max) || !(p_max > p_min)) return PIC_ERR_ARG;
+  pic_batch* b = g->b;
+  const double inv_dp = (double)p_bins / (p_max - p_min);
+  if (pic::launch_phase(dgaps(b), g->idx, species, x_bins, p_bins, p_min, inv_dp,
+                        reinterpret_cast<unsigned long long*>(d_counts), b->precision == PIC_MIXED,
+                        b->stream) != hipSuccess)
+    return PIC_ERR_DEVICE;
+  return PIC_OK;
+}
+
+pic_status pic_event_map(pic_gap* g, int64_t* d_map, int32_t x_bins, int32_t steps_per_row, int32_t rows) {
+  if (!g) return PIC_ERR_ARG;
+  if (d_map && (x_bins < 1 || steps_per_row < 1 || rows < 1)) return PIC_ERR_ARG;
+  if (d_map && (int64_t)x_bins * rows > ((int64_t)1 << 34)) return PIC_ERR_ARG;
+  pic_batch* b = g->b;
+  GapDev G;
+  pic_status st = read_desc(b, g->idx, &G);
+  if (st != PIC_OK) return st;
+  if (d_map && pic::launch_zero(reinterpret_cast<long long*>(d_map), (long long)x_bins * rows, b->stream) != hipSuccess)
+    return PIC_ERR_DEVICE;
+  G.evmap = reinterpret_cast<unsigned long long*>(d_map);
+  G.ev_x = d_map ? x_bins : 0;
+  G.ev_steps = d_map ? steps_per_row : 1;
+  G.ev_rows = d_map ? rows : 1;
+  return write_desc(b, g->idx, &G);
+}
+
 pic_status pic_read_flux(pic_gap* g, int64_t* flux, int32_t n_cells) {
   if (!g || !flux) return PIC_ERR_ARG;
   pic_batch* b = g->b;

@@ -235,6 +235,53 @@ def test_autotuned_sort_cadence_matches_fixed(precision):
     assert not f["autotuned"] and f["sort_every"] == 20, f
 
 
+# ------------------------------------------------------ figure diagnostics
+def _np_phase(parts, n_cells, x_bins, p_bins, p_min, p_max):
+    """The phase-space binning, written out: cell c -> c * x_bins // n_cells,
+    p -> floor((p - p_min) * (p_bins / (p_max - p_min))) clamped."""
+    inv = p_bins / (p_max - p_min)
+    xb = parts["cell"].astype(np.int64) * x_bins // n_cells
+    q = np.floor((parts["p"] - p_min) * inv)
+    q = np.clip(q, 0, p_bins - 1).astype(np.int64)
+    out = np.zeros(x_bins * p_bins, np.int64)
+    np.add.at(out, xb * p_bins + q, 1)
+    return out.reshape(x_bins, p_bins)
+
+
+@pytest.mark.parametrize("precision", [workloads.FP64, workloads.MIXED])
+def test_phase_space_matches_oracle_particles(precision):
+    """Fig. 2's momentum distributions and section 7's phase spaces, counted
+    on the device, equal the same binning of the oracle's leptons."""
+    cfg = workloads.config("c1_fp64_reference_gap")
+    cfg.update(precision=precision)
+    gg, go = _run_pair(cfg, 300)
+    for s in (0, 1):
+        parts = go.particles(s)
+        for x_bins, p_bins, lo, hi in ((1, 200, -150.0, 150.0), (16, 64, -120.0, 80.0),
+                                       (128, 128, -100.0, 100.0)):
+            got = gg.phase_space(s, x_bins, p_bins, lo, hi)
+            want = _np_phase(parts, cfg["n_cells"], x_bins, p_bins, lo, hi)
+            assert np.array_equal(got, want), (s, x_bins, p_bins)
+            assert got.sum() == len(parts["p"])
+
+
+@pytest.mark.parametrize("l_gamma,boundary", [(20.0, workloads.ABSORBING), (0.0, workloads.PERIODIC)])
+def test_event_map_matches_oracle(l_gamma, boundary):
+    """Section 7's pair-event map (pairs made by photon conversion, or in
+    place), counted on the device, equals the oracle's."""
+    cfg = workloads.config("c1_fp64_reference_gap")
+    cfg.update(l_gamma=l_gamma, boundary=boundary, history_rows=610)
+    go = pc.make_oracle(cfg)
+    gg = pc.make_gpu(cfg, capacity=400_000, photon_capacity=400_000)
+    go.event_map(64, 25, 24)
+    gg.set_event_map(64, 25, 24)
+    assert go.step(600) == 0
+    gg.step_n(600)
+    m_o, m_g = go.read_event_map(), gg.read_event_map()
+    assert m_o.sum() > 1000
+    assert np.array_equal(m_g, m_o)
+
+
 def test_run_twice_is_bitwise_identical():
     cfg = workloads.config("c3_mixed_single_gap")
     out = []
