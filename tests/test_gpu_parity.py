@@ -235,6 +235,31 @@ def test_autotuned_sort_cadence_matches_fixed(precision):
     assert not f["autotuned"] and f["sort_every"] == 20, f
 
 
+@pytest.mark.parametrize("precision", [workloads.FP64, workloads.MIXED])
+def test_photon_store_matches_oracle(precision):
+    """The photons in flight (conversion point on the 2^-K grid, conversion
+    step, direction, child id) form the same multiset as the oracle's at
+    several points of a run, across re-sorts of the store."""
+    cfg = workloads.config("c1_fp64_reference_gap")
+    cfg.update(precision=precision, history_rows=700)
+    go = pc.make_oracle(cfg)
+    gg = pc.make_gpu(cfg)
+    done = 0
+    sizes = []
+    for n in (15, 6, 19, 7, 53, 200):  # ends of steps 14, 20, 39, 46, 99, 299
+        assert go.step(n) == 0
+        gg.step_n(n)
+        done += n
+        a, b = gg.read_photons(), go.photons()
+        key = lambda d: np.lexsort((d["child"], d["dir"], d["conv_step"], d["xq"]))
+        ka, kb = key(a), key(b)
+        assert len(ka) == len(kb), (done, len(ka), len(kb))
+        for k in ("xq", "conv_step", "dir", "child"):
+            assert np.array_equal(np.asarray(a[k])[ka], np.asarray(b[k])[kb]), (done, k)
+        sizes.append(len(ka))
+    assert done == 300 and max(sizes) > 5000, sizes
+
+
 # ------------------------------------------------------ figure diagnostics
 def _np_phase(parts, n_cells, x_bins, p_bins, p_min, p_max):
     """The phase-space binning, written out: cell c -> c * x_bins // n_cells,
