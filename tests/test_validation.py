@@ -1,0 +1,210 @@
+"""The HIP path at the paper's scale against the analytic results of
+sections 3-6 (arXiv:2012.05587).
+
+Setup of section 3: a seed pair plasma at rest in a uniform field E0,
+periodic, pairs made in place.  2000 cells over L = 10^1.5 c/omega_p0,
+dt = 10^-3.5, E0 = 10^3.5, gamma_thr = 500, 2000 seed pairs of weight dx
+(seed density 1 per species).  The cascade grows to 1e7-1e8 leptons per
+species, so only the GPU runs it; the oracle's pins cover the same
+relations at small scale.
+
+Measured against:
+- energy: field + kinetic stays constant (pairs made in place lose nothing);
+- section 3: growth rate (exact root of Eqs. 1-2), screening time t_s, the
+  screening density of Eq. 5, which the paper finds to overestimate the
+  density at the end of the cascade;
+- section 4: mean Lorentz factor at screening, Eq. 10;
+- section 5: each half period of the large-amplitude oscillation of <E>
+  against omega_0^2 = 2 n <1/gamma^3> (normalised), with n and
+  <1/gamma^3> measured on the device over that half period;
+- section 6 (f = 0.1): secondary bursts once per cycle near <E> = 0, and
+  the damping of the oscillation amplitude fitted by Eq. 24.
+
+f = 10^-3 (the smallest f the paper reports checking) needs f gamma_thr >= 2
+for a pair to hold two rest masses, so it runs with gamma_thr = 5000.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import analytic as A
+
+pytestmark = pytest.mark.gpu
+
+SAMPLE = 50      # steps between <1/gamma^3> samples
+P_RANGE = 64.0   # momentum range of the <1/gamma^3> histogram
+P_BINS = 8192
+# (f, precision, gamma_thr, steps): the steps cover screening and at least
+# four half periods of the oscillation (ten for f = 0.1 in mixed precision)
+CASES = [(0.1, workloads.MIXED, 500.0, 12000), (0.03, workloads.MIXED, 500.0, 4800),
+         (0.01, workloads.MIXED, 500.0, 4800), (0.1, workloads.FP64, 500.0, 7600),
+         (0.001, workloads.MIXED, 5000.0, 44000)]
+
+
+def _inv_gamma3(g):
+    """<1/gamma^3> over both species from device histograms of p in
+    [-P_RANGE, P_RANGE].  The two edge bins also hold the leptons outside the
+    range, whose 1/gamma^3 < 4e-6, and are counted with weight 0."""
+    dp = 2.0 * P_RANGE / P_BINS
+    pc = -P_RANGE + (np.arange(P_BINS) + 0.5) * dp
+    w = (1.0 + pc * pc) ** -1.5
+    w[0] = w[-1] = 0.0
+    num = den = 0.0
+    for sp in (0, 1):
+        h = g.phase_space(sp, 1, P_BINS, -P_RANGE, P_RANGE)[0].astype(np.float64)
+        num += float(h @ w)
+        den += float(h.sum())
+    return num / den if den else float("nan")
+
+
+def run_uniform_cascade(f, precision, gamma_thr, steps):
+    """Runs the section 3 setup on the GPU; returns the configuration, the
+    history and the sampled <1/gamma^3>."""
+    import torch
+
+    import paper_2012_05587_amd as P
+    from tests.pic_cases import gpu_params
+    cfg = workloads.uniform_cascade(f, gamma_thr=gamma_thr, precision=precision)
+    g = P.Gap(gpu_params(cfg, history_rows=steps + 8, diag_every=1),
+              stream=torch.cuda.Stream())
+    try:
+        g.seed_particles(cfg["seed_mode"], cfg["n_pairs"], cfg["macro_per_pair"])
+        samples = []
+        done = 0
+        while done < steps:
+            k = min(SAMPLE, steps - done)
+            g.step_n(k)
+            done += k
+            samples.append((done - 1, _inv_gamma3(g)))
+        h = g.read_history()
+    finally:
+        g.close()
+        del g
+        torch.cuda.empty_cache()
+    return cfg, h, np.array(samples)
+
+
+def measure(cfg, h, samples):
+    f, dt, e0, gthr = cfg["f"], cfg["dt"], cfg["e0"], cfg["gamma_thr"]
+    L = cfg["n_cells"] * cfg["dx"]
+    w = cfg["weight"]
+    t = (h["step"] + 1) * dt
+    n = h["n_minus"].astype(np.float64) * w / L            # density per species
+    W = h["kinetic"] + h["field"] + h["photon_energy"] + h["lost_energy"]
+    W0 = e0 * e0 / 2.0 * L + 2.0 * cfg["n_pairs"] * w      # field plus rest mass of the seed
+    ta = A.t_accel(e0, gthr)
+    G_exact = A.growth_rate_exact(f, ta)
+    sel = (t > ta) & (t < 3.0 * ta)
+    G = float(np.polyfit(t[sel], np.log(h["n_minus"][sel].astype(np.float64)), 1)[0])
+    i_s = int(np.argmax(h["e_mean"] < 0.0))
+    n0 = cfg["n_pairs"] * w / L
+    ts_formula = A.screening_time(e0, n0, G_exact)
+    ns = A.screening_density(e0, gthr, f)
+    gmean = h["kinetic"] / (w * (h["n_minus"] + h["n_plus"]).astype(np.float64))
+    # half periods of <E> after screening
+    em = h["e_mean"]
+    pc = h["pairs_created"].astype(np.float64)
+    rate = np.convolve(np.diff(pc, prepend=pc[0]), np.ones(51) / 51.0, mode="same")
+    zc = np.nonzero(np.sign(em[i_s:-1]) != np.sign(em[i_s + 1:]))[0] + i_s
+    zc = np.concatenate([[i_s - 1], zc])  # i_s is the first step with <E> < 0
+    half = []
+    for a, b in zip(zc[:-1], zc[1:]):
+        m = (samples[:, 0] > a) & (samples[:, 0] <= b)
+        if m.sum() < 3:
+            continue
+        ig3 = float(np.mean(samples[m, 1]))
+        nm = float(np.mean(n[a:b + 1]))
+        half.append(dict(a=int(a), b=int(b), omega=math.pi / ((b - a) * dt),
+                         omega_th=A.relativistic_plasma_frequency(nm, ig3), inv_g3=ig3,
+                         amp=float(np.max(np.abs(em[a:b + 1]))), pairs=float(pc[b] - pc[a]),
+                         burst_at=float((np.argmax(rate[a:b]) + 0.5) / (b - a))))
+    return dict(
+        f=f, energy_drift=float(np.max(np.abs(W / W0 - 1.0))),
+        G=G, G_exact=G_exact, i_s=i_s, t_s=float(t[i_s]), t_s_formula=ts_formula, t_a=ta,
+        growth_s=float(h["n_minus"][i_s] / cfg["n_pairs"]),
+        kinetic_over_W0=float(h["kinetic"][i_s] / W0), n_s=float(n[i_s]), n_s_eq5=ns,
+        gmean_s=float(gmean[i_s]), gmean_eq10=A.mean_gamma(gthr, f),
+        inv_g3_exp=math.log(2.0 / f) / (2.0 * gthr), half_periods=half)
+
+
+def damping_fit(half, cycles):
+    """Eq. 24 with the residual term dropped: the amplitude of <E> decays as
+    exp(-eps0 omega0 t / (4 pi)), i.e. by a factor 1 - eps0/2 per cycle.
+    Fits eps0 to the amplitudes of the first 2 * cycles half periods, and
+    measures eps, the jump of omega^2 per cycle that the jump conditions of
+    section 6 call eps_n, from the half-period frequencies."""
+    hp = half[:2 * cycles]
+    tc = np.array([(x["a"] + x["b"]) / 2.0 for x in hp])
+    amp = np.array([x["amp"] for x in hp])
+    om = np.array([x["omega"] for x in hp])
+    slope = np.polyfit(tc, np.log(amp), 1)[0]        # per step
+    om2 = np.polyfit(tc, np.log(om * om), 1)[0]      # per step
+    steps_per_cycle = 2.0 * (hp[-1]["b"] - hp[0]["a"]) / len(hp)
+    return dict(eps0_fit=float(-2.0 * slope * steps_per_cycle),
+                eps_omega=float(om2 * steps_per_cycle), omega0=float(np.mean(om)),
+                amp_loss_per_cycle=float(1.0 - math.exp(slope * steps_per_cycle)))
+
+
+def _id(case):
+    f, p, gthr, _ = case
+    return f"f{f}-{'fp64' if p == workloads.FP64 else 'mixed'}-g{int(gthr)}"
+
+
+@pytest.mark.parametrize("case", CASES, ids=[_id(c) for c in CASES])
+def test_uniform_cascade_at_paper_scale(case):
+    f, precision, gthr, steps = case
+    cfg, h, samples = run_uniform_cascade(f, precision, gthr, steps)
+    r = measure(cfg, h, samples)
+    print({k: v for k, v in r.items() if k != "half_periods"})
+    for x in r["half_periods"]:
+        print(x)
+    assert len(h) == steps and h["step"][-1] == steps - 1
+    # pairs made in place conserve field plus kinetic energy up to the scheme's error
+    assert r["energy_drift"] < 2e-3, r["energy_drift"]
+    # at screening nearly all the field energy sits in the leptons
+    assert r["kinetic_over_W0"] > 0.98, r["kinetic_over_W0"]
+    if f >= 0.01:
+        # section 3: growth over [t_a, 3 t_a] (two generations) against Eqs. 1-2
+        assert abs(r["G"] / r["G_exact"] - 1.0) < 0.08, (r["G"], r["G_exact"])
+        # screening: the first sign change of <E>, against t_s of section 3
+        # (exponential growth from t = 0, so the first generation's delay of
+        # about t_a makes the measured time longer)
+        assert 1.0 < r["t_s"] / r["t_s_formula"] < 1.3, (r["t_s"], r["t_s_formula"])
+        # Eq. 5 overestimates the density at screening (the paper reports a
+        # factor 1.5-2; energy balance with Eq. 10 gives a factor 2)
+        assert 0.25 < r["n_s"] / r["n_s_eq5"] < 0.7, (r["n_s"], r["n_s_eq5"])
+        # section 4, Eq. 10
+        assert 0.8 < r["gmean_s"] / r["gmean_eq10"] < 1.7, (r["gmean_s"], r["gmean_eq10"])
+    else:
+        # One pair per cell screens E0 as the second generation starts to
+        # emit: the first generation alone multiplies the seed by about
+        # 1 + 2/f, more than screening needs.  No exponential phase exists,
+        # so the relations of sections 3-4 that assume one are not checked.
+        assert r["t_s"] < 3.0 * r["t_a"] and r["growth_s"] < 1.0 + 2.0 / f, r
+    # section 5: four half periods of the oscillation against omega_0
+    hp = r["half_periods"]
+    assert len(hp) >= 4, hp
+    for x in hp[:4]:
+        assert abs(x["omega"] / x["omega_th"] - 1.0) < 0.08, x
+        if f >= 0.01:
+            # <1/gamma^3> of the exponential distribution of Eq. 8 over
+            # [1, gamma_thr] is about ln(2/f) / (2 gamma_thr)
+            assert 0.8 < x["inv_g3"] / r["inv_g3_exp"] < 2.0, (x, r["inv_g3_exp"])
+    if f == 0.1 and precision == workloads.MIXED:
+        # section 6: one secondary burst per cycle, peaking in the last tenth
+        # or so of a half period, just before <E> returns to zero
+        for c in range(4):
+            x, y = hp[2 * c], hp[2 * c + 1]
+            big, small = (x, y) if x["pairs"] > y["pairs"] else (y, x)
+            assert small["pairs"] < 0.2 * big["pairs"], (x, y)
+            assert big["burst_at"] > 0.8, big
+        # Eq. 24 over three cycles.  The jump conditions of section 6 keep
+        # E omega continuous across a burst, so the amplitude falls at least
+        # by the measured jump of omega^2; the fitted eps0 lies within a
+        # factor 2 of that jump.
+        d = damping_fit(hp, 3)
+        print(d)
+        assert d["amp_loss_per_cycle"] > 0.01, d
+        assert 0.8 < d["eps0_fit"] / d["eps_omega"] < 2.0, d
