@@ -67,6 +67,8 @@ def _workload(name, precision=None):
         gaps = workloads.batched_scan(256, precision=workloads.MIXED if precision is None else precision)
     elif name == "n1_corotating":
         gaps = [workloads.corotating_gap(precision=workloads.MIXED if precision is None else precision)]
+    elif name == "n4_nonuniform":
+        gaps = [workloads.nonuniform_gap(precision=workloads.MIXED if precision is None else precision)]
     else:
         gaps = [workloads.config(name)]
         if precision is not None:
@@ -87,6 +89,8 @@ def _make(P, gaps, stream):
             v.seed_particles(workloads.SEED_RANDOM, c["n_pairs"], c["macro_per_pair"])
         for sp, (cell, off, p, ids) in sorted(c.get("explicit", {}).items()):
             v.seed_explicit(sp, cell, off, p, ids)
+        if c.get("E_init") is not None:
+            v.set_fields(c["E_init"])
     return g, views
 
 
@@ -182,8 +186,16 @@ def _oracle_gap(args):
     c, steps = args
     sys.path.insert(0, ROOT)
     import oracle
-    o = oracle.OracleGap(**{k: c[k] for k in workloads.GAP_KEYS}, capacity=0)
-    o.seed(workloads.SEED_RANDOM, c["n_pairs"], c["macro_per_pair"])
+    kw = {k: c[k] for k in workloads.GAP_KEYS}
+    if c.get("j_m"):
+        kw["j_m"] = c["j_m"]
+    o = oracle.OracleGap(**kw, capacity=0)
+    if c["n_pairs"]:
+        o.seed(workloads.SEED_RANDOM, c["n_pairs"], c["macro_per_pair"])
+    for sp, (cell, off, p, ids) in sorted(c.get("explicit", {}).items()):
+        o.seed_explicit(sp, cell, off, p, ids)
+    if c.get("E_init") is not None:
+        o.set_fields(c["E_init"])
     n0 = o.count(0) + o.count(1)
     o.step(steps)
     h = o.history()
@@ -370,7 +382,7 @@ def main():
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default: whole job)")
     ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--workload", default="c4_batched",
-                    choices=["c4_batched", "n1_corotating"] + sorted(workloads.CONFIGS))
+                    choices=["c4_batched", "n1_corotating", "n4_nonuniform"] + sorted(workloads.CONFIGS))
     ap.add_argument("--sort-every", type=int, default=None,
                     help="re-sort cadence for every gap (0 = tuned while running; default: the workload's)")
     ap.add_argument("--cpu-gaps", type=int, default=32)
@@ -462,6 +474,10 @@ def main():
         cfg.update(n_cells=gaps[0]["n_cells"], seed_pairs=gaps[0]["n_pairs"], e0=gaps[0]["e0"],
                    gamma_thr=gaps[0]["gamma_thr"], l_gamma=gaps[0]["l_gamma"],
                    peak_leptons=main_run["peak_leptons"])
+        if gaps[0].get("E_init") is not None:
+            cfg.update(e_profile="E0 exp(-x / (L/4)) from the surface wall", dt=gaps[0]["dt"],
+                       dx=gaps[0]["dx"], f=gaps[0]["f"],
+                       seed="pairs at rest, density exp(-x / (L/4)), mean 1 per cell")
         if gaps[0].get("j_m"):
             cfg.update(j_m=gaps[0]["j_m"], dt=gaps[0]["dt"], dx=gaps[0]["dx"], f=gaps[0]["f"],
                        seed="cold streams: electrons at density 2, -0.5 c; positrons at 1, +0.5 c")

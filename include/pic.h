@@ -221,7 +221,10 @@ pic_status pic_read_particles(pic_gap* g, int32_t species, int64_t max_n, int32_
 pic_status pic_read_photons(pic_gap* g, int64_t max_n, int64_t* xq, int64_t* conv_step,
                             int32_t* dir, uint64_t* child, int64_t* n_out);
 
-/* Overwrites E from a host buffer of n_cells finite values (resume). */
+/* Overwrites E from a host buffer of n_cells finite values: a resume, or a
+ * non-uniform initial field (the conclusion's field decaying with altitude).
+ * The background charge dE/dx such a field implies is fixed and enters no
+ * update (dE/dt depends on the current only). */
 pic_status pic_set_fields(pic_gap* g, const double* E, int32_t n_cells);
 
 /* Offset grid bits K of this gap (40 or 24). */

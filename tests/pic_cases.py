@@ -24,6 +24,8 @@ def make_oracle(cfg, capacity=0):
                cfg.get("macro_per_pair", 1), cfg.get("p0_minus", 0.0), cfg.get("p0_plus", 0.0))
     for sp, (cell, off, p, ids) in sorted(cfg.get("explicit", {}).items()):
         g.seed_explicit(sp, cell, off, p, ids)
+    if cfg.get("E_init") is not None:
+        g.set_fields(cfg["E_init"])
     return g
 
 
@@ -47,6 +49,8 @@ def make_gpu(cfg, stream=None, **over):
                          cfg.get("p0_plus", 0.0))
     for sp, (cell, off, p, ids) in sorted(cfg.get("explicit", {}).items()):
         g.seed_explicit(sp, cell, off, p, ids)
+    if cfg.get("E_init") is not None:
+        g.set_fields(cfg["E_init"])
     return g
 
 

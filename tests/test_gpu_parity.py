@@ -127,6 +127,28 @@ def test_corotating_gap(precision):
 
 
 @pytest.mark.parametrize("precision", [workloads.FP64, workloads.MIXED])
+def test_nonuniform_field_and_seed(precision):
+    """The non-uniform start of the paper's conclusion: E decaying with
+    altitude from the surface wall, a seed concentrated near the surface;
+    against the oracle, and Gauss's law with the background charge of the
+    initial field on the GPU's own fields."""
+    cfg = workloads.nonuniform_gap(n_cells=1024, length=1024.0, dt=0.45, seed_pairs=512,
+                                   seed_scale=0.1, e0=100.0, gamma_thr=100.0, f=0.5,
+                                   l_gamma=20.0, weight=1.0, precision=precision,
+                                   capacity=400_000, photon_capacity=400_000)
+    gg, go = _run_pair(cfg, 800)
+    stats, err, exact = _check_all(gg, go, precision)
+    h = gg.read_history()
+    assert h["pairs_created"][-1] > 5000 and h["absorbed_minus"][-1] > 0
+    F = gg.read_fields(rho=True)
+    E, rho = F["E"], F["rho"]
+    E0 = cfg["E_init"]
+    resid = (E[1:] - E[:-1]) - (E0[1:] - E0[:-1]) - rho[1:-1]
+    assert np.max(np.abs(resid)) <= 1e-12 * np.max(np.abs(E0))
+    print("p err", stats, "E err", err, "E bitwise", exact)
+
+
+@pytest.mark.parametrize("precision", [workloads.FP64, workloads.MIXED])
 def test_in_place_pairs_periodic(precision):
     """The paper's own model: pairs made in place, periodic domain."""
     cfg = dict(n_cells=300, dx=1.0, dt=0.45, boundary=workloads.PERIODIC, e0=30.0,

@@ -466,3 +466,118 @@ def test_event_map_rows_match_history():
     made = np.diff(np.concatenate([[0], h["pairs_created"]]))
     assert made.sum() > 1000
     assert np.array_equal(m.sum(axis=1), made.reshape(20, 25).sum(axis=1))
+
+
+# ------------------------------------------------- non-uniform field and seed
+LAM, E_SURF = 64.0, 2.0  # E(x) = E_SURF exp(-x / LAM) at the cell centres
+
+
+def _exp_field_gap(r, gamma_thr=1e300, precision=oracle.FP64, weight=0.0, n_cells=256):
+    """Gap of n_cells/dx = 256 length units, dx = 1/r, dt = 0.4/r, with the
+    decaying field sampled at the cell centres (x = (c + 1/2) dx)."""
+    dx, dt = 1.0 / r, 0.4 / r
+    nc = n_cells * r
+    g = oracle.OracleGap(n_cells=nc, dx=dx, dt=dt, boundary=oracle.ABSORBING, e0=0.0,
+                         gamma_thr=gamma_thr, f=0.5, l_gamma=0.0, weight=weight, seed=1,
+                         precision=precision)
+    g.set_fields(E_SURF * np.exp(-(np.arange(nc) + 0.5) * dx / LAM))
+    return g, dx, dt
+
+
+def _put(g, species, x0, dx, pid):
+    c = int(x0 / dx)
+    g.seed_explicit(species, [c], [x0 / dx - c], [0.0], [pid])
+
+
+def _energy_error(r, precision=oracle.FP64, T=100.0, x0=20.0):
+    """Positron from rest at x0: in a static field gamma(x) = 1 + q (phi(x0) -
+    phi(x)) = 1 + E_SURF LAM (exp(-x0/LAM) - exp(-x/LAM)).  p^{n+1/2} is
+    compared at the midpoint of x^n and x^{n+1}."""
+    g, dx, dt = _exp_field_gap(r, precision=precision)
+    _put(g, 1, x0, dx, 3)
+    n = int(round(T / dt))
+    assert g.step(n - 1) == oracle.OK
+    P = g.particles(1)
+    xa = (P["cell"][0] + P["off"][0]) * dx
+    assert g.step(1) == oracle.OK
+    P = g.particles(1)
+    xm = 0.5 * (xa + (P["cell"][0] + P["off"][0]) * dx)
+    exact = 1.0 + E_SURF * LAM * (math.exp(-x0 / LAM) - math.exp(-xm / LAM))
+    return math.sqrt(1.0 + P["p"][0] ** 2) - exact
+
+
+def test_nonuniform_field_energy_gain_second_order():
+    """Energy gained in the decaying field against the potential drop: the
+    node-averaged linear gather and the leapfrog are both second order, so
+    the error falls by 4 per halving of dx and dt (a gather displaced by a
+    fraction of a cell would make it first order)."""
+    errs = [_energy_error(r) for r in (1, 2, 4, 8)]
+    assert abs(errs[0]) < 0.05
+    for a, b in zip(errs[:-1], errs[1:]):
+        assert 3.8 < a / b < 4.2, errs
+    # binary32 particles: same error until its round-off (p ~ 100, 2^-24)
+    for r in (1, 2):
+        assert abs(_energy_error(r, oracle.MIXED) - errs[r // 2]) < 2e-3
+
+
+@pytest.mark.parametrize("species,x0", [(1, 10.0), (1, 60.0), (0, 60.0), (1, 100.0)])
+def test_nonuniform_field_first_emission_matches_ode(species, x0):
+    """First emission of a lepton released at rest in the decaying field
+    against the equations of motion dp/dt = q E(x), dx/dt = p / gamma solved
+    by scipy (rtol 1e-11): emission at the first step whose p^{n+1/2} has
+    gamma >= gamma_thr.  A positron at x0 = 100 sees a potential drop of only
+    E_SURF LAM exp(-100/LAM) = 27 < gamma_thr - 1 ahead of it and never emits."""
+    from scipy.integrate import solve_ivp
+    gthr, r = 40.0, 4
+    g, dx, dt = _exp_field_gap(r, gamma_thr=gthr)
+    _put(g, species, x0, dx, 5)
+    steps = 3000
+    assert g.step(steps) == oracle.OK
+    h = g.history()
+    fired = np.nonzero(h["photons_emitted"] > 0)[0]
+    q = 1.0 if species == 1 else -1.0
+    L = 256.0
+
+    def rhs(t, y):
+        x = min(max(y[0], 0.0), L)
+        return [y[1] / math.sqrt(1.0 + y[1] ** 2), q * E_SURF * math.exp(-x / LAM)]
+
+    def reach(t, y):
+        return math.sqrt(1.0 + y[1] ** 2) - gthr
+    reach.terminal = True
+
+    def wall(t, y):
+        return y[0] * (L - y[0])
+    wall.terminal = True
+    sol = solve_ivp(rhs, (0.0, steps * dt), [x0, 0.0], events=(reach, wall), rtol=1e-11,
+                    atol=1e-12)
+    if len(sol.t_events[0]) == 0:
+        assert fired.size == 0, fired[:3]
+        return
+    # p^{n+1/2} is the momentum at (n + 1) dt after release at rest
+    t_star = sol.t_events[0][0]
+    assert fired.size > 0
+    assert abs(fired[0] - (t_star / dt - 1.0)) <= 1.5, (fired[0], t_star / dt - 1.0)
+
+
+@pytest.mark.parametrize("precision", [oracle.FP64, oracle.MIXED])
+def test_gauss_residual_with_nonuniform_start(precision):
+    """A decaying initial field implies a fixed background charge dE/dx; the
+    deposit keeps E_c - E_{c-1} - (E0_c - E0_{c-1}) = rho_c - rho0_c on the
+    interior nodes at round-off, with a non-uniform seed and a cascade."""
+    import workloads
+    cfg = workloads.nonuniform_gap(n_cells=512, length=512.0, dt=0.45, seed_pairs=256,
+                                   seed_scale=0.1, e0=50.0, gamma_thr=100.0, f=0.5,
+                                   l_gamma=20.0, weight=1.0, precision=precision,
+                                   capacity=100_000, photon_capacity=100_000)
+    from tests.pic_cases import make_oracle
+    g = make_oracle(cfg)
+    F0 = g.fields()
+    assert g.step(400) == oracle.OK
+    assert g.history()["pairs_created"][-1] > 1000
+    F = g.fields()
+    E, rho = F["E"], F["rho"]
+    dE = (E[1:] - E[:-1]) - (F0["E"][1:] - F0["E"][:-1])
+    r = dE - (rho[1:-1] - F0["rho"][1:-1])
+    # 400 binary64 field updates of values below 50
+    assert np.max(np.abs(r)) < 400 * 50.0 * 2.0**-52

@@ -18,7 +18,9 @@ Measured against:
   against omega_0^2 = 2 n <1/gamma^3> (normalised), with n and
   <1/gamma^3> measured on the device over that half period;
 - section 6 (f = 0.1): secondary bursts once per cycle near <E> = 0, and
-  the damping of the oscillation amplitude fitted by Eq. 24.
+  the damping of the oscillation amplitude fitted by Eq. 24;
+- the non-uniform start of the conclusion (field and seed decaying with
+  altitude): screening at each altitude on the local clock of section 3.
 
 f = 10^-3 (the smallest f the paper reports checking) needs f gamma_thr >= 2
 for a pair to hold two rest masses, so it runs with gamma_thr = 5000.
@@ -208,3 +210,55 @@ def test_uniform_cascade_at_paper_scale(case):
         print(d)
         assert d["amp_loss_per_cycle"] > 0.01, d
         assert 0.8 < d["eps0_fit"] / d["eps_omega"] < 2.0, d
+
+
+def test_nonuniform_gap_screens_on_the_local_clock():
+    """The non-uniform start of the paper's conclusion at the section 3
+    resolution: E0 exp(-x / (L/4)) from the surface wall and a seed of
+    density exp(-x / (L/4)).  Ampere's law is local in 1D and leptons cross
+    only a few percent of L before screening, so each altitude screens on
+    its own clock: t_s of section 3 with the local E and seed density (the
+    growth rate from Eqs. 1-2 at the local t_a).  Measured: the first step
+    at which the mean E over a twentieth of the gap turns negative."""
+    import torch
+
+    from tests.pic_cases import make_gpu
+    cfg = workloads.nonuniform_gap()
+    steps, every, nb = 24000, 100, 20
+    cfg = dict(cfg, history_rows=steps + 8, diag_every=1)
+    g = make_gpu(cfg, stream=torch.cuda.Stream())
+    try:
+        Es = []
+        for _ in range(steps // every):
+            g.step_n(every)
+            Es.append(g.read_fields(rho=False)["E"])
+        h = g.read_history()
+    finally:
+        g.close()
+        del g
+        torch.cuda.empty_cache()
+    Es = np.array(Es)
+    nc, dt, e0, gthr, f = cfg["n_cells"], cfg["dt"], cfg["e0"], cfg["gamma_thr"], cfg["f"]
+    L = nc * cfg["dx"]
+    W = h["kinetic"] + h["field"] + h["photon_energy"] + h["lost_energy"]
+    assert np.max(np.abs(W / W[0] - 1.0)) < 1e-3
+    ls = 0.25 * L                      # seed scale height
+    npairs = len(cfg["explicit"][0][0])
+    rows = []
+    for b in range(nb):
+        x = (b + 0.5) / nb * L
+        Eb = Es[:, b * nc // nb:(b + 1) * nc // nb].mean(axis=1)
+        neg = np.nonzero(Eb < 0.0)[0]
+        Ex = e0 * math.exp(-x / (0.25 * L))
+        n0 = npairs * cfg["weight"] * math.exp(-x / ls) / (ls * -math.expm1(-L / ls))
+        ta = A.t_accel(Ex, gthr)
+        t_form = A.screening_time(Ex, n0, A.growth_rate_exact(f, ta))
+        t_meas = (neg[0] + 1) * every * dt if neg.size else float("nan")
+        rows.append((b, t_meas, t_form))
+    print(rows)
+    screened = [r for r in rows if not math.isnan(r[1])]
+    assert len(screened) >= nb // 2, rows
+    for b, tm, tf in screened:
+        assert 0.9 < tm / tf < 1.3, (b, tm, tf)
+    t = [r[1] for r in screened]
+    assert all(a < c for a, c in zip(t[:-1], t[1:])), t  # the front moves up

@@ -129,6 +129,47 @@ def uniform_cascade(f, gamma_thr=500.0, n_cells=2000, precision=MIXED, seed=BASE
                 photon_capacity=0)
 
 
+def nonuniform_gap(n_cells=2000, length=10.0 ** 1.5, dt=10.0 ** -3.5, e0=10.0 ** 3.5,
+                   e_scale=0.25, seed_pairs=2000, seed_scale=0.25, gamma_thr=500.0, f=0.1,
+                   l_gamma=0.0, weight=None, precision=MIXED, steps=20000, capacity=None,
+                   photon_capacity=0, seed=BASE_SEED + 40):
+    """A gap with the non-uniform start that the paper's conclusion names as
+    a limitation of its uniform runs: the field decays with altitude and so
+    does the seed.  The surface is the left wall (x = 0), walls absorbing.
+    Defaults: the resolution and E0 of the section 3 runs (2000 cells over
+    L = 10^1.5, dt = 10^-3.5, surface field 10^3.5, gamma_thr = 500), f = 0.1,
+    pairs made in place, weight dx (mean seed density 1 per species).
+
+    E(x) = e0 exp(-x / (e_scale L)) at the cell centres x = (c + 1/2) dx,
+    in "E_init"; Gauss's law then holds with a fixed background charge
+    dE/dx.  Seed pairs at rest, electron and positron at the same point, at
+    positions drawn from the density exp(-x / (seed_scale L)) on [0, L)
+    (inverse CDF of numpy's default_rng uniforms), on the 2^-24 grid.
+    Slots per species by default: 1.25 E0^2 ln(2/f) / (2 gamma_thr) L / w,
+    the uniform gap's bound.  Returns the configuration with the explicit
+    seed in "explicit"."""
+    L = float(length)
+    dx = L / n_cells
+    w = dx if weight is None else float(weight)
+    if capacity is None:
+        capacity = int(1.25 * e0 * e0 * math.log(2.0 / f) / (2.0 * gamma_thr) * L / w)
+    xc = (np.arange(n_cells) + 0.5) * dx
+    E = e0 * np.exp(-xc / (e_scale * L))
+    rng = np.random.default_rng(seed)
+    u = rng.random(seed_pairs)
+    ls = seed_scale * L
+    x = -ls * np.log1p(-u * -np.expm1(-L / ls))
+    X = np.minimum(np.floor(x / dx * (1 << 24)).astype(np.int64), n_cells * (1 << 24) - 1)
+    cell = (X >> 24).astype(np.int32)
+    off = (X & 0xFFFFFF).astype(np.float64) / float(1 << 24)
+    i = np.arange(seed_pairs, dtype=np.uint64)
+    explicit = {sp: (cell, off, np.zeros(seed_pairs), 2 * i + np.uint64(sp)) for sp in (0, 1)}
+    return dict(n_cells=n_cells, dx=dx, dt=dt, boundary=ABSORBING, e0=e0, gamma_thr=gamma_thr,
+                f=f, l_gamma=l_gamma, weight=w, seed=seed, precision=precision, n_pairs=0,
+                macro_per_pair=1, steps=steps, capacity=capacity,
+                photon_capacity=photon_capacity, E_init=E, explicit=explicit)
+
+
 def scaled(name, **over):
     """A configuration with some fields replaced (smaller parity cases)."""
     c = config(name)
