@@ -26,7 +26,7 @@ class Params(C.Structure):
         ("boundary", C.c_int32), ("e0", C.c_double), ("gamma_thr", C.c_double),
         ("f", C.c_double), ("l_gamma", C.c_double), ("weight", C.c_double),
         ("seed", C.c_uint64), ("precision", C.c_int32), ("capacity", C.c_int64),
-        ("j_m", C.c_double),
+        ("j_m", C.c_double), ("gamma_thr_spread", C.c_double),
     ]
 
 
@@ -88,9 +88,9 @@ def _ptr(a):
 
 
 def make_params(n_cells, dx, dt, boundary, e0, gamma_thr, f, l_gamma, weight, seed,
-                precision=FP64, capacity=0, j_m=0.0):
+                precision=FP64, capacity=0, j_m=0.0, gamma_thr_spread=0.0):
     return Params(n_cells, dx, dt, boundary, e0, gamma_thr, f, l_gamma, weight, seed,
-                  precision, capacity, j_m)
+                  precision, capacity, j_m, gamma_thr_spread)
 
 
 def validate(**kw):

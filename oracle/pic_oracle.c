@@ -44,6 +44,7 @@
 
 #define ORC_TAG_SEED   1u
 #define ORC_TAG_PHOTON 2u
+#define ORC_TAG_THRESHOLD 3u
 #define ORC_MAX_EMIT   64
 
 typedef struct {
@@ -162,6 +163,20 @@ static double gamma_of(const orc_gap* g, double p) {
   return R(g, sqrt(R(g, 1.0 + R(g, p * p))));
 }
 
+/* Emission threshold of lepton `id` under a spread sigma of gamma_thr: a
+ * fixed property of the lepton, uniform in gamma_thr (1 - sigma, 1 + sigma).
+ * u = (top 53 bits of word 0 of the tag-3 draw at counter (0, 0, 3, 0)) /
+ * 2^53, then gamma_thr (1 + sigma (2u - 1)) in binary64, one rounding per
+ * operation, rounded to the particle precision at the end. */
+static double lepton_threshold(const orc_gap* g, uint64_t id) {
+  uint64_t u[4];
+  draw(id, g->prm.seed, 0, 0, ORC_TAG_THRESHOLD, u);
+  const double x = ldexp((double)(u[0] >> 11), -53);
+  const double a = 2.0 * x - 1.0;
+  const double t = g->prm.gamma_thr * (1.0 + g->prm.gamma_thr_spread * a);
+  return R(g, t);
+}
+
 int orc_validate(const orc_params* p) {
   if (!p) return ORC_ERR_ARG;
   if (p->n_cells < 2) return ORC_ERR_ARG;
@@ -176,6 +191,11 @@ int orc_validate(const orc_params* p) {
   if (!(p->l_gamma >= 0.0) || !isfinite(p->l_gamma)) return ORC_ERR_ARG;
   if (!(p->weight >= 0.0) || !isfinite(p->weight)) return ORC_ERR_ARG;
   if (!isfinite(p->j_m)) return ORC_ERR_ARG;
+  if (!(p->gamma_thr_spread >= 0.0) || !(p->gamma_thr_spread < 1.0)) return ORC_ERR_ARG;
+  /* the lowest threshold still leaves the emitter gamma >= 1 after an emission */
+  if (p->gamma_thr_spread > 0.0 && isfinite(p->gamma_thr) &&
+      !((1.0 - p->f - p->gamma_thr_spread) * p->gamma_thr >= 1.0))
+    return ORC_ERR_ARG;
   if (p->precision != ORC_FP64 && p->precision != ORC_MIXED) return ORC_ERR_ARG;
   if (p->capacity < 0) return ORC_ERR_ARG;
   return ORC_OK;
@@ -481,8 +501,9 @@ static int step_once(orc_gap* g) {
     for (int64_t i = 0; i < n_pushed[s]; ++i) {
       if (!alive[s][i]) continue;
       double gm = gam_new[s][i];
+      const double thr = P->gamma_thr_spread > 0.0 ? lepton_threshold(g, S->id[i]) : gthr;
       int k = 0;
-      while (gm >= gthr) {
+      while (gm >= thr) {
         gm = R(g, gm - gpair);
         ++k;
         if (k > ORC_MAX_EMIT) { err = ORC_ERR_EMISSION; break; }

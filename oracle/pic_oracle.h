@@ -43,6 +43,9 @@ typedef struct {
   int64_t  capacity;    /* max live leptons per species; 0 = unlimited */
   double   j_m;         /* imposed current density (section 7, co-rotating frame):
                            dE/dt = -(J - j_m); 0 outside that setup */
+  double   gamma_thr_spread; /* sigma in [0, 1): each lepton's threshold is fixed, uniform
+                           in gamma_thr (1 - sigma, 1 + sigma), drawn from its id (the
+                           spread the paper's conclusion names); 0 = one threshold */
 } orc_params;
 
 typedef struct {

@@ -8,7 +8,8 @@ than the oracle's generator.  Counting births, deaths and conversions per
 step then gives the per-step totals the oracle must reproduce exactly.
 
 The emission model is that of section 2 of arXiv:2012.05587 (threshold
-gamma_thr, pair energy f*gamma_thr split equally, emitter direction kept);
+gamma_thr, pair energy f*gamma_thr split equally, emitter direction kept),
+optionally with a per-lepton spread of the threshold;
 the photon path and the fixed-point move are the readings documented in the
 oracle.
 """
@@ -17,6 +18,7 @@ import math
 import numpy as np
 
 TAG_PHOTON = 2
+TAG_THRESHOLD = 3
 
 
 def philox(ctr, key):
@@ -40,7 +42,17 @@ def conv_table(dt, dx, l_gamma):
             return t
 
 
-def run(n_cells, dx, dt, absorbing, e0, gamma_thr, f, l_gamma, seeds, n_steps, seed):
+def threshold(pid, seed, gamma_thr, spread):
+    """A lepton's own threshold under a spread of gamma_thr: uniform in
+    gamma_thr (1 - spread, 1 + spread) from the top 53 bits of the first word
+    of its tag-3 draw (counter (0, 0, 3, 0)), in binary64."""
+    u = philox((0, 0, TAG_THRESHOLD, 0), (pid, seed))
+    x = (u[0] >> 11) * 2.0 ** -53
+    return gamma_thr * (1.0 + spread * (2.0 * x - 1.0))
+
+
+def run(n_cells, dx, dt, absorbing, e0, gamma_thr, f, l_gamma, seeds, n_steps, seed,
+        gamma_thr_spread=0.0):
     """seeds: list of (species, cell, offq, p, id) with offq in units of 2^-40.
 
     Returns per-step totals and the final leptons {id: (species, cell, offq, p)}.
@@ -71,6 +83,8 @@ def run(n_cells, dx, dt, absorbing, e0, gamma_thr, f, l_gamma, seeds, n_steps, s
         q = -1 if s == 0 else 1
         qdt = q * dt
         died_at = None
+        thr = (threshold(pid, seed, gamma_thr, gamma_thr_spread) if gamma_thr_spread > 0.0
+               else gamma_thr)
         for n in range(first, n_steps):
             # uniform field: the node average and the interpolation give E0
             p = p + qdt * e0
@@ -93,7 +107,7 @@ def run(n_cells, dx, dt, absorbing, e0, gamma_thr, f, l_gamma, seeds, n_steps, s
             oq = nq
             gm = gam
             k = 0
-            while gm >= gamma_thr:
+            while gm >= thr:
                 gm = gm - gpair
                 k += 1
             if k:

@@ -201,14 +201,17 @@ def test_cold_plasma_frequency_matches_leapfrog_dispersion():
 
 
 # ------------------------------------------------------------ brute force
-@pytest.mark.parametrize("l_gamma,absorbing", [(0.0, True), (6.0, True), (6.0, False)])
-def test_frozen_field_tree_matches_brute_force(l_gamma, absorbing):
+@pytest.mark.parametrize("l_gamma,absorbing,spread", [
+    (0.0, True, 0.0), (6.0, True, 0.0), (6.0, False, 0.0), (0.0, True, 0.3), (6.0, False, 0.3)])
+def test_frozen_field_tree_matches_brute_force(l_gamma, absorbing, spread):
     """Zero weight freezes E at E0; per-step lepton, photon, conversion, escape
     and absorption counts and every final lepton agree exactly with an
-    independent lineage-by-lineage simulation using numpy's Philox."""
+    independent lineage-by-lineage simulation using numpy's Philox (also with
+    a spread of the threshold, each lepton's own drawn there independently)."""
     prm = dict(n_cells=48, dx=1.0, dt=0.45,
                boundary=oracle.ABSORBING if absorbing else oracle.PERIODIC,
-               e0=50.0, gamma_thr=100.0, f=0.5, l_gamma=l_gamma, weight=0.0, seed=2012055870)
+               e0=50.0, gamma_thr=100.0, f=0.5, l_gamma=l_gamma, weight=0.0, seed=2012055870,
+               gamma_thr_spread=spread)
     steps = 32 if l_gamma == 0.0 else 60
     g = oracle.OracleGap(**prm)
     g.seed(oracle.SEED_RANDOM, 3, 1)
@@ -219,7 +222,8 @@ def test_frozen_field_tree_matches_brute_force(l_gamma, absorbing):
             seeds.append((s, int(c), int(round(o * 2**40)), float(p), int(i)))
     assert g.step(steps) == oracle.OK
     ref = brute_tree.run(prm["n_cells"], prm["dx"], prm["dt"], absorbing, prm["e0"],
-                         prm["gamma_thr"], prm["f"], l_gamma, seeds, steps, prm["seed"])
+                         prm["gamma_thr"], prm["f"], l_gamma, seeds, steps, prm["seed"],
+                         gamma_thr_spread=spread)
     h = g.history()
     for key in ("n_minus", "n_plus", "n_photons", "photons_emitted", "photons_escaped",
                 "pairs_created", "absorbed_minus", "absorbed_plus"):
@@ -581,3 +585,42 @@ def test_gauss_residual_with_nonuniform_start(precision):
     r = dE - (rho[1:-1] - F0["rho"][1:-1])
     # 400 binary64 field updates of values below 50
     assert np.max(np.abs(r)) < 400 * 50.0 * 2.0**-52
+
+
+# ------------------------------------------------------- spread of gamma_thr
+def test_threshold_spread_first_emissions_are_uniform():
+    """Leptons released at rest in a frozen uniform field reach gamma ~
+    E0 dt (n + 1) at step n, so each one's first emission marks its own
+    threshold.  With a spread sigma the thresholds are uniform in
+    gamma_thr (1 - sigma, 1 + sigma): no emission before gamma_thr (1 - sigma),
+    and first emissions spread evenly over the steps (chi-square over 18 bins,
+    within the window before any lepton emits a second time and before any
+    child reaches threshold)."""
+    e0, dt, gthr, f, sigma = 1.0, 0.5, 1000.0, 0.5, 0.3
+    g = oracle.OracleGap(n_cells=64, dx=1.0, dt=dt, boundary=oracle.PERIODIC, e0=e0,
+                         gamma_thr=gthr, f=f, l_gamma=0.0, weight=0.0, seed=2012055871,
+                         gamma_thr_spread=sigma)
+    n_pairs = 10000
+    g.seed(oracle.SEED_RANDOM, n_pairs, 1)
+    # p^{n+1/2} = (n + 1) E0 dt: step n passes the thresholds in (gamma_{n-1}, gamma_n]
+    lo = int(gthr * (1 - sigma) / (e0 * dt))   # first step past gamma_thr (1 - sigma)
+    hi = lo + 900                              # a child needs 900 steps to reach it
+    assert g.step(hi) == oracle.OK
+    em = np.diff(g.history()["photons_emitted"], prepend=0)
+    assert em[:lo].sum() == 0 and em[lo] > 0
+    n = np.arange(lo, hi)
+    gam = np.sqrt(1.0 + ((n + 1) * e0 * dt) ** 2) - np.sqrt(1.0 + (n * e0 * dt) ** 2)
+    expect = (2 * n_pairs * gam / (2 * sigma * gthr)).reshape(18, 50).sum(axis=1)
+    counts = em[lo:hi].reshape(18, 50).sum(axis=1)
+    chi2 = float(((counts - expect) ** 2 / expect).sum())
+    assert chi2 < 42.3, (chi2, counts, expect)  # 99.9% point of chi2 with 18 dof
+
+
+def test_threshold_spread_validation():
+    """sigma in [0, 1), and the lowest threshold minus gamma_pair keeps gamma >= 1."""
+    base = dict(n_cells=8, dx=1.0, dt=0.5, boundary=oracle.PERIODIC, e0=1.0, gamma_thr=100.0,
+                f=0.5, l_gamma=0.0, weight=1.0, seed=1)
+    assert oracle.validate(**base, gamma_thr_spread=0.0) == oracle.OK
+    assert oracle.validate(**base, gamma_thr_spread=0.49) == oracle.OK
+    for bad in (-0.1, 0.5, 1.0, float("nan")):
+        assert oracle.validate(**base, gamma_thr_spread=bad) == oracle.ERR_ARG, bad
