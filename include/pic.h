@@ -100,7 +100,16 @@ enum { PIC_ELECTRON = 0, PIC_POSITRON = 1 };
  *  history_rows rows kept in the device history ring (0 = 4096).
  *  j_m       imposed current density of the frame co-rotating with the
  *            star (section 7): Ampere's law becomes dE/dt = -(J - j_m);
- *            0 everywhere else.                                          */
+ *            0 everywhere else.
+ *  gamma_thr_spread  sigma in [0, 1): a spread of the threshold, which the
+ *            paper's conclusion names as absent from its model.  Each lepton
+ *            then emits at its own fixed threshold, uniform in
+ *            gamma_thr (1 - sigma, 1 + sigma): u = (top 53 bits of word 0 of
+ *            the Philox4x64-10 block at counter (0, 0, 3, 0), key (id, seed))
+ *            / 2^53, threshold gamma_thr (1 + sigma (2u - 1)) in binary64,
+ *            rounded to the particle precision.  gamma_pair stays
+ *            f * gamma_thr.  Requires (1 - f - sigma) gamma_thr >= 1.  0 is
+ *            the paper's single threshold.                              */
 typedef struct {
   int32_t  n_cells;
   double   dx, dt;
@@ -115,6 +124,7 @@ typedef struct {
   int32_t  sort_every, diag_every;
   int32_t  history_rows;
   double   j_m;
+  double   gamma_thr_spread;
 } pic_gap_params;
 
 /* One row per diagnosed step (the quantities of Figs. 1 and 3). */

@@ -64,7 +64,7 @@ struct PushCfg<double> {
 };
 constexpr int kStripes = 32;          // striped per-gap accumulators of the push kernel
 constexpr int kStripeStride = 16;     // doubles between stripes (one 128-byte line each)
-constexpr uint64_t kTagSeed = 1, kTagPhoton = 2;
+constexpr uint64_t kTagSeed = 1, kTagPhoton = 2, kTagThreshold = 3;
 
 // One gap, in device memory.  The host fills the constant part at creation;
 // kernels update the counters.  Particle and photon arrays are double
@@ -76,6 +76,7 @@ struct GapDev {
   int64_t one, domain, photon_step, cap, ph_cap;
   double dt, dx, weight, wq, e0;
   double jmdt;                       // imposed current times dt (section 7), 0 elsewhere
+  double sigma, gthr64, thr_lo;      // spread of gamma_thr, gamma_thr in binary64, lowest threshold
   double dtdx, gthr, gpair, pchild;  // values exactly representable in the particle type
   double gpair64, child_gamma64;     // binary64 pair energy; child gamma in the particle precision
   uint64_t seed;
@@ -165,6 +166,20 @@ __device__ __forceinline__ U64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_
   U64x4 o;
   o.v[0] = c0; o.v[1] = c1; o.v[2] = c2; o.v[3] = c3;
   return o;
+}
+
+// Emission threshold of lepton `id` under a spread sigma of gamma_thr, a fixed
+// property of the lepton, uniform in gamma_thr (1 - sigma, 1 + sigma): the top
+// 53 bits of word 0 of its tag-3 draw as a fraction u, then
+// gamma_thr (1 + sigma (2u - 1)) in binary64 with one rounding per operation,
+// rounded to the particle precision.
+template <typename T>
+__device__ __forceinline__ T lepton_threshold(uint64_t id, uint64_t seed, double gthr64,
+                                              double sigma) {
+  const U64x4 u = philox4x64_10(0, 0, kTagThreshold, 0, id, seed);
+  const double x = (double)(u.v[0] >> 11) * 0x1p-53;
+  const double a = 2.0 * x - 1.0;
+  return (T)(gthr64 * (1.0 + sigma * a));
 }
 
 // Accumulator a (0 kinetic energy, 1 lost energy, 2-3 absorbed electrons /

@@ -188,8 +188,10 @@ __device__ __forceinline__ void push_item(long long local, long long chunks0, lo
 // software-pipelined: the lepton state of the next chunk of the same gap is
 // loaded while the current one is pushed, and the E values of the current
 // chunk are requested before that prefetch, so waiting for them leaves the
-// prefetch in flight.  The gap's constants are read once per gap.
-template <typename T>
+// prefetch in flight.  The gap's constants are read once per gap.  kSpread
+// instantiates the per-lepton thresholds of a spread of gamma_thr; batches
+// without one run the kernel without that code.
+template <typename T, bool kSpread>
 __global__ __launch_bounds__(kBlock, PushCfg<T>::waves) void k_push(GapDev* __restrict__ gaps,
                                                  const long long* __restrict__ wi, int B,
                                                  int32_t* __restrict__ emit_cnt,
@@ -228,8 +230,10 @@ __global__ __launch_bounds__(kBlock, PushCfg<T>::waves) void k_push(GapDev* __re
   gptr<const T> E = nullptr;
   gptr<unsigned long long> F = nullptr;
   I ONE = 0;
-  T scale = 0, inv_scale = 0, dt_t = 0, dtdx = 0, gthr = 0, gpair = 0;
-  double w_d = 0.0;
+  T scale = 0, inv_scale = 0, dt_t = 0, dtdx = 0, gthr = 0, gpair = 0, thr_lo = 0;
+  double w_d = 0.0, sigma = 0.0, gthr64 = 0.0;
+  uint64_t kseed = 0;
+  gptr<uint64_t> idS[2] = {nullptr, nullptr};
   GapDev* __restrict__ G = gaps;
 
   // lepton state of the chunk about to be pushed (prefetched when `have`)
@@ -254,6 +258,7 @@ __global__ __launch_bounds__(kBlock, PushCfg<T>::waves) void k_push(GapDev* __re
         cellS[sp] = glb(G->cell[buf][sp]);
         offS[sp] = glb<T>(G->off[buf][sp]);
         pS[sp] = glb<T>(G->p[buf][sp]);
+        if constexpr (kSpread) idS[sp] = glb(G->id[buf][sp]);
       }
       E = ESrc<T>::of(G);
       F = glb<unsigned long long>((void*)G->F);
@@ -267,6 +272,12 @@ __global__ __launch_bounds__(kBlock, PushCfg<T>::waves) void k_push(GapDev* __re
       gthr = (T)G->gthr;
       gpair = (T)G->gpair;
       w_d = G->weight;
+      if constexpr (kSpread) {
+        sigma = G->sigma;
+        gthr64 = G->gthr64;
+        thr_lo = (T)G->thr_lo;
+        kseed = G->seed;
+      }
       have = false;
     }
     if (tid == 0) emit_cnt[w] = 0;
@@ -277,6 +288,7 @@ __global__ __launch_bounds__(kBlock, PushCfg<T>::waves) void k_push(GapDev* __re
     gptr<int32_t> cellA = cellS[s];
     gptr<T> offA = offS[s];
     gptr<T> pA = pS[s];
+    gptr<uint64_t> idA = idS[s];
     if (!have) {
       // unconditional loads (slots past the end read slot 0 and are discarded),
       // so that all of them are in flight at once
@@ -392,9 +404,14 @@ __global__ __launch_bounds__(kBlock, PushCfg<T>::waves) void k_push(GapDev* __re
         if (!isfinite(pn) || !isfinite(gam)) bad = true;
         if (keep) {
           // emission: repeated subtraction of gamma_pair while at or above threshold
+          // (the lepton's own threshold under a spread of gamma_thr, needed only at
+          // or above the lowest one)
+          T thr = gthr;
+          if constexpr (kSpread)
+            if (sigma != 0.0 && gam >= thr_lo) thr = lepton_threshold<T>(idA[i], kseed, gthr64, sigma);
           int k = 0;
           T gm = gam;
-          while (gm >= gthr && k <= kMaxEmit) {
+          while (gm >= thr && k <= kMaxEmit) {
             gm = gm - gpair;
             ++k;
           }
@@ -1587,13 +1604,20 @@ static int grid_for(long long want, int cap) {
   return (int)(want < 1 ? 1 : (want < cap ? want : cap));
 }
 
+template <typename T, bool kSpread>
+static void push_kernel(const StepLaunch& L) {
+  hipLaunchKernelGGL((k_push<T, kSpread>), dim3(kPushGrid), dim3(kBlock), 0, L.stream, L.gaps, L.wi,
+                     L.B, L.emit_cnt, L.emit_ent, L.wg_emit, L.stripes);
+}
+
 hipError_t launch_push(const StepLaunch& L, bool mixed) {
-  if (mixed)
-    hipLaunchKernelGGL(k_push<float>, dim3(kPushGrid), dim3(kBlock), 0, L.stream, L.gaps, L.wi, L.B,
-                       L.emit_cnt, L.emit_ent, L.wg_emit, L.stripes);
-  else
-    hipLaunchKernelGGL(k_push<double>, dim3(kPushGrid), dim3(kBlock), 0, L.stream, L.gaps, L.wi, L.B,
-                       L.emit_cnt, L.emit_ent, L.wg_emit, L.stripes);
+  if (mixed) {
+    if (L.spread) push_kernel<float, true>(L);
+    else push_kernel<float, false>(L);
+  } else {
+    if (L.spread) push_kernel<double, true>(L);
+    else push_kernel<double, false>(L);
+  }
   return hipGetLastError();
 }
 

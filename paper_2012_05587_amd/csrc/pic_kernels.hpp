@@ -21,6 +21,7 @@ struct StepLaunch {
   uint32_t* wg_emit;   // emitters listed by each push workgroup, kPushGrid entries (device)
   double* stripes;     // striped push tallies, B x 4 x kStripes x kStripeStride (device)
   hipStream_t stream;
+  bool spread;         // some gap draws per-lepton thresholds (gamma_thr_spread > 0)
 };
 
 hipError_t launch_step(const StepLaunch& L, bool mixed);

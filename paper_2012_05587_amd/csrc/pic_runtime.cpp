@@ -88,6 +88,10 @@ pic_status validate(const pic_gap_params* p) {
   if (!(p->l_gamma >= 0.0) || !std::isfinite(p->l_gamma)) return PIC_ERR_ARG;
   if (!(p->weight >= 0.0) || !std::isfinite(p->weight)) return PIC_ERR_ARG;
   if (!std::isfinite(p->j_m)) return PIC_ERR_ARG;
+  if (!(p->gamma_thr_spread >= 0.0) || !(p->gamma_thr_spread < 1.0)) return PIC_ERR_ARG;
+  if (p->gamma_thr_spread > 0.0 && std::isfinite(p->gamma_thr) &&
+      !((1.0 - p->f - p->gamma_thr_spread) * p->gamma_thr >= 1.0))
+    return PIC_ERR_ARG;
   if (p->capacity < 1 || p->capacity >= (int64_t)1 << 31) return PIC_ERR_ARG;
   if (p->photon_capacity < 0 || p->photon_capacity >= (int64_t)1 << 31) return PIC_ERR_ARG;
   if (p->l_gamma > 0.0 && p->photon_capacity < 1) return PIC_ERR_ARG;
@@ -170,6 +174,8 @@ void fill_precision_constants(GapDev& G, const pic_gap_params& p) {
   const T pchild = std::sqrt(ghalf * ghalf - (T)1);
   G.dtdx = (double)(T)(p.dt / p.dx);
   G.gthr = (double)gthr;
+  // the lowest threshold a lepton can draw: the spread formula at 2u - 1 = -1
+  G.thr_lo = (double)(T)(p.gamma_thr * (1.0 + p.gamma_thr_spread * -1.0));
   G.gpair = (double)gpair;
   G.pchild = (double)pchild;
   G.child_gamma64 = (double)std::sqrt((T)1 + pchild * pchild);
@@ -324,6 +330,8 @@ pic_status create_batch(const pic_gap_params* params, int n_gaps, void* d_ws, si
     G.wq = std::ldexp(p.weight, -G.K);
     G.e0 = p.e0;
     G.jmdt = p.j_m * p.dt;
+    G.sigma = p.gamma_thr_spread;
+    G.gthr64 = p.gamma_thr;
     G.gpair64 = p.f * p.gamma_thr;
     G.seed = p.seed;
     if (p.precision == PIC_MIXED) fill_precision_constants<float>(G, p);
@@ -390,6 +398,8 @@ pic_status create_batch(const pic_gap_params* params, int n_gaps, void* d_ws, si
   b->launch.wg_emit = reinterpret_cast<uint32_t*>(ws + L.wg_emit);
   b->launch.stripes = reinterpret_cast<double*>(ws + L.stripes);
   b->launch.stream = b->stream;
+  b->launch.spread = false;
+  for (int i = 0; i < n_gaps; ++i) b->launch.spread |= params[i].gamma_thr_spread > 0.0;
   if (st == PIC_OK &&
       hipMemcpy(b->launch.cwi, cwi.data(), sizeof(long long) * cwi.size(), hipMemcpyHostToDevice) != hipSuccess)
     st = PIC_ERR_DEVICE;

@@ -448,6 +448,49 @@ def test_batch_mixed_matches_single_gaps():
         pc.compare_particles(view, go, PTOL[workloads.MIXED])
 
 
+# ----------------------------------------------------- spread of gamma_thr
+@pytest.mark.parametrize("name", ["c1_fp64_reference_gap", "c3_mixed_single_gap"])
+def test_threshold_spread_full_run(name):
+    """Configuration 1 (binary64) and 3 (mixed) with each lepton's threshold
+    drawn uniform in gamma_thr (1 +/- 0.3), over the full 2000 steps."""
+    cfg = dict(workloads.config(name), gamma_thr_spread=0.3)
+    gg, go = _run_pair(cfg, 2000)
+    stats, err, exact = _check_all(gg, go, cfg["precision"])
+    assert gg.read_history()["photons_emitted"][-1] > 5000
+    print("p err", stats, "E err", err, "E bitwise", exact)
+
+
+@pytest.mark.parametrize("precision", [workloads.FP64, workloads.MIXED])
+def test_threshold_spread_in_place_periodic(precision):
+    cfg = dict(n_cells=300, dx=1.0, dt=0.45, boundary=workloads.PERIODIC, e0=30.0,
+               gamma_thr=60.0, f=0.25, l_gamma=0.0, weight=0.2, seed=78, precision=precision,
+               n_pairs=200, macro_per_pair=3, capacity=200_000, photon_capacity=0,
+               gamma_thr_spread=0.5)
+    gg, go = _run_pair(cfg, 400)
+    _check_all(gg, go, precision)
+
+
+def test_batch_with_and_without_spread():
+    """A batch where one gap has a spread runs the per-lepton-threshold push
+    for all; the gaps without one give the same results as alone."""
+    import paper_2012_05587_amd as P
+    gaps = workloads.batched_scan(n_gaps=3, precision=workloads.MIXED, steps=120)
+    for i, c in enumerate(gaps):
+        c.update(n_cells=min(c["n_cells"], 3000), n_pairs=min(c["n_pairs"], 400),
+                 e0=min(c["e0"], 120.0), gamma_thr=max(c["gamma_thr"], 150.0),
+                 capacity=1_000_000, photon_capacity=1_000_000, history_rows=200,
+                 gamma_thr_spread=0.2 if i == 1 else 0.0)
+    b = P.Batch([pc.gpu_params(c) for c in gaps])
+    for view, c in zip(b.gaps, gaps):
+        view.seed_particles(0, c["n_pairs"], 1)
+    assert np.all(b.step_n(120, statuses=True) == 0)
+    for view, c in zip(b.gaps, gaps):
+        go = pc.make_oracle(c)
+        assert go.step(120) == 0
+        pc.compare_history(view.read_history(), go.history())
+        pc.compare_particles(view, go, PTOL[workloads.MIXED])
+
+
 # ------------------------------------------------- full-size sampled parity
 def test_config2_full_size_sampled_step():
     """At configuration 2's full slot count and the benchmark's launch shape:
