@@ -17,6 +17,7 @@ _LIB = None
 FP64, MIXED = 0, 1
 PERIODIC, ABSORBING = 0, 1
 SEED_RANDOM, SEED_LATTICE = 0, 1
+SHAPE_LINEAR, SHAPE_QUADRATIC = 0, 1
 OK, ERR_ARG, ERR_CAPACITY, ERR_STATE, ERR_NONFINITE, ERR_EMISSION = 0, -1, -3, -5, -6, -7
 
 
@@ -26,7 +27,7 @@ class Params(C.Structure):
         ("boundary", C.c_int32), ("e0", C.c_double), ("gamma_thr", C.c_double),
         ("f", C.c_double), ("l_gamma", C.c_double), ("weight", C.c_double),
         ("seed", C.c_uint64), ("precision", C.c_int32), ("capacity", C.c_int64),
-        ("j_m", C.c_double), ("gamma_thr_spread", C.c_double),
+        ("j_m", C.c_double), ("gamma_thr_spread", C.c_double), ("shape", C.c_int32),
     ]
 
 
@@ -88,9 +89,9 @@ def _ptr(a):
 
 
 def make_params(n_cells, dx, dt, boundary, e0, gamma_thr, f, l_gamma, weight, seed,
-                precision=FP64, capacity=0, j_m=0.0, gamma_thr_spread=0.0):
+                precision=FP64, capacity=0, j_m=0.0, gamma_thr_spread=0.0, shape=0):
     return Params(n_cells, dx, dt, boundary, e0, gamma_thr, f, l_gamma, weight, seed,
-                  precision, capacity, j_m, gamma_thr_spread)
+                  precision, capacity, j_m, gamma_thr_spread, shape)
 
 
 def validate(**kw):

@@ -196,6 +196,10 @@ int orc_validate(const orc_params* p) {
   if (p->gamma_thr_spread > 0.0 && isfinite(p->gamma_thr) &&
       !((1.0 - p->f - p->gamma_thr_spread) * p->gamma_thr >= 1.0))
     return ORC_ERR_ARG;
+  if (p->shape != ORC_SHAPE_LINEAR && p->shape != ORC_SHAPE_QUADRATIC) return ORC_ERR_ARG;
+  /* a three-node shape reaches past a wall: periodic gaps only */
+  if (p->shape == ORC_SHAPE_QUADRATIC && (p->boundary != ORC_BC_PERIODIC || p->n_cells < 4))
+    return ORC_ERR_ARG;
   if (p->precision != ORC_FP64 && p->precision != ORC_MIXED) return ORC_ERR_ARG;
   if (p->capacity < 0) return ORC_ERR_ARG;
   return ORC_OK;
@@ -314,6 +318,25 @@ static int32_t wrap_cell(const orc_gap* g, int32_t c) {
   return c;
 }
 
+/* Quadratic-spline (triangular-shaped cloud) weights of a lepton at X, in
+ * units of 2^-K cells from some node.  Its nearest node is j = floor(X/2^K +
+ * 1/2) and delta = X/2^K - j lies in [-1/2, 1/2).  The spline gives the
+ * nodes j-1, j, j+1 the charge fractions (1/2 - delta)^2 / 2,
+ * 3/4 - delta^2, (1/2 + delta)^2 / 2.  As integers in 2^-K: the outer two
+ * are rounded down, the middle one takes the rest, so the three sum to 2^K
+ * exactly and the deposit built from them conserves charge exactly. */
+static void tsc_weights(const orc_gap* g, int64_t X, int64_t* j, int64_t W[3]) {
+  const int64_t ONE = g->one, HALF = g->one / 2;
+  int64_t jj = (X + HALF) >= 0 ? (X + HALF) / ONE : -((-(X + HALF) + ONE - 1) / ONE);
+  const int64_t delta = X - jj * ONE;
+  const unsigned __int128 a = (unsigned __int128)(HALF - delta);
+  const unsigned __int128 b = (unsigned __int128)(HALF + delta);
+  W[0] = (int64_t)((a * a) >> (g->K + 1));
+  W[2] = (int64_t)((b * b) >> (g->K + 1));
+  W[1] = ONE - W[0] - W[2];
+  *j = jj;
+}
+
 /* E at cell centre c seen by the gather, with the boundary ghosts:
  * periodic wraps, absorbing repeats the edge value (zero gradient). */
 static double e_ghost(const orc_gap* g, int32_t c) {
@@ -430,11 +453,29 @@ static int step_once(orc_gap* g) {
       int32_t c = S->cell[i];
       int64_t oq = S->offq[i];
       double o = ldexp((double)oq, -g->K);
-      /* gather: E averaged to the nodes c and c+1, then linear in the offset */
-      double Em = R(g, e_ghost(g, c - 1)), Ec = R(g, e_ghost(g, c)), Ep = R(g, e_ghost(g, c + 1));
-      double el = R(g, 0.5 * R(g, Em + Ec));
-      double er = R(g, 0.5 * R(g, Ec + Ep));
-      double Epart = R(g, el + R(g, o * R(g, er - el)));
+      double Epart;
+      int64_t jo = 0, Wo[3] = {0, 0, 0};
+      if (P->shape == ORC_SHAPE_LINEAR) {
+        /* gather: E averaged to the nodes c and c+1, then linear in the offset */
+        double Em = R(g, e_ghost(g, c - 1)), Ec = R(g, e_ghost(g, c)), Ep = R(g, e_ghost(g, c + 1));
+        double el = R(g, 0.5 * R(g, Em + Ec));
+        double er = R(g, 0.5 * R(g, Ec + Ep));
+        Epart = R(g, el + R(g, o * R(g, er - el)));
+      } else {
+        /* gather: E averaged to the nodes c+jo-1, c+jo, c+jo+1 (node k lies
+         * between cells k-1 and k), weighted by the lepton's own spline
+         * weights; jo is 0 or 1 */
+        tsc_weights(g, oq, &jo, Wo);
+        const int32_t k0 = c + (int32_t)jo - 1;
+        double e[4];
+        for (int k = 0; k < 4; ++k) e[k] = R(g, e_ghost(g, k0 - 1 + k));
+        double en[3], sw[3];
+        for (int k = 0; k < 3; ++k) {
+          en[k] = R(g, 0.5 * R(g, e[k] + e[k + 1]));
+          sw[k] = R(g, ldexp((double)Wo[k], -g->K));
+        }
+        Epart = R(g, R(g, R(g, sw[0] * en[0]) + R(g, sw[1] * en[1])) + R(g, sw[2] * en[2]));
+      }
       /* push: p^{n+1/2} = p^{n-1/2} + q E dt */
       double p = R(g, S->p[i] + R(g, qdt * Epart));
       double gam = R(g, sqrt(R(g, 1.0 + R(g, p * p))));
@@ -445,7 +486,25 @@ static int step_once(orc_gap* g) {
       int64_t dq = (int64_t)rint(d * scale);
       int64_t nq = oq + dq;
       int keep = 1;
-      if (nq >= ONE) {
+      if (P->shape == ORC_SHAPE_QUADRATIC) {
+        /* charge-conserving deposit of the spline: the flux through cell k
+         * (between nodes k and k+1) is the charge that left the nodes <= k,
+         * the running sum of old minus new weight over nodes from the
+         * leftmost one either spline touches; positions relative to node c */
+        int64_t jn, Wn[3];
+        tsc_weights(g, nq, &jn, Wn);
+        const int64_t lo = (jo < jn ? jo : jn) - 1, hi = (jo > jn ? jo : jn) + 1;
+        int64_t run = 0;
+        for (int64_t k = lo; k < hi; ++k) {
+          const int64_t wo = (k >= jo - 1 && k <= jo + 1) ? Wo[k - jo + 1] : 0;
+          const int64_t wn = (k >= jn - 1 && k <= jn + 1) ? Wn[k - jn + 1] : 0;
+          run += wo - wn;
+          g->F[wrap_cell(g, c + (int32_t)k)] += q * run;
+        }
+        /* the lepton's own cell and offset after the move (periodic) */
+        if (nq >= ONE) { nq -= ONE; c = wrap_cell(g, c + 1); }
+        else if (nq < 0) { nq += ONE; c = wrap_cell(g, c - 1); }
+      } else if (nq >= ONE) {
         g->F[c] += q * (ONE - oq);
         int32_t c1 = c + 1;
         nq -= ONE;
@@ -629,7 +688,7 @@ int orc_read_photons(const orc_gap* g, int64_t max_n, int64_t* xq, int64_t* conv
   return ORC_OK;
 }
 
-/* rho: cloud-in-cell charge per node, integrated over a cell width
+/* rho: charge per node by the particle shape, integrated over a cell width
  * (Gauss: E_c - E_{c-1} = rho_c), nodes 0..n_cells (node n_cells is the
  * right wall; periodic folds it onto node 0). */
 int orc_read_fields(const orc_gap* g, double* E, double* rho, int64_t* last_flux) {
@@ -643,6 +702,16 @@ int orc_read_fields(const orc_gap* g, double* E, double* rho, int64_t* last_flux
       const int64_t q = s == 0 ? -1 : 1;
       for (int64_t i = 0; i < g->sp[s].n; ++i) {
         int32_t c = g->sp[s].cell[i];
+        if (g->prm.shape == ORC_SHAPE_QUADRATIC) {
+          int64_t j, W[3];
+          tsc_weights(g, g->sp[s].offq[i], &j, W);
+          for (int k = 0; k < 3; ++k) {
+            int32_t node = c + (int32_t)j - 1 + k;     /* periodic: fold into [0, N) */
+            node = node < 0 ? node + N : (node >= N ? node - N : node);
+            acc[node] += q * W[k];
+          }
+          continue;
+        }
         acc[c] += q * (g->one - g->sp[s].offq[i]);
         acc[c + 1] += q * g->sp[s].offq[i];
       }

@@ -28,6 +28,7 @@ enum { ORC_OK = 0, ORC_ERR_ARG = -1, ORC_ERR_CAPACITY = -3, ORC_ERR_STATE = -5,
 enum { ORC_BC_PERIODIC = 0, ORC_BC_ABSORBING = 1 };
 enum { ORC_FP64 = 0, ORC_MIXED = 1 };
 enum { ORC_SEED_RANDOM = 0, ORC_SEED_LATTICE = 1 };
+enum { ORC_SHAPE_LINEAR = 0, ORC_SHAPE_QUADRATIC = 1 };
 
 typedef struct {
   int32_t  n_cells;
@@ -46,6 +47,9 @@ typedef struct {
   double   gamma_thr_spread; /* sigma in [0, 1): each lepton's threshold is fixed, uniform
                            in gamma_thr (1 - sigma, 1 + sigma), drawn from its id (the
                            spread the paper's conclusion names); 0 = one threshold */
+  int32_t  shape;       /* particle shape: ORC_SHAPE_LINEAR (cloud in cell) or
+                           ORC_SHAPE_QUADRATIC (quadratic spline over three nodes,
+                           periodic gaps only) */
 } orc_params;
 
 typedef struct {
