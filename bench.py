@@ -58,7 +58,7 @@ def _params(P, c):
                          c["f"], c["l_gamma"], c["weight"], int(c["capacity"]),
                          int(c["photon_capacity"]), c["seed"], c["precision"],
                          c.get("sort_every", 0), c.get("diag_every", 0), c.get("history_rows", 0),
-                         c.get("j_m", 0.0), c.get("gamma_thr_spread", 0.0))
+                         c.get("j_m", 0.0), c.get("gamma_thr_spread", 0.0), c.get("shape", 0))
 
 
 def _workload(name, precision=None):
@@ -67,10 +67,11 @@ def _workload(name, precision=None):
         gaps = workloads.batched_scan(256, precision=workloads.MIXED if precision is None else precision)
     elif name == "n1_corotating":
         gaps = [workloads.corotating_gap(precision=workloads.MIXED if precision is None else precision)]
-    elif name in ("n3_uniform", "n4_spread"):
+    elif name in ("n3_uniform", "n4_spread", "n4_spline"):
         gaps = [workloads.uniform_cascade(
             0.1, precision=workloads.MIXED if precision is None else precision,
-            gamma_thr_spread=0.25 if name == "n4_spread" else 0.0)]
+            gamma_thr_spread=0.25 if name == "n4_spread" else 0.0,
+            shape=1 if name == "n4_spline" else 0)]
     elif name == "n4_nonuniform":
         gaps = [workloads.nonuniform_gap(precision=workloads.MIXED if precision is None else precision)]
     else:
@@ -191,7 +192,7 @@ def _oracle_gap(args):
     sys.path.insert(0, ROOT)
     import oracle
     kw = {k: c[k] for k in workloads.GAP_KEYS}
-    for k in ("j_m", "gamma_thr_spread"):
+    for k in ("j_m", "gamma_thr_spread", "shape"):
         if c.get(k):
             kw[k] = c[k]
     o = oracle.OracleGap(**kw, capacity=0)
@@ -388,7 +389,8 @@ def main():
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default: whole job)")
     ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--workload", default="c4_batched",
-                    choices=["c4_batched", "n1_corotating", "n3_uniform", "n4_spread", "n4_nonuniform"]
+                    choices=["c4_batched", "n1_corotating", "n3_uniform", "n4_spread", "n4_spline",
+                             "n4_nonuniform"]
                     + sorted(workloads.CONFIGS))
     ap.add_argument("--sort-every", type=int, default=None,
                     help="re-sort cadence for every gap (0 = tuned while running; default: the workload's)")
@@ -481,9 +483,10 @@ def main():
         cfg.update(n_cells=gaps[0]["n_cells"], seed_pairs=gaps[0]["n_pairs"], e0=gaps[0]["e0"],
                    gamma_thr=gaps[0]["gamma_thr"], l_gamma=gaps[0]["l_gamma"],
                    peak_leptons=main_run["peak_leptons"])
-        if gaps[0].get("gamma_thr_spread") or args.workload == "n3_uniform":
+        if args.workload in ("n3_uniform", "n4_spread", "n4_spline"):
             cfg.update(f=gaps[0]["f"], dt=gaps[0]["dt"], dx=gaps[0]["dx"], boundary="periodic",
                        gamma_thr_spread=gaps[0].get("gamma_thr_spread", 0.0),
+                       shape="quadratic spline" if gaps[0].get("shape") else "cloud in cell",
                        seed="one pair per cell at rest, random positions")
         if gaps[0].get("E_init") is not None:
             cfg.update(e_profile="E0 exp(-x / (L/4)) from the surface wall", dt=gaps[0]["dt"],

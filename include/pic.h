@@ -64,6 +64,7 @@ enum {
 enum { PIC_BC_PERIODIC = 0, PIC_BC_ABSORBING = 1 };
 enum { PIC_FP64 = 0, PIC_MIXED = 1 };
 enum { PIC_SEED_RANDOM = 0, PIC_SEED_LATTICE = 1 };
+enum { PIC_SHAPE_LINEAR = 0, PIC_SHAPE_QUADRATIC = 1 };
 enum { PIC_ELECTRON = 0, PIC_POSITRON = 1 };
 
 /* Parameters of one gap.  Paper sections 2-3 give E0, gamma_thr, f, the
@@ -109,7 +110,18 @@ enum { PIC_ELECTRON = 0, PIC_POSITRON = 1 };
  *            / 2^53, threshold gamma_thr (1 + sigma (2u - 1)) in binary64,
  *            rounded to the particle precision.  gamma_pair stays
  *            f * gamma_thr.  Requires (1 - f - sigma) gamma_thr >= 1.  0 is
- *            the paper's single threshold.                              */
+ *            the paper's single threshold.
+ *  shape     particle shape, the same for every gap of a batch.
+ *            PIC_SHAPE_LINEAR (0): cloud in cell, charge on the two nodes
+ *            of the lepton's cell, node-averaged linear gather.
+ *            PIC_SHAPE_QUADRATIC (1): quadratic spline over the nearest
+ *            node j = floor(x + 1/2) and its neighbours, with d = x - j the
+ *            fractions (1/2 - d)^2/2, 3/4 - d^2, (1/2 + d)^2/2 held as
+ *            integers in 2^-K (outer two rounded down, the middle one the
+ *            rest); the flux is the running sum of their change, so Gauss's
+ *            law stays exact, and the gather weights node-averaged E with
+ *            the same fractions.  Periodic gaps of at least 4 cells only
+ *            (the spline reaches 3/2 cells).                              */
 typedef struct {
   int32_t  n_cells;
   double   dx, dt;
@@ -125,6 +137,7 @@ typedef struct {
   int32_t  history_rows;
   double   j_m;
   double   gamma_thr_spread;
+  int32_t  shape;
 } pic_gap_params;
 
 /* One row per diagnosed step (the quantities of Figs. 1 and 3). */

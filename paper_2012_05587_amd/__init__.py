@@ -51,6 +51,7 @@ class GapParams(C.Structure):
         ("capacity", C.c_int64), ("photon_capacity", C.c_int64), ("seed", C.c_uint64),
         ("precision", C.c_int32), ("sort_every", C.c_int32), ("diag_every", C.c_int32),
         ("history_rows", C.c_int32), ("j_m", C.c_double), ("gamma_thr_spread", C.c_double),
+        ("shape", C.c_int32),
     ]
 
 
@@ -153,10 +154,10 @@ def _ptr(a):
 
 def make_params(n_cells, dx, dt, boundary, e0, gamma_thr, f, l_gamma, weight, capacity,
                 photon_capacity=0, seed=0, precision=FP64, sort_every=0, diag_every=0,
-                history_rows=0, j_m=0.0, gamma_thr_spread=0.0):
+                history_rows=0, j_m=0.0, gamma_thr_spread=0.0, shape=0):
     return GapParams(n_cells, dx, dt, boundary, e0, gamma_thr, f, l_gamma, weight, capacity,
                      photon_capacity, seed, precision, sort_every, diag_every, history_rows, j_m,
-                     gamma_thr_spread)
+                     gamma_thr_spread, shape)
 
 
 def pic_validate_params(params):

@@ -72,7 +72,7 @@ constexpr uint64_t kTagSeed = 1, kTagPhoton = 2, kTagThreshold = 3;
 struct GapDev {
   // ---- constants
   int32_t n_cells, boundary, K, table_len;
-  int32_t precision, diag_every, hist_rows, pad0;
+  int32_t precision, diag_every, hist_rows, shape;
   int64_t one, domain, photon_step, cap, ph_cap;
   double dt, dx, weight, wq, e0;
   double jmdt;                       // imposed current times dt (section 7), 0 elsewhere

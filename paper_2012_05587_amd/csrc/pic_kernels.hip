@@ -164,6 +164,73 @@ __device__ __forceinline__ void load_e3(gptr<const T> E, int cl, bool periodic, 
   ep = E[cp];
 }
 
+// E at the four cells around the nodes jo-1, jo, jo+1 of the quadratic
+// spline of a lepton in cell cl (jo = 1 when its offset is at least 1/2):
+// cells cl+jo-2 .. cl+jo+1, periodic (the spline runs on periodic gaps only).
+template <typename T>
+__device__ __forceinline__ void load_e4(gptr<const T> E, int cl, T off, int nc, T& e0, T& e1,
+                                        T& e2, T& e3) {
+  const int c = cl == kDead ? 0 : cl;
+  const int k0 = c + (off >= (T)0.5 ? 1 : 0) - 2;
+  int i0 = k0, i1 = k0 + 1, i2 = k0 + 2, i3 = k0 + 3;
+  i0 = i0 < 0 ? i0 + nc : i0;
+  i1 = i1 < 0 ? i1 + nc : i1;
+  i2 = i2 >= nc ? i2 - nc : i2;
+  i3 = i3 >= nc ? i3 - nc : i3;
+  e0 = E[i0];
+  e1 = E[i1];
+  e2 = E[i2];
+  e3 = E[i3];
+}
+
+// Quadratic-spline weights of a lepton at X (units 2^-K cells from a node):
+// nearest node j = floor(X / 2^K + 1/2), delta = X - j 2^K in [-1/2, 1/2) 2^K;
+// the outer nodes get floor((2^(K-1) -/+ delta)^2 / 2^(K+1)), the middle one
+// the rest of 2^K, so the three sum to 2^K exactly.
+template <typename I>
+__device__ __forceinline__ void spline_weights(I X, I ONE, int K, int& j, long long& wl,
+                                               long long& wc, long long& wr) {
+  const I HALF = ONE >> 1;
+  const I t = X + HALF;
+  j = t < 0 ? -1 : (t >= 2 * ONE ? 2 : (t >= ONE ? 1 : 0));
+  const I delta = X - (I)j * ONE;
+  const unsigned long long a = (unsigned long long)(HALF - delta);
+  const unsigned long long b = (unsigned long long)(HALF + delta);
+  if constexpr (sizeof(I) == 4) {
+    wl = (long long)((a * a) >> (K + 1));
+    wr = (long long)((b * b) >> (K + 1));
+  } else {
+    wl = (long long)(((unsigned __int128)a * a) >> (K + 1));
+    wr = (long long)(((unsigned __int128)b * b) >> (K + 1));
+  }
+  wc = (long long)ONE - wl - wr;
+}
+
+// E at a lepton at offset o (oq on the 2^-K grid) of its cell, from the E
+// values around it: linear shape (em, ec, ep = cells c-1, c, c+1): the node
+// averages interpolated linearly; spline (em..ex = cells c+j-2 .. c+j+1):
+// the averages at the nodes j-1, j, j+1 weighted by the lepton's integer
+// weights, which are exact in the particle type.
+template <typename T, typename I, bool kSpline>
+__device__ __forceinline__ T gather_e(T o, I oq, I ONE, int K, T inv_scale, T em, T ec, T ep,
+                                      T ex) {
+  const T half_t = (T)0.5;
+  if constexpr (kSpline) {
+    int j;
+    long long w0, w1, w2;
+    spline_weights<I>(oq, ONE, K, j, w0, w1, w2);
+    const T en0 = half_t * (em + ec);
+    const T en1 = half_t * (ec + ep);
+    const T en2 = half_t * (ep + ex);
+    const T sw0 = (T)w0 * inv_scale, sw1 = (T)w1 * inv_scale, sw2 = (T)w2 * inv_scale;
+    return (sw0 * en0 + sw1 * en1) + sw2 * en2;
+  } else {
+    const T el = half_t * (em + ec);
+    const T er = half_t * (ec + ep);
+    return el + o * (er - el);
+  }
+}
+
 // Lepton range of work item w of gap G: species s, indices [i0, i1).
 __device__ __forceinline__ void push_item(long long local, long long chunks0, long long n0,
                                           long long n1, int& s, long long& i0, long long& i1) {
@@ -189,9 +256,10 @@ __device__ __forceinline__ void push_item(long long local, long long chunks0, lo
 // loaded while the current one is pushed, and the E values of the current
 // chunk are requested before that prefetch, so waiting for them leaves the
 // prefetch in flight.  The gap's constants are read once per gap.  kSpread
-// instantiates the per-lepton thresholds of a spread of gamma_thr; batches
-// without one run the kernel without that code.
-template <typename T, bool kSpread>
+// instantiates the per-lepton thresholds of a spread of gamma_thr, kSpline
+// the quadratic-spline shape (periodic gaps); batches without them run the
+// kernel without that code.
+template <typename T, bool kSpread, bool kSpline>
 __global__ __launch_bounds__(kBlock, PushCfg<T>::waves) void k_push(GapDev* __restrict__ gaps,
                                                  const long long* __restrict__ wi, int B,
                                                  int32_t* __restrict__ emit_cnt,
@@ -205,6 +273,10 @@ __global__ __launch_bounds__(kBlock, PushCfg<T>::waves) void k_push(GapDev* __re
   __shared__ double s_d[8];
   __shared__ unsigned long long s_u[8];
   __shared__ int s_emit_n, s_emit_k;
+  // leptons of the chunk that need their own threshold, and the thresholds
+  __shared__ uint32_t s_cand[kSpread ? kChunk : 1];
+  __shared__ T s_thr[kSpread ? kChunk : 1];
+  __shared__ int s_ncand;
 
   // the flux tile is kept zero between chunks (each flush clears what it
   // read), so it is zeroed once here
@@ -232,6 +304,7 @@ __global__ __launch_bounds__(kBlock, PushCfg<T>::waves) void k_push(GapDev* __re
   I ONE = 0;
   T scale = 0, inv_scale = 0, dt_t = 0, dtdx = 0, gthr = 0, gpair = 0, thr_lo = 0;
   double w_d = 0.0, sigma = 0.0, gthr64 = 0.0;
+  int Kb = 0;  // offset grid bits (the spline's weights)
   uint64_t kseed = 0;
   gptr<uint64_t> idS[2] = {nullptr, nullptr};
   GapDev* __restrict__ G = gaps;
@@ -272,6 +345,7 @@ __global__ __launch_bounds__(kBlock, PushCfg<T>::waves) void k_push(GapDev* __re
       gthr = (T)G->gthr;
       gpair = (T)G->gpair;
       w_d = G->weight;
+      if constexpr (kSpline) Kb = G->K;
       if constexpr (kSpread) {
         sigma = G->sigma;
         gthr64 = G->gthr64;
@@ -307,15 +381,22 @@ __global__ __launch_bounds__(kBlock, PushCfg<T>::waves) void k_push(GapDev* __re
 #pragma unroll
     for (int j = 0; j < kItems; ++j)
       if (cl[j] != kDead) { mn = min(mn, cl[j]); mx = max(mx, cl[j]); }
-    if (tid == 0) { s_emit_n = 0; s_emit_k = 0; }
+    if (tid == 0) {
+      s_emit_n = 0;
+      s_emit_k = 0;
+      if constexpr (kSpread) s_ncand = 0;
+    }
     block_minmax_pp(mn, mx, s_red, parity);
     // E at the cells around each lepton (dead slots read cell 0), requested
     // for the first group of items now and for later groups just before
     // they are pushed
     constexpr int kEG = PushCfg<T>::e_group;
-    T Em[kItems], Ec[kItems], Ep[kItems];
+    T Em[kItems], Ec[kItems], Ep[kItems], Ex[kItems];
 #pragma unroll
-    for (int j = 0; j < kEG; ++j) load_e3(E, cl[j], periodic, nc, Em[j], Ec[j], Ep[j]);
+    for (int j = 0; j < kEG; ++j) {
+      if constexpr (kSpline) load_e4(E, cl[j], ov[j], nc, Em[j], Ec[j], Ep[j], Ex[j]);
+      else load_e3(E, cl[j], periodic, nc, Em[j], Ec[j], Ep[j]);
+    }
     // prefetch the next chunk of this gap; the loads are issued whether or
     // not there is one (then they read slot 0 and are discarded), so the
     // wait for the E values above never waits for them
@@ -341,65 +422,134 @@ __global__ __launch_bounds__(kBlock, PushCfg<T>::waves) void k_push(GapDev* __re
       }
     }
     if (mx >= mn) {  // uniform: some lepton of this chunk is alive
-      const int base = mn - 1;
-      const int span = mx - mn + 3;
+      // cells a lepton's current can reach: c-1..c+1 (linear), c-2..c+2 (spline)
+      constexpr int kReach = kSpline ? 2 : 1;
+      const int base = mn - kReach;
+      const int span = mx - mn + 1 + 2 * kReach;
       const bool lds = span <= kTile;
       const T qdt = s == 0 ? -dt_t : dt_t;
-      const T one_t = (T)1, half_t = (T)0.5;
+      const T one_t = (T)1;
       bool bad = false, emit_bad = false;
+      // Under a spread of gamma_thr, every item is pushed first; the leptons
+      // at or above the lowest threshold are listed in LDS and the workgroup
+      // draws their thresholds together, one lepton per thread, instead of
+      // each wave drawing for whichever of its lanes need it.
+      [[maybe_unused]] T pre_pn[kItems], pre_gam[kItems];
+      [[maybe_unused]] int cpos[kItems];
+      if constexpr (kSpread) {
+        static_assert(PushCfg<T>::e_group == kItems, "the E values of every item are loaded here");
+#pragma unroll
+        for (int j = 0; j < kItems; ++j) {
+          const T o = ov[j];
+          const I oq = (I)(o * scale);
+          const T Epart = gather_e<T, I, kSpline>(o, oq, ONE, Kb, inv_scale, Em[j], Ec[j], Ep[j], Ex[j]);
+          pre_pn[j] = pv[j] + qdt * Epart;
+          pre_gam[j] = sqrt(one_t + pre_pn[j] * pre_pn[j]);
+          cpos[j] = -1;
+          if (cl[j] != kDead && sigma != 0.0 && pre_gam[j] >= thr_lo) {
+            cpos[j] = atomicAdd(&s_ncand, 1);
+            s_cand[cpos[j]] = (uint32_t)(tid + j * kBlock);
+          }
+        }
+        __syncthreads();
+        const int ncand = s_ncand;
+        for (int q = tid; q < ncand; q += kBlock)
+          s_thr[q] = lepton_threshold<T>(idA[i0 + s_cand[q]], kseed, gthr64, sigma);
+        __syncthreads();
+      }
 #pragma unroll
       for (int j = 0; j < kItems; ++j) {
         if (j > 0 && j % kEG == 0) {
 #pragma unroll
-          for (int jj = j; jj < j + kEG; ++jj) load_e3(E, cl[jj], periodic, nc, Em[jj], Ec[jj], Ep[jj]);
+          for (int jj = j; jj < j + kEG; ++jj) {
+            if constexpr (kSpline) load_e4(E, cl[jj], ov[jj], nc, Em[jj], Ec[jj], Ep[jj], Ex[jj]);
+            else load_e3(E, cl[jj], periodic, nc, Em[jj], Ec[jj], Ep[jj]);
+          }
         }
         const long long i = i0 + tid + (long long)j * kBlock;
         const int c = cl[j];
         if (c == kDead) continue;
         const T o = ov[j];
         const I oq = (I)(o * scale);
-        // gather: node averages, then linear in the offset
-        const T el = half_t * (Em[j] + Ec[j]);
-        const T er = half_t * (Ec[j] + Ep[j]);
-        const T Epart = el + o * (er - el);
-        // push and move
-        T pn = pv[j] + qdt * Epart;
-        const T gam = sqrt(one_t + pn * pn);
+        // gather, push and move
+        T pn, gam;
+        if constexpr (kSpread) {
+          pn = pre_pn[j];
+          gam = pre_gam[j];
+        } else {
+          const T Epart = gather_e<T, I, kSpline>(o, oq, ONE, Kb, inv_scale, Em[j], Ec[j], Ep[j], Ex[j]);
+          pn = pv[j] + qdt * Epart;
+          gam = sqrt(one_t + pn * pn);
+        }
         const T v = pn / gam;
         const T d = v * dtdx;
         const I dq = (I)rint(d * scale);
         I nq = oq + dq;
-        I a1, a2 = 0;   // flux of a positive charge through this cell and the next
-        int cross = 0;  // -1, 0, +1: node crossed to the left / none / right
         int c2 = c;
         bool keep = true;
-        if (nq >= ONE) {
-          a1 = ONE - oq;
-          cross = 1;
-          c2 = c + 1;
-          nq -= ONE;
-          a2 = nq;
-          if (c2 >= nc) { if (periodic) c2 = 0; else keep = false; }
-        } else if (nq < 0) {
-          a1 = -oq;
-          cross = -1;
-          c2 = c - 1;
-          nq += ONE;
-          a2 = nq - ONE;
-          if (c2 < 0) { if (periodic) c2 = nc - 1; else keep = false; }
+        if constexpr (kSpline) {
+          // charge-conserving deposit of the spline: the flux through cell c+k
+          // (between nodes c+k and c+k+1) is the charge that left the nodes up
+          // to c+k, the running sum of old minus new weight from the leftmost
+          // node either spline touches (it returns to zero after the last)
+          int jo, jn;
+          long long wo0, wo1, wo2, wn0, wn1, wn2;
+          spline_weights<I>(oq, ONE, Kb, jo, wo0, wo1, wo2);
+          spline_weights<I>(nq, ONE, Kb, jn, wn0, wn1, wn2);
+          const int lo = min(jo, jn) - 1;
+          long long run = 0;
+#pragma unroll
+          for (int r = 0; r < 3; ++r) {
+            const int k = lo + r;
+            const int ko = k - jo + 1, kn = k - jn + 1;
+            const long long wo = ko == 0 ? wo0 : (ko == 1 ? wo1 : (ko == 2 ? wo2 : 0));
+            const long long wn = kn == 0 ? wn0 : (kn == 1 ? wn1 : (kn == 2 ? wn2 : 0));
+            run += wo - wn;
+            const long long f = s == 0 ? -run : run;
+            if (f != 0) {
+              if (lds) {
+                // unwrapped tile index: c - 2 .. c + 2 lie in [base, base + span)
+                atomicAdd((unsigned long long*)&s_flux[c + k - base], as_u64(f));
+              } else {
+                int cc = c + k;
+                cc = cc < 0 ? cc + nc : (cc >= nc ? cc - nc : cc);
+                gadd(F + cc, as_u64(f));
+              }
+            }
+          }
+          if (nq >= ONE) { nq -= ONE; c2 = c + 1 >= nc ? 0 : c + 1; }
+          else if (nq < 0) { nq += ONE; c2 = c - 1 < 0 ? nc - 1 : c - 1; }
         } else {
-          a1 = dq;
-        }
-        const long long f1 = s == 0 ? -(long long)a1 : (long long)a1;
-        const long long f2 = s == 0 ? -(long long)a2 : (long long)a2;
-        const bool second = cross != 0 && keep;
-        if (lds) {
-          // tile indices are unwrapped: c - 1 .. c + 1 all lie in [base, base + span)
-          atomicAdd((unsigned long long*)&s_flux[c - base], as_u64(f1));
-          if (second) atomicAdd((unsigned long long*)&s_flux[c + cross - base], as_u64(f2));
-        } else {
-          gadd(F + c, as_u64(f1));
-          if (second) gadd(F + c2, as_u64(f2));
+          I a1, a2 = 0;   // flux of a positive charge through this cell and the next
+          int cross = 0;  // -1, 0, +1: node crossed to the left / none / right
+          if (nq >= ONE) {
+            a1 = ONE - oq;
+            cross = 1;
+            c2 = c + 1;
+            nq -= ONE;
+            a2 = nq;
+            if (c2 >= nc) { if (periodic) c2 = 0; else keep = false; }
+          } else if (nq < 0) {
+            a1 = -oq;
+            cross = -1;
+            c2 = c - 1;
+            nq += ONE;
+            a2 = nq - ONE;
+            if (c2 < 0) { if (periodic) c2 = nc - 1; else keep = false; }
+          } else {
+            a1 = dq;
+          }
+          const long long f1 = s == 0 ? -(long long)a1 : (long long)a1;
+          const long long f2 = s == 0 ? -(long long)a2 : (long long)a2;
+          const bool second = cross != 0 && keep;
+          if (lds) {
+            // tile indices are unwrapped: c - 1 .. c + 1 all lie in [base, base + span)
+            atomicAdd((unsigned long long*)&s_flux[c - base], as_u64(f1));
+            if (second) atomicAdd((unsigned long long*)&s_flux[c + cross - base], as_u64(f2));
+          } else {
+            gadd(F + c, as_u64(f1));
+            if (second) gadd(F + c2, as_u64(f2));
+          }
         }
         if (!isfinite(pn) || !isfinite(gam)) bad = true;
         if (keep) {
@@ -408,7 +558,7 @@ __global__ __launch_bounds__(kBlock, PushCfg<T>::waves) void k_push(GapDev* __re
           // or above the lowest one)
           T thr = gthr;
           if constexpr (kSpread)
-            if (sigma != 0.0 && gam >= thr_lo) thr = lepton_threshold<T>(idA[i], kseed, gthr64, sigma);
+            if (cpos[j] >= 0) thr = s_thr[cpos[j]];
           int k = 0;
           T gm = gam;
           while (gm >= thr && k <= kMaxEmit) {
@@ -1547,6 +1697,19 @@ __global__ __launch_bounds__(kBlock) void k_rho(GapDev* __restrict__ gaps, int g
       const int c = G->cell[buf][s][i];
       if (c == kDead) continue;
       const long long oq = (long long)(((const T*)G->off[buf][s])[i] * scale);
+      if (G->shape == PIC_SHAPE_QUADRATIC) {
+        // the spline's three nodes, folded into [0, n_cells) (periodic)
+        int j;
+        long long w0, w1, w2;
+        spline_weights<long long>(oq, (long long)G->one, G->K, j, w0, w1, w2);
+        const long long wk[3] = {w0, w1, w2};
+        for (int k = 0; k < 3; ++k) {
+          int node = c + j - 1 + k;
+          node = node < 0 ? node + G->n_cells : (node >= G->n_cells ? node - G->n_cells : node);
+          atomicAdd((unsigned long long*)&G->rho_acc[node], as_u64(q * wk[k]));
+        }
+        continue;
+      }
       atomicAdd((unsigned long long*)&G->rho_acc[c], as_u64(q * (G->one - oq)));
       atomicAdd((unsigned long long*)&G->rho_acc[c + 1], as_u64(q * oq));
     }
@@ -1604,20 +1767,26 @@ static int grid_for(long long want, int cap) {
   return (int)(want < 1 ? 1 : (want < cap ? want : cap));
 }
 
-template <typename T, bool kSpread>
+template <typename T, bool kSpread, bool kSpline>
 static void push_kernel(const StepLaunch& L) {
-  hipLaunchKernelGGL((k_push<T, kSpread>), dim3(kPushGrid), dim3(kBlock), 0, L.stream, L.gaps, L.wi,
-                     L.B, L.emit_cnt, L.emit_ent, L.wg_emit, L.stripes);
+  hipLaunchKernelGGL((k_push<T, kSpread, kSpline>), dim3(kPushGrid), dim3(kBlock), 0, L.stream,
+                     L.gaps, L.wi, L.B, L.emit_cnt, L.emit_ent, L.wg_emit, L.stripes);
+}
+
+template <typename T>
+static void push_for(const StepLaunch& L) {
+  if (L.spline) {
+    if (L.spread) push_kernel<T, true, true>(L);
+    else push_kernel<T, false, true>(L);
+  } else {
+    if (L.spread) push_kernel<T, true, false>(L);
+    else push_kernel<T, false, false>(L);
+  }
 }
 
 hipError_t launch_push(const StepLaunch& L, bool mixed) {
-  if (mixed) {
-    if (L.spread) push_kernel<float, true>(L);
-    else push_kernel<float, false>(L);
-  } else {
-    if (L.spread) push_kernel<double, true>(L);
-    else push_kernel<double, false>(L);
-  }
+  if (mixed) push_for<float>(L);
+  else push_for<double>(L);
   return hipGetLastError();
 }
 

@@ -22,6 +22,7 @@ struct StepLaunch {
   double* stripes;     // striped push tallies, B x 4 x kStripes x kStripeStride (device)
   hipStream_t stream;
   bool spread;         // some gap draws per-lepton thresholds (gamma_thr_spread > 0)
+  bool spline;         // the batch's leptons have the quadratic-spline shape
 };
 
 hipError_t launch_step(const StepLaunch& L, bool mixed);

@@ -89,6 +89,10 @@ pic_status validate(const pic_gap_params* p) {
   if (!(p->weight >= 0.0) || !std::isfinite(p->weight)) return PIC_ERR_ARG;
   if (!std::isfinite(p->j_m)) return PIC_ERR_ARG;
   if (!(p->gamma_thr_spread >= 0.0) || !(p->gamma_thr_spread < 1.0)) return PIC_ERR_ARG;
+  if (p->shape != PIC_SHAPE_LINEAR && p->shape != PIC_SHAPE_QUADRATIC) return PIC_ERR_ARG;
+  // a three-node shape reaches past a wall: periodic gaps only
+  if (p->shape == PIC_SHAPE_QUADRATIC && (p->boundary != PIC_BC_PERIODIC || p->n_cells < 4))
+    return PIC_ERR_ARG;
   if (p->gamma_thr_spread > 0.0 && std::isfinite(p->gamma_thr) &&
       !((1.0 - p->f - p->gamma_thr_spread) * p->gamma_thr >= 1.0))
     return PIC_ERR_ARG;
@@ -280,7 +284,8 @@ pic_status create_batch(const pic_gap_params* params, int n_gaps, void* d_ws, si
   for (int i = 0; i < n_gaps; ++i) {
     if (validate(&params[i]) != PIC_OK) return PIC_ERR_ARG;
     if (params[i].precision != params[0].precision || params[i].sort_every != params[0].sort_every ||
-        params[i].diag_every != params[0].diag_every || params[i].history_rows != params[0].history_rows)
+        params[i].diag_every != params[0].diag_every || params[i].history_rows != params[0].history_rows ||
+        params[i].shape != params[0].shape)
       return PIC_ERR_ARG;
   }
   if (!batch_slots_ok(params, n_gaps)) return PIC_ERR_ARG;
@@ -317,6 +322,7 @@ pic_status create_batch(const pic_gap_params* params, int n_gaps, void* d_ws, si
     G.boundary = p.boundary;
     G.K = offset_bits(p.precision);
     G.precision = p.precision;
+    G.shape = p.shape;
     G.diag_every = b->diag_every;
     G.hist_rows = b->hist_rows;
     G.one = (int64_t)1 << G.K;
@@ -398,6 +404,7 @@ pic_status create_batch(const pic_gap_params* params, int n_gaps, void* d_ws, si
   b->launch.wg_emit = reinterpret_cast<uint32_t*>(ws + L.wg_emit);
   b->launch.stripes = reinterpret_cast<double*>(ws + L.stripes);
   b->launch.stream = b->stream;
+  b->launch.spline = params[0].shape == PIC_SHAPE_QUADRATIC;
   b->launch.spread = false;
   for (int i = 0; i < n_gaps; ++i) b->launch.spread |= params[i].gamma_thr_spread > 0.0;
   if (st == PIC_OK &&

@@ -11,8 +11,8 @@ HIST_FLOAT = ("kinetic", "field", "photon_energy", "lost_energy")
 
 def gap_kwargs(cfg):
     kw = {k: cfg[k] for k in workloads.GAP_KEYS}
-    for k in ("j_m", "gamma_thr_spread"):
-        if cfg.get(k, 0.0):
+    for k in ("j_m", "gamma_thr_spread", "shape"):
+        if cfg.get(k, 0):
             kw[k] = cfg[k]
     return kw
 
@@ -38,7 +38,8 @@ def gpu_params(cfg, **over):
         c["n_cells"], c["dx"], c["dt"], c["boundary"], c["e0"], c["gamma_thr"], c["f"],
         c["l_gamma"], c["weight"], int(c["capacity"]), int(c.get("photon_capacity", c["capacity"])),
         c["seed"], c["precision"], c.get("sort_every", 0), c.get("diag_every", 0),
-        c.get("history_rows", 0), c.get("j_m", 0.0), c.get("gamma_thr_spread", 0.0))
+        c.get("history_rows", 0), c.get("j_m", 0.0), c.get("gamma_thr_spread", 0.0),
+        c.get("shape", 0))
 
 
 def make_gpu(cfg, stream=None, **over):

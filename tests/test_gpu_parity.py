@@ -491,6 +491,79 @@ def test_batch_with_and_without_spread():
         pc.compare_particles(view, go, PTOL[workloads.MIXED])
 
 
+# ------------------------------------------------- quadratic particle shape
+def _spline(cfg, **over):
+    c = dict(cfg, boundary=workloads.PERIODIC, shape=1)
+    c.update(over)
+    return c
+
+
+@pytest.mark.parametrize("name", ["c1_fp64_reference_gap", "c3_mixed_single_gap"])
+def test_quadratic_shape_full_run(name):
+    """Configuration 1 (binary64) and 3 (mixed), periodic, with the
+    quadratic-spline shape, over the full 2000 steps, and Gauss's law on the
+    GPU's own fields."""
+    cfg = _spline(workloads.config(name))
+    gg, go = _run_pair(cfg, 2000)
+    stats, err, exact = _check_all(gg, go, cfg["precision"])
+    h = gg.read_history()
+    assert h["pairs_created"][-1] > 1000
+    F = gg.read_fields(rho=True)
+    E, rho = F["E"], F["rho"]
+    r = (E - np.roll(E, 1)) - rho[:-1]
+    assert np.max(np.abs(r)) <= 1e-12 * max(np.max(np.abs(E)), 1.0)
+    assert np.array_equal(rho, go.fields()["rho"])
+    print("p err", stats, "E err", err, "E bitwise", exact)
+
+
+@pytest.mark.parametrize("precision", [workloads.FP64, workloads.MIXED])
+def test_quadratic_shape_in_place_and_spread(precision):
+    """The spline with pairs made in place and a spread of the threshold."""
+    cfg = dict(n_cells=300, dx=1.0, dt=0.45, boundary=workloads.PERIODIC, e0=30.0,
+               gamma_thr=60.0, f=0.25, l_gamma=0.0, weight=0.2, seed=79, precision=precision,
+               n_pairs=200, macro_per_pair=3, capacity=200_000, photon_capacity=0,
+               gamma_thr_spread=0.4, shape=1)
+    gg, go = _run_pair(cfg, 400)
+    _check_all(gg, go, precision)
+
+
+@pytest.mark.parametrize("precision", [workloads.FP64, workloads.MIXED])
+def test_quadratic_shape_lattice_drift(precision):
+    """A drifting lattice: the spline's flux, cell by cell, equals the
+    oracle's exactly (both are integers)."""
+    cfg = dict(n_cells=257, dx=1.0, dt=0.45, boundary=workloads.PERIODIC, e0=0.5,
+               gamma_thr=1e300, f=0.5, l_gamma=0.0, weight=1.0, seed=5, precision=precision,
+               n_pairs=257 * 3 + 5, macro_per_pair=1, seed_mode=workloads.SEED_LATTICE,
+               p0_minus=0.3, p0_plus=-0.2, capacity=2000, photon_capacity=0, shape=1)
+    gg, go = _run_pair(cfg, 150)
+    _check_all(gg, go, precision)
+    assert np.array_equal(gg.read_flux(), go.fields()["flux"])
+
+
+def test_quadratic_shape_batch():
+    """A batch of spline gaps (periodic) of different sizes against per-gap
+    oracle runs; a batch mixing shapes is rejected."""
+    import paper_2012_05587_amd as P
+    gaps = workloads.batched_scan(n_gaps=3, precision=workloads.MIXED, steps=120)
+    for c in gaps:
+        c.update(n_cells=min(c["n_cells"], 3000), n_pairs=min(c["n_pairs"], 400),
+                 e0=min(c["e0"], 120.0), gamma_thr=max(c["gamma_thr"], 150.0),
+                 capacity=1_000_000, photon_capacity=1_000_000, history_rows=200,
+                 boundary=workloads.PERIODIC, shape=1)
+    b = P.Batch([pc.gpu_params(c) for c in gaps])
+    for view, c in zip(b.gaps, gaps):
+        view.seed_particles(0, c["n_pairs"], 1)
+    assert np.all(b.step_n(120, statuses=True) == 0)
+    for view, c in zip(b.gaps, gaps):
+        go = pc.make_oracle(c)
+        assert go.step(120) == 0
+        pc.compare_history(view.read_history(), go.history())
+        pc.compare_particles(view, go, PTOL[workloads.MIXED])
+    mixed = [pc.gpu_params(gaps[0]), pc.gpu_params(dict(gaps[1], shape=0))]
+    with pytest.raises(P.PicError):
+        P.Batch(mixed)
+
+
 # ------------------------------------------------- full-size sampled parity
 def test_config2_full_size_sampled_step():
     """At configuration 2's full slot count and the benchmark's launch shape:

@@ -112,7 +112,7 @@ def corotating_gap(n_cells=10000, dx=0.1, dt=1e-3, ppc_plus=10, gamma_thr=5000.0
 
 
 def uniform_cascade(f, gamma_thr=500.0, n_cells=2000, precision=MIXED, seed=BASE_SEED + 30,
-                    gamma_thr_spread=0.0, steps=12000):
+                    gamma_thr_spread=0.0, steps=12000, shape=0):
     """The cascade of sections 3-5 at the resolution of the paper's runs: a
     uniform seed of pairs at rest (one pair per cell, random positions) in
     a uniform field E0 = 10^3.5, periodic, pairs made in place, gamma_thr =
@@ -120,7 +120,8 @@ def uniform_cascade(f, gamma_thr=500.0, n_cells=2000, precision=MIXED, seed=BASE
     masses), L = 10^1.5 c/omega_p0 over n_cells cells, dt = 10^-3.5 and
     macro-particle weight dx (seed density 1 per species).  Slots per
     species: 1.25 * E0^2 ln(2/f) / (2 gamma_thr) * n_cells.  gamma_thr_spread
-    gives each lepton its own threshold, uniform in gamma_thr (1 +/- spread)."""
+    gives each lepton its own threshold, uniform in gamma_thr (1 +/- spread);
+    shape 1 the quadratic-spline particle shape."""
     L = 10.0 ** 1.5
     dx = L / n_cells
     e0, gthr = 10.0 ** 3.5, float(gamma_thr)
@@ -128,7 +129,7 @@ def uniform_cascade(f, gamma_thr=500.0, n_cells=2000, precision=MIXED, seed=BASE
     return dict(n_cells=n_cells, dx=dx, dt=10.0 ** -3.5, boundary=PERIODIC, e0=e0,
                 gamma_thr=gthr, f=f, l_gamma=0.0, weight=dx, seed=seed, precision=precision,
                 n_pairs=n_cells, macro_per_pair=1, seed_mode=SEED_RANDOM, capacity=cap,
-                photon_capacity=0, gamma_thr_spread=gamma_thr_spread, steps=steps)
+                photon_capacity=0, gamma_thr_spread=gamma_thr_spread, steps=steps, shape=shape)
 
 
 def nonuniform_gap(n_cells=2000, length=10.0 ** 1.5, dt=10.0 ** -3.5, e0=10.0 ** 3.5,
