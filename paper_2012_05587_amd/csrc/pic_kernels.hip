@@ -188,37 +188,34 @@ __device__ __forceinline__ void load_e4(gptr<const T> E, int cl, T off, int nc, 
 // the outer nodes get floor((2^(K-1) -/+ delta)^2 / 2^(K+1)), the middle one
 // the rest of 2^K, so the three sum to 2^K exactly.
 template <typename I>
-__device__ __forceinline__ void spline_weights(I X, I ONE, int K, int& j, long long& wl,
-                                               long long& wc, long long& wr) {
+__device__ __forceinline__ void spline_weights(I X, I ONE, int K, int& j, I& wl, I& wc, I& wr) {
   const I HALF = ONE >> 1;
   const I t = X + HALF;
   j = t < 0 ? -1 : (t >= 2 * ONE ? 2 : (t >= ONE ? 1 : 0));
   const I delta = X - (I)j * ONE;
-  const unsigned long long a = (unsigned long long)(HALF - delta);
-  const unsigned long long b = (unsigned long long)(HALF + delta);
   if constexpr (sizeof(I) == 4) {
-    wl = (long long)((a * a) >> (K + 1));
-    wr = (long long)((b * b) >> (K + 1));
+    // 2^-24 grid: both factors fit 32 bits, one 32 x 32 -> 64 product each
+    const uint32_t a = (uint32_t)(HALF - delta), b = (uint32_t)(HALF + delta);
+    wl = (I)(((uint64_t)a * a) >> (K + 1));
+    wr = (I)(((uint64_t)b * b) >> (K + 1));
   } else {
-    wl = (long long)(((unsigned __int128)a * a) >> (K + 1));
-    wr = (long long)(((unsigned __int128)b * b) >> (K + 1));
+    const unsigned long long a = (unsigned long long)(HALF - delta);
+    const unsigned long long b = (unsigned long long)(HALF + delta);
+    wl = (I)(((unsigned __int128)a * a) >> (K + 1));
+    wr = (I)(((unsigned __int128)b * b) >> (K + 1));
   }
-  wc = (long long)ONE - wl - wr;
+  wc = ONE - wl - wr;
 }
 
-// E at a lepton at offset o (oq on the 2^-K grid) of its cell, from the E
-// values around it: linear shape (em, ec, ep = cells c-1, c, c+1): the node
-// averages interpolated linearly; spline (em..ex = cells c+j-2 .. c+j+1):
-// the averages at the nodes j-1, j, j+1 weighted by the lepton's integer
-// weights, which are exact in the particle type.
-template <typename T, typename I, bool kSpline>
-__device__ __forceinline__ T gather_e(T o, I oq, I ONE, int K, T inv_scale, T em, T ec, T ep,
-                                      T ex) {
+// E at a lepton at offset o of its cell, from the E values around it:
+// linear shape (em, ec, ep = cells c-1, c, c+1): the node averages
+// interpolated linearly; spline (em..ex = cells c+j-2 .. c+j+1): the
+// averages at the nodes j-1, j, j+1 weighted by the lepton's integer weights
+// w0..w2 (in 2^-K; exact in the particle type).
+template <typename T, bool kSpline, typename I>
+__device__ __forceinline__ T gather_e(T o, I w0, I w1, I w2, T inv_scale, T em, T ec, T ep, T ex) {
   const T half_t = (T)0.5;
   if constexpr (kSpline) {
-    int j;
-    long long w0, w1, w2;
-    spline_weights<I>(oq, ONE, K, j, w0, w1, w2);
     const T en0 = half_t * (em + ec);
     const T en1 = half_t * (ec + ep);
     const T en2 = half_t * (ep + ex);
@@ -441,8 +438,10 @@ __global__ __launch_bounds__(kBlock, PushCfg<T>::waves) void k_push(GapDev* __re
 #pragma unroll
         for (int j = 0; j < kItems; ++j) {
           const T o = ov[j];
-          const I oq = (I)(o * scale);
-          const T Epart = gather_e<T, I, kSpline>(o, oq, ONE, Kb, inv_scale, Em[j], Ec[j], Ep[j], Ex[j]);
+          int jw = 0;
+          I w0 = 0, w1 = 0, w2 = 0;
+          if constexpr (kSpline) spline_weights<I>((I)(o * scale), ONE, Kb, jw, w0, w1, w2);
+          const T Epart = gather_e<T, kSpline>(o, w0, w1, w2, inv_scale, Em[j], Ec[j], Ep[j], Ex[j]);
           pre_pn[j] = pv[j] + qdt * Epart;
           pre_gam[j] = sqrt(one_t + pre_pn[j] * pre_pn[j]);
           cpos[j] = -1;
@@ -471,13 +470,17 @@ __global__ __launch_bounds__(kBlock, PushCfg<T>::waves) void k_push(GapDev* __re
         if (c == kDead) continue;
         const T o = ov[j];
         const I oq = (I)(o * scale);
+        // the spline's weights at the start of the step serve gather and deposit
+        int jo = 0;
+        I wo0 = 0, wo1 = 0, wo2 = 0;
+        if constexpr (kSpline) spline_weights<I>(oq, ONE, Kb, jo, wo0, wo1, wo2);
         // gather, push and move
         T pn, gam;
         if constexpr (kSpread) {
           pn = pre_pn[j];
           gam = pre_gam[j];
         } else {
-          const T Epart = gather_e<T, I, kSpline>(o, oq, ONE, Kb, inv_scale, Em[j], Ec[j], Ep[j], Ex[j]);
+          const T Epart = gather_e<T, kSpline>(o, wo0, wo1, wo2, inv_scale, Em[j], Ec[j], Ep[j], Ex[j]);
           pn = pv[j] + qdt * Epart;
           gam = sqrt(one_t + pn * pn);
         }
@@ -492,20 +495,19 @@ __global__ __launch_bounds__(kBlock, PushCfg<T>::waves) void k_push(GapDev* __re
           // (between nodes c+k and c+k+1) is the charge that left the nodes up
           // to c+k, the running sum of old minus new weight from the leftmost
           // node either spline touches (it returns to zero after the last)
-          int jo, jn;
-          long long wo0, wo1, wo2, wn0, wn1, wn2;
-          spline_weights<I>(oq, ONE, Kb, jo, wo0, wo1, wo2);
+          int jn;
+          I wn0, wn1, wn2;
           spline_weights<I>(nq, ONE, Kb, jn, wn0, wn1, wn2);
           const int lo = min(jo, jn) - 1;
-          long long run = 0;
+          I run = 0;  // at most 2^K in magnitude
 #pragma unroll
           for (int r = 0; r < 3; ++r) {
             const int k = lo + r;
             const int ko = k - jo + 1, kn = k - jn + 1;
-            const long long wo = ko == 0 ? wo0 : (ko == 1 ? wo1 : (ko == 2 ? wo2 : 0));
-            const long long wn = kn == 0 ? wn0 : (kn == 1 ? wn1 : (kn == 2 ? wn2 : 0));
+            const I wo = ko == 0 ? wo0 : (ko == 1 ? wo1 : (ko == 2 ? wo2 : (I)0));
+            const I wn = kn == 0 ? wn0 : (kn == 1 ? wn1 : (kn == 2 ? wn2 : (I)0));
             run += wo - wn;
-            const long long f = s == 0 ? -run : run;
+            const long long f = s == 0 ? -(long long)run : (long long)run;
             if (f != 0) {
               if (lds) {
                 // unwrapped tile index: c - 2 .. c + 2 lie in [base, base + span)
@@ -1701,7 +1703,7 @@ __global__ __launch_bounds__(kBlock) void k_rho(GapDev* __restrict__ gaps, int g
         // the spline's three nodes, folded into [0, n_cells) (periodic)
         int j;
         long long w0, w1, w2;
-        spline_weights<long long>(oq, (long long)G->one, G->K, j, w0, w1, w2);
+        spline_weights<long long>(oq, (long long)G->one, G->K, j, w0, w1, w2);  // any K
         const long long wk[3] = {w0, w1, w2};
         for (int k = 0; k < 3; ++k) {
           int node = c + j - 1 + k;

@@ -40,11 +40,13 @@ pytestmark = pytest.mark.gpu
 SAMPLE = 50      # steps between <1/gamma^3> samples
 P_RANGE = 64.0   # momentum range of the <1/gamma^3> histogram
 P_BINS = 8192
-# (f, precision, gamma_thr, steps): the steps cover screening and at least
-# four half periods of the oscillation (ten for f = 0.1 in mixed precision)
-CASES = [(0.1, workloads.MIXED, 500.0, 12000), (0.03, workloads.MIXED, 500.0, 4800),
-         (0.01, workloads.MIXED, 500.0, 4800), (0.1, workloads.FP64, 500.0, 7600),
-         (0.001, workloads.MIXED, 5000.0, 44000)]
+# (f, precision, gamma_thr, steps, shape): the steps cover screening and at
+# least four half periods of the oscillation (ten for f = 0.1 in mixed
+# precision); shape 1 is the quadratic spline, which at this resolution must
+# give the same physics as the linear shape
+CASES = [(0.1, workloads.MIXED, 500.0, 12000, 0), (0.03, workloads.MIXED, 500.0, 4800, 0),
+         (0.01, workloads.MIXED, 500.0, 4800, 0), (0.1, workloads.FP64, 500.0, 7600, 0),
+         (0.001, workloads.MIXED, 5000.0, 44000, 0), (0.1, workloads.MIXED, 500.0, 12000, 1)]
 
 
 def _inv_gamma3(g):
@@ -63,7 +65,7 @@ def _inv_gamma3(g):
     return num / den if den else float("nan")
 
 
-def run_uniform_cascade(f, precision, gamma_thr, steps, spread=0.0):
+def run_uniform_cascade(f, precision, gamma_thr, steps, spread=0.0, shape=0):
     """Runs the section 3 setup on the GPU; returns the configuration, the
     history and the sampled <1/gamma^3>."""
     import torch
@@ -71,7 +73,7 @@ def run_uniform_cascade(f, precision, gamma_thr, steps, spread=0.0):
     import paper_2012_05587_amd as P
     from tests.pic_cases import gpu_params
     cfg = workloads.uniform_cascade(f, gamma_thr=gamma_thr, precision=precision,
-                                    gamma_thr_spread=spread)
+                                    gamma_thr_spread=spread, shape=shape)
     g = P.Gap(gpu_params(cfg, history_rows=steps + 8, diag_every=1),
               stream=torch.cuda.Stream())
     try:
@@ -153,14 +155,15 @@ def damping_fit(half, cycles):
 
 
 def _id(case):
-    f, p, gthr, _ = case
-    return f"f{f}-{'fp64' if p == workloads.FP64 else 'mixed'}-g{int(gthr)}"
+    f, p, gthr, _, shape = case
+    return (f"f{f}-{'fp64' if p == workloads.FP64 else 'mixed'}-g{int(gthr)}"
+            + ("-spline" if shape else ""))
 
 
 @pytest.mark.parametrize("case", CASES, ids=[_id(c) for c in CASES])
 def test_uniform_cascade_at_paper_scale(case):
-    f, precision, gthr, steps = case
-    cfg, h, samples = run_uniform_cascade(f, precision, gthr, steps)
+    f, precision, gthr, steps, shape = case
+    cfg, h, samples = run_uniform_cascade(f, precision, gthr, steps, shape=shape)
     r = measure(cfg, h, samples)
     print({k: v for k, v in r.items() if k != "half_periods"})
     for x in r["half_periods"]:
