@@ -291,8 +291,10 @@ def summarize(args):
         bench = json.loads(f.read().strip().splitlines()[-1])
     workload = bench["config"]["workload"]
     prec = workloads.MIXED if bench["dtype"] != "f64" else workloads.FP64
-    # the push instantiation without per-lepton thresholds (the benchmark's)
-    kname = "k_push<float, false>" if prec == workloads.MIXED else "k_push<double, false>"
+    # the push instantiation without per-lepton thresholds and with the linear
+    # shape (the benchmark's)
+    kname = ("k_push<float, false, false>" if prec == workloads.MIXED
+             else "k_push<double, false, false>")
     n = 2 * bench["steps"]  # the timed graph run and the evented run of the same steps
     rows = _db_rows(args.trace_db, "select name, start, end from kernels order by start")
     per = {}
