@@ -606,3 +606,64 @@ def test_config2_full_size_sampled_step():
         assert np.array_equal(got["off"], ref["off"])
         assert np.all(np.abs(got["p"] - ref["p"]) <= 1e-12 * np.maximum(np.abs(ref["p"]), 1))
         assert len(got["id"]) > 0.9 * len(pick)
+
+
+def test_config4_full_batch_sampled_step():
+    """The benchmark's own workload in its launch configuration: the 256-gap
+    mixed batch of configuration 4 at full size, advanced 300 steps by graph
+    replay at the tuned re-sort cadence.  One further step is recomputed by
+    the oracle lepton by lepton (weight 0 in the GPU's field) for a sample of
+    leptons of 8 gaps, and the invariants that hold at any size are checked
+    on every gap."""
+    import oracle
+
+    import paper_2012_05587_amd as P
+    gaps = workloads.batched_scan(256, precision=workloads.MIXED)
+    for c in gaps:
+        c["history_rows"] = 400
+    b = P.Batch([pc.gpu_params(c) for c in gaps])
+    for view, c in zip(b.gaps, gaps):
+        view.seed_particles(workloads.SEED_RANDOM, c["n_pairs"], c["macro_per_pair"])
+    b.step_n(300)
+    rng = np.random.default_rng(4)
+    sample = [int(i) for i in rng.choice(len(gaps), size=8, replace=False)
+              if b.gaps[int(i)].read_moments().status == 0]
+    assert len(sample) >= 4
+    fields, before = {}, {}
+    for gi in sample:
+        fields[gi] = b.gaps[gi].read_fields(rho=True)["E"]
+        before[gi] = [b.gaps[gi].read_particles(s) for s in (0, 1)]
+    b.step_n(1)
+    for view in b.gaps:
+        h = view.read_history()
+        assert np.all((h["n_minus"] - h["n_plus"]) == -(h["absorbed_minus"] - h["absorbed_plus"]))
+        assert np.all(h["photons_emitted"] == h["n_photons"] + h["pairs_created"] + h["photons_escaped"])
+        F = view.read_fields(rho=True)
+        r = pc.gauss_residual(F["E"], F["rho"], periodic=False)
+        assert np.abs(r).max() <= 10 * np.finfo(float).eps * 301 * max(np.abs(F["E"]).max(), 1.0)
+    checked = 0
+    for gi in sample:
+        cfg = gaps[gi]
+        after = [pc.by_id(b.gaps[gi].read_particles(s)) for s in (0, 1)]
+        for s in (0, 1):
+            n = len(before[gi][s]["id"])
+            if n == 0:
+                continue
+            pick = rng.choice(n, size=min(1000, n), replace=False)
+            og = oracle.OracleGap(**pc.gap_kwargs(dict(cfg, weight=0.0)), capacity=0)
+            og.set_fields(fields[gi])
+            og.seed_explicit(s, before[gi][s]["cell"][pick], before[gi][s]["off"][pick],
+                             before[gi][s]["p"][pick], before[gi][s]["id"][pick])
+            assert og.step(1) == 0
+            ref = pc.by_id(og.particles(s))
+            sel = np.isin(after[s]["id"], ref["id"])
+            got = {k: v[sel] for k, v in after[s].items()}
+            keep = np.isin(ref["id"], got["id"])
+            ref = {k: v[keep] for k, v in ref.items()}
+            assert np.array_equal(got["id"], ref["id"])
+            assert np.array_equal(got["cell"], ref["cell"])
+            assert np.array_equal(got["off"], ref["off"])
+            assert np.all(np.abs(got["p"] - ref["p"]) <= PTOL[workloads.MIXED] * np.maximum(np.abs(ref["p"]), 1))
+            assert len(got["id"]) > 0.9 * len(pick)
+            checked += len(got["id"])
+    assert checked > 4000
