@@ -13,7 +13,8 @@ Measured against:
 - section 3: growth rate (exact root of Eqs. 1-2), screening time t_s, the
   screening density of Eq. 5, which the paper finds to overestimate the
   density at the end of the cascade;
-- section 4: mean Lorentz factor at screening, Eq. 10;
+- section 4: the exponential spectrum of Eq. 8 and its mean, Eq. 10, at
+  screening;
 - section 5: each half period of the large-amplitude oscillation of <E>
   against omega_0^2 = 2 n <1/gamma^3> (normalised), with n and
   <1/gamma^3> measured on the device over that half period;
@@ -49,6 +50,11 @@ CASES = [(0.1, workloads.MIXED, 500.0, 12000, 0), (0.03, workloads.MIXED, 500.0,
          (0.001, workloads.MIXED, 5000.0, 44000, 0), (0.1, workloads.MIXED, 500.0, 12000, 1)]
 
 
+def _spectrum(g):
+    """Counts of both species in 1000 momentum bins over [-1000, 1000]."""
+    return sum(g.phase_space(sp, 1, 1000, -1000.0, 1000.0)[0] for sp in (0, 1))
+
+
 def _inv_gamma3(g):
     """<1/gamma^3> over both species from device histograms of p in
     [-P_RANGE, P_RANGE].  The two edge bins also hold the leptons outside the
@@ -78,19 +84,38 @@ def run_uniform_cascade(f, precision, gamma_thr, steps, spread=0.0, shape=0):
               stream=torch.cuda.Stream())
     try:
         g.seed_particles(cfg["seed_mode"], cfg["n_pairs"], cfg["macro_per_pair"])
-        samples = []
+        samples, spectra = [], []
         done = 0
         while done < steps:
             k = min(SAMPLE, steps - done)
             g.step_n(k)
             done += k
             samples.append((done - 1, _inv_gamma3(g)))
+            spectra.append(_spectrum(g))
         h = g.read_history()
     finally:
         g.close()
         del g
         torch.cuda.empty_cache()
-    return cfg, h, np.array(samples)
+    return cfg, h, np.array(samples), np.array(spectra)
+
+
+def spectrum_fit(cfg, samples, spectra, step):
+    """Eq. 8 at the sample nearest `step`: a line through ln(counts) against
+    gamma over [0.15, 0.85] gamma_thr (|p| bins, both signs and species), its
+    slope times gamma_thr, R^2, and the mean gamma of the binned leptons."""
+    j = int(np.argmin(np.abs(samples[:, 0] - step)))
+    h = spectra[j].astype(np.float64)
+    edges = np.linspace(-1000.0, 1000.0, 1001)
+    gam = np.sqrt(1.0 + (0.5 * (edges[1:] + edges[:-1])) ** 2)
+    hp, g = h[500:] + h[:500][::-1], gam[500:]
+    gthr = cfg["gamma_thr"]
+    sel = (g > 0.15 * gthr) & (g < 0.85 * gthr) & (hp > 0)
+    y = np.log(hp[sel])
+    a = np.polyfit(g[sel], y, 1)
+    r = y - np.polyval(a, g[sel])
+    return dict(slope=float(a[0] * gthr), r2=float(1.0 - (r @ r) / ((y - y.mean()) @ (y - y.mean()))),
+                mean_gamma=float((hp * g).sum() / hp.sum()), step=int(samples[j, 0]))
 
 
 def measure(cfg, h, samples):
@@ -163,7 +188,7 @@ def _id(case):
 @pytest.mark.parametrize("case", CASES, ids=[_id(c) for c in CASES])
 def test_uniform_cascade_at_paper_scale(case):
     f, precision, gthr, steps, shape = case
-    cfg, h, samples = run_uniform_cascade(f, precision, gthr, steps, shape=shape)
+    cfg, h, samples, spectra = run_uniform_cascade(f, precision, gthr, steps, shape=shape)
     r = measure(cfg, h, samples)
     print({k: v for k, v in r.items() if k != "half_periods"})
     for x in r["half_periods"]:
@@ -185,6 +210,14 @@ def test_uniform_cascade_at_paper_scale(case):
         assert 0.25 < r["n_s"] / r["n_s_eq5"] < 0.7, (r["n_s"], r["n_s_eq5"])
         # section 4, Eq. 10
         assert 0.8 < r["gmean_s"] / r["gmean_eq10"] < 1.7, (r["gmean_s"], r["gmean_eq10"])
+        # section 4, Eq. 8: at screening the spectrum is exponential in gamma
+        # below gamma_thr, with a slope near ln(2/f) / gamma_thr (shallower
+        # as the mean is higher than Eq. 10) and a mean of 1 / slope
+        sp = spectrum_fit(cfg, samples, spectra, r["i_s"])
+        print("Eq. 8", sp)
+        assert sp["r2"] > 0.85, sp
+        assert 0.5 < -sp["slope"] / math.log(2.0 / f) < 1.1, sp
+        assert 0.8 < sp["mean_gamma"] * -sp["slope"] / gthr < 1.2, sp
     else:
         # One pair per cell screens E0 as the second generation starts to
         # emit: the first generation alone multiplies the seed by about
@@ -241,7 +274,7 @@ def test_threshold_spread_smooths_the_cascade():
     less."""
     res = {}
     for spread in (0.0, 0.25):
-        cfg, h, samples = run_uniform_cascade(0.1, workloads.MIXED, 500.0, 12000, spread)
+        cfg, h, samples, _ = run_uniform_cascade(0.1, workloads.MIXED, 500.0, 12000, spread)
         r = measure(cfg, h, samples)
         r["windows"] = _window_growth(cfg, h, r["t_a"])
         r["damping"] = damping_fit(r["half_periods"], 3)
