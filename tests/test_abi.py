@@ -54,6 +54,8 @@ def test_validate_accepts_configs():
     ("dt", 1.0), ("dt", -0.1), ("n_cells", 1), ("boundary", 5), ("f", 0.0), ("f", 1.0),
     ("f", 0.01), ("gamma_thr", 1.0), ("l_gamma", -2.0), ("weight", -1.0), ("capacity", 0),
     ("capacity", 2**31), ("precision", 3), ("e0", float("inf")), ("sort_every", -1),
+    ("j_m", float("nan")), ("gamma_thr_spread", -0.1), ("gamma_thr_spread", 1.0),
+    ("gamma_thr_spread", 0.5), ("shape", 2), ("shape", 1),
 ])
 def test_validate_rejects(field, value):
     import paper_2012_05587_amd as P
@@ -61,6 +63,29 @@ def test_validate_rejects(field, value):
     c[field] = value
     assert P.pic_validate_params(pc.gpu_params(c)) == P.ERR_ARG
     assert P.pic_workspace_bytes(pc.gpu_params(c)) == 0
+
+
+def test_variants_validate_alike_in_library_and_oracle():
+    """The library and the oracle accept and reject the same variant
+    parameters: a spread of gamma_thr needs (1 - f - sigma) gamma_thr >= 1,
+    the quadratic shape periodic walls and at least 4 cells."""
+    import oracle
+
+    import paper_2012_05587_amd as P
+    cases = []
+    for spread in (0.0, 0.2, 0.49, 0.5, 0.99):
+        for shape in (0, 1):
+            for bc in (workloads.PERIODIC, workloads.ABSORBING):
+                for nc in (3, 4, 512):
+                    cases.append(dict(_valid(), gamma_thr_spread=spread, shape=shape,
+                                      boundary=bc, n_cells=nc))
+    accepted = 0
+    for c in cases:
+        lib_ok = P.pic_validate_params(pc.gpu_params(c)) == P.OK
+        orc_ok = oracle.validate(**pc.gap_kwargs(c)) == oracle.OK
+        assert lib_ok == orc_ok, c
+        accepted += lib_ok
+    assert 0 < accepted < len(cases)
 
 
 def test_photon_store_required_for_finite_path():
