@@ -197,9 +197,7 @@ int orc_validate(const orc_params* p) {
       !((1.0 - p->f - p->gamma_thr_spread) * p->gamma_thr >= 1.0))
     return ORC_ERR_ARG;
   if (p->shape != ORC_SHAPE_LINEAR && p->shape != ORC_SHAPE_QUADRATIC) return ORC_ERR_ARG;
-  /* a three-node shape reaches past a wall: periodic gaps only */
-  if (p->shape == ORC_SHAPE_QUADRATIC && (p->boundary != ORC_BC_PERIODIC || p->n_cells < 4))
-    return ORC_ERR_ARG;
+  if (p->shape == ORC_SHAPE_QUADRATIC && p->n_cells < 4) return ORC_ERR_ARG;
   if (p->precision != ORC_FP64 && p->precision != ORC_MIXED) return ORC_ERR_ARG;
   if (p->capacity < 0) return ORC_ERR_ARG;
   return ORC_OK;
@@ -490,20 +488,37 @@ static int step_once(orc_gap* g) {
         /* charge-conserving deposit of the spline: the flux through cell k
          * (between nodes k and k+1) is the charge that left the nodes <= k,
          * the running sum of old minus new weight over nodes from the
-         * leftmost one either spline touches; positions relative to node c */
+         * leftmost one either spline touches; positions relative to node c.
+         * A lepton leaving through an absorbing wall is carried on to 3/2
+         * cells beyond it, where its spline no longer touches the wall node,
+         * and removed; fluxes through cells outside the domain are dropped. */
+        const int64_t X = (int64_t)c * ONE + nq;  /* from the left wall */
+        int64_t target = nq;
+        if (absorbing && X < 0) { target = -(ONE + ONE / 2) - (int64_t)c * ONE; keep = 0; }
+        if (absorbing && X >= domain) {
+          target = domain + ONE + ONE / 2 - (int64_t)c * ONE;
+          keep = 0;
+        }
         int64_t jn, Wn[3];
-        tsc_weights(g, nq, &jn, Wn);
+        tsc_weights(g, target, &jn, Wn);
         const int64_t lo = (jo < jn ? jo : jn) - 1, hi = (jo > jn ? jo : jn) + 1;
         int64_t run = 0;
         for (int64_t k = lo; k < hi; ++k) {
           const int64_t wo = (k >= jo - 1 && k <= jo + 1) ? Wo[k - jo + 1] : 0;
           const int64_t wn = (k >= jn - 1 && k <= jn + 1) ? Wn[k - jn + 1] : 0;
           run += wo - wn;
-          g->F[wrap_cell(g, c + (int32_t)k)] += q * run;
+          const int64_t cell = (int64_t)c + k;
+          if (absorbing) {
+            if (cell >= 0 && cell < P->n_cells) g->F[cell] += q * run;
+          } else {
+            g->F[wrap_cell(g, (int32_t)cell)] += q * run;
+          }
         }
-        /* the lepton's own cell and offset after the move (periodic) */
-        if (nq >= ONE) { nq -= ONE; c = wrap_cell(g, c + 1); }
-        else if (nq < 0) { nq += ONE; c = wrap_cell(g, c - 1); }
+        /* the lepton's own cell and offset after the move */
+        if (keep) {
+          if (nq >= ONE) { nq -= ONE; c = absorbing ? c + 1 : wrap_cell(g, c + 1); }
+          else if (nq < 0) { nq += ONE; c = absorbing ? c - 1 : wrap_cell(g, c - 1); }
+        }
       } else if (nq >= ONE) {
         g->F[c] += q * (ONE - oq);
         int32_t c1 = c + 1;
@@ -706,8 +721,12 @@ int orc_read_fields(const orc_gap* g, double* E, double* rho, int64_t* last_flux
           int64_t j, W[3];
           tsc_weights(g, g->sp[s].offq[i], &j, W);
           for (int k = 0; k < 3; ++k) {
-            int32_t node = c + (int32_t)j - 1 + k;     /* periodic: fold into [0, N) */
-            node = node < 0 ? node + N : (node >= N ? node - N : node);
+            int32_t node = c + (int32_t)j - 1 + k;
+            if (g->prm.boundary == ORC_BC_PERIODIC) {   /* fold into [0, N) */
+              node = node < 0 ? node + N : (node >= N ? node - N : node);
+            } else if (node < 0 || node > N) {
+              continue;                                  /* beyond a wall node */
+            }
             acc[node] += q * W[k];
           }
           continue;

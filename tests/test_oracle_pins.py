@@ -216,7 +216,7 @@ def test_cold_plasma_frequency_matches_leapfrog_dispersion(shape):
 # ------------------------------------------------------------ brute force
 @pytest.mark.parametrize("l_gamma,absorbing,spread,shape", [
     (0.0, True, 0.0, 0), (6.0, True, 0.0, 0), (6.0, False, 0.0, 0), (0.0, True, 0.3, 0),
-    (6.0, False, 0.3, 0), (6.0, False, 0.0, 1)])
+    (6.0, False, 0.3, 0), (6.0, False, 0.0, 1), (6.0, True, 0.0, 1)])
 def test_frozen_field_tree_matches_brute_force(l_gamma, absorbing, spread, shape):
     """Zero weight freezes E at E0; per-step lepton, photon, conversion, escape
     and absorption counts and every final lepton agree exactly with an
@@ -671,11 +671,14 @@ def test_quadratic_shape_charge_of_one_lepton(precision, cell, off):
     assert rho[N] == rho[0] and rho[:N].sum() == 1.0
 
 
+@pytest.mark.parametrize("boundary", [oracle.PERIODIC, oracle.ABSORBING])
 @pytest.mark.parametrize("precision", [oracle.FP64, oracle.MIXED])
-def test_gauss_residual_quadratic_shape(precision):
+def test_gauss_residual_quadratic_shape(precision, boundary):
     """The spline deposit conserves charge exactly: E_c - E_{c-1} = rho_c at
-    every node at round-off, through a cascade with photons."""
-    g = oracle.OracleGap(n_cells=128, dx=1.0, dt=0.45, boundary=oracle.PERIODIC, e0=20.0,
+    every node (every interior node with absorbing walls) at round-off,
+    through a cascade with photons, and with absorbing walls through the
+    removal of the leptons that leave (carried 3/2 cells past the wall)."""
+    g = oracle.OracleGap(n_cells=128, dx=1.0, dt=0.45, boundary=boundary, e0=20.0,
                          gamma_thr=60.0, f=0.5, l_gamma=8.0, weight=0.5, seed=11,
                          precision=precision, shape=oracle.SHAPE_QUADRATIC)
     g.seed(oracle.SEED_RANDOM, 256, 1)
@@ -683,7 +686,12 @@ def test_gauss_residual_quadratic_shape(precision):
     assert g.step(steps) == oracle.OK
     F = g.fields()
     E, rho = F["E"], F["rho"]
-    r = (E - np.roll(E, 1)) - rho[:-1]
+    if boundary == oracle.PERIODIC:
+        r = (E - np.roll(E, 1)) - rho[:-1]
+    else:
+        r = (E[1:] - E[:-1]) - rho[1:-1]
+        h = g.history()
+        assert h["absorbed_minus"][-1] > 100 and h["absorbed_plus"][-1] > 100
     assert np.abs(r).max() <= 10 * np.finfo(float).eps * steps * np.abs(E).max()
     assert g.history()["pairs_created"][-1] > 256
 
@@ -714,9 +722,34 @@ def test_quadratic_shape_heats_an_unresolved_plasma_less():
 
 
 def test_quadratic_shape_validation():
-    """The spline needs periodic walls and at least four cells."""
+    """The spline needs at least four cells."""
     base = dict(dx=1.0, dt=0.5, e0=1.0, gamma_thr=100.0, f=0.5, l_gamma=0.0, weight=1.0, seed=1)
     assert oracle.validate(n_cells=8, boundary=oracle.PERIODIC, shape=1, **base) == oracle.OK
-    assert oracle.validate(n_cells=8, boundary=oracle.ABSORBING, shape=1, **base) == oracle.ERR_ARG
+    assert oracle.validate(n_cells=8, boundary=oracle.ABSORBING, shape=1, **base) == oracle.OK
     assert oracle.validate(n_cells=3, boundary=oracle.PERIODIC, shape=1, **base) == oracle.ERR_ARG
     assert oracle.validate(n_cells=8, boundary=oracle.PERIODIC, shape=2, **base) == oracle.ERR_ARG
+
+
+def test_quadratic_shape_lepton_leaving_through_a_wall():
+    """A positron driven out through the right wall: Gauss's law, counted
+    from the initial field and charge, holds on every interior node at every
+    step; once the positron has left, no interior node holds any charge (its
+    charge went out through the last cells as current)."""
+    N = 16
+    g = oracle.OracleGap(n_cells=N, dx=1.0, dt=0.45, boundary=oracle.ABSORBING, e0=5.0,
+                         gamma_thr=1e300, f=0.5, l_gamma=0.0, weight=1.0, seed=1,
+                         shape=oracle.SHAPE_QUADRATIC)
+    g.seed_explicit(1, [N - 3], [0.5], [0.0], [3])
+    F0 = g.fields()
+    E0, rho0 = F0["E"].copy(), F0["rho"].copy()
+    assert rho0[1:-1].sum() == 1.0
+    left_at = None
+    for n in range(40):
+        assert g.step(1) == oracle.OK
+        F = g.fields()
+        r = (F["E"][1:] - F["E"][:-1]) - (E0[1:] - E0[:-1]) - (F["rho"][1:-1] - rho0[1:-1])
+        assert np.abs(r).max() < 1e-12, (n, r)
+        if g.count(1) == 0 and left_at is None:
+            left_at = n
+            assert np.all(F["rho"][1:-1] == 0.0)
+    assert left_at is not None and g.history()["absorbed_plus"][-1] == 1
