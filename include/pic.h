@@ -120,8 +120,11 @@ enum { PIC_ELECTRON = 0, PIC_POSITRON = 1 };
  *            integers in 2^-K (outer two rounded down, the middle one the
  *            rest); the flux is the running sum of their change, so Gauss's
  *            law stays exact, and the gather weights node-averaged E with
- *            the same fractions.  Periodic gaps of at least 4 cells only
- *            (the spline reaches 3/2 cells).                              */
+ *            the same fractions.  At least 4 cells.  With absorbing walls
+ *            the gather repeats the edge E (as for the linear shape), flux
+ *            through cells beyond a wall is dropped, and a lepton leaving
+ *            is carried 3/2 cells past the wall before it is removed, so
+ *            that its charge leaves the wall node as current.             */
 typedef struct {
   int32_t  n_cells;
   double   dx, dt;

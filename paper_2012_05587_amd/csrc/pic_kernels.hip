@@ -166,32 +166,41 @@ __device__ __forceinline__ void load_e3(gptr<const T> E, int cl, bool periodic, 
 
 // E at the four cells around the nodes jo-1, jo, jo+1 of the quadratic
 // spline of a lepton in cell cl (jo = 1 when its offset is at least 1/2):
-// cells cl+jo-2 .. cl+jo+1, periodic (the spline runs on periodic gaps only).
+// cells cl+jo-2 .. cl+jo+1, wrapped (periodic) or clamped to the edge cells
+// (absorbing: the gather's zero-gradient ghosts).
 template <typename T>
-__device__ __forceinline__ void load_e4(gptr<const T> E, int cl, T off, int nc, T& e0, T& e1,
-                                        T& e2, T& e3) {
+__device__ __forceinline__ void load_e4(gptr<const T> E, int cl, T off, bool periodic, int nc,
+                                        T& e0, T& e1, T& e2, T& e3) {
   const int c = cl == kDead ? 0 : cl;
   const int k0 = c + (off >= (T)0.5 ? 1 : 0) - 2;
   int i0 = k0, i1 = k0 + 1, i2 = k0 + 2, i3 = k0 + 3;
-  i0 = i0 < 0 ? i0 + nc : i0;
-  i1 = i1 < 0 ? i1 + nc : i1;
-  i2 = i2 >= nc ? i2 - nc : i2;
-  i3 = i3 >= nc ? i3 - nc : i3;
+  if (periodic) {
+    i0 = i0 < 0 ? i0 + nc : i0;
+    i1 = i1 < 0 ? i1 + nc : i1;
+    i2 = i2 >= nc ? i2 - nc : i2;
+    i3 = i3 >= nc ? i3 - nc : i3;
+  } else {
+    i0 = i0 < 0 ? 0 : i0;
+    i1 = i1 < 0 ? 0 : i1;
+    i2 = i2 >= nc ? nc - 1 : i2;
+    i3 = i3 >= nc ? nc - 1 : i3;
+  }
   e0 = E[i0];
   e1 = E[i1];
   e2 = E[i2];
   e3 = E[i3];
 }
 
-// Quadratic-spline weights of a lepton at X (units 2^-K cells from a node):
+// Quadratic-spline weights of a lepton at X (units 2^-K cells from a node,
+// -3/2 .. 5/2 cells):
 // nearest node j = floor(X / 2^K + 1/2), delta = X - j 2^K in [-1/2, 1/2) 2^K;
 // the outer nodes get floor((2^(K-1) -/+ delta)^2 / 2^(K+1)), the middle one
 // the rest of 2^K, so the three sum to 2^K exactly.
 template <typename I>
 __device__ __forceinline__ void spline_weights(I X, I ONE, int K, int& j, I& wl, I& wc, I& wr) {
   const I HALF = ONE >> 1;
-  const I t = X + HALF;
-  j = t < 0 ? -1 : (t >= 2 * ONE ? 2 : (t >= ONE ? 1 : 0));
+  const I t = X + HALF;  // in [-2^K, 3 2^K]: a move within a cell, or one carried past a wall
+  j = t < 0 ? -1 : (t >= 3 * ONE ? 3 : (t >= 2 * ONE ? 2 : (t >= ONE ? 1 : 0)));
   const I delta = X - (I)j * ONE;
   if constexpr (sizeof(I) == 4) {
     // 2^-24 grid: both factors fit 32 bits, one 32 x 32 -> 64 product each
@@ -391,7 +400,7 @@ __global__ __launch_bounds__(kBlock, PushCfg<T>::waves) void k_push(GapDev* __re
     T Em[kItems], Ec[kItems], Ep[kItems], Ex[kItems];
 #pragma unroll
     for (int j = 0; j < kEG; ++j) {
-      if constexpr (kSpline) load_e4(E, cl[j], ov[j], nc, Em[j], Ec[j], Ep[j], Ex[j]);
+      if constexpr (kSpline) load_e4(E, cl[j], ov[j], periodic, nc, Em[j], Ec[j], Ep[j], Ex[j]);
       else load_e3(E, cl[j], periodic, nc, Em[j], Ec[j], Ep[j]);
     }
     // prefetch the next chunk of this gap; the loads are issued whether or
@@ -461,7 +470,7 @@ __global__ __launch_bounds__(kBlock, PushCfg<T>::waves) void k_push(GapDev* __re
         if (j > 0 && j % kEG == 0) {
 #pragma unroll
           for (int jj = j; jj < j + kEG; ++jj) {
-            if constexpr (kSpline) load_e4(E, cl[jj], ov[jj], nc, Em[jj], Ec[jj], Ep[jj], Ex[jj]);
+            if constexpr (kSpline) load_e4(E, cl[jj], ov[jj], periodic, nc, Em[jj], Ec[jj], Ep[jj], Ex[jj]);
             else load_e3(E, cl[jj], periodic, nc, Em[jj], Ec[jj], Ep[jj]);
           }
         }
@@ -495,6 +504,33 @@ __global__ __launch_bounds__(kBlock, PushCfg<T>::waves) void k_push(GapDev* __re
           // (between nodes c+k and c+k+1) is the charge that left the nodes up
           // to c+k, the running sum of old minus new weight from the leftmost
           // node either spline touches (it returns to zero after the last)
+          // A lepton can leave only from an edge cell.  Through an absorbing
+          // wall it is carried on to 3/2 cells beyond it, where its spline no
+          // longer touches the wall node, and removed; fluxes through cells
+          // outside the domain are dropped.
+          const bool out_left = !periodic && c == 0 && nq < 0;
+          const bool out_right = !periodic && c == nc - 1 && nq >= ONE;
+          if (out_left || out_right) {
+            const I target = out_left ? -(ONE + (ONE >> 1)) : 2 * ONE + (ONE >> 1);
+            int jn;
+            I wn0, wn1, wn2;
+            spline_weights<I>(target, ONE, Kb, jn, wn0, wn1, wn2);
+            const int lo = min(jo, jn) - 1, hi = max(jo, jn) + 1;
+            I run = 0;
+            for (int k = lo; k < hi; ++k) {
+              const int ko = k - jo + 1, kn = k - jn + 1;
+              const I wo = ko == 0 ? wo0 : (ko == 1 ? wo1 : (ko == 2 ? wo2 : (I)0));
+              const I wn = kn == 0 ? wn0 : (kn == 1 ? wn1 : (kn == 2 ? wn2 : (I)0));
+              run += wo - wn;
+              const int cc = c + k;
+              const long long f = s == 0 ? -(long long)run : (long long)run;
+              if (f != 0 && cc >= 0 && cc < nc) {
+                if (lds) atomicAdd((unsigned long long*)&s_flux[cc - base], as_u64(f));
+                else gadd(F + cc, as_u64(f));
+              }
+            }
+            keep = false;
+          } else {
           int jn;
           I wn0, wn1, wn2;
           spline_weights<I>(nq, ONE, Kb, jn, wn0, wn1, wn2);
@@ -508,19 +544,23 @@ __global__ __launch_bounds__(kBlock, PushCfg<T>::waves) void k_push(GapDev* __re
             const I wn = kn == 0 ? wn0 : (kn == 1 ? wn1 : (kn == 2 ? wn2 : (I)0));
             run += wo - wn;
             const long long f = s == 0 ? -(long long)run : (long long)run;
-            if (f != 0) {
+            const int cu = c + k;  // unwrapped cell
+            // beside an absorbing wall the spline's flux through the cells
+            // beyond it is dropped; periodic gaps wrap it (at the flush)
+            if (f != 0 && (periodic || (cu >= 0 && cu < nc))) {
               if (lds) {
                 // unwrapped tile index: c - 2 .. c + 2 lie in [base, base + span)
-                atomicAdd((unsigned long long*)&s_flux[c + k - base], as_u64(f));
+                atomicAdd((unsigned long long*)&s_flux[cu - base], as_u64(f));
               } else {
-                int cc = c + k;
-                cc = cc < 0 ? cc + nc : (cc >= nc ? cc - nc : cc);
+                const int cc = cu < 0 ? cu + nc : (cu >= nc ? cu - nc : cu);
                 gadd(F + cc, as_u64(f));
               }
             }
           }
+          // the lepton's cell after the move (inside the domain here)
           if (nq >= ONE) { nq -= ONE; c2 = c + 1 >= nc ? 0 : c + 1; }
           else if (nq < 0) { nq += ONE; c2 = c - 1 < 0 ? nc - 1 : c - 1; }
+          }
         } else {
           I a1, a2 = 0;   // flux of a positive charge through this cell and the next
           int cross = 0;  // -1, 0, +1: node crossed to the left / none / right
@@ -1700,14 +1740,18 @@ __global__ __launch_bounds__(kBlock) void k_rho(GapDev* __restrict__ gaps, int g
       if (c == kDead) continue;
       const long long oq = (long long)(((const T*)G->off[buf][s])[i] * scale);
       if (G->shape == PIC_SHAPE_QUADRATIC) {
-        // the spline's three nodes, folded into [0, n_cells) (periodic)
+        // the spline's three nodes, folded into [0, n_cells) (periodic) or
+        // dropped beyond the wall nodes (absorbing)
         int j;
         long long w0, w1, w2;
         spline_weights<long long>(oq, (long long)G->one, G->K, j, w0, w1, w2);  // any K
         const long long wk[3] = {w0, w1, w2};
         for (int k = 0; k < 3; ++k) {
           int node = c + j - 1 + k;
-          node = node < 0 ? node + G->n_cells : (node >= G->n_cells ? node - G->n_cells : node);
+          if (G->boundary == PIC_BC_PERIODIC)
+            node = node < 0 ? node + G->n_cells : (node >= G->n_cells ? node - G->n_cells : node);
+          else if (node < 0 || node > G->n_cells)
+            continue;  // beyond a wall node
           atomicAdd((unsigned long long*)&G->rho_acc[node], as_u64(q * wk[k]));
         }
         continue;

@@ -90,9 +90,7 @@ pic_status validate(const pic_gap_params* p) {
   if (!std::isfinite(p->j_m)) return PIC_ERR_ARG;
   if (!(p->gamma_thr_spread >= 0.0) || !(p->gamma_thr_spread < 1.0)) return PIC_ERR_ARG;
   if (p->shape != PIC_SHAPE_LINEAR && p->shape != PIC_SHAPE_QUADRATIC) return PIC_ERR_ARG;
-  // a three-node shape reaches past a wall: periodic gaps only
-  if (p->shape == PIC_SHAPE_QUADRATIC && (p->boundary != PIC_BC_PERIODIC || p->n_cells < 4))
-    return PIC_ERR_ARG;
+  if (p->shape == PIC_SHAPE_QUADRATIC && p->n_cells < 4) return PIC_ERR_ARG;
   if (p->gamma_thr_spread > 0.0 && std::isfinite(p->gamma_thr) &&
       !((1.0 - p->f - p->gamma_thr_spread) * p->gamma_thr >= 1.0))
     return PIC_ERR_ARG;

@@ -55,7 +55,7 @@ def test_validate_accepts_configs():
     ("f", 0.01), ("gamma_thr", 1.0), ("l_gamma", -2.0), ("weight", -1.0), ("capacity", 0),
     ("capacity", 2**31), ("precision", 3), ("e0", float("inf")), ("sort_every", -1),
     ("j_m", float("nan")), ("gamma_thr_spread", -0.1), ("gamma_thr_spread", 1.0),
-    ("gamma_thr_spread", 0.5), ("shape", 2), ("shape", 1),
+    ("gamma_thr_spread", 0.5), ("shape", 2), ("shape", -1),
 ])
 def test_validate_rejects(field, value):
     import paper_2012_05587_amd as P
@@ -68,7 +68,7 @@ def test_validate_rejects(field, value):
 def test_variants_validate_alike_in_library_and_oracle():
     """The library and the oracle accept and reject the same variant
     parameters: a spread of gamma_thr needs (1 - f - sigma) gamma_thr >= 1,
-    the quadratic shape periodic walls and at least 4 cells."""
+    the quadratic shape at least 4 cells."""
     import oracle
 
     import paper_2012_05587_amd as P
