@@ -48,8 +48,8 @@ typedef struct {
                            in gamma_thr (1 - sigma, 1 + sigma), drawn from its id (the
                            spread the paper's conclusion names); 0 = one threshold */
   int32_t  shape;       /* particle shape: ORC_SHAPE_LINEAR (cloud in cell) or
-                           ORC_SHAPE_QUADRATIC (quadratic spline over three nodes,
-                           periodic gaps only) */
+                           ORC_SHAPE_QUADRATIC (quadratic spline over three nodes;
+                           at least 4 cells) */
 } orc_params;
 
 typedef struct {
