@@ -5,11 +5,14 @@
 //              integer charge-conserving flux (per-workgroup LDS tile reduced
 //              into the global int64 grid), absorb/wrap, and the threshold
 //              test: the emitter loses k * gamma_pair and is listed;
-//   k_emit     listed emitters draw their photons (or in-place pairs) from
-//              Philox and append them;
-//   k_field    Ampere's law E -= w 2^-K F (Eq. 4 in normalised units) and the
-//              field diagnostics;
-//   k_convert  photons due this step become pairs (appended);
+//              instantiated with the linear or quadratic-spline shape and
+//              with or without per-lepton thresholds;
+//   k_post     four roles on disjoint block ranges of one launch: Ampere's
+//              law E -= w 2^-K F (Eq. 4 in normalised units; plus j_m dt in
+//              the co-rotating frame) with the field diagnostics; the listed
+//              emitters draw their photons (or in-place pairs) from Philox
+//              and append them; photons due this step become pairs; the
+//              striped push tallies are folded;
 //   k_finalize counters, history row and the work plan of the next step.
 // Every S steps the leptons are re-sorted by cell and the photon store by
 // conversion step (counting sorts), which drops absorbed leptons and
@@ -27,17 +30,6 @@
 #include "pic_kernels.hpp"
 
 namespace pic {
-
-__device__ __forceinline__ int wrap_or_clamp(const GapDev& G, int c) {
-  if (G.boundary == PIC_BC_PERIODIC) {
-    if (c < 0) c += G.n_cells;
-    else if (c >= G.n_cells) c -= G.n_cells;
-  } else {
-    if (c < 0) c = 0;
-    else if (c >= G.n_cells) c = G.n_cells - 1;
-  }
-  return c;
-}
 
 __device__ __forceinline__ unsigned long long as_u64(long long v) { return (unsigned long long)v; }
 
@@ -263,7 +255,7 @@ __device__ __forceinline__ void push_item(long long local, long long chunks0, lo
 // chunk are requested before that prefetch, so waiting for them leaves the
 // prefetch in flight.  The gap's constants are read once per gap.  kSpread
 // instantiates the per-lepton thresholds of a spread of gamma_thr, kSpline
-// the quadratic-spline shape (periodic gaps); batches without them run the
+// the quadratic-spline shape; batches without them run the
 // kernel without that code.
 template <typename T, bool kSpread, bool kSpline>
 __global__ __launch_bounds__(kBlock, PushCfg<T>::waves) void k_push(GapDev* __restrict__ gaps,
