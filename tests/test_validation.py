@@ -23,7 +23,10 @@ Measured against:
 - the non-uniform start of the conclusion (field and seed decaying with
   altitude): screening at each altitude on the local clock of section 3;
 - a spread of the threshold (also named in the conclusion): growth, omega_0,
-  and the smoothing it brings to the generations and the bursts.
+  and the smoothing it brings to the generations and the bursts;
+- the co-rotating gap of section 7 at the paper's scale: equilibrium bulk,
+  the gap at one wall, the first pairs once its potential drop exceeds
+  gamma_thr, and the screening by the bursts.
 
 f = 10^-3 (the smallest f the paper reports checking) needs f gamma_thr >= 2
 for a pair to hold two rest masses, so it runs with gamma_thr = 5000.
@@ -340,3 +343,57 @@ def test_nonuniform_gap_screens_on_the_local_clock():
         assert 0.9 < tm / tf < 1.3, (b, tm, tf)
     t = [r[1] for r in screened]
     assert all(a < c for a, c in zip(t[:-1], t[1:])), t  # the front moves up
+
+
+def test_corotating_gap_at_paper_scale():
+    """Section 7's co-rotating gap at the paper's scale: L = 1000 c/omega_p,GJ
+    in 10000 cells, dt = 1e-3, j_m = -1.5 rho_GJ c, gamma_thr = 5000,
+    f = 0.01, pairs in place, to t = 300.  The two-density cold loading is an
+    equilibrium, so E stays zero in the bulk (to the rounding of the loaded
+    velocities).  A gap opens at the
+    wall the positrons leave through, its field growing linearly in time.
+    No lepton can gain more than the gap's potential drop, so the first
+    pairs appear only once that drop exceeds gamma_thr, and next to that
+    wall.  The bursts then screen the gap field."""
+    import torch
+
+    from tests.pic_cases import make_gpu
+    steps, every = 300000, 1000
+    cfg = dict(workloads.corotating_gap(), history_rows=steps // 10 + 8, diag_every=10)
+    g = make_gpu(cfg, stream=torch.cuda.Stream())
+    try:
+        g.set_event_map(500, every, steps // every)
+        Es = []
+        for _ in range(steps // every):
+            g.step_n(every)
+            Es.append(g.read_fields(rho=False)["E"])
+        emap = g.read_event_map()
+        assert g.read_moments().status == 0
+    finally:
+        g.close()
+        del g
+        torch.cuda.empty_cache()
+    E = np.array(Es)  # row r: E after (r + 1) * every steps, t = r + 1
+    nc, dx = cfg["n_cells"], cfg["dx"]
+    # the loaded streams' binary32 velocities differ from j_m in the last
+    # bits: at most steps * j_m dt * 2^-23 ~ 5e-5 of drift in the bulk
+    bulk = E[:, int(0.3 * nc):int(0.7 * nc)]
+    assert np.abs(bulk).max() < 1e-4, np.abs(bulk).max()
+    rows = np.nonzero(emap.sum(axis=1))[0]
+    assert rows.size > 0
+    first = int(rows[0])  # pairs first made during t in (first, first + 1]
+    emax = np.abs(E).max(axis=1)
+    peak_at = np.argmax(np.abs(E), axis=1)
+    # before the first pairs the field peaks at the last cells of the right wall
+    assert np.all(peak_at[:first] >= nc - 10), peak_at[:first].min()
+    # and grows linearly in time
+    assert abs(emax[99] / emax[49] - 2.0) < 0.1, (emax[49], emax[99])
+    # the potential drop across the gap (the bulk carries none)
+    V = E.sum(axis=1) * dx
+    gthr = cfg["gamma_thr"]
+    assert V[first - 1] >= gthr and V[first] <= 3.0 * gthr, (V[first - 1], V[first])
+    # the first pairs are made next to that wall
+    assert np.nonzero(emap[first])[0].min() >= int(0.9 * emap.shape[1])
+    # the bursts screen the gap field
+    assert emax[-1] < 0.6 * emax[first], (emax[first], emax[-1])
+    print("first pairs at t", first + 1, "drop", V[first], "E max", emax[first], "->", emax[-1])
