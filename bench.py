@@ -72,6 +72,8 @@ def _workload(name, precision=None):
             0.1, precision=workloads.MIXED if precision is None else precision,
             gamma_thr_spread=0.25 if name == "n4_spread" else 0.0,
             shape=1 if name == "n4_spline" else 0)]
+    elif name == "ubench_lattice":
+        gaps = [workloads.stream_lattice(precision=workloads.MIXED if precision is None else precision)]
     elif name == "n4_nonuniform":
         gaps = [workloads.nonuniform_gap(precision=workloads.MIXED if precision is None else precision)]
     else:
@@ -91,7 +93,8 @@ def _make(P, gaps, stream):
         views = g.gaps
     for v, c in zip(views, gaps):
         if c["n_pairs"]:
-            v.seed_particles(workloads.SEED_RANDOM, c["n_pairs"], c["macro_per_pair"])
+            v.seed_particles(c.get("seed_mode", workloads.SEED_RANDOM), c["n_pairs"],
+                             c["macro_per_pair"])
         for sp, (cell, off, p, ids) in sorted(c.get("explicit", {}).items()):
             v.seed_explicit(sp, cell, off, p, ids)
         if c.get("E_init") is not None:
@@ -197,7 +200,7 @@ def _oracle_gap(args):
             kw[k] = c[k]
     o = oracle.OracleGap(**kw, capacity=0)
     if c["n_pairs"]:
-        o.seed(workloads.SEED_RANDOM, c["n_pairs"], c["macro_per_pair"])
+        o.seed(c.get("seed_mode", workloads.SEED_RANDOM), c["n_pairs"], c["macro_per_pair"])
     for sp, (cell, off, p, ids) in sorted(c.get("explicit", {}).items()):
         o.seed_explicit(sp, cell, off, p, ids)
     if c.get("E_init") is not None:
@@ -392,7 +395,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--workload", default="c4_batched",
                     choices=["c4_batched", "n1_corotating", "n3_uniform", "n4_spread", "n4_spline",
-                             "n4_nonuniform"]
+                             "n4_nonuniform", "ubench_lattice"]
                     + sorted(workloads.CONFIGS))
     ap.add_argument("--sort-every", type=int, default=None,
                     help="re-sort cadence for every gap (0 = tuned while running; default: the workload's)")

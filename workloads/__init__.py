@@ -173,6 +173,19 @@ def nonuniform_gap(n_cells=2000, length=10.0 ** 1.5, dt=10.0 ** -3.5, e0=10.0 **
                 photon_capacity=photon_capacity, E_init=E, explicit=explicit)
 
 
+def stream_lattice(n_pairs=100_000_000, n_cells=65536, precision=MIXED, steps=200,
+                   seed=BASE_SEED + 50):
+    """The push alone: emission off (gamma_thr = inf), periodic, n_pairs
+    pairs on the lattice x_i = (i + 1/2) n_cells / N at rest, E0 = 1, weight
+    1e-6 (so the plasma barely moves the field).  Every chunk stays sorted
+    and nothing is appended, so the step is one streaming push of every
+    lepton plus the cheap field update."""
+    return dict(n_cells=n_cells, dx=1.0, dt=0.45, boundary=PERIODIC, e0=1.0,
+                gamma_thr=float("inf"), f=0.5, l_gamma=0.0, weight=1e-6, seed=seed,
+                precision=precision, n_pairs=n_pairs, macro_per_pair=1,
+                seed_mode=SEED_LATTICE, steps=steps, capacity=n_pairs, photon_capacity=0)
+
+
 def scaled(name, **over):
     """A configuration with some fields replaced (smaller parity cases)."""
     c = config(name)
