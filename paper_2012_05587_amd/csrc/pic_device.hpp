@@ -37,6 +37,11 @@ constexpr int kTile = 2048;           // cells of the per-workgroup LDS current 
 constexpr int kPhChunk = kBlock * 4;  // photons per convert work item
 constexpr int kCellChunk = kBlock * 4;
 constexpr int kSortTile = 8192;       // cells of the LDS histogram of the lepton sort
+// lepton chunks per iteration of the lepton sort: counting holds only the
+// cells, moving holds the whole lepton state
+template <int PASS>
+struct SortPer { static constexpr int value = PASS == 0 ? 4 : 2; };
+constexpr int kPhUnroll = 4;          // photons per thread per iteration of the photon sort
 constexpr int kPhBins = 8192;         // conversion steps of the LDS histogram of the photon sort
 constexpr int32_t kDead = INT32_MIN;  // cell of an absorbed lepton until re-sort
 constexpr int kMaxEmit = 64;

@@ -1431,35 +1431,47 @@ __global__ __launch_bounds__(kBlock) void k_sort_zero(GapDev* __restrict__ gaps,
 // other buffer.  A chunk whose cells span at most kSortTile counts in an LDS
 // histogram first and touches each global bucket once; wider chunks (leptons
 // appended since the last sort) use one global atomic per run of equal cells.
+// An iteration takes up to SortPer consecutive chunks of one (gap, species),
+// so the barriers and the round trip of the bucket atomics are shared.
 template <int PASS, typename T>
 __global__ __launch_bounds__(kBlock) void k_sort_pass(GapDev* __restrict__ gaps,
                                                       const long long* __restrict__ wi, int B) {
+  constexpr int kPer = SortPer<PASS>::value;
+  constexpr int kN = kItems * kPer;  // leptons per thread per iteration
   __shared__ int32_t s_hist[kSortTile];
   __shared__ int s_red[8];
   const long long total = wi[B];
   long long w0, w1;
   xcd_range(total, w0, w1);
   const int lane = lane_id();
-  for (long long w = w0; w < w1; ++w) {
+  for (long long w = w0; w < w1;) {
     const int g = find_gap(wi, B, w);
     GapDev* __restrict__ G = gaps + g;
-    if (G->status != PIC_OK) continue;
-    const int buf = G->buf;
     const long long chunks0 = ((long long)G->n[0] + kChunk - 1) / kChunk;
     const long long local = w - wi[g];
     const int s = local < chunks0 ? 0 : 1;
+    // chunks [w, wn): the same species of the same gap, inside this range
+    // (w lies below both ends, so at least one chunk is taken)
+    const long long seg_end = s == 0 ? wi[g] + chunks0 : wi[g + 1];
+    long long wn = w + kPer;
+    if (wn > seg_end) wn = seg_end;
+    if (wn > w1) wn = w1;
+    const long long nch = wn - w;
+    w = wn;
+    if (G->status != PIC_OK) continue;
+    const int buf = G->buf;
     const long long i0 = (s == 0 ? local : local - chunks0) * kChunk;
     const long long nS = (long long)G->n[s];
-    const long long i1 = i0 + kChunk < nS ? i0 + kChunk : nS;
+    const long long i1 = i0 + nch * kChunk < nS ? i0 + nch * kChunk : nS;
     gptr<int32_t> cnt = glb(G->sort_cnt[s]);
     gptr<const int32_t> cin = glb<const int32_t>((void*)G->cell[buf][s]);
     // the whole lepton state is requested at once (slots past the end read
     // slot 0 and are discarded), before any store of this chunk
-    int cvs[kItems];
-    T ov[kItems], pv[kItems];
-    uint64_t idv[kItems];
+    int cvs[kN];
+    T ov[kN], pv[kN];
+    uint64_t idv[kN];
 #pragma unroll
-    for (int j = 0; j < kItems; ++j) {
+    for (int j = 0; j < kN; ++j) {
       const long long i = i0 + threadIdx.x + (long long)j * kBlock;
       const long long ii = i < i1 ? i : 0;
       const int cv = cin[ii];
@@ -1472,19 +1484,27 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(GapDev* __restrict__ gaps,
     }
     int mn = INT32_MAX, mx = INT32_MIN;
 #pragma unroll
-    for (int j = 0; j < kItems; ++j)
+    for (int j = 0; j < kN; ++j)
       if (cvs[j] != kDead) { mn = min(mn, cvs[j]); mx = max(mx, cvs[j]); }
     block_minmax(mn, mx, s_red);
     if (mx < mn) continue;  // no live lepton in this chunk (uniform)
-    long long dst[kItems];
+    long long dst[kN];
     if (mx - mn < kSortTile) {
       const int span = mx - mn + 1;
       for (int k = threadIdx.x; k < span; k += kBlock) s_hist[k] = 0;
       __syncthreads();
-      int rank[kItems];
+      // sorted leptons share cells, so the lanes of a wave form long runs:
+      // one LDS atomic per run, the rank within it from the lane
+      int rank[kN];
 #pragma unroll
-      for (int j = 0; j < kItems; ++j)
-        rank[j] = cvs[j] != kDead ? atomicAdd(&s_hist[cvs[j] - mn], 1) : 0;
+      for (int j = 0; j < kN; ++j) {
+        const int cv = cvs[j];
+        int head_lane, run_len;
+        wave_runs(cv, head_lane, run_len);
+        int r = 0;
+        if (run_len > 0 && cv != kDead) r = atomicAdd(&s_hist[cv - mn], run_len);
+        rank[j] = __shfl(r, head_lane, 64) + (lane - head_lane);
+      }
       __syncthreads();
       for (int k = threadIdx.x; k < span; k += kBlock) {
         const int c = s_hist[k];
@@ -1497,11 +1517,11 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(GapDev* __restrict__ gaps,
       if (PASS == 0) continue;  // the next chunk's block_minmax orders the LDS reuse
       __syncthreads();
 #pragma unroll
-      for (int j = 0; j < kItems; ++j)
+      for (int j = 0; j < kN; ++j)
         dst[j] = cvs[j] != kDead ? (long long)s_hist[cvs[j] - mn] + rank[j] : 0;
     } else {
 #pragma unroll
-      for (int j = 0; j < kItems; ++j) {
+      for (int j = 0; j < kN; ++j) {
         const int cv = cvs[j];
         int head_lane, run_len;
         wave_runs(cv, head_lane, run_len);
@@ -1521,7 +1541,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(GapDev* __restrict__ gaps,
     gptr<T> pout = glb<T>(G->p[nb][s]);
     gptr<uint64_t> iout = glb(G->id[nb][s]);
 #pragma unroll
-    for (int j = 0; j < kItems; ++j) {
+    for (int j = 0; j < kN; ++j) {
       if (cvs[j] == kDead) continue;
       const long long d = dst[j];
       cout[d] = cvs[j];
@@ -1603,9 +1623,22 @@ __global__ __launch_bounds__(kBlock) void k_ph_pass(GapDev* __restrict__ gaps,
     if (L <= kPhBins) {
       for (int k = threadIdx.x; k < L; k += kBlock) s_hist[k] = 0;
       __syncthreads();
-      for (long long i = p0 + threadIdx.x; i < p1; i += kBlock) {
-        const long long cs = sin[i];
-        if (cs >= stepn) atomicAdd(&s_hist[cs - stepn], 1);
+      // one LDS atomic per run of equal keys in a wave (the sorted body of
+      // the store holds long runs)
+      for (long long r = p0; r < p1; r += kPhUnroll * kBlock) {
+        int key[kPhUnroll];
+#pragma unroll
+        for (int k = 0; k < kPhUnroll; ++k) {
+          const long long i = r + threadIdx.x + (long long)k * kBlock;
+          const long long cs = i < p1 ? (long long)sin[i] : (long long)INT32_MIN;
+          key[k] = cs >= stepn ? (int)(cs - stepn) : -1;
+        }
+#pragma unroll
+        for (int k = 0; k < kPhUnroll; ++k) {
+          int head_lane, run_len;
+          wave_runs(key[k], head_lane, run_len);
+          if (run_len > 0 && key[k] >= 0) atomicAdd(&s_hist[key[k]], run_len);
+        }
       }
       __syncthreads();
       for (int k = threadIdx.x; k < L; k += kBlock) {
@@ -1618,13 +1651,40 @@ __global__ __launch_bounds__(kBlock) void k_ph_pass(GapDev* __restrict__ gaps,
       }
       if (PASS == 1) {
         __syncthreads();
-        for (long long i = p0 + threadIdx.x; i < p1; i += kBlock) {
-          const long long cs = sin[i];
-          if (cs < stepn) continue;
-          const long long dst = atomicAdd(&s_hist[cs - stepn], 1);
-          G->ph_x[pb ^ 1][dst] = G->ph_x[pb][i];
-          G->ph_step[pb ^ 1][dst] = (int32_t)cs;
-          G->ph_child[pb ^ 1][dst] = G->ph_child[pb][i];
+        for (long long r = p0; r < p1; r += kPhUnroll * kBlock) {
+          int key[kPhUnroll];
+          long long xv[kPhUnroll];
+          uint64_t chv[kPhUnroll];
+#pragma unroll
+          for (int k = 0; k < kPhUnroll; ++k) {
+            const long long i = r + threadIdx.x + (long long)k * kBlock;
+            const long long cs = i < p1 ? (long long)sin[i] : (long long)INT32_MIN;
+            key[k] = cs >= stepn ? (int)(cs - stepn) : -1;
+          }
+          // the kept photons' state is requested before the ranks are taken
+#pragma unroll
+          for (int k = 0; k < kPhUnroll; ++k) {
+            const long long i = r + threadIdx.x + (long long)k * kBlock;
+            xv[k] = 0;
+            chv[k] = 0;
+            if (key[k] >= 0) {
+              xv[k] = G->ph_x[pb][i];
+              chv[k] = G->ph_child[pb][i];
+            }
+          }
+#pragma unroll
+          for (int k = 0; k < kPhUnroll; ++k) {
+            int head_lane, run_len;
+            wave_runs(key[k], head_lane, run_len);
+            int b = 0;
+            if (run_len > 0 && key[k] >= 0) b = atomicAdd(&s_hist[key[k]], run_len);
+            b = __shfl(b, head_lane, 64);
+            if (key[k] < 0) continue;
+            const long long dst = (long long)b + (lane - head_lane);
+            G->ph_x[pb ^ 1][dst] = xv[k];
+            G->ph_step[pb ^ 1][dst] = (int32_t)(stepn + key[k]);
+            G->ph_child[pb ^ 1][dst] = chv[k];
+          }
         }
       }
       __syncthreads();  // s_hist is zeroed for the next range
