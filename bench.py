@@ -174,6 +174,29 @@ def run_gpu(gaps, steps, profile=True, dump=None):
     return out
 
 
+def measure_copy_gbs(nbytes=1 << 30, reps=10):
+    """Bandwidth of a plain device copy (bytes read plus bytes written per
+    second, the fastest of `reps` copies of `nbytes`): the streaming ceiling
+    the push kernel is also compared with.  Untimed by the benchmark."""
+    import torch
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1) * 1e-3)
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / min(times) / 1e9
+
+
 def warm_up(steps):
     """Loads the code objects and builds a graph on a small batch."""
     import torch
@@ -455,6 +478,7 @@ def main():
                           f"{cb['seconds']:.1f} s)")
 
     warm_up(args.warmup)
+    copy_gbs = None if args.timed_only else measure_copy_gbs()
     main_run = run_gpu(gaps, steps, profile=not args.timed_only, dump=args.dump_history)
     value = main_run["pushes"] / main_run["seconds"]
     bpp = BYTES_PER_PUSH[prec]
@@ -525,6 +549,7 @@ def main():
                      "alg_bytes_per_launch": main_run["evented_pushes"] * bpp / max(main_run["push_launches"], 1),
                      "evented_run": {"pushes": main_run["evented_pushes"],
                                      "sort_every": main_run["tuning"]["sort_every"]},
+                     "copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs,
                      "kernel": "k_push", "bytes_per_push": bpp,
                      "kernel_ms": main_run["push_ms"], "launches": main_run["push_launches"]},
         "cpu_baseline": cpu,
