@@ -80,7 +80,11 @@ enum { PIC_ELECTRON = 0, PIC_POSITRON = 1 };
  *            split equally; requires 0 < f < 1, f*gamma_thr >= 2 and
  *            (1-f)*gamma_thr >= 1.  gamma_thr = +inf turns emission off.
  *  l_gamma   mean photon path in cells before conversion; 0 makes the pair
- *            in place, as in the paper's model.
+ *            in place, as in the paper's model.  Positions are int64
+ *            multiples of 2^-K cells, so the domain and the longest photon
+ *            path (about 22.2 l_gamma cells, where the conversion table ends)
+ *            must each stay below 2^62 of them: with binary64 (K = 40) that
+ *            is n_cells <= 2^22 and l_gamma below about 1.9e5 cells.
  *  weight    macro-particle weight w >= 0 (w = 0 gives test particles).
  *  capacity, photon_capacity  slots per species / in the photon store.  A
  *            step whose appends do not fit freezes the gap (the state of

@@ -200,6 +200,19 @@ int orc_validate(const orc_params* p) {
   if (p->shape == ORC_SHAPE_QUADRATIC && p->n_cells < 4) return ORC_ERR_ARG;
   if (p->precision != ORC_FP64 && p->precision != ORC_MIXED) return ORC_ERR_ARG;
   if (p->capacity < 0) return ORC_ERR_ARG;
+  /* Positions are int64 multiples of 2^-K cells.  The domain and a photon's
+   * longest path stay below 2^62 of them.  The conversion table ends after
+   * at most ceil(32 ln 2 / r) + 3 entries, r = dt / (l_gamma dx), and a
+   * photon moves dt/dx cells per step. */
+  {
+    const double unit = ldexp(1.0, p->precision == ORC_MIXED ? 24 : 40);
+    if ((double)p->n_cells * unit > 0x1p62) return ORC_ERR_ARG;
+    if (p->l_gamma > 0.0) {
+      const double r = p->dt / (p->l_gamma * p->dx);
+      const double len = ceil(32.0 * log(2.0) / r) + 3.0;
+      if ((len + 1.0) * (p->dt / p->dx * unit + 1.0) >= 0x1p62) return ORC_ERR_ARG;
+    }
+  }
   return ORC_OK;
 }
 

@@ -56,8 +56,10 @@ int offset_bits(int precision) { return precision == PIC_MIXED ? 24 : 40; }
 int64_t table_length(const pic_gap_params& p) {
   if (!(p.l_gamma > 0.0)) return 0;
   const double r = p.dt / (p.l_gamma * p.dx);
-  // the entries vanish once k r > 32 ln 2
-  return (int64_t)std::ceil(32.0 * std::log(2.0) / r) + 3;
+  // the entries vanish once k r > 32 ln 2; a length beyond any valid table
+  // is clamped before the conversion to an integer
+  const double len = std::ceil(32.0 * std::log(2.0) / r) + 3.0;
+  return len < 0x1p40 ? (int64_t)len : (int64_t)1 << 40;
 }
 
 std::vector<uint32_t> build_table(const pic_gap_params& p) {
@@ -100,6 +102,15 @@ pic_status validate(const pic_gap_params* p) {
   if (p->precision != PIC_FP64 && p->precision != PIC_MIXED) return PIC_ERR_ARG;
   if (p->sort_every < 0 || p->diag_every < 0 || p->history_rows < 0) return PIC_ERR_ARG;
   if (table_length(*p) > (int64_t)1 << 28) return PIC_ERR_ARG;
+  // Positions are int64 multiples of 2^-K cells: a photon's longest path
+  // (the last step of the conversion table, dt/dx cells per step) and the
+  // domain each stay below 2^62 of them, so a conversion point never
+  // overflows.
+  const double unit = std::ldexp(1.0, offset_bits(p->precision));
+  if ((double)p->n_cells * unit > 0x1p62) return PIC_ERR_ARG;
+  if (table_length(*p) > 0 &&
+      (double)(table_length(*p) + 1) * (p->dt / p->dx * unit + 1.0) >= 0x1p62)
+    return PIC_ERR_ARG;
   return PIC_OK;
 }
 

@@ -396,6 +396,35 @@ def test_ragged_counts(n_pairs):
     _check_all(gg, go, cfg["precision"])
 
 
+@pytest.mark.parametrize("precision", [workloads.FP64, workloads.MIXED])
+@pytest.mark.parametrize("boundary", [workloads.ABSORBING, workloads.PERIODIC])
+def test_maximum_cell_count(precision, boundary):
+    """The largest gap the library takes: 2^22 cells, a domain of 2^62 units
+    of the binary64 offset grid.  4096 pairs at random over it cascade with
+    photons 20 cells long, and the sort's histograms span far more cells
+    than one LDS tile.  64 positrons in the last cells and 64 electrons in
+    the first, driven outward near gamma_thr, emit photons across the ends:
+    their conversion points wrap (periodic) or escape (absorbing), and the
+    leptons themselves wrap or leave."""
+    n = 2**22
+    k = np.arange(64)
+    ids = (1 << 60) + 2 * k
+    cfg = workloads.config("c1_fp64_reference_gap")
+    cfg.update(n_cells=n, e0=50.0, gamma_thr=200.0, l_gamma=20.0, n_pairs=4096,
+               macro_per_pair=1, precision=precision, boundary=boundary, capacity=300_000,
+               photon_capacity=300_000, sort_every=20,
+               explicit={0: (k.astype(np.int32), np.full(64, 0.5), np.full(64, -150.0), ids),
+                         1: ((n - 64 + k).astype(np.int32), np.full(64, 0.5), np.full(64, 150.0),
+                             ids + 1)})
+    gg, go = _run_pair(cfg, 45)
+    _check_all(gg, go, precision)
+    h = go.history()
+    assert h["photons_emitted"][-1] > 10_000 and h["pairs_created"][-1] > 0
+    if boundary == workloads.ABSORBING:
+        assert h["photons_escaped"][-1] > 0
+        assert h["absorbed_minus"][-1] > 0 and h["absorbed_plus"][-1] > 0
+
+
 def test_capacity_overflow_freezes_gap():
     """A tiny slot count freezes the gap at the last completed step; the
     history up to then is the oracle's (periodic, in place: slots = live)."""

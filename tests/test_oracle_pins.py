@@ -296,8 +296,11 @@ def test_invalid_parameters_rejected():
     assert oracle.validate(**base) == oracle.OK
     for k, v in [("dt", 1.0), ("dt", 1.5), ("f", 0.01), ("f", 1.0), ("gamma_thr", 1.0),
                  ("n_cells", 1), ("boundary", 7), ("l_gamma", -1.0), ("weight", -1.0),
-                 ("e0", float("nan"))]:
+                 ("e0", float("nan")), ("n_cells", 2**22 + 1), ("l_gamma", 1e6),
+                 ("l_gamma", 1e30)]:
         assert oracle.validate(**{**base, k: v}) == oracle.ERR_ARG, k
+    # positions on the 2^-24 grid of the mixed path leave room for longer paths
+    assert oracle.validate(**{**base, "l_gamma": 1e6, "precision": oracle.MIXED}) == oracle.OK
 
 
 # -------------------------------------------------------- analytic physics
