@@ -221,7 +221,10 @@ pic_status pic_seed_explicit(pic_gap* g, int32_t species, int64_t n, const int32
  * pairs and appends the new leptons.  Returns without waiting; *out (may be
  * NULL) is filled after a stream synchronisation if non-NULL.
  * Errors: PIC_ERR_STATE if the gap is already frozen; a new freeze is
- * reported by the status in *out, pic_read_moments, or the next call. */
+ * reported by the status in *out, pic_read_moments, or the next call.
+ * A gap runs at most 2^31 - 2^28 - 1 steps in all (photon conversion steps
+ * are 32-bit); a call that would pass that enqueues nothing and returns
+ * PIC_ERR_ARG. */
 pic_status pic_step_n(pic_gap* g, int64_t n_steps, pic_step_report* out);
 
 /* Copies E (n_cells binary64 values) and, if rho is non-NULL, the
@@ -311,7 +314,8 @@ size_t     pic_batch_workspace_bytes(const pic_gap_params* params, int32_t n_gap
 pic_status pic_create_batch(const pic_gap_params* params, int32_t n_gaps, void* d_ws,
                             size_t ws_bytes, void* hip_stream, pic_batch** out);
 /* Enqueues n_steps steps of every gap that is not frozen; per_gap (may be
- * NULL, n_gaps entries) receives each gap's status after a synchronisation. */
+ * NULL, n_gaps entries) receives each gap's status after a synchronisation.
+ * The step limit of pic_step_n applies. */
 pic_status pic_batch_step_n(pic_batch* b, int64_t n_steps, pic_status* per_gap);
 /* Borrowed view of gap i, valid until pic_destroy_batch; usable with the
  * seed, read and set calls above (not with pic_step_n or pic_destroy). */

@@ -25,6 +25,9 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int kDefaultSort = 20;
+// Steps a gap may run in total: conversion steps of photons are 32-bit and a
+// photon converts at most 2^28 steps after its emission (the table limit).
+constexpr int64_t kMaxSteps = ((int64_t)1 << 31) - ((int64_t)1 << 28) - 1;
 constexpr int kDefaultHist = 4096;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -766,6 +769,7 @@ pic_status pic_step_n(pic_gap* g, int64_t n_steps, pic_step_report* out) {
   if (!g || n_steps < 0) return PIC_ERR_ARG;
   if (!g->standalone) return PIC_ERR_STATE;
   pic_batch* b = g->b;
+  if (n_steps > kMaxSteps - b->host_step) return PIC_ERR_ARG;
   if (b->known_status[0] != PIC_OK) return PIC_ERR_STATE;
   pic_status st = enqueue_steps(b, n_steps);
   if (st != PIC_OK) return st;
@@ -782,6 +786,7 @@ pic_status pic_step_n(pic_gap* g, int64_t n_steps, pic_step_report* out) {
 
 pic_status pic_batch_step_n(pic_batch* b, int64_t n_steps, pic_status* per_gap) {
   if (!b || n_steps < 0) return PIC_ERR_ARG;
+  if (n_steps > kMaxSteps - b->host_step) return PIC_ERR_ARG;
   pic_status st = enqueue_steps(b, n_steps);
   if (st != PIC_OK) return st;
   if (per_gap) {

@@ -425,6 +425,26 @@ def test_maximum_cell_count(precision, boundary):
         assert h["absorbed_minus"][-1] > 0 and h["absorbed_plus"][-1] > 0
 
 
+def test_step_count_limit():
+    """Photon conversion steps are 32-bit, so a gap runs at most
+    2^31 - 2^28 - 1 steps: a call that would pass that enqueues nothing and
+    is rejected, and the gap still steps afterwards."""
+    import paper_2012_05587_amd as P
+    cfg = workloads.config("c1_fp64_reference_gap")
+    g = pc.make_gpu(cfg)
+    limit = 2**31 - 2**28 - 1
+    with pytest.raises(P.PicError):
+        g.step_n(limit + 1)
+    g.step_n(3)
+    with pytest.raises(P.PicError):
+        g.step_n(limit - 2)
+    assert g.read_moments().steps_done == 3
+    b = P.Batch([pc.gpu_params(cfg)] * 2)
+    with pytest.raises(P.PicError):
+        b.step_n(limit + 1)
+    b.close()
+
+
 def test_capacity_overflow_freezes_gap():
     """A tiny slot count freezes the gap at the last completed step; the
     history up to then is the oracle's (periodic, in place: slots = live)."""
