@@ -16,7 +16,8 @@ Prints one JSON line.  The roofline entry is for the push kernel, which
 moves the lepton state: 4 B cell + 4 B offset + 4 B momentum read and written
 (24 B per push) in mixed precision, 40 B per push in binary64.  Its time is
 summed from HIP events bracketing every push launch on the library's stream,
-in a second run identical to the timed one.  The cpu_baseline entry times the
+in a second run of the same steps launched directly (an autotuned re-sort
+cadence is tuned there the same way).  The cpu_baseline entry times the
 oracle on a bounded sample of the same workload, one gap per process.
 """
 import argparse
@@ -154,20 +155,22 @@ def run_gpu(gaps, steps, profile=True, dump=None):
     del g, views, v
     torch.cuda.empty_cache()
     if profile:
-        # the evented run launches directly, at the cadence the timed run settled on
-        gaps = [dict(c, sort_every=tune["sort_every"]) for c in gaps]
+        # the evented run launches every kernel directly; an autotuned cadence
+        # is tuned there the same way, from the timed S-step segments
         g, views = _make(P, gaps, stream)
         g.profile_push(True)
         log("timing the push kernel with events")
         g.step_n(steps)
         push_ms, launches = g.read_push_time()
-        # The evented run repeats the same steps at one fixed cadence.  Its
-        # pushes equal the timed run's unless a gap runs out of slots: slots
-        # of absorbed leptons are freed at re-sorts, so the step at which a
-        # gap freezes can depend on the cadence.  The kernel rate uses the
-        # evented run's own pushes.
+        # The evented run repeats the same steps; its cadence follows the
+        # same policy but may switch at other steps.  Its pushes equal the
+        # timed run's unless a gap runs out of slots: slots of absorbed
+        # leptons are freed at re-sorts, so the step at which a gap freezes
+        # can depend on the cadence.  The kernel rate uses the evented run's
+        # own pushes.
         again = sum(int(x.read_moments().pushes) for x in views)
-        out.update(push_ms=push_ms, push_launches=launches, evented_pushes=again)
+        out.update(push_ms=push_ms, push_launches=launches, evented_pushes=again,
+                   evented_tuning=g.tuning())
         g.close()
         del g, views
         torch.cuda.empty_cache()
@@ -548,7 +551,8 @@ def main():
                      "traffic_unit": "B/launch",
                      "alg_bytes_per_launch": main_run["evented_pushes"] * bpp / max(main_run["push_launches"], 1),
                      "evented_run": {"pushes": main_run["evented_pushes"],
-                                     "sort_every": main_run["tuning"]["sort_every"]},
+                                     "sort_every": main_run["evented_tuning"]["sort_every"],
+                                     "switches": main_run["evented_tuning"]["switches"]},
                      "copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs,
                      "kernel": "k_push", "bytes_per_push": bpp,
                      "kernel_ms": main_run["push_ms"], "launches": main_run["push_launches"]},

@@ -27,8 +27,10 @@
  *    no host pointer after a call returns.  Handles are host objects owned by
  *    the library and freed by pic_destroy / pic_destroy_batch.
  *  - Streams.  All device work is enqueued on the HIP stream given at
- *    creation (NULL = the null stream).  pic_step_n returns without waiting;
- *    pic_read_* and pic_set_fields synchronise that stream.
+ *    creation (NULL = the null stream).  pic_step_n returns without waiting,
+ *    except that with sort_every = 0 it keeps at most 8 of its timed graph
+ *    replays in flight (a long call returns once all but the last 8 have
+ *    run); pic_read_* and pic_set_fields synchronise that stream.
  *  - A handle is not thread-safe.
  *  - Capacity.  Each species has `capacity` slots and the photon store
  *    `photon_capacity` slots; slots of absorbed leptons and converted photons

@@ -209,8 +209,10 @@ struct pic_gap {
 // changes results, only cost: sorting often costs sort passes, sorting
 // rarely lets chunks spread over more cells and leaves appended leptons
 // unsorted longer.  Each candidate cadence S has its own captured graph (S
-// steps and the sort); every replay is timed with events that are read
-// without blocking.  Periods of kTunePeriod replays start with a probe
+// steps and the sort); every replay is timed with events, read as replays
+// complete (a call keeps at most kTuneAhead of them in flight, so the
+// tuner also acts within one long call).  Periods of kTunePeriod replays
+// start with a probe
 // (current, challenger, current, challenger), the challenger alternating
 // between half and twice the current cadence; comparing it with the replays
 // beside it cancels the growth of the cascade, and a challenger faster per
@@ -220,6 +222,10 @@ constexpr int kTuneN = 5;
 constexpr int kTuneStart = 2;  // 20 steps
 constexpr int kTunePeriod = 16;
 constexpr double kTuneGain = 0.03;
+// Timed replays in flight at most: a long call waits for the oldest before
+// enqueueing more, so the tuner reads its probes while the call runs (the
+// device still has this many replays queued).
+constexpr size_t kTuneAhead = 8;
 
 struct Tuner {
   bool on = false;
@@ -588,30 +594,47 @@ pic_status enqueue_steps(pic_batch* b, int64_t n_steps) {
   const bool graphs = b->stream != nullptr && !b->profiling && !b->graph_failed;
   Tuner& t = b->tune;
   while (n_steps > 0) {
-    if (graphs && t.on && b->since_sort == 0) {
+    if (t.on && b->since_sort == 0) {
+      while (t.pending.size() >= kTuneAhead) {
+        if (hipEventSynchronize(t.pending.front().b) != hipSuccess) return PIC_ERR_DEVICE;
+        tune_harvest(t);
+      }
       tune_harvest(t);
       int round = -1;
       const int ci = tune_pick(t, round);
       const int S = kTuneCand[ci];
+      b->sort_every = S;  // eager steps that follow keep this cadence
       if (n_steps >= S) {
-        if (!b->tgraph[ci] && !build_graph(b, S, &b->ttmpl[ci], &b->tgraph[ci])) {
+        // one timed replay: S steps and the re-sort, as a graph launch or,
+        // without graphs (null stream, failed capture, per-push events), as
+        // S eager steps
+        if (graphs && !b->tgraph[ci] && !build_graph(b, S, &b->ttmpl[ci], &b->tgraph[ci])) {
           b->graph_failed = true;
           return enqueue_steps(b, n_steps);
         }
         hipEvent_t e0 = tune_event(t), e1 = tune_event(t);
         if (!e0 || !e1) return PIC_ERR_DEVICE;
         if (hipEventRecord(e0, b->stream) != hipSuccess) return PIC_ERR_DEVICE;
-        if (hipGraphLaunch(b->tgraph[ci], b->stream) != hipSuccess) return PIC_ERR_DEVICE;
+        if (graphs) {
+          if (hipGraphLaunch(b->tgraph[ci], b->stream) != hipSuccess) return PIC_ERR_DEVICE;
+          b->host_step += S;
+        } else {
+          for (int k = 0; k < S; ++k) {
+            const pic_status st = eager_step(b);  // the S-th step re-sorts
+            if (st != PIC_OK) {
+              t.spare.push_back(e0);
+              t.spare.push_back(e1);
+              return st;
+            }
+          }
+        }
         if (hipEventRecord(e1, b->stream) != hipSuccess) return PIC_ERR_DEVICE;
         t.pending.push_back(Tuner::Rec{e0, e1, ci, round});
         t.launches += 1;
-        b->sort_every = S;  // eager steps that follow keep this cadence
-        b->host_step += S;
         n_steps -= S;
         continue;
       }
       // fewer steps left than the cadence: finish them eagerly at this cadence
-      b->sort_every = S;
     }
     if (graphs && !t.on && b->since_sort == 0 && n_steps >= b->sort_every) {
       if (!b->graph && !build_graph(b, b->sort_every, &b->graph_tmpl, &b->graph)) {

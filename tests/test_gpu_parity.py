@@ -255,15 +255,20 @@ def test_graph_replay_matches_eager_and_oracle(precision):
 
 
 @pytest.mark.parametrize("precision", [workloads.FP64, workloads.MIXED])
-def test_autotuned_sort_cadence_matches_fixed(precision):
-    """With sort_every = 0 the library times its graph replays and changes
-    the re-sort cadence as it runs; the state must stay exactly that of a
-    fixed cadence, and the tuner must report a cadence it can use."""
+@pytest.mark.parametrize("mode", ["graphs", "eager", "evented"])
+def test_autotuned_sort_cadence_matches_fixed(precision, mode):
+    """With sort_every = 0 the library times its replays of S steps and the
+    re-sort (graph launches on a side stream; eager launches on the null
+    stream or with per-push events) and changes the cadence as it runs; the
+    state must stay exactly that of a fixed cadence, and the tuner must
+    report a cadence it can use."""
     import torch
     cfg = workloads.config("c1_fp64_reference_gap")
     cfg.update(precision=precision, history_rows=1300)
-    side = torch.cuda.Stream()
+    side = torch.cuda.Stream() if mode != "eager" else None
     gt = pc.make_gpu(cfg, stream=side, sort_every=0)
+    if mode == "evented":
+        gt.profile_push(True)
     gf = pc.make_gpu(cfg, sort_every=20)
     for n in (800, 37, 400):
         gt.step_n(n)
@@ -281,6 +286,9 @@ def test_autotuned_sort_cadence_matches_fixed(precision):
     assert t["replays"] >= 16, t
     f = gf.tuning()
     assert not f["autotuned"] and f["sort_every"] == 20, f
+    if mode == "evented":
+        ms, launches = gt.read_push_time()
+        assert launches == 800 + 37 + 400 and ms > 0
 
 
 @pytest.mark.parametrize("precision", [workloads.FP64, workloads.MIXED])
