@@ -42,6 +42,7 @@ constexpr int kSortTile = 8192;       // cells of the LDS histogram of the lepto
 template <int PASS>
 struct SortPer { static constexpr int value = PASS == 0 ? 4 : 2; };
 constexpr int kPhUnroll = 4;          // photons per thread per iteration of the photon sort
+constexpr int kTailEvery = 5;         // steps between sorts of the appended leptons
 constexpr int kPhBins = 8192;         // conversion steps of the LDS histogram of the photon sort
 constexpr int32_t kDead = INT32_MIN;  // cell of an absorbed lepton until re-sort
 constexpr int kMaxEmit = 64;
@@ -118,6 +119,7 @@ struct GapDev {
   unsigned long long pushes;
   unsigned long long hist_count;
   unsigned long long sorted_n[2], ph_sorted;
+  unsigned long long body_n[2];  // leptons sorted by the last full re-sort (the rest were appended since)
   unsigned long long ph_body_n;  // photons in the sorted body of the store
   long long ph_base;             // conversion step of bucket 0 of the sorted body
   long long step;
@@ -187,9 +189,6 @@ __device__ __forceinline__ T lepton_threshold(uint64_t id, uint64_t seed, double
   return (T)(gthr64 * (1.0 + sigma * a));
 }
 
-// Accumulator a (0 kinetic energy, 1 lost energy, 2-3 absorbed electrons /
-// positrons) of gap g, stripe st: each stripe on its own cache line, so the
-// workgroups of the push kernel do not all hit one address.
 // Pair-event map: pairs made at step n in cell c count in row
 // (n / ev_steps) % ev_rows, column c * ev_x / n_cells.
 __device__ __forceinline__ void count_pairs(const GapDev* G, long long step, int c, unsigned long long k) {
@@ -198,6 +197,9 @@ __device__ __forceinline__ void count_pairs(const GapDev* G, long long step, int
   atomicAdd(G->evmap + row * G->ev_x + col, k);
 }
 
+// Accumulator a (0 kinetic energy, 1 lost energy, 2-3 absorbed electrons /
+// positrons) of gap g, stripe st: each stripe on its own cache line, so the
+// workgroups of the push kernel do not all hit one address.
 __device__ __forceinline__ double* stripe_slot(double* stripes, int g, int a, int st) {
   return stripes + (((size_t)g * 4 + a) * kStripes + st) * kStripeStride;
 }

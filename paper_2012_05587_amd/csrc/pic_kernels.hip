@@ -1426,6 +1426,71 @@ __global__ __launch_bounds__(kBlock) void k_sort_zero(GapDev* __restrict__ gaps,
   if (blockIdx.x == cwi[g] && threadIdx.x == 0) { G->sorted_n[0] = 0; G->sorted_n[1] = 0; }
 }
 
+// Between full re-sorts, the leptons of a species appended since the last
+// one (slots body_n .. n) are sorted by cell among themselves every
+// kTailEvery steps, where they are many: their chunks then fit the push's
+// LDS tile instead of depositing through global atomics.  Nothing moves
+// out of the tail and nothing is dropped; dead leptons keep their slots in
+// an extra bucket after the last cell.
+// A species' tail is sorted when its gap is wider than the push's tile (in
+// a narrower gap every chunk fits the tile anyway) and the tail holds at
+// least a chunk and a 32nd of the species.
+__device__ __forceinline__ bool tail_sorted(const GapDev* G, int s) {
+  const unsigned long long n = G->n[s], body = G->body_n[s];
+  const unsigned long long tail = n - body;
+  return G->status == PIC_OK && G->n_cells > kTile - 8 && tail >= (unsigned long long)kChunk &&
+         tail * 32 >= n;
+}
+
+// Chunks of the tail sort for species s of gap G: kChunk leptons each from
+// slot body_n[s].
+__device__ __forceinline__ long long tail_chunks(const GapDev* G, int s) {
+  if (!tail_sorted(G, s)) return 0;
+  return ((long long)(G->n[s] - G->body_n[s]) + kChunk - 1) / kChunk;
+}
+
+// Work-item prefix of the tail sort (species 0 then 1 per gap), one block.
+__global__ __launch_bounds__(1024) void k_tail_plan(GapDev* __restrict__ gaps, int B,
+                                                    long long* __restrict__ twi) {
+  __shared__ long long s_sum[1024];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int per = (B + nt - 1) / nt;
+  long long loc = 0;
+  for (int g = tid * per; g < (tid + 1) * per && g < B; ++g)
+    loc += tail_chunks(gaps + g, 0) + tail_chunks(gaps + g, 1);
+  s_sum[tid] = loc;
+  __syncthreads();
+  for (int d = 1; d < nt; d <<= 1) {
+    const long long y = tid >= d ? s_sum[tid - d] : 0;
+    __syncthreads();
+    s_sum[tid] += y;
+    __syncthreads();
+  }
+  long long run = s_sum[tid] - loc;
+  for (int g = tid * per; g < (tid + 1) * per && g < B; ++g) {
+    twi[g] = run;
+    run += tail_chunks(gaps + g, 0) + tail_chunks(gaps + g, 1);
+  }
+  if (tid == nt - 1) twi[B] = s_sum[nt - 1];
+}
+
+__global__ __launch_bounds__(kBlock) void k_tail_zero(GapDev* __restrict__ gaps,
+                                                      const long long* __restrict__ cwi, int B) {
+  const int g = find_gap(cwi, B, blockIdx.x);
+  GapDev* __restrict__ G = gaps + g;
+  const long long c0 = (blockIdx.x - cwi[g]) * (long long)kCellChunk;
+  const int nc = G->n_cells;
+  for (int s = 0; s < 2; ++s) {
+    if (!tail_sorted(G, s)) continue;
+    for (int k = threadIdx.x; k < kCellChunk; k += kBlock) {
+      const long long c = c0 + k;
+      if (c >= nc) break;
+      G->sort_cnt[s][c] = 0;
+    }
+    if (blockIdx.x == cwi[g] && threadIdx.x == 0) G->sort_cnt[s][nc] = 0;  // the dead bucket
+  }
+}
+
 // Counting sort of the leptons by cell.  PASS 0 counts, PASS 1 (after the
 // scan turned the counts into bucket starts) moves each live lepton to the
 // other buffer.  A chunk whose cells span at most kSortTile counts in an LDS
@@ -1433,7 +1498,9 @@ __global__ __launch_bounds__(kBlock) void k_sort_zero(GapDev* __restrict__ gaps,
 // appended since the last sort) use one global atomic per run of equal cells.
 // An iteration takes up to SortPer consecutive chunks of one (gap, species),
 // so the barriers and the round trip of the bucket atomics are shared.
-template <int PASS, typename T>
+// TAIL sorts only the appended leptons of the species that have many
+// (tail_sorted), into the same slots of the other buffer.
+template <int PASS, typename T, bool TAIL>
 __global__ __launch_bounds__(kBlock) void k_sort_pass(GapDev* __restrict__ gaps,
                                                       const long long* __restrict__ wi, int B) {
   constexpr int kPer = SortPer<PASS>::value;
@@ -1447,7 +1514,9 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(GapDev* __restrict__ gaps,
   for (long long w = w0; w < w1;) {
     const int g = find_gap(wi, B, w);
     GapDev* __restrict__ G = gaps + g;
-    const long long chunks0 = ((long long)G->n[0] + kChunk - 1) / kChunk;
+    // chunks of species 0, then 1: all slots (full sort) or the tail from
+    // slot body_n (tail sort, whose prefix holds only the tails it sorts)
+    const long long chunks0 = TAIL ? tail_chunks(G, 0) : ((long long)G->n[0] + kChunk - 1) / kChunk;
     const long long local = w - wi[g];
     const int s = local < chunks0 ? 0 : 1;
     // chunks [w, wn): the same species of the same gap, inside this range
@@ -1459,28 +1528,33 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(GapDev* __restrict__ gaps,
     const long long nch = wn - w;
     w = wn;
     if (G->status != PIC_OK) continue;
+    const long long lo = TAIL ? (long long)G->body_n[s] : 0;  // first slot taking part
     const int buf = G->buf;
-    const long long i0 = (s == 0 ? local : local - chunks0) * kChunk;
+    const int nc = G->n_cells;
+    const long long i0 = lo + (s == 0 ? local : local - chunks0) * kChunk;
     const long long nS = (long long)G->n[s];
     const long long i1 = i0 + nch * kChunk < nS ? i0 + nch * kChunk : nS;
     gptr<int32_t> cnt = glb(G->sort_cnt[s]);
     gptr<const int32_t> cin = glb<const int32_t>((void*)G->cell[buf][s]);
     // the whole lepton state is requested at once (slots past the end read
-    // slot 0 and are discarded), before any store of this chunk
+    // the first slot and are discarded), before any store of this chunk
     int cvs[kN];
     T ov[kN], pv[kN];
     uint64_t idv[kN];
 #pragma unroll
     for (int j = 0; j < kN; ++j) {
       const long long i = i0 + threadIdx.x + (long long)j * kBlock;
-      const long long ii = i < i1 ? i : 0;
+      const bool in = i < i1;
+      const long long ii = in ? i : i0;
       const int cv = cin[ii];
       if (PASS == 1) {
         ov[j] = glb<const T>(G->off[buf][s])[ii];
         pv[j] = glb<const T>(G->p[buf][s])[ii];
         idv[j] = glb<const uint64_t>((void*)G->id[buf][s])[ii];
       }
-      cvs[j] = i < i1 ? cv : kDead;
+      // kDead marks what takes no part: slots outside the range and, in the
+      // full sort, dead leptons; the tail sort keeps those in bucket n_cells
+      cvs[j] = in ? (TAIL && cv == kDead ? nc : cv) : kDead;
     }
     int mn = INT32_MAX, mx = INT32_MIN;
 #pragma unroll
@@ -1543,8 +1617,8 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(GapDev* __restrict__ gaps,
 #pragma unroll
     for (int j = 0; j < kN; ++j) {
       if (cvs[j] == kDead) continue;
-      const long long d = dst[j];
-      cout[d] = cvs[j];
+      const long long d = lo + dst[j];
+      cout[d] = TAIL && cvs[j] == nc ? kDead : cvs[j];
       oout[d] = ov[j];
       pout[d] = pv[j];
       iout[d] = idv[j];
@@ -1575,14 +1649,44 @@ __device__ long long block_scan_counts(int32_t* __restrict__ cnt, int n, long lo
   return s_sum[nt - 1];
 }
 
-// Exclusive scan of the per-cell counts of one (gap, species) in place.
+// Exclusive scan of the per-cell counts of one (gap, species) in place (the
+// tail sort also scans its dead bucket).
+template <bool TAIL>
 __global__ __launch_bounds__(1024) void k_sort_scan(GapDev* __restrict__ gaps, int B) {
   __shared__ long long s_sum[1024];
   const int g = blockIdx.x >> 1, s = blockIdx.x & 1;
   GapDev* __restrict__ G = gaps + g;
   if (G->status != PIC_OK) return;
-  const long long tot = block_scan_counts(G->sort_cnt[s], G->n_cells, s_sum);
-  if (threadIdx.x == blockDim.x - 1) G->sorted_n[s] = (unsigned long long)tot;
+  if (TAIL && !tail_sorted(G, s)) return;  // (tail_sorted also requires PIC_OK)
+  const long long tot = block_scan_counts(G->sort_cnt[s], G->n_cells + (TAIL ? 1 : 0), s_sum);
+  if (!TAIL && threadIdx.x == blockDim.x - 1) G->sorted_n[s] = (unsigned long long)tot;
+}
+
+// The sorted tails back from the other buffer into their slots (wi is the
+// tail sort's prefix).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_tail_copy(GapDev* __restrict__ gaps,
+                                                      const long long* __restrict__ wi, int B) {
+  const long long total = wi[B];
+  long long w0, w1;
+  xcd_range(total, w0, w1);
+  for (long long w = w0; w < w1; ++w) {
+    const int g = find_gap(wi, B, w);
+    GapDev* __restrict__ G = gaps + g;
+    const long long chunks0 = tail_chunks(G, 0);
+    const long long local = w - wi[g];
+    const int s = local < chunks0 ? 0 : 1;
+    const long long i0 = (long long)G->body_n[s] + (s == 0 ? local : local - chunks0) * kChunk;
+    const long long nS = (long long)G->n[s];
+    const long long i1 = i0 + kChunk < nS ? i0 + kChunk : nS;
+    const int buf = G->buf, nb = buf ^ 1;
+    for (long long i = i0 + threadIdx.x; i < i1; i += kBlock) {
+      G->cell[buf][s][i] = G->cell[nb][s][i];
+      ((T*)G->off[buf][s])[i] = ((const T*)G->off[nb][s])[i];
+      ((T*)G->p[buf][s])[i] = ((const T*)G->p[nb][s])[i];
+      G->id[buf][s][i] = G->id[nb][s][i];
+    }
+  }
 }
 
 // ---- photon store: counting sort by conversion step, dropping the photons
@@ -1730,6 +1834,7 @@ __global__ __launch_bounds__(1024) void k_sort_finish(GapDev* __restrict__ gaps,
     for (int s = 0; s < 2; ++s) {
       G->n[s] = G->sorted_n[s];
       G->live[s] = G->sorted_n[s];
+      G->body_n[s] = G->sorted_n[s];
       G->dead[s] = 0;
     }
     G->buf ^= 1;
@@ -1913,15 +2018,31 @@ hipError_t launch_step(const StepLaunch& L, bool mixed) {
 hipError_t launch_sort(const StepLaunch& L, bool mixed) {
   hipLaunchKernelGGL(k_sort_zero, dim3(grid_for(L.cell_items, 1 << 30)), dim3(kBlock), 0, L.stream, L.gaps, L.cwi, L.B);
   hipLaunchKernelGGL(k_ph_zero, dim3(L.B), dim3(kBlock), 0, L.stream, L.gaps, L.B);
-  if (mixed) hipLaunchKernelGGL((k_sort_pass<0, float>), dim3(L.push_grid), dim3(kBlock), 0, L.stream, L.gaps, L.wi, L.B);
-  else hipLaunchKernelGGL((k_sort_pass<0, double>), dim3(L.push_grid), dim3(kBlock), 0, L.stream, L.gaps, L.wi, L.B);
+  if (mixed) hipLaunchKernelGGL((k_sort_pass<0, float, false>), dim3(L.push_grid), dim3(kBlock), 0, L.stream, L.gaps, L.wi, L.B);
+  else hipLaunchKernelGGL((k_sort_pass<0, double, false>), dim3(L.push_grid), dim3(kBlock), 0, L.stream, L.gaps, L.wi, L.B);
   hipLaunchKernelGGL(k_ph_pass<0>, dim3(L.ph_sort_grid), dim3(kBlock), 0, L.stream, L.gaps, L.qwi, L.B);
-  hipLaunchKernelGGL(k_sort_scan, dim3(2 * L.B), dim3(1024), 0, L.stream, L.gaps, L.B);
+  hipLaunchKernelGGL(k_sort_scan<false>, dim3(2 * L.B), dim3(1024), 0, L.stream, L.gaps, L.B);
   hipLaunchKernelGGL(k_ph_scan, dim3(L.B), dim3(1024), 0, L.stream, L.gaps, L.B);
-  if (mixed) hipLaunchKernelGGL((k_sort_pass<1, float>), dim3(L.push_grid), dim3(kBlock), 0, L.stream, L.gaps, L.wi, L.B);
-  else hipLaunchKernelGGL((k_sort_pass<1, double>), dim3(L.push_grid), dim3(kBlock), 0, L.stream, L.gaps, L.wi, L.B);
+  if (mixed) hipLaunchKernelGGL((k_sort_pass<1, float, false>), dim3(L.push_grid), dim3(kBlock), 0, L.stream, L.gaps, L.wi, L.B);
+  else hipLaunchKernelGGL((k_sort_pass<1, double, false>), dim3(L.push_grid), dim3(kBlock), 0, L.stream, L.gaps, L.wi, L.B);
   hipLaunchKernelGGL(k_ph_pass<1>, dim3(L.ph_sort_grid), dim3(kBlock), 0, L.stream, L.gaps, L.qwi, L.B);
   hipLaunchKernelGGL(k_sort_finish, dim3(1), dim3(1024), 0, L.stream, L.gaps, L.B, L.wi, L.pwi, L.qwi);
+  return hipGetLastError();
+}
+
+template <typename T>
+static void tail_sort_for(const StepLaunch& L) {
+  hipLaunchKernelGGL(k_tail_plan, dim3(1), dim3(1024), 0, L.stream, L.gaps, L.B, L.twi);
+  hipLaunchKernelGGL(k_tail_zero, dim3(grid_for(L.cell_items, 1 << 30)), dim3(kBlock), 0, L.stream, L.gaps, L.cwi, L.B);
+  hipLaunchKernelGGL((k_sort_pass<0, T, true>), dim3(L.push_grid), dim3(kBlock), 0, L.stream, L.gaps, L.twi, L.B);
+  hipLaunchKernelGGL(k_sort_scan<true>, dim3(2 * L.B), dim3(1024), 0, L.stream, L.gaps, L.B);
+  hipLaunchKernelGGL((k_sort_pass<1, T, true>), dim3(L.push_grid), dim3(kBlock), 0, L.stream, L.gaps, L.twi, L.B);
+  hipLaunchKernelGGL(k_tail_copy<T>, dim3(L.push_grid), dim3(kBlock), 0, L.stream, L.gaps, L.twi, L.B);
+}
+
+hipError_t launch_tail_sort(const StepLaunch& L, bool mixed) {
+  if (mixed) tail_sort_for<float>(L);
+  else tail_sort_for<double>(L);
   return hipGetLastError();
 }
 

@@ -12,6 +12,7 @@ struct StepLaunch {
   long long* wi;       // particle work-item prefix, B + 1 entries (device)
   long long* pwi;      // due-photon work-item prefix, B + 1 entries (device)
   long long* qwi;      // photon-store work-item prefix (re-sort), B + 1 entries (device)
+  long long* twi;      // work-item prefix of the tail sort, B + 1 entries (device)
   long long* cwi;      // cell work-item prefix, B + 1 entries (device, static)
   long long cell_items;
   int B;
@@ -29,6 +30,7 @@ hipError_t launch_step(const StepLaunch& L, bool mixed);
 hipError_t launch_push(const StepLaunch& L, bool mixed);
 hipError_t launch_step_after_push(const StepLaunch& L, bool mixed);
 hipError_t launch_sort(const StepLaunch& L, bool mixed);
+hipError_t launch_tail_sort(const StepLaunch& L, bool mixed);
 hipError_t launch_plan(const StepLaunch& L);
 hipError_t launch_seed(GapDev* gaps, int g, int mode, long long N, double p0m, double p0p,
                        long long base0, long long base1, bool mixed, hipStream_t st);

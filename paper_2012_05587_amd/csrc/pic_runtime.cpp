@@ -42,7 +42,7 @@ struct GapLayout {
 };
 
 struct Layout {
-  size_t gaps, wi, pwi, qwi, cwi, emit_cnt, emit_ent, wg_emit, stripes, total;
+  size_t gaps, wi, pwi, qwi, twi, cwi, emit_cnt, emit_ent, wg_emit, stripes, total;
   long long max_chunks, max_ph_chunks;
   std::vector<GapLayout> g;
   long long cell_items;
@@ -132,6 +132,7 @@ Layout make_layout(const pic_gap_params* prm, int B) {
   L.wi = o; o = align_up(o + sizeof(long long) * (size_t)(B + 1));
   L.pwi = o; o = align_up(o + sizeof(long long) * (size_t)(B + 1));
   L.qwi = o; o = align_up(o + sizeof(long long) * (size_t)(B + 1));
+  L.twi = o; o = align_up(o + sizeof(long long) * (size_t)(B + 1));
   L.cwi = o; o = align_up(o + sizeof(long long) * (size_t)(B + 1));
   L.cell_items = 0;
   // one emission slice per particle chunk the plan can hold
@@ -160,7 +161,8 @@ Layout make_layout(const pic_gap_params* prm, int B) {
     G.rho = o; o = align_up(o + 8 * (nc + 1));
     G.table_len = (int64_t)build_table(p).size();
     G.table = o; o = align_up(o + 4 * (size_t)G.table_len);
-    for (int s = 0; s < 2; ++s) { G.sort_cnt[s] = o; o = align_up(o + 4 * nc); }
+    // per-cell counts of the sorts, and the dead bucket of the tail sort
+    for (int s = 0; s < 2; ++s) { G.sort_cnt[s] = o; o = align_up(o + 4 * (nc + 1)); }
     G.hist = o; o = align_up(o + sizeof(pic_history_row) * (size_t)hist);
     for (int b = 0; b < 2; ++b)
       for (int s = 0; s < 2; ++s) {
@@ -249,6 +251,7 @@ struct pic_batch {
   hipGraphExec_t tgraph[kTuneN] = {};
   hipGraph_t ttmpl[kTuneN] = {};
   long long since_sort = 0;  // steps enqueued since the last re-sort
+  bool tail_sorts = false;   // some gap is wider than the push's tile (see launch_tail_sort)
   hipStream_t stream = nullptr;
   char* ws = nullptr;
   size_t ws_bytes = 0;
@@ -407,6 +410,7 @@ pic_status create_batch(const pic_gap_params* params, int n_gaps, void* d_ws, si
   b->launch.wi = reinterpret_cast<long long*>(ws + L.wi);
   b->launch.pwi = reinterpret_cast<long long*>(ws + L.pwi);
   b->launch.qwi = reinterpret_cast<long long*>(ws + L.qwi);
+  b->launch.twi = reinterpret_cast<long long*>(ws + L.twi);
   b->launch.cwi = reinterpret_cast<long long*>(ws + L.cwi);
   b->launch.cell_items = L.cell_items;
   b->launch.B = n_gaps;
@@ -425,6 +429,8 @@ pic_status create_batch(const pic_gap_params* params, int n_gaps, void* d_ws, si
   b->launch.spline = params[0].shape == PIC_SHAPE_QUADRATIC;
   b->launch.spread = false;
   for (int i = 0; i < n_gaps; ++i) b->launch.spread |= params[i].gamma_thr_spread > 0.0;
+  // in gaps no wider than the push's tile every chunk fits it: no tail sorts
+  for (int i = 0; i < n_gaps; ++i) b->tail_sorts |= params[i].n_cells > pic::kTile - 8;
   if (st == PIC_OK &&
       hipMemcpy(b->launch.cwi, cwi.data(), sizeof(long long) * cwi.size(), hipMemcpyHostToDevice) != hipSuccess)
     st = PIC_ERR_DEVICE;
@@ -498,18 +504,25 @@ pic_status eager_step(pic_batch* b) {
   if (b->since_sort >= b->sort_every) {
     if (pic::launch_sort(b->launch, mixed) != hipSuccess) return PIC_ERR_DEVICE;
     b->since_sort = 0;
+  } else if (b->tail_sorts && b->since_sort % pic::kTailEvery == 0) {
+    if (pic::launch_tail_sort(b->launch, mixed) != hipSuccess) return PIC_ERR_DEVICE;
   }
   return PIC_OK;
 }
 
-// Captures sort_every steps and the re-sort that ends them as one graph.
+// Captures sort_every steps and the re-sort that ends them as one graph,
+// with the sorts of the appended leptons every kTailEvery steps between.
 // Every kernel reads its counts and plans from device memory, so the graph
 // can be replayed at any step that is a multiple of sort_every.
 bool build_graph(pic_batch* b, int S, hipGraph_t* tmpl, hipGraphExec_t* exec) {
   const bool mixed = b->precision == PIC_MIXED;
   if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeRelaxed) != hipSuccess) return false;
   bool ok = true;
-  for (int k = 0; k < S && ok; ++k) ok = pic::launch_step(b->launch, mixed) == hipSuccess;
+  for (int k = 1; k <= S && ok; ++k) {
+    ok = pic::launch_step(b->launch, mixed) == hipSuccess;
+    if (ok && b->tail_sorts && k < S && k % pic::kTailEvery == 0)
+      ok = pic::launch_tail_sort(b->launch, mixed) == hipSuccess;
+  }
   if (ok) ok = pic::launch_sort(b->launch, mixed) == hipSuccess;
   hipGraph_t g = nullptr;
   const hipError_t e = hipStreamEndCapture(b->stream, &g);

@@ -433,6 +433,28 @@ def test_maximum_cell_count(precision, boundary):
         assert h["absorbed_minus"][-1] > 0 and h["absorbed_plus"][-1] > 0
 
 
+@pytest.mark.parametrize("precision", [workloads.FP64, workloads.MIXED])
+def test_tail_sort_matches_oracle(precision):
+    """A gap wider than the push's tile (4096 cells) cascades for 150 steps
+    with absorbing walls, so between full re-sorts its appended leptons,
+    dead ones among them, are sorted among themselves every 5 steps.  At
+    cadences 40, 7 and tuned the results equal the oracle's bit for bit."""
+    cfg = workloads.config("c2_fp64_single_gap")
+    cfg.update(n_cells=4096, n_pairs=512, capacity=2_000_000, photon_capacity=4_000_000,
+               precision=precision, history_rows=160)
+    print(f"[case] tail sort prec={precision}", flush=True)
+    go = pc.make_oracle(cfg)
+    assert go.step(150) == 0
+    h = go.history()
+    assert h["pairs_created"][-1] > 100_000 and h["absorbed_minus"][-1] > 1000
+    for every in (40, 7, 0):
+        gg = pc.make_gpu(cfg, sort_every=every)
+        gg.step_n(150)
+        pc.compare_history(gg.read_history(), h)
+        pc.compare_particles(gg, go, PTOL[precision])
+        pc.compare_fields(gg, go)
+
+
 def test_step_count_limit():
     """Photon conversion steps are 32-bit, so a gap runs at most
     2^31 - 2^28 - 1 steps: a call that would pass that enqueues nothing and
