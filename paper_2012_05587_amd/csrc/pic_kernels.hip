@@ -2030,14 +2030,18 @@ hipError_t launch_sort(const StepLaunch& L, bool mixed) {
   return hipGetLastError();
 }
 
+// The tails are a small part of the leptons, so their passes take a quarter
+// of the full sort's grid (which also keeps the launches cheap when there is
+// nothing to sort).
 template <typename T>
 static void tail_sort_for(const StepLaunch& L) {
+  const int grid = L.push_grid / 4;
   hipLaunchKernelGGL(k_tail_plan, dim3(1), dim3(1024), 0, L.stream, L.gaps, L.B, L.twi);
   hipLaunchKernelGGL(k_tail_zero, dim3(grid_for(L.cell_items, 1 << 30)), dim3(kBlock), 0, L.stream, L.gaps, L.cwi, L.B);
-  hipLaunchKernelGGL((k_sort_pass<0, T, true>), dim3(L.push_grid), dim3(kBlock), 0, L.stream, L.gaps, L.twi, L.B);
+  hipLaunchKernelGGL((k_sort_pass<0, T, true>), dim3(grid), dim3(kBlock), 0, L.stream, L.gaps, L.twi, L.B);
   hipLaunchKernelGGL(k_sort_scan<true>, dim3(2 * L.B), dim3(1024), 0, L.stream, L.gaps, L.B);
-  hipLaunchKernelGGL((k_sort_pass<1, T, true>), dim3(L.push_grid), dim3(kBlock), 0, L.stream, L.gaps, L.twi, L.B);
-  hipLaunchKernelGGL(k_tail_copy<T>, dim3(L.push_grid), dim3(kBlock), 0, L.stream, L.gaps, L.twi, L.B);
+  hipLaunchKernelGGL((k_sort_pass<1, T, true>), dim3(grid), dim3(kBlock), 0, L.stream, L.gaps, L.twi, L.B);
+  hipLaunchKernelGGL(k_tail_copy<T>, dim3(grid), dim3(kBlock), 0, L.stream, L.gaps, L.twi, L.B);
 }
 
 hipError_t launch_tail_sort(const StepLaunch& L, bool mixed) {

@@ -454,6 +454,9 @@ pic_status append_counts(pic_batch* b, int g, long long add0, long long add1) {
   if (st != PIC_OK) return st;
   G.n[0] += (unsigned long long)add0; G.live[0] += (unsigned long long)add0;
   G.n[1] += (unsigned long long)add1; G.live[1] += (unsigned long long)add1;
+  // the seed counts as the body of the first full re-sort, not as appended
+  G.body_n[0] = G.n[0];
+  G.body_n[1] = G.n[1];
   st = write_desc(b, g, &G);
   if (st != PIC_OK) return st;
   if (pic::launch_plan(b->launch) != hipSuccess) return PIC_ERR_DEVICE;
