@@ -100,9 +100,11 @@ enum { PIC_ELECTRON = 0, PIC_POSITRON = 1 };
  *            and momentum; the current, E and all diagnostics stay exact
  *            integer or binary64.
  *  sort_every   steps between particle re-sorts; 0 lets the library choose
- *               it while running (see pic_batch_tuning).  The cadence
- *               changes cost only: results do not depend on it while no
- *               gap runs out of slots.
+ *               it while running (see pic_batch_tuning).  Between re-sorts,
+ *               every 5 steps, the leptons appended since the last one are
+ *               sorted among themselves in gaps wider than 2040 cells.  The
+ *               cadence changes cost only: results do not depend on it while
+ *               no gap runs out of slots.
  *  diag_every   steps between history rows (0 = 1).
  *  history_rows rows kept in the device history ring (0 = 4096).
  *  j_m       imposed current density of the frame co-rotating with the
