@@ -46,10 +46,6 @@ constexpr int kTailEvery = 5;         // steps between sorts of the appended lep
 constexpr int kPhBins = 8192;         // conversion steps of the LDS histogram of the photon sort
 constexpr int32_t kDead = INT32_MIN;  // cell of an absorbed lepton until re-sort
 constexpr int kMaxEmit = 64;
-// emit_cnt of a chunk packs its emitter count (at most kChunk) below bit
-// kEmitShift and its photon count (at most kChunk * kMaxEmit) above it.
-constexpr int kEmitShift = 11;
-constexpr uint32_t kEmitMask = (1u << kEmitShift) - 1u;
 constexpr int kPushGrid = 4096;       // workgroups of the push kernel
 // Push pipelining per particle type: whether the next chunk's lepton state
 // is prefetched, how many items' E values are requested together, and the

@@ -270,7 +270,7 @@ __global__ __launch_bounds__(kBlock, PushCfg<T>::waves) void k_push(GapDev* __re
   __shared__ int s_red[2][8];
   __shared__ double s_d[8];
   __shared__ unsigned long long s_u[8];
-  __shared__ int s_emit_n, s_emit_k;
+  __shared__ int s_emit_n;
   // leptons of the chunk that need their own threshold, and the thresholds
   __shared__ uint32_t s_cand[kSpread ? kChunk : 1];
   __shared__ T s_thr[kSpread ? kChunk : 1];
@@ -381,7 +381,6 @@ __global__ __launch_bounds__(kBlock, PushCfg<T>::waves) void k_push(GapDev* __re
       if (cl[j] != kDead) { mn = min(mn, cl[j]); mx = max(mx, cl[j]); }
     if (tid == 0) {
       s_emit_n = 0;
-      s_emit_k = 0;
       if constexpr (kSpread) s_ncand = 0;
     }
     block_minmax_pp(mn, mx, s_red, parity);
@@ -606,7 +605,6 @@ __global__ __launch_bounds__(kBlock, PushCfg<T>::waves) void k_push(GapDev* __re
             pn = pn > (T)0 ? mag : -mag;
             gnew = sqrt(one_t + pn * pn);
             const int pos = atomicAdd(&s_emit_n, 1);
-            atomicAdd(&s_emit_k, k);
             s_emit[pos] = ((uint32_t)(i - i0) << 8) | (uint32_t)k;
           }
           __builtin_nontemporal_store(pn, &pA[i]);
@@ -646,7 +644,7 @@ __global__ __launch_bounds__(kBlock, PushCfg<T>::waves) void k_push(GapDev* __re
       const int ne = s_emit_n;
       if (ne > 0) {
         if (tid == 0) {
-          emit_cnt[w] = ne | (s_emit_k << kEmitShift);
+          emit_cnt[w] = ne;
           my_emitters += (uint32_t)ne;
         }
         gptr<uint32_t> el = glb(emit_ent + w * (long long)kChunk);
@@ -807,7 +805,7 @@ __device__ unsigned long long emit_walk(GapDev* __restrict__ G, long long& x, lo
   unsigned long long run = 0;
   while (x < xend && Q < qb) {
     const long long xc0 = x + threadIdx.x;
-    const int ne = xc0 < xend ? (int)(cntA[xc0] & kEmitMask) : 0;
+    const int ne = xc0 < xend ? (int)cntA[xc0] : 0;
     int nwin;
     const int nb = block_excl_scan(ne, s_tmp, nwin);
     s_nb[threadIdx.x] = nb;
