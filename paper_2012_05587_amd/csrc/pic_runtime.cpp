@@ -223,7 +223,7 @@ constexpr int kTuneCand[] = {5, 10, 20, 40, 80};
 constexpr int kTuneN = 5;
 constexpr int kTuneStart = 2;  // 20 steps
 constexpr int kTunePeriod = 16;
-constexpr double kTuneGain = 0.03;
+constexpr double kTuneGain = 0.02;
 // Timed replays in flight at most: a long call waits for the oldest before
 // enqueueing more, so the tuner reads its probes while the call runs (the
 // device still has this many replays queued).
