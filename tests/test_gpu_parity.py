@@ -455,6 +455,22 @@ def test_tail_sort_matches_oracle(precision):
         pc.compare_fields(gg, go)
 
 
+@pytest.mark.parametrize("precision", [workloads.FP64, workloads.MIXED])
+@pytest.mark.parametrize("l_gamma", [0.0, 20.0])
+def test_children_born_at_rest(precision, l_gamma):
+    """The degenerate pair energy f gamma_thr = 2 (gamma_thr = 4, f = 1/2):
+    each child gets gamma' = 1, so it is born at rest (momentum +-0) and
+    moves only once the field has pushed it; in place (periodic) and from
+    photons (absorbing), over 250 steps."""
+    cfg = workloads.config("c1_fp64_reference_gap")
+    cfg.update(e0=0.5, gamma_thr=4.0, f=0.5, l_gamma=l_gamma, weight=0.01, precision=precision,
+               capacity=400_000, photon_capacity=400_000,
+               boundary=workloads.PERIODIC if l_gamma == 0.0 else workloads.ABSORBING)
+    gg, go = _run_pair(cfg, 250)
+    _check_all(gg, go, precision)
+    assert go.history()["pairs_created"][-1] > 1000
+
+
 def test_step_count_limit():
     """Photon conversion steps are 32-bit, so a gap runs at most
     2^31 - 2^28 - 1 steps: a call that would pass that enqueues nothing and
