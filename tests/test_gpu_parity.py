@@ -471,6 +471,20 @@ def test_children_born_at_rest(precision, l_gamma):
     assert go.history()["pairs_created"][-1] > 1000
 
 
+@pytest.mark.parametrize("precision", [workloads.FP64, workloads.MIXED])
+@pytest.mark.parametrize("e0,dt", [(-50.0, 0.45), (50.0, 0.99)])
+def test_reversed_field_and_long_step(precision, e0, dt):
+    """Configuration 1 with the field reversed (positrons run to -x) and with
+    dt = 0.99 dx (a relativistic lepton crosses a node almost every step),
+    300 steps through a cascade with absorption at both walls."""
+    cfg = workloads.config("c1_fp64_reference_gap")
+    cfg.update(e0=e0, dt=dt, precision=precision)
+    gg, go = _run_pair(cfg, 300)
+    _check_all(gg, go, precision)
+    h = go.history()
+    assert h["pairs_created"][-1] > 5000 and min(h["absorbed_minus"][-1], h["absorbed_plus"][-1]) > 1000
+
+
 def test_step_count_limit():
     """Photon conversion steps are 32-bit, so a gap runs at most
     2^31 - 2^28 - 1 steps: a call that would pass that enqueues nothing and
