@@ -564,6 +564,34 @@ def test_batch_matches_oracle_per_gap():
         pc.compare_particles(view, go, PTOL[workloads.FP64])
 
 
+def test_large_batch_plans_in_two_passes():
+    """5000 small cascading gaps in one batch: more than the 4096 whose work
+    items the one-pass plan keeps in registers (4 per thread of one block),
+    so every step's plans take the two-pass path.  Sampled gaps, either
+    side of the 4096th, equal their own oracle runs bit for bit."""
+    import paper_2012_05587_amd as P
+    base = workloads.config("c1_fp64_reference_gap")
+    gaps = []
+    for i in range(5000):
+        c = dict(base)
+        c.update(n_cells=32 + (i % 7) * 8, n_pairs=2 + i % 5, macro_per_pair=1,
+                 seed=base["seed"] + 1000 + i, capacity=4000, photon_capacity=4000,
+                 history_rows=70)
+        gaps.append(c)
+    print("[case] 5000-gap batch", flush=True)
+    b = P.Batch([pc.gpu_params(c) for c in gaps])
+    for view, c in zip(b.gaps, gaps):
+        view.seed_particles(0, c["n_pairs"], 1)
+    st = b.step_n(60, statuses=True)
+    assert np.all(st == 0)
+    for i in (0, 1, 2500, 4095, 4096, 4999):
+        go = pc.make_oracle(gaps[i])
+        assert go.step(60) == 0
+        pc.compare_history(b.gaps[i].read_history(), go.history())
+        pc.compare_particles(b.gaps[i], go, PTOL[workloads.FP64])
+    b.close()
+
+
 def test_batch_mixed_matches_single_gaps():
     import paper_2012_05587_amd as P
     gaps = workloads.batched_scan(n_gaps=4, precision=workloads.MIXED, steps=100)
