@@ -525,6 +525,43 @@ def test_capacity_overflow_freezes_gap():
         gg.step_n(1)
 
 
+@pytest.mark.parametrize("precision", [workloads.FP64, workloads.MIXED])
+def test_emission_overflow_detected(precision):
+    """A lepton that would emit more than 64 times in one step (E0 dt = 180
+    against gamma_pair = 2) freezes the gap with PIC_ERR_EMISSION at the
+    oracle's step; the rows before it equal the oracle's."""
+    import paper_2012_05587_amd as P
+    cfg = dict(n_cells=64, dx=1.0, dt=0.45, boundary=workloads.PERIODIC, e0=400.0,
+               gamma_thr=100.0, f=0.02, l_gamma=0.0, weight=0.01, seed=7, precision=precision,
+               n_pairs=8, macro_per_pair=1, capacity=100_000, photon_capacity=0, history_rows=40)
+    go = pc.make_oracle(cfg)
+    assert go.step(20) == -7
+    gg = pc.make_gpu(cfg)
+    rep = gg.step_n(20, report=True)
+    assert rep.status == P.ERR_EMISSION
+    assert rep.steps_done == go.steps_done
+    pc.compare_history(gg.read_history(), go.history())
+    with pytest.raises(P.PicError):
+        gg.step_n(1)
+
+
+def test_photon_store_overflow_freezes_gap():
+    """Configuration 1 with 500 photon slots: the store fills within a few
+    steps and the gap freezes with PIC_ERR_CAPACITY; every row before the
+    freeze equals the oracle's, whose store is unbounded."""
+    import paper_2012_05587_amd as P
+    cfg = workloads.config("c1_fp64_reference_gap")
+    cfg.update(photon_capacity=500, history_rows=400)
+    go = pc.make_oracle(cfg)
+    assert go.step(60) == 0
+    gg = pc.make_gpu(cfg)
+    rep = gg.step_n(60, report=True)
+    assert rep.status == P.ERR_CAPACITY and 0 < rep.steps_done < 60
+    hg = gg.read_history()
+    assert len(hg) == rep.steps_done
+    pc.compare_history(hg, go.history()[:len(hg)])
+
+
 def test_nonfinite_detected():
     import paper_2012_05587_amd as P
     cfg = workloads.config("c1_fp64_reference_gap")
