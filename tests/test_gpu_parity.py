@@ -434,15 +434,18 @@ def test_maximum_cell_count(precision, boundary):
 
 
 @pytest.mark.parametrize("precision", [workloads.FP64, workloads.MIXED])
-def test_tail_sort_matches_oracle(precision):
+@pytest.mark.parametrize("variant", ["linear", "spline", "spread"])
+def test_tail_sort_matches_oracle(precision, variant):
     """A gap wider than the push's tile (4096 cells) cascades for 150 steps
     with absorbing walls, so between full re-sorts its appended leptons,
-    dead ones among them, are sorted among themselves every 5 steps.  At
+    dead ones among them, are sorted among themselves every 5 steps; with
+    the linear shape, the quadratic spline and a spread of gamma_thr.  At
     cadences 40, 7 and tuned the results equal the oracle's bit for bit."""
     cfg = workloads.config("c2_fp64_single_gap")
     cfg.update(n_cells=4096, n_pairs=512, capacity=2_000_000, photon_capacity=4_000_000,
                precision=precision, history_rows=160)
-    print(f"[case] tail sort prec={precision}", flush=True)
+    cfg.update({"linear": {}, "spline": {"shape": 1}, "spread": {"gamma_thr_spread": 0.3}}[variant])
+    print(f"[case] tail sort prec={precision} {variant}", flush=True)
     go = pc.make_oracle(cfg)
     assert go.step(150) == 0
     h = go.history()
