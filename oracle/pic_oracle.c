@@ -157,11 +157,10 @@ static int64_t conv_steps(const orc_gap* g, uint32_t u) {
 /* ------------------------------------------------------------------------ */
 static double R(const orc_gap* g, double x) { return g->mixed ? (double)(float)x : x; }
 
-/* Lorentz factor of momentum p as the push computes it, in the particle
- * precision; energies are summed from it in binary64. */
-static double gamma_of(const orc_gap* g, double p) {
-  return R(g, sqrt(R(g, 1.0 + R(g, p * p))));
-}
+/* Energy diagnostics stay binary64 in both precisions: a lepton's Lorentz
+ * factor is re-evaluated in binary64 from its stored momentum (a binary32
+ * value in mixed precision), not taken from the push's binary32 gamma. */
+static double gamma64(double p) { return sqrt(1.0 + p * p); }
 
 /* Emission threshold of lepton `id` under a spread sigma of gamma_thr: a
  * fixed property of the lepton, uniform in gamma_thr (1 - sigma, 1 + sigma).
@@ -414,7 +413,7 @@ static void record_history(orc_gap* g) {
   double w = g->prm.weight;
   double ke = 0.0;
   for (int s = 0; s < 2; ++s)
-    for (int64_t i = 0; i < g->sp[s].n; ++i) ke += w * gamma_of(g, g->sp[s].p[i]);
+    for (int64_t i = 0; i < g->sp[s].n; ++i) ke += w * gamma64(g->sp[s].p[i]);
   r.kinetic = ke;
   double fe = 0.0, es = 0.0;
   for (int32_t c = 0; c < g->prm.n_cells; ++c) {
@@ -561,7 +560,7 @@ static int step_once(orc_gap* g) {
         S->offq[i] = nq;
       } else {
         g->absorbed[s]++;
-        g->lost_energy += P->weight * gamma_of(g, p);
+        g->lost_energy += P->weight * gamma64(p);
       }
     }
   }

@@ -60,8 +60,8 @@ typedef struct {
   int64_t photons_emitted; /* cumulative */
   int64_t photons_escaped; /* cumulative, absorbing boundary only */
   int64_t absorbed_minus, absorbed_plus; /* cumulative */
-  double  kinetic;         /* sum w*gamma over live leptons (rest mass included; gamma in
-                              the particle precision, summed in binary64) */
+  double  kinetic;         /* sum w*gamma over live leptons (rest mass included), gamma
+                              = sqrt(1 + p^2) in binary64 from the stored momentum */
   double  field;           /* sum E_c^2 dx / 2 */
   double  photon_energy;   /* energy carried by photons in flight */
   double  lost_energy;     /* cumulative energy of absorbed leptons and escaped photons */
