@@ -84,13 +84,14 @@ def _workload(name, precision=None):
     return gaps
 
 
-def _make(P, gaps, stream):
-    """A Batch of the gaps (or a Gap for one), seeded."""
+def _make(P, gaps, stream, workspace=None):
+    """A Batch of the gaps (or a Gap for one), seeded; `workspace` (a device
+    tensor from an earlier batch of the same workload) is reused."""
     if len(gaps) == 1:
-        g = P.Gap(_params(P, gaps[0]), stream=stream)
+        g = P.Gap(_params(P, gaps[0]), stream=stream, workspace=workspace)
         views = [g]
     else:
-        g = P.Batch([_params(P, c) for c in gaps], stream=stream)
+        g = P.Batch([_params(P, c) for c in gaps], stream=stream, workspace=workspace)
         views = g.gaps
     for v, c in zip(views, gaps):
         if c["n_pairs"]:
@@ -103,29 +104,63 @@ def _make(P, gaps, stream):
     return g, views
 
 
-def run_gpu(gaps, steps, profile=True, dump=None):
-    """Times `steps` steps from the seeded start (graph replay on a side
-    stream); with profile, repeats the run launching every kernel directly
-    with the push kernel bracketed by HIP events, for that kernel's time."""
+def _frozen(views):
+    """Gaps that stopped early: (index, status, steps completed)."""
+    out = []
+    for i, v in enumerate(views):
+        m = v.read_moments()
+        if m.status != 0:
+            out.append((i, int(m.status), int(m.steps_done)))
+    return out
+
+
+def run_gpu(gaps, steps, warmup=0, reps=5, profile=True, dump=None):
+    """Times `steps` steps from the seeded start, `reps` times on fresh
+    batches of the same workload (one device workspace, re-created and
+    re-seeded to the identical state; graph replay on a side stream), and
+    keeps the median.  Before each timed run the batch is prepared (seed
+    sorted by cell, step graphs captured and uploaded); that time is reported
+    apart.  `warmup` steps of a throwaway batch of the same workload come
+    first.  With profile, a further fresh batch runs the same steps launching
+    every kernel directly, the push kernel bracketed by HIP events, for that
+    kernel's time."""
     import torch
     import paper_2012_05587_amd as P
     P.lib()
     gaps = [dict(c, history_rows=steps + 8) for c in gaps]
     stream = torch.cuda.Stream()
-    g, views = _make(P, gaps, stream)
-    torch.cuda.synchronize()
-    log(f"timing {steps} steps of {len(gaps)} gap(s), precision {gaps[0]['precision']}")
-    t0 = time.perf_counter()
-    g.step_n(steps)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    log(f"done in {t1 - t0:.2f} s")
-    pushes, peak, frozen, done = 0, 0, 0, 0
-    for v in views:
-        m = v.read_moments()
-        pushes += int(m.pushes)
-        frozen += int(m.status != 0)
-        done = max(done, int(m.steps_done))
+    ws = None
+    if warmup > 0:
+        g, _ = _make(P, gaps, stream)
+        ws = g.workspace
+        g.prepare()
+        log(f"warm-up: {warmup} steps of the same workload")
+        g.step_n(warmup)
+        torch.cuda.synchronize()
+        g.close()
+    runs = []
+    for r in range(reps):
+        g, views = _make(P, gaps, stream, ws)
+        ws = g.workspace
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.prepare()
+        t_prep = time.perf_counter() - t0
+        log(f"run {r + 1}/{reps}: {steps} steps of {len(gaps)} gap(s), precision {gaps[0]['precision']}")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.step_n(steps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        pushes = sum(int(v.read_moments().pushes) for v in views)
+        done = max(int(v.read_moments().steps_done) for v in views)
+        log(f"done in {t1 - t0:.4f} s ({pushes / (t1 - t0):.3e} pushes/s; prepare {t_prep:.3f} s)")
+        runs.append(dict(seconds=t1 - t0, prepare_s=t_prep, pushes=pushes, steps=done))
+        if r < reps - 1:
+            g.close()
+    order = sorted(range(reps), key=lambda k: runs[k]["seconds"])
+    med = runs[order[reps // 2]]
+    peak = 0
     if len(views) == 1:
         h = views[0].read_history()
         peak = int((h["n_minus"] + h["n_plus"]).max()) if len(h) else 0
@@ -149,32 +184,55 @@ def run_gpu(gaps, steps, profile=True, dump=None):
             out_h["running"][k] += 1
         np.save(dump, out_h)
     tune = g.tuning()
-    out = dict(seconds=t1 - t0, pushes=pushes, steps=done, frozen=frozen, peak_leptons=peak,
+    frozen = _frozen(views)
+    out = dict(seconds=med["seconds"], pushes=med["pushes"], steps=med["steps"],
+               frozen=len(frozen), frozen_gaps=frozen, peak_leptons=peak,
+               prepare_s=[round(x["prepare_s"], 4) for x in runs],
+               run_seconds=[round(x["seconds"], 6) for x in runs],
                push_ms=None, push_launches=None, tuning=tune)
     g.close()
-    del g, views, v
-    torch.cuda.empty_cache()
+    del g, views
     if profile:
         # the evented run launches every kernel directly; an autotuned cadence
         # is tuned there the same way, from the timed S-step segments
-        g, views = _make(P, gaps, stream)
+        g, views = _make(P, gaps, stream, ws)
         g.profile_push(True)
         log("timing the push kernel with events")
         g.step_n(steps)
         push_ms, launches = g.read_push_time()
-        # The evented run repeats the same steps; its cadence follows the
-        # same policy but may switch at other steps.  Its pushes equal the
-        # timed run's unless a gap runs out of slots: slots of absorbed
-        # leptons are freed at re-sorts, so the step at which a gap freezes
-        # can depend on the cadence.  The kernel rate uses the evented run's
-        # own pushes.
+        # the evented run repeats the same steps and pushes the same leptons
         again = sum(int(x.read_moments().pushes) for x in views)
         out.update(push_ms=push_ms, push_launches=launches, evented_pushes=again,
                    evented_tuning=g.tuning())
         g.close()
         del g, views
-        torch.cuda.empty_cache()
+    del ws
+    torch.cuda.empty_cache()
     return out
+
+
+def run_counter_pass(gaps, steps):
+    """A bounded run for hardware-counter passes: the workload's first
+    `steps` steps launched directly (no graphs), one step at a time, printing
+    a line after each, so that a profiler serialising every dispatch still
+    shows progress.  Prints a JSON line with the leptons pushed per step."""
+    import torch
+    import paper_2012_05587_amd as P
+    P.lib()
+    gaps = [dict(c, history_rows=steps + 8) for c in gaps]
+    g, views = _make(P, gaps, None)
+    g.prepare()
+    torch.cuda.synchronize()
+    per_step = []
+    for k in range(steps):
+        before = sum(int(v.read_moments().pushes) for v in views)
+        g.step_n(1)
+        torch.cuda.synchronize()
+        after = sum(int(v.read_moments().pushes) for v in views)
+        per_step.append(after - before)
+        print(f"[pmc] step {k + 1}/{steps}: {after - before} leptons pushed", flush=True)
+    print(json.dumps({"counter_pass": True, "steps": steps, "pushes_per_step": per_step}), flush=True)
+    g.close()
 
 
 def measure_copy_gbs(nbytes=1 << 30, reps=10):
@@ -198,22 +256,6 @@ def measure_copy_gbs(nbytes=1 << 30, reps=10):
     del a, b
     torch.cuda.empty_cache()
     return 2.0 * nbytes / min(times) / 1e9
-
-
-def warm_up(steps):
-    """Loads the code objects and builds a graph on a small batch."""
-    import torch
-    import paper_2012_05587_amd as P
-    if steps <= 0:
-        return
-    gaps = workloads.batched_scan(4, precision=workloads.MIXED, steps=steps)
-    for c in gaps:
-        c.update(capacity=200_000, photon_capacity=200_000)
-    for prec in (workloads.MIXED, workloads.FP64):
-        g, _ = _make(P, [dict(c, precision=prec) for c in gaps], torch.cuda.Stream())
-        g.step_n(steps)
-        torch.cuda.synchronize()
-        g.close()
 
 
 def _oracle_gap(args):
@@ -405,10 +447,23 @@ def summarize(args):
     print(base + ".md")
 
 
+def host_cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo), for the CPU baseline."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def _leg(r, precision):
     bpp = BYTES_PER_PUSH[precision]
     leg = dict(value=r["pushes"] / r["seconds"], unit="pushes/s", pushes=r["pushes"],
-               seconds=r["seconds"], steps=r["steps"], frozen_gaps=r["frozen"])
+               seconds=r["seconds"], steps=r["steps"], frozen_gaps=r["frozen"],
+               run_seconds=r["run_seconds"])
     if r["push_ms"]:
         leg["push_kernel_GBs"] = r["evented_pushes"] * bpp / (r["push_ms"] * 1e-3) / 1e9
     return leg
@@ -418,7 +473,10 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default: whole job)")
-    ap.add_argument("--warmup", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=5,
+                    help="untimed steps of a throwaway batch of the same workload first")
+    ap.add_argument("--reps", type=int, default=5,
+                    help="timed runs on fresh batches; the median is reported")
     ap.add_argument("--workload", default="c4_batched",
                     choices=["c4_batched", "n1_corotating", "n3_uniform", "n4_spread", "n4_spline",
                              "n4_nonuniform", "ubench_lattice"]
@@ -432,6 +490,8 @@ def main():
     ap.add_argument("--dump-history", default=None, help="save the history rows (.npy, single gap)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy a 1 GiB device buffer 3 times (counter calibration)")
+    ap.add_argument("--counter-pass", type=int, default=0, metavar="STEPS",
+                    help="only run the first STEPS steps eagerly, one line per step (PMC passes)")
     ap.add_argument("--timed-only", action="store_true",
                     help="skip the evented rerun (counter passes: same push dispatches, graph-replayed)")
     ap.add_argument("--summarize", action="store_true",
@@ -466,6 +526,9 @@ def main():
     gaps = _workload(args.workload)
     if args.sort_every is not None:
         gaps = [dict(c, sort_every=args.sort_every) for c in gaps]
+    if args.counter_pass:
+        run_counter_pass(gaps, args.counter_pass)
+        return
     prec = gaps[0]["precision"]
     steps = args.steps if args.steps is not None else DEFAULT_STEPS.get(args.workload, gaps[0]["steps"])
 
@@ -478,11 +541,12 @@ def main():
         cpu = dict(value=cb["value"], unit="pushes/s", cores=procs, kind="oracle",
                    sample=f"first {min(args.cpu_steps, steps)} steps of {len(sample)} gap(s) of "
                           f"{args.workload}, one gap per process ({cb['pushes']} pushes, "
-                          f"{cb['seconds']:.1f} s)")
+                          f"{cb['seconds']:.1f} s)",
+                   host_nproc=os.cpu_count(), host_cpu=host_cpu_model())
 
-    warm_up(args.warmup)
     copy_gbs = None if args.timed_only else measure_copy_gbs()
-    main_run = run_gpu(gaps, steps, profile=not args.timed_only, dump=args.dump_history)
+    main_run = run_gpu(gaps, steps, warmup=args.warmup, reps=args.reps,
+                       profile=not args.timed_only, dump=args.dump_history)
     value = main_run["pushes"] / main_run["seconds"]
     bpp = BYTES_PER_PUSH[prec]
     if args.timed_only:
@@ -494,21 +558,29 @@ def main():
     extra = {}
     if not args.no_compare:
         if args.workload == "c4_batched":
-            r = run_gpu(_workload("c4_batched", workloads.FP64), steps, profile=False)
+            r = run_gpu(_workload("c4_batched", workloads.FP64), steps, warmup=args.warmup,
+                        reps=args.reps, profile=False)
             extra["fp64_batched_same_workload"] = _leg(r, workloads.FP64)
             c2 = _workload("c2_fp64_single_gap")
-            r = run_gpu(c2, DEFAULT_STEPS["c2_fp64_single_gap"], profile=True)
+            r = run_gpu(c2, DEFAULT_STEPS["c2_fp64_single_gap"], warmup=args.warmup, reps=1,
+                        profile=True)
             leg = _leg(r, workloads.FP64)
             leg["workload"] = "c2_fp64_single_gap (8192 cells, 1024 seed pairs, first 10000 steps)"
             extra["plain_fp64_single_gap"] = leg
         elif prec == workloads.FP64:
-            r = run_gpu(_workload(args.workload, workloads.MIXED), steps, profile=True)
+            r = run_gpu(_workload(args.workload, workloads.MIXED), steps, warmup=args.warmup,
+                        reps=args.reps, profile=True)
             extra["mixed_same_workload"] = _leg(r, workloads.MIXED)
 
     pmc = stored_traffic(args.workload, prec, steps)
     tu = main_run["tuning"]
     cfg = {"workload": args.workload, "gaps": len(gaps), "steps": steps,
            "pushes": main_run["pushes"], "frozen_gaps": main_run["frozen"],
+           "frozen": [{"gap": i, "status": st, "steps_done": n} for i, st, n in main_run["frozen_gaps"]],
+           "timed_runs": {"reps": args.reps, "statistic": "median",
+                          "seconds": main_run["run_seconds"],
+                          "prepare_seconds": main_run["prepare_s"],
+                          "warmup_steps": args.warmup},
            "sort_every": {"autotuned": tu["autotuned"], "final": tu["sort_every"],
                           "switches": tu["switches"], "timed_replays": tu["replays"]}}
     if len(gaps) == 1:

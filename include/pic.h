@@ -32,13 +32,18 @@
  *    replays in flight (a long call returns once all but the last 8 have
  *    run); pic_read_* and pic_set_fields synchronise that stream.
  *  - A handle is not thread-safe.
- *  - Capacity.  Each species has `capacity` slots and the photon store
- *    `photon_capacity` slots; slots of absorbed leptons and converted photons
- *    are reclaimed when particles are re-sorted.  A step that would need more
- *    slots is not completed: the gap is frozen with PIC_ERR_CAPACITY, its
- *    step counter and history stay at the last completed step, and its
- *    particle arrays are not meaningful.  Later pic_step_n calls return
- *    PIC_ERR_STATE.
+ *  - Capacity.  `capacity` bounds the live leptons of each species, as the
+ *    model's memory bound: a step after which a species holds more live
+ *    leptons than that is not completed.  The gap is frozen with
+ *    PIC_ERR_CAPACITY; its step counter and history stay at the last
+ *    completed step, while E and the particle arrays already hold that
+ *    step's push and are not meaningful.  Later pic_step_n calls return
+ *    PIC_ERR_STATE.  Each species has capacity + capacity/8 + 2048 slots:
+ *    absorbed leptons keep their slots until the next re-sort, and a step
+ *    whose appends do not fit the slots although the live leptons stay
+ *    within capacity freezes the gap the same way with PIC_ERR_SLOTS.  The
+ *    photon store has `photon_capacity` slots, reclaimed at re-sorts; a step
+ *    that overflows it freezes with PIC_ERR_CAPACITY.
  *  - Non-finite momenta freeze the gap with PIC_ERR_NONFINITE the same way.
  */
 #ifndef PIC_H
@@ -56,11 +61,13 @@ enum {
   PIC_OK = 0,
   PIC_ERR_ARG = -1,        /* invalid argument or parameter set */
   PIC_ERR_WORKSPACE = -2,  /* workspace too small or misaligned */
-  PIC_ERR_CAPACITY = -3,   /* particle or photon slots exhausted */
+  PIC_ERR_CAPACITY = -3,   /* live leptons above the capacity, or photon store full */
   PIC_ERR_DEVICE = -4,     /* a HIP runtime call failed */
   PIC_ERR_STATE = -5,      /* wrong call order, or the gap is frozen */
   PIC_ERR_NONFINITE = -6,  /* a momentum became NaN or infinite */
-  PIC_ERR_EMISSION = -7    /* more than 64 emissions by one lepton in one step */
+  PIC_ERR_EMISSION = -7,   /* more than 64 emissions by one lepton in one step */
+  PIC_ERR_SLOTS = -8       /* lepton slots exhausted by absorbed leptons not yet
+                              reclaimed, while the live leptons fit the capacity */
 };
 
 enum { PIC_BC_PERIODIC = 0, PIC_BC_ABSORBING = 1 };
@@ -88,12 +95,11 @@ enum { PIC_ELECTRON = 0, PIC_POSITRON = 1 };
  *            must each stay below 2^62 of them: with binary64 (K = 40) that
  *            is n_cells <= 2^22 and l_gamma below about 1.9e5 cells.
  *  weight    macro-particle weight w >= 0 (w = 0 gives test particles).
- *  capacity, photon_capacity  slots per species / in the photon store.  A
- *            step whose appends do not fit freezes the gap (the state of
- *            the last completed step stays readable).  Slots of absorbed
- *            leptons and converted photons are reused only after the next
- *            re-sort, so with absorbing walls the step at which a gap
- *            freezes can depend on sort_every.
+ *  capacity  live leptons per species at the end of a step (above it the
+ *            gap freezes, see Capacity above); below 2^31 with its slot
+ *            reserve.
+ *  photon_capacity  slots of the photon store (l_gamma > 0); converted and
+ *            escaped photons are reclaimed at re-sorts.
  *  seed      key of the Philox4x64-10 streams of this gap.
  *  precision PIC_FP64: per-particle arithmetic in binary64, offsets on a
  *            2^-40 cell grid.  PIC_MIXED: binary32 push, offset (2^-24 grid)
@@ -104,7 +110,7 @@ enum { PIC_ELECTRON = 0, PIC_POSITRON = 1 };
  *               every 5 steps, the leptons appended since the last one are
  *               sorted among themselves in gaps wider than 2040 cells.  The
  *               cadence changes cost only: results do not depend on it while
- *               no gap runs out of slots.
+ *               no gap runs out of slots (PIC_ERR_SLOTS).
  *  diag_every   steps between history rows (0 = 1).
  *  history_rows rows kept in the device history ring (0 = 4096).
  *  j_m       imposed current density of the frame co-rotating with the
@@ -207,8 +213,11 @@ pic_status pic_create_gap(const pic_gap_params* p, void* d_ws, size_t ws_bytes,
  * cell = (u0 >> 32) * n_cells >> 32, offset = (u1 >> 40) * 2^-24.
  * PIC_SEED_LATTICE: x_i = (i + 1/2) n_cells / N on the 2^-24 grid.
  * Momenta are p0_minus / p0_plus (taken as p at t = -dt/2).
- * Errors: PIC_ERR_ARG, PIC_ERR_STATE (after the first step),
- * PIC_ERR_CAPACITY (more pairs than slots), PIC_ERR_DEVICE. */
+ * The seed is sorted by cell before the first step (by pic_prepare or the
+ * first pic_step_n), so that its chunks deposit through the LDS tile.
+ * Errors: PIC_ERR_ARG, PIC_ERR_STATE (after the first step, or when the gap
+ * already holds leptons: the seed ids start at 0), PIC_ERR_CAPACITY (more
+ * pairs than the capacity), PIC_ERR_DEVICE. */
 pic_status pic_seed_particles(pic_gap* g, int32_t mode, int64_t n_pairs,
                               int32_t macro_per_pair, double p0_minus, double p0_plus);
 
@@ -217,6 +226,14 @@ pic_status pic_seed_particles(pic_gap* g, int32_t mode, int64_t n_pairs,
  * momentum p, 64-bit id.  Only before the first step. */
 pic_status pic_seed_explicit(pic_gap* g, int32_t species, int64_t n, const int32_t* cell,
                              const double* off, const double* p, const uint64_t* id);
+
+/* Makes a seeded gap ready to step: enqueues the sort of the seed by cell
+ * and, on a non-NULL stream, captures and uploads the HIP graphs of the
+ * step sequence (every candidate re-sort cadence when sort_every = 0), so
+ * that pic_step_n only launches them.  Optional: pic_step_n does the same
+ * work on first use.  Synchronises the stream.  Errors: PIC_ERR_STATE
+ * after the first step, PIC_ERR_DEVICE. */
+pic_status pic_prepare(pic_gap* g);
 
 /* Enqueues n_steps steps.  Each step pushes every lepton in the field
  * gathered at its position, moves it with a charge-conserving current,
@@ -329,11 +346,13 @@ pic_status pic_destroy_batch(pic_batch* b);
 /* Kernel timing of a batch, as pic_profile_push / pic_read_push_time. */
 pic_status pic_batch_profile_push(pic_batch* b, int32_t enable);
 pic_status pic_batch_read_push_time(pic_batch* b, double* ms, int64_t* launches);
+/* pic_prepare for every gap of a batch. */
+pic_status pic_batch_prepare(pic_batch* b);
 /* Re-sort cadence.  The sort is not part of the paper's method: it only
  * reorders leptons for memory locality.  With sort_every = 0 the library times every
  * replayed graph of S steps plus the sort, S in {5, 10, 20, 40, 80}, and
  * every 16 replays probes half and twice the current S, switching when the
- * challenger is more than 3% faster per step.  Synchronises the stream.
+ * challenger is more than 2% faster per step.  Synchronises the stream.
  * Outputs (each may be NULL): the cadence in use, whether it is tuned, the
  * number of timed replays and of switches so far. */
 pic_status pic_batch_tuning(pic_batch* b, int32_t* sort_every, int32_t* autotuned,

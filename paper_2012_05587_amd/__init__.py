@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libpic_cascade.so")
 
 OK, ERR_ARG, ERR_WORKSPACE, ERR_CAPACITY, ERR_DEVICE, ERR_STATE, ERR_NONFINITE, ERR_EMISSION = \
     0, -1, -2, -3, -4, -5, -6, -7
+ERR_SLOTS = -8
 BC_PERIODIC, BC_ABSORBING = 0, 1
 FP64, MIXED = 0, 1
 SEED_RANDOM, SEED_LATTICE = 0, 1
@@ -32,7 +33,7 @@ EXPORTS = [
     "pic_batch_workspace_bytes", "pic_create_batch", "pic_batch_step_n", "pic_batch_gap",
     "pic_batch_size", "pic_destroy_batch", "pic_profile_push", "pic_read_push_time",
     "pic_batch_profile_push", "pic_batch_read_push_time", "pic_batch_tuning", "pic_tuning",
-    "pic_phase_space", "pic_event_map",
+    "pic_phase_space", "pic_event_map", "pic_prepare", "pic_batch_prepare",
 ]
 
 
@@ -92,6 +93,9 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2012_05587_amd/build.py")
+    # torch first: its HIP runtime is then the one the library binds to, so
+    # the device memory and streams torch hands over are valid in the library
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     vp, i32, i64, u64, dbl, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_double, C.c_size_t
     P = C.POINTER
@@ -101,6 +105,8 @@ def lib():
     L.pic_seed_particles.argtypes = [vp, i32, i64, i32, dbl, dbl]; L.pic_seed_particles.restype = i32
     L.pic_seed_explicit.argtypes = [vp, i32, i64, vp, vp, vp, vp]; L.pic_seed_explicit.restype = i32
     L.pic_step_n.argtypes = [vp, i64, P(StepReport)]; L.pic_step_n.restype = i32
+    L.pic_prepare.argtypes = [vp]; L.pic_prepare.restype = i32
+    L.pic_batch_prepare.argtypes = [vp]; L.pic_batch_prepare.restype = i32
     L.pic_read_fields.argtypes = [vp, vp, vp, i32]; L.pic_read_fields.restype = i32
     L.pic_read_flux.argtypes = [vp, vp, i32]; L.pic_read_flux.restype = i32
     L.pic_read_moments.argtypes = [vp, P(Moments)]; L.pic_read_moments.restype = i32
@@ -168,10 +174,17 @@ def pic_workspace_bytes(params):
     return lib().pic_workspace_bytes(C.byref(params))
 
 
-def _device_workspace(nbytes, device):
+def _device_workspace(nbytes, device, reuse=None):
+    """A uint8 device tensor of at least nbytes: `reuse` if it is large enough
+    (a caller recreating gaps on the same memory), else a new one."""
     import torch
-    # 256-byte alignment is guaranteed by the caching allocator for fresh blocks
-    ws = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+    if reuse is not None:
+        if reuse.numel() < nbytes:
+            raise ValueError(f"workspace of {reuse.numel()} bytes is smaller than {nbytes}")
+        ws = reuse
+    else:
+        # 256-byte alignment is guaranteed by the caching allocator for fresh blocks
+        ws = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
     if ws.data_ptr() % 256:
         raise RuntimeError("workspace is not 256-byte aligned")
     return ws
@@ -298,17 +311,21 @@ class _GapView:
 class Gap(_GapView):
     """One gap over a torch-allocated device workspace (pic_create_gap)."""
 
-    def __init__(self, params, device="cuda", stream=None):
+    def __init__(self, params, device="cuda", stream=None, workspace=None):
         L = lib()
         st = L.pic_validate_params(C.byref(params))
         _check("pic_validate_params", st)
         nbytes = L.pic_workspace_bytes(C.byref(params))
-        self.workspace = _device_workspace(nbytes, device)
+        self.workspace = _device_workspace(nbytes, device, workspace)
         sh, self.stream = _stream_handle(stream)
         h = C.c_void_p()
         _check("pic_create_gap", L.pic_create_gap(C.byref(params), C.c_void_p(self.workspace.data_ptr()),
                                                   nbytes, sh, C.byref(h)))
         super().__init__(h, params, None)
+
+    def prepare(self):
+        """Sorts the seed and captures the step graphs now (pic_prepare)."""
+        _check("pic_prepare", lib().pic_prepare(self._h))
 
     def step_n(self, n_steps, report=False):
         rep = StepReport() if report else None
@@ -343,13 +360,13 @@ class Gap(_GapView):
 class Batch:
     """Many independent gaps advanced by the same launches (pic_create_batch)."""
 
-    def __init__(self, params_list, device="cuda", stream=None):
+    def __init__(self, params_list, device="cuda", stream=None, workspace=None):
         L = lib()
         arr = (GapParams * len(params_list))(*params_list)
         nbytes = L.pic_batch_workspace_bytes(arr, len(params_list))
         if nbytes == 0:
             raise PicError("pic_batch_workspace_bytes", ERR_ARG)
-        self.workspace = _device_workspace(nbytes, device)
+        self.workspace = _device_workspace(nbytes, device, workspace)
         sh, self.stream = _stream_handle(stream)
         h = C.c_void_p()
         _check("pic_create_batch", L.pic_create_batch(arr, len(params_list),
@@ -359,6 +376,10 @@ class Batch:
         self._arr = arr
         self.gaps = [_GapView(L.pic_batch_gap(h, i), params_list[i], self)
                      for i in range(len(params_list))]
+
+    def prepare(self):
+        """Sorts the seeds and captures the step graphs now (pic_batch_prepare)."""
+        _check("pic_batch_prepare", lib().pic_batch_prepare(self._h))
 
     def step_n(self, n_steps, statuses=False):
         out = np.zeros(len(self.gaps), np.int32) if statuses else None

@@ -57,12 +57,18 @@ struct PushCfg<float> {
   static constexpr bool prefetch = PIC_PUSH_F_PREFETCH;
   static constexpr int e_group = PIC_PUSH_F_EGROUP;
   static constexpr int waves = PIC_PUSH_F_WAVES;
+  // the per-lepton-threshold instantiations hold more state per item; at 128
+  // VGPRs the compiler spilled some of it inside a divergent branch, where a
+  // spill store writes only the active lanes and the others later reloaded
+  // stale values, so they get 168 VGPRs (3 waves per SIMD) and spill nothing
+  static constexpr int spread_waves = 3;
 };
 template <>
 struct PushCfg<double> {
   static constexpr bool prefetch = PIC_PUSH_D_PREFETCH;
   static constexpr int e_group = PIC_PUSH_D_EGROUP;
   static constexpr int waves = PIC_PUSH_D_WAVES;
+  static constexpr int spread_waves = PIC_PUSH_D_WAVES;
 };
 constexpr int kStripes = 32;          // striped per-gap accumulators of the push kernel
 constexpr int kStripeStride = 16;     // doubles between stripes (one 128-byte line each)
@@ -76,6 +82,8 @@ struct GapDev {
   int32_t n_cells, boundary, K, table_len;
   int32_t precision, diag_every, hist_rows, shape;
   int64_t one, domain, photon_step, cap, ph_cap;
+  int64_t slots;                     // lepton slots per species: cap plus the reserve that
+                                     // absorbed leptons hold until the next re-sort
   double dt, dx, weight, wq, e0;
   double jmdt;                       // imposed current times dt (section 7), 0 elsewhere
   double sigma, gthr64, thr_lo;      // spread of gamma_thr, gamma_thr in binary64, lowest threshold
@@ -114,15 +122,22 @@ struct GapDev {
   unsigned long long pairs_created, photons_emitted, photons_escaped, absorbed[2];
   unsigned long long pushes;
   unsigned long long hist_count;
+  // order-independent sums of the step, cleared by the finalize: the sum of
+  // the Lorentz factors of the leptons pushed this step and of those
+  // absorbed (fix64, four limbs), and the field energy and the positive and
+  // negative parts of the sum of E (wide_add, kWideLimbs limbs)
+  unsigned long long ke_limb[4], lost_limb[4];
+  unsigned long long fe_wide[8], esp_wide[8], esn_wide[8];
+  // their values, written by the first phase of the finalize
+  double ke_step, lost_step, fe_step, es_step;
   unsigned long long sorted_n[2], ph_sorted;
   unsigned long long body_n[2];  // leptons sorted by the last full re-sort (the rest were appended since)
   unsigned long long ph_body_n;  // photons in the sorted body of the store
   long long ph_base;             // conversion step of bucket 0 of the sorted body
   long long step;
   int32_t status, buf, phbuf, pad2;
-  int32_t overflow, nonfinite, emit_err, pad1;
-  double lost_energy;
-  double ke_acc, fe_acc, es_acc;
+  int32_t overflow, nonfinite, emit_err, slot_overflow;
+  double lost_energy;  // cumulative, a binary64 sum over steps in step order
   pic_history_row last;
 };
 
@@ -193,11 +208,116 @@ __device__ __forceinline__ void count_pairs(const GapDev* G, long long step, int
   atomicAdd(G->evmap + row * G->ev_x + col, k);
 }
 
-// Accumulator a (0 kinetic energy, 1 lost energy, 2-3 absorbed electrons /
-// positrons) of gap g, stripe st: each stripe on its own cache line, so the
-// workgroups of the push kernel do not all hit one address.
-__device__ __forceinline__ double* stripe_slot(double* stripes, int g, int a, int st) {
+// Accumulator a (0 kinetic energy, 1 lost energy: four limbs each; 2-3
+// absorbed electrons / positrons) of gap g, stripe st: each stripe on its own
+// cache line, so the workgroups of the push kernel do not all hit one address.
+__device__ __forceinline__ unsigned long long* stripe_slot(unsigned long long* stripes, int g, int a,
+                                                           int st) {
   return stripes + (((size_t)g * 4 + a) * kStripes + st) * kStripeStride;
+}
+
+// ------------------------------------------------- order-independent sums
+// A binary64 diagnostic summed over leptons or cells must not depend on the
+// order in which threads, workgroups or atomics visit them (leptons change
+// slots at every re-sort).  Two exact integer accumulations serve:
+//  - Lorentz factors (each at least 1; the uniform weight is applied to the
+//    total): each term is rounded once, toward zero, onto the fixed grid
+//    2^-64 as a signed 128-bit integer (below 2^63), summed in registers and
+//    then as four 32-bit limbs added to 64-bit accumulators with integer
+//    atomics, which commute;
+//  - field sums, whose terms can be arbitrarily small (a screened or
+//    equilibrium field): each workgroup's partial sum over its cells, taken in
+//    a fixed order, is added exactly to a 256-bit accumulator on the grid
+//    2^-192 (wide_add; magnitudes below 2^-192 vanish, which is far below any
+//    field the diagnostics resolve).
+// The value of accumulated limbs is the exact sum of the rounded terms,
+// converted to binary64 by a fixed sequence of roundings.
+__device__ __forceinline__ __int128 fix64(double t) {
+  const unsigned long long bits = (unsigned long long)__double_as_longlong(t);
+  const int e = (int)((bits >> 52) & 0x7FF);
+  if (e == 0 || e == 0x7FF) return 0;  // zero, subnormal (far below 2^-64), or not finite
+  const unsigned long long m = (bits & 0xFFFFFFFFFFFFFull) | (1ull << 52);
+  const int sh = e - 1075 + 64;        // t = m 2^(e - 1075); the grid unit is 2^-64
+  __int128 v;
+  if (sh >= 0) v = (__int128)m << (sh < 74 ? sh : 74);
+  else v = sh > -53 ? (__int128)(m >> -sh) : (__int128)0;
+  return (bits >> 63) ? -v : v;
+}
+
+// Sum of a 128-bit integer over the 64 lanes of a wave (every lane gets it).
+__device__ __forceinline__ __int128 wave_sum128(__int128 x) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    const unsigned long long lo = (unsigned long long)x, hi = (unsigned long long)(x >> 64);
+    const unsigned long long ol = __shfl_xor(lo, d, 64), oh = __shfl_xor(hi, d, 64);
+    x += (__int128)(((unsigned __int128)oh << 64) | ol);
+  }
+  return x;
+}
+
+// Adds a 128-bit integer to four limb accumulators (two's complement limbs;
+// the sum is taken modulo 2^128 when read, which is exact for any true sum
+// below 2^127 in magnitude).
+__device__ __forceinline__ void limbs_add(unsigned long long* acc, __int128 v) {
+  if (v == 0) return;
+  const unsigned __int128 u = (unsigned __int128)v;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const unsigned long long l = (unsigned long long)(u >> (32 * k)) & 0xFFFFFFFFull;
+    if (l) __hip_atomic_fetch_add(acc + k, l, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+constexpr int kWideLimbs = 8;   // 256 bits
+constexpr int kWideLow = 192;   // grid 2^-192
+
+// Adds |t| (finite, below 2^63) on the grid 2^-192 to kWideLimbs limb
+// accumulators: the 53-bit significand lands in at most three 32-bit limbs.
+__device__ __forceinline__ void wide_add(unsigned long long* acc, double t) {
+  const unsigned long long bits = (unsigned long long)__double_as_longlong(t);
+  const int e = (int)((bits >> 52) & 0x7FF);
+  if (e == 0 || e == 0x7FF) return;
+  unsigned long long m = (bits & 0xFFFFFFFFFFFFFull) | (1ull << 52);
+  int pos = e - 1075 + kWideLow;  // bit index of the significand's lowest bit
+  if (pos < 0) {
+    if (pos <= -53) return;
+    m >>= -pos;
+    pos = 0;
+  }
+  const int k = pos >> 5;
+  const unsigned __int128 v = (unsigned __int128)m << (pos & 31);
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const unsigned long long l = (unsigned long long)(v >> (32 * q)) & 0xFFFFFFFFull;
+    if (l && k + q < kWideLimbs)
+      __hip_atomic_fetch_add(acc + k + q, l, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// Value of kWideLimbs limb accumulators.  Limb k holds h_k 2^32 + l_k, so
+// position j (weight 2^(32 j - 192)) collects l_j + h_(j-1), below 2^33 and
+// exact in binary64; the positions are summed from the most significant
+// down, a fixed sequence of roundings.
+__device__ __forceinline__ double wide_value(const unsigned long long* acc) {
+  double v = 0.0;
+#pragma unroll
+  for (int j = kWideLimbs; j >= 0; --j) {
+    const unsigned long long lo = j < kWideLimbs ? (acc[j] & 0xFFFFFFFFull) : 0ull;
+    const unsigned long long hi = j > 0 ? (acc[j - 1] >> 32) : 0ull;
+    v += ldexp((double)(lo + hi), 32 * j - kWideLow);
+  }
+  return v;
+}
+
+// Value of four limb accumulators: the 128-bit sum times 2^-64.
+__device__ __forceinline__ double limbs_value(const unsigned long long* acc) {
+  unsigned __int128 s = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) s += (unsigned __int128)acc[k] << (32 * k);
+  const __int128 v = (__int128)s;
+  const long long hi = (long long)(v >> 64);
+  const unsigned long long lo = (unsigned long long)v;
+  return ((double)hi * 0x1p64 + (double)lo) * 0x1p-64;
 }
 
 // ---------------------------------------------------------- wave helpers
@@ -232,20 +352,38 @@ __device__ __forceinline__ int find_gap(const long long* __restrict__ start, int
   return lo;
 }
 
-// Contiguous share of `total` work items for this workgroup, with the
-// workgroup index remapped so that each of the 8 XCDs (which receive
-// workgroups round-robin) walks one contiguous eighth of the items and keeps
-// the field lines of its cells in its own L2.
+// Contiguous share of `total` work items for each workgroup.  Workgroups
+// reach the 8 XCDs round-robin (workgroup b runs on XCD b % 8), so the items
+// are first cut into 8 consecutive eighths, one per XCD, and each XCD's
+// workgroups split its eighth: the field lines of an XCD's cells stay in its
+// own L2, and every XCD has work however few items there are.  The logical
+// index of workgroup b (xcd_logical) orders the shares by item: share lb
+// starts where share lb - 1 ends.
 __device__ __forceinline__ int xcd_logical(int b, int nb) {
   return (nb & 7) == 0 ? (b & 7) * (nb >> 3) + (b >> 3) : b;
 }
 
+// Items [w0, w1) of logical share lb of nb.
+__device__ __forceinline__ void share_range(long long total, int lb, int nb, long long& w0,
+                                            long long& w1) {
+  if ((nb & 7) != 0) {
+    const long long per = (total + nb - 1) / nb;
+    w0 = (long long)lb * per;
+    w0 = w0 < total ? w0 : total;
+    w1 = w0 + per < total ? w0 + per : total;
+    return;
+  }
+  const int x = lb / (nb >> 3), r = lb % (nb >> 3);
+  const long long t0 = total * x / 8, t1 = total * (x + 1) / 8;
+  const long long per = (t1 - t0 + (nb >> 3) - 1) / (nb >> 3);
+  w0 = t0 + (long long)r * per;
+  w0 = w0 < t1 ? w0 : t1;
+  w1 = w0 + per < t1 ? w0 + per : t1;
+}
+
 __device__ __forceinline__ void xcd_range(long long total, long long& w0, long long& w1,
                                           int b, int nb) {
-  const int lb = xcd_logical(b, nb);
-  long long per = (total + nb - 1) / nb;
-  w0 = (long long)lb * per;
-  w1 = w0 + per < total ? w0 + per : total;
+  share_range(total, xcd_logical(b, nb), nb, w0, w1);
 }
 
 __device__ __forceinline__ void xcd_range(long long total, long long& w0, long long& w1) {

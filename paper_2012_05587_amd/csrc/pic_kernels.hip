@@ -98,37 +98,40 @@ __device__ __forceinline__ void block_minmax_pp(int& mn, int& mx, int (*s_red)[8
 }
 
 // ------------------------------------------------------------------ push
-// Sums of one workgroup over the work items of one gap, flushed with one
-// atomic each when the workgroup moves to another gap or finishes.
-struct PushTally {
-  double ke, lost;
-  unsigned long long absorbed[2];
-};
-
-__device__ __forceinline__ void flush_tally(double* __restrict__ stripes, int g, PushTally& t,
-                                            bool diag, double* s_d, unsigned long long* s_u) {
-  const double ke = wave_sum(t.ke), lost = wave_sum(t.lost);
-  const unsigned long long a0 = wave_sum(t.absorbed[0]), a1 = wave_sum(t.absorbed[1]);
+// Sums of one workgroup over the work items of one gap, flushed to the
+// gap's stripes when the workgroup moves to another gap or finishes.  The
+// energies are exact integer sums of terms on the 2^-64 grid (fix64), so
+// they do not depend on which slots the leptons occupy.  The kinetic energy
+// is summed in each thread's registers; absorbed leptons are rare, so their
+// count and lost energy go to LDS with atomics (s_abs[0..1] counts, s_abs[2..5]
+// the limbs of the lost energy).
+__device__ __forceinline__ void flush_tally(unsigned long long* __restrict__ stripes, int g,
+                                            __int128& ke_t, bool diag, __int128* s_e,
+                                            unsigned long long* s_abs) {
+  const __int128 ke = wave_sum128(ke_t);
   const int w = threadIdx.x >> 6;
   __syncthreads();
-  if (lane_id() == 0) {
-    s_d[w] = ke; s_d[4 + w] = lost;
-    s_u[w] = a0; s_u[4 + w] = a1;
-  }
+  if (lane_id() == 0) s_e[w] = ke;
   __syncthreads();
   if (threadIdx.x == 0) {
-    const double k = (s_d[0] + s_d[1]) + (s_d[2] + s_d[3]);
-    const double l = (s_d[4] + s_d[5]) + (s_d[6] + s_d[7]);
-    const unsigned long long b0 = s_u[0] + s_u[1] + s_u[2] + s_u[3];
-    const unsigned long long b1 = s_u[4] + s_u[5] + s_u[6] + s_u[7];
+    const __int128 k = (s_e[0] + s_e[1]) + (s_e[2] + s_e[3]);
     const int st = blockIdx.x & (kStripes - 1);
-    if (diag && k != 0.0) atomicAdd(stripe_slot(stripes, g, 0, st), k);
-    if (l != 0.0) atomicAdd(stripe_slot(stripes, g, 1, st), l);
-    if (b0) atomicAdd((unsigned long long*)stripe_slot(stripes, g, 2, st), b0);
-    if (b1) atomicAdd((unsigned long long*)stripe_slot(stripes, g, 3, st), b1);
+    if (diag) limbs_add(stripe_slot(stripes, g, 0, st), k);
+    unsigned long long* lost = stripe_slot(stripes, g, 1, st);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (s_abs[2 + q]) atomicAdd(lost + q, s_abs[2 + q]);
+    if (s_abs[0]) atomicAdd(stripe_slot(stripes, g, 2, st), s_abs[0]);
+    if (s_abs[1]) atomicAdd(stripe_slot(stripes, g, 3, st), s_abs[1]);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) s_abs[q] = 0;
   }
-  t.ke = 0.0; t.lost = 0.0; t.absorbed[0] = 0; t.absorbed[1] = 0;
+  ke_t = 0;
 }
+
+// Lorentz factor of a lepton of momentum p (the stored value, binary32 in
+// mixed precision) for the diagnostics: sqrt(1 + p^2) in binary64.
+__device__ __forceinline__ double lepton_gamma64(double p) { return sqrt(1.0 + p * p); }
 
 // E at the cells left of, at and right of cell cl (a dead slot reads cell 0),
 // with the boundary ghosts of the gather.  The binary32 push reads the
@@ -258,18 +261,18 @@ __device__ __forceinline__ void push_item(long long local, long long chunks0, lo
 // the quadratic-spline shape; batches without them run the
 // kernel without that code.
 template <typename T, bool kSpread, bool kSpline>
-__global__ __launch_bounds__(kBlock, PushCfg<T>::waves) void k_push(GapDev* __restrict__ gaps,
+__global__ __launch_bounds__(kBlock, kSpread ? PushCfg<T>::spread_waves : PushCfg<T>::waves) void k_push(GapDev* __restrict__ gaps,
                                                  const long long* __restrict__ wi, int B,
                                                  int32_t* __restrict__ emit_cnt,
                                                  uint32_t* __restrict__ emit_ent,
                                                  uint32_t* __restrict__ wg_emit,
-                                                 double* __restrict__ stripes) {
+                                                 unsigned long long* __restrict__ stripes) {
   using I = typename Fixed<T>::I;
   __shared__ long long s_flux[kTile];
   __shared__ uint32_t s_emit[kChunk];  // chunk-local index << 8 | k
   __shared__ int s_red[2][8];
-  __shared__ double s_d[8];
-  __shared__ unsigned long long s_u[8];
+  __shared__ __int128 s_e[4];
+  __shared__ unsigned long long s_abs[6];
   __shared__ int s_emit_n;
   // leptons of the chunk that need their own threshold, and the thresholds
   __shared__ uint32_t s_cand[kSpread ? kChunk : 1];
@@ -279,6 +282,7 @@ __global__ __launch_bounds__(kBlock, PushCfg<T>::waves) void k_push(GapDev* __re
   // the flux tile is kept zero between chunks (each flush clears what it
   // read), so it is zeroed once here
   for (int k = threadIdx.x; k < kTile; k += kBlock) s_flux[k] = 0;
+  if (threadIdx.x < 6) s_abs[threadIdx.x] = 0;
   __syncthreads();
   int parity = 0;
 
@@ -287,7 +291,7 @@ __global__ __launch_bounds__(kBlock, PushCfg<T>::waves) void k_push(GapDev* __re
   xcd_range(total, w0, w1);
   const int tid = threadIdx.x;
   const int lane = lane_id();
-  PushTally tally = {0.0, 0.0, {0, 0}};
+  __int128 ke_t = 0;  // this thread's kinetic energy terms (diagnosed steps)
   uint32_t my_emitters = 0;  // emitters listed by this workgroup (thread 0)
 
   // constants of the current gap
@@ -301,7 +305,7 @@ __global__ __launch_bounds__(kBlock, PushCfg<T>::waves) void k_push(GapDev* __re
   gptr<unsigned long long> F = nullptr;
   I ONE = 0;
   T scale = 0, inv_scale = 0, dt_t = 0, dtdx = 0, gthr = 0, gpair = 0, thr_lo = 0;
-  double w_d = 0.0, sigma = 0.0, gthr64 = 0.0;
+  double sigma = 0.0, gthr64 = 0.0;
   int Kb = 0;  // offset grid bits (the spline's weights)
   uint64_t kseed = 0;
   gptr<uint64_t> idS[2] = {nullptr, nullptr};
@@ -314,7 +318,7 @@ __global__ __launch_bounds__(kBlock, PushCfg<T>::waves) void k_push(GapDev* __re
 
   for (long long w = w0; w < w1; ++w) {
     if (w >= gend) {  // uniform: the first chunk of another gap
-      if (g >= 0) flush_tally(stripes, g, tally, diag, s_d, s_u);
+      if (g >= 0) flush_tally(stripes, g, ke_t, diag, s_e, s_abs);
       g = find_gap(wi, B, w);
       G = gaps + g;
       gbeg = wi[g];
@@ -342,7 +346,6 @@ __global__ __launch_bounds__(kBlock, PushCfg<T>::waves) void k_push(GapDev* __re
       dtdx = (T)G->dtdx;
       gthr = (T)G->gthr;
       gpair = (T)G->gpair;
-      w_d = G->weight;
       if constexpr (kSpline) Kb = G->K;
       if constexpr (kSpread) {
         sigma = G->sigma;
@@ -599,22 +602,27 @@ __global__ __launch_bounds__(kBlock, PushCfg<T>::waves) void k_push(GapDev* __re
             ++k;
           }
           if (k > kMaxEmit) { emit_bad = true; k = 0; }
-          T gnew = gam;
           if (k > 0) {
+            // the recoil keeps the direction: the stored momentum's sign bit
+            // is the emitter's direction even when its magnitude is zero
             const T mag = sqrt(gm * gm - one_t);
             pn = pn > (T)0 ? mag : -mag;
-            gnew = sqrt(one_t + pn * pn);
             const int pos = atomicAdd(&s_emit_n, 1);
             s_emit[pos] = ((uint32_t)(i - i0) << 8) | (uint32_t)k;
           }
           __builtin_nontemporal_store(pn, &pA[i]);
           __builtin_nontemporal_store((T)nq * inv_scale, &offA[i]);
           if (c2 != c) __builtin_nontemporal_store(c2, &cellA[i]);
-          // energy: the Lorentz factor in the particle precision, summed in binary64
-          if (diag) tally.ke += w_d * (double)gnew;
+          // energy diagnostics in binary64 from the stored momentum
+          if (diag) ke_t += fix64(lepton_gamma64((double)pn));
         } else {
-          tally.lost += w_d * (double)gam;
-          tally.absorbed[s] += 1;
+          const unsigned __int128 u = (unsigned __int128)fix64(lepton_gamma64((double)pn));
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const unsigned long long l = (unsigned long long)(u >> (32 * q)) & 0xFFFFFFFFull;
+            if (l) atomicAdd(&s_abs[2 + q], l);
+          }
+          atomicAdd(&s_abs[s], 1ull);
           pA[i] = pn;
           cellA[i] = kDead;
         }
@@ -658,7 +666,7 @@ __global__ __launch_bounds__(kBlock, PushCfg<T>::waves) void k_push(GapDev* __re
     }
     have = pre;
   }
-  if (g >= 0) flush_tally(stripes, g, tally, diag, s_d, s_u);
+  if (g >= 0) flush_tally(stripes, g, ke_t, diag, s_e, s_abs);
   // emitters of this workgroup's chunk range, indexed in chunk order
   if (tid == 0) wg_emit[xcd_logical((int)blockIdx.x, (int)gridDim.x)] = my_emitters;
 }
@@ -695,11 +703,13 @@ __device__ __forceinline__ unsigned long long lanes_below() {
 }
 
 // Pairs of a step share one slot cursor: the workgroup reserves `tot` pairs
-// (electron slots from n[0], positron slots from n[1]).
+// (electron slots from n[0], positron slots from n[1]).  Appends beyond the
+// slots are not written and freeze the gap; the capacity itself (live
+// leptons) is checked by the finalize.
 __device__ __forceinline__ unsigned long long reserve_pairs(GapDev* G, unsigned long long tot) {
   const unsigned long long b = atomicAdd(&G->pair_next, tot);
-  const unsigned long long cap = (unsigned long long)G->cap;
-  if (G->n[0] + b + tot > cap || G->n[1] + b + tot > cap) G->overflow = 1;
+  const unsigned long long slots = (unsigned long long)G->slots;
+  if (G->n[0] + b + tot > slots || G->n[1] + b + tot > slots) G->slot_overflow = 1;
   return b;
 }
 
@@ -736,14 +746,16 @@ __device__ __forceinline__ unsigned emit_one(GapDev* __restrict__ G, int s, long
   const uint64_t id = G->id[buf][s][i];
   const uint64_t stepn = (uint64_t)G->step;
   const uint64_t seed = G->seed;
-  const int dir = pv > (T)0 ? 1 : -1;
+  // the direction of the emitter before its recoil: the push stores +|p| or
+  // -|p|, so the sign bit holds it also when the recoil leaves |p| = 0
+  const int dir = signbit(pv) ? -1 : 1;
   unsigned esc = 0;
   if (in_place) {
     // pair made in place (the paper's zero mean free path)
     const T pchild = (T)G->pchild;
     const T pc = dir > 0 ? pchild : -pchild;
     const T offn = (T)oq * ((T)1 / scale);
-    const unsigned long long cap = (unsigned long long)G->cap;
+    const unsigned long long cap = (unsigned long long)G->slots;
     const unsigned long long ne0 = G->n[0], ne1 = G->n[1];
     for (int jj = 0; jj < k; ++jj) {
       const U64x4 u = philox4x64_10(stepn, (uint64_t)jj, kTagPhoton, 0, id, seed);
@@ -895,8 +907,8 @@ __device__ void emit_role(GapDev* __restrict__ gaps, const long long* __restrict
     const int mid = (a + b + 1) >> 1;
     if (s_pre[mid] <= q0) a = mid; else b = mid - 1;
   }
-  const long long per = (total + kPushGrid - 1) / kPushGrid;
-  long long x = (long long)a * per;
+  long long x, xa_end;
+  share_range(total, a, kPushGrid, x, xa_end);
   unsigned long long Q = s_pre[a];
   gptr<const uint32_t> cntA = glb<const uint32_t>((void*)emit_cnt);
   gptr<const uint32_t> entA = glb<const uint32_t>((void*)emit_ent);
@@ -958,14 +970,17 @@ __device__ void field_role(GapDev* __restrict__ gaps, const long long* __restric
     fe += e * e * dxh * 0.5;
     es += e;
   }
+  // the chunk's partial sums in a fixed order (cells are fixed to threads),
+  // then added exactly across chunks
   fe = wave_sum(fe);
   es = wave_sum(es);
   const int w = threadIdx.x >> 6;
   if (lane_id() == 0) { s_red[w] = fe; s_red[4 + w] = es; }
   __syncthreads();
   if (threadIdx.x == 0) {
-    atomicAdd(&G->fe_acc, (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]));
-    atomicAdd(&G->es_acc, (s_red[4] + s_red[5]) + (s_red[6] + s_red[7]));
+    wide_add(G->fe_wide, (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]));
+    const double esum = (s_red[4] + s_red[5]) + (s_red[6] + s_red[7]);
+    wide_add(esum >= 0.0 ? G->esp_wide : G->esn_wide, esum);
   }
 }
 
@@ -985,10 +1000,10 @@ __device__ __forceinline__ void photon_ranges(const GapDev* G, long long& b0, lo
   t1 = (long long)G->n_ph;
 }
 
-__device__ __forceinline__ void convert_item(const GapDev* G, long long local, long long& i0,
-                                             long long& i1) {
-  long long b0, b1, t0, t1;
-  photon_ranges(G, b0, b1, t0, t1);
+// Photons [i0, i1) of due-photon item `local` of a gap whose due ranges are
+// [b0, b1) (sorted body) and [t0, t1) (unsorted tail).
+__device__ __forceinline__ void convert_item(long long b0, long long b1, long long t0, long long t1,
+                                             long long local, long long& i0, long long& i1) {
   const long long nb = (b1 - b0 + kPhChunk - 1) / kPhChunk;
   if (local < nb) {
     i0 = b0 + local * kPhChunk;
@@ -1006,6 +1021,7 @@ __device__ void convert_role(GapDev* __restrict__ gaps, const long long* __restr
   // An item holds kPhChunk = 16 runs of 64 photons; wave v takes runs v, v + 4, v + 8, v + 12.
   constexpr int kWaves = kBlock / 64;
   constexpr int kRuns = kPhChunk / 64 / kWaves;
+  constexpr int kConvGroup = 4;  // items whose keys are held at once
   const int lane = lane_id();
   const int v = threadIdx.x >> 6;
   const long long total = pwi[B];
@@ -1018,65 +1034,77 @@ __device__ void convert_role(GapDev* __restrict__ gaps, const long long* __restr
     if (G->status != PIC_OK) { w = wend; continue; }
     const int pb = G->phbuf, buf = G->buf;
     const int stepn = (int)G->step;
+    const long long wg0 = pwi[g];
+    long long rb0, rb1, rt0, rt1;  // the gap's due ranges, read once
+    photon_ranges(G, rb0, rb1, rt0, rt1);
     gptr<const int32_t> phs = glb<const int32_t>((void*)G->ph_step[pb]);
-    // pass 1: due photons of this wave's runs
-    unsigned long long cnt = 0;
-    for (long long x = w; x < wend; ++x) {
-      long long i0, i1;
-      convert_item(G, x - pwi[g], i0, i1);
-      int st[kRuns];
-#pragma unroll
-      for (int t = 0; t < kRuns; ++t) {
-        const long long i = i0 + (long long)(v + kWaves * t) * 64 + lane;
-        st[t] = i < i1 ? phs[i] : INT32_MIN;
-      }
-#pragma unroll
-      for (int t = 0; t < kRuns; ++t) cnt += st[t] == stepn ? 1u : 0u;
-    }
-    cnt = wave_sum(cnt);
-    __syncthreads();  // s_wave and s_base of the previous gap are consumed
-    if (lane == 0) s_wave[v] = cnt;
-    __syncthreads();
-    unsigned long long pre;
-    const unsigned long long tot = wave_shares(s_wave, pre);
-    if (tot == 0) { w = wend; continue; }
-    if (threadIdx.x == 0) s_base[0] = reserve_pairs(G, tot);
-    __syncthreads();
-    const unsigned long long base = s_base[0] + pre;
     const unsigned long long ne0 = G->n[0], ne1 = G->n[1];
-    const unsigned long long cap = (unsigned long long)G->cap;
+    const unsigned long long cap = (unsigned long long)G->slots;
     const long long ONE = G->one;
     const T inv_scale = (T)(1.0 / (double)ONE);
     const T pchild = (T)G->pchild;
-    unsigned long long run = 0;
-    // pass 2: the same runs in the same order; ballots give the slots
-    for (long long x = w; x < wend; ++x) {
-      long long i0, i1;
-      convert_item(G, x - pwi[g], i0, i1);
+    const bool evmap = G->evmap != nullptr;
+    // Groups of kConvGroup items: every key of the group is requested at
+    // once and kept in registers; the due photons are counted with ballots,
+    // the workgroup reserves their pair slots with one atomic, and the same
+    // ballots give each due photon its slot.
+    for (long long x = w; x < wend; x += kConvGroup) {
+      int st[kConvGroup][kRuns];
 #pragma unroll
-      for (int t = 0; t < kRuns; ++t) {
-        const long long i = i0 + (long long)(v + kWaves * t) * 64 + lane;
-        const bool due = i < i1 && phs[i] == stepn;
-        const unsigned long long m = __ballot(due);
-        const unsigned long long ex = run + (unsigned long long)__popcll(m & lanes_below());
-        run += (unsigned long long)__popcll(m);
-        if (!due) continue;
-        const long long X = G->ph_x[pb][i];
-        const uint64_t ch = G->ph_child[pb][i];
-        const int c = (int)(X / ONE);
-        const T offn = (T)(X % ONE) * inv_scale;
-        const T pc = (ch & 1u) ? pchild : -pchild;
-        const uint64_t child = ch & ~(uint64_t)1;
-        const unsigned long long se = ne0 + base + ex, sp = ne1 + base + ex;
-        if (se < cap) {
-          G->cell[buf][0][se] = c; ((T*)G->off[buf][0])[se] = offn;
-          ((T*)G->p[buf][0])[se] = pc; G->id[buf][0][se] = child;
+      for (int it = 0; it < kConvGroup; ++it) {
+        long long i0 = 0, i1 = 0;
+        if (x + it < wend) convert_item(rb0, rb1, rt0, rt1, x + it - wg0, i0, i1);
+#pragma unroll
+        for (int t = 0; t < kRuns; ++t) {
+          const long long i = i0 + (long long)(v + kWaves * t) * 64 + lane;
+          st[it][t] = i < i1 ? phs[i] : INT32_MIN;
         }
-        if (sp < cap) {
-          G->cell[buf][1][sp] = c; ((T*)G->off[buf][1])[sp] = offn;
-          ((T*)G->p[buf][1])[sp] = pc; G->id[buf][1][sp] = child | 1u;
+      }
+      unsigned long long cnt = 0;
+#pragma unroll
+      for (int it = 0; it < kConvGroup; ++it)
+#pragma unroll
+        for (int t = 0; t < kRuns; ++t) cnt += (unsigned long long)__popcll(__ballot(st[it][t] == stepn));
+      __syncthreads();  // s_wave and s_base of the previous group are consumed
+      if (lane == 0) s_wave[v] = cnt;
+      __syncthreads();
+      unsigned long long pre;
+      const unsigned long long tot = wave_shares(s_wave, pre);
+      if (tot == 0) continue;  // uniform
+      if (threadIdx.x == 0) s_base[0] = reserve_pairs(G, tot);
+      __syncthreads();
+      const unsigned long long base = s_base[0] + pre;
+      unsigned long long run = 0;
+#pragma unroll
+      for (int it = 0; it < kConvGroup; ++it) {
+        long long i0 = 0, i1 = 0;
+        if (x + it < wend) convert_item(rb0, rb1, rt0, rt1, x + it - wg0, i0, i1);
+#pragma unroll
+        for (int t = 0; t < kRuns; ++t) {
+          const bool due = st[it][t] == stepn;
+          const unsigned long long m = __ballot(due);
+          if (m == 0) continue;  // uniform
+          const unsigned long long ex = run + (unsigned long long)__popcll(m & lanes_below());
+          run += (unsigned long long)__popcll(m);
+          if (!due) continue;
+          const long long i = i0 + (long long)(v + kWaves * t) * 64 + lane;
+          const long long X = G->ph_x[pb][i];
+          const uint64_t ch = G->ph_child[pb][i];
+          const int c = (int)(X / ONE);
+          const T offn = (T)(X % ONE) * inv_scale;
+          const T pc = (ch & 1u) ? pchild : -pchild;
+          const uint64_t child = ch & ~(uint64_t)1;
+          const unsigned long long se = ne0 + base + ex, sp = ne1 + base + ex;
+          if (se < cap) {
+            G->cell[buf][0][se] = c; ((T*)G->off[buf][0])[se] = offn;
+            ((T*)G->p[buf][0])[se] = pc; G->id[buf][0][se] = child;
+          }
+          if (sp < cap) {
+            G->cell[buf][1][sp] = c; ((T*)G->off[buf][1])[sp] = offn;
+            ((T*)G->p[buf][1])[sp] = pc; G->id[buf][1][sp] = child | 1u;
+          }
+          if (evmap) count_pairs(G, (long long)stepn, c, 1ull);
         }
-        if (G->evmap) count_pairs(G, (long long)stepn, c, 1ull);
       }
     }
     w = wend;
@@ -1215,6 +1243,7 @@ __global__ __launch_bounds__(1024) void k_plan(GapDev* __restrict__ gaps, int B,
 // out together.
 __device__ __forceinline__ PlanIn finalize_gap(GapDev* __restrict__ G) {
   const int status = G->status, nonfinite = G->nonfinite, overflow = G->overflow;
+  const int slot_overflow = G->slot_overflow;
   const int emit_err = G->emit_err, table_len = G->table_len, diag_every = G->diag_every;
   const int hist_rows = G->hist_rows, n_cells = G->n_cells;
   const unsigned long long pair_next = G->pair_next, esc_next = G->esc_next;
@@ -1228,12 +1257,12 @@ __device__ __forceinline__ PlanIn finalize_gap(GapDev* __restrict__ G) {
   const long long done = G->step, ph_base = G->ph_base;
   const int32_t* bucket = G->ph_bucket;
   const double weight = G->weight, gpair64 = G->gpair64, child_gamma64 = G->child_gamma64;
-  double ke = G->ke_acc, lost = G->lost_energy;
-  const double fe = G->fe_acc, es = G->es_acc;
-
-  G->ke_acc = 0.0;
-  G->fe_acc = 0.0;
-  G->es_acc = 0.0;
+  const unsigned long long cap = (unsigned long long)G->cap;
+  // energies: the weight times the exact sums of Lorentz factors
+  double ke = weight * G->ke_step;
+  const double lost_step = weight * G->lost_step;
+  const double fe = G->fe_step, es = G->es_step;
+  double lost = G->lost_energy;
   PlanIn out;
   out.ok = false;
   out.table_len = table_len;
@@ -1241,26 +1270,32 @@ __device__ __forceinline__ PlanIn finalize_gap(GapDev* __restrict__ G) {
   out.ph_base = ph_base;
   out.bucket = bucket;
   if (status != PIC_OK) return out;
-  const int st = nonfinite ? PIC_ERR_NONFINITE
-               : overflow  ? PIC_ERR_CAPACITY
-               : emit_err  ? PIC_ERR_EMISSION : PIC_OK;
+  // what this step appended: dp pairs (in place or converted), dph photons
+  // stored, de of which left the domain
+  const unsigned long long dp = pair_next, dph = n_ph_next - n_ph, de = esc_next;
+  const unsigned long long nn0 = n0 + dp, nn1 = n1 + dp;
+  const unsigned long long nl0 = nn0 - dead0, nl1 = nn1 - dead1;
+  // the capacity bounds live leptons, as at the end of a step of the
+  // oracle; the slots (capacity plus the reserve absorbed leptons hold until
+  // the next re-sort) and the photon store bound what can be written
+  const int st = nonfinite              ? PIC_ERR_NONFINITE
+               : emit_err               ? PIC_ERR_EMISSION
+               : (nl0 > cap || nl1 > cap) ? PIC_ERR_CAPACITY
+               : overflow               ? PIC_ERR_CAPACITY
+               : slot_overflow          ? PIC_ERR_SLOTS : PIC_OK;
   if (st != PIC_OK) {
     G->status = st;
     return out;
   }
-  // what this step appended: dp pairs (in place or converted), dph photons
-  // stored, de of which left the domain
-  const unsigned long long dp = pair_next, dph = n_ph_next - n_ph, de = esc_next;
   const bool in_place = table_len == 0;
   const bool diag = done % diag_every == 0;
   const unsigned long long created = created0 + dp;
   const unsigned long long emitted = emitted0 + (in_place ? dp : dph);
   const unsigned long long escaped = escaped0 + de;
   const unsigned long long inflight = in_place ? inflight0 : inflight0 + dph - de - dp;
+  lost += lost_step;
   if (de) lost += (double)de * weight * gpair64;
   if (diag && dp) ke += (double)dp * 2.0 * weight * child_gamma64;
-  const unsigned long long nn0 = n0 + dp, nn1 = n1 + dp;
-  const unsigned long long nl0 = nn0 - dead0, nl1 = nn1 - dead1;
   G->pairs_created = created;
   G->photons_emitted = emitted;
   G->photons_escaped = escaped;
@@ -1303,9 +1338,38 @@ __device__ __forceinline__ PlanIn finalize_gap(GapDev* __restrict__ G) {
   return out;
 }
 
+// The order-independent sums of the step, turned into binary64 values in
+// the descriptor; the limbs are cleared for the next step.  A phase of its
+// own, so that the end of step below keeps its registers.
+__device__ __forceinline__ void diag_values(GapDev* __restrict__ G) {
+  const double ke = limbs_value(G->ke_limb);
+  const double lost = limbs_value(G->lost_limb);
+  const double fe = wide_value(G->fe_wide);
+  const double es = wide_value(G->esp_wide) - wide_value(G->esn_wide);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    G->ke_limb[k] = 0;
+    G->lost_limb[k] = 0;
+  }
+#pragma unroll
+  for (int k = 0; k < kWideLimbs; ++k) {
+    G->fe_wide[k] = 0;
+    G->esp_wide[k] = 0;
+    G->esn_wide[k] = 0;
+  }
+  G->ke_step = ke;
+  G->lost_step = lost;
+  G->fe_step = fe;
+  G->es_step = es;
+}
+
 __device__ void finalize_body(GapDev* __restrict__ gaps, int B, long long* __restrict__ wi,
                               long long* __restrict__ pwi, long long* __restrict__ qwi) {
   const int per = (B + (int)blockDim.x - 1) / (int)blockDim.x;
+  // each thread converts the sums of the gaps it ends below
+#pragma unroll 1
+  for (int g = threadIdx.x * per; g < (int)(threadIdx.x + 1) * per && g < B; ++g) diag_values(gaps + g);
+  __syncthreads();
   if (per <= kPlanPer) {
     // each thread ends its own gaps and plans them from the values in hand
     long long a[kPlanPer], b[kPlanPer], c[kPlanPer];
@@ -1328,33 +1392,35 @@ __device__ void finalize_body(GapDev* __restrict__ gaps, int B, long long* __res
 // (gap, accumulator) pair, clear them, and add the sum to the descriptor
 // with one atomic (accumulators 0-1 are binary64 energies, 2-3 counts of
 // absorbed electrons and positrons).
-__device__ void fold_role(GapDev* __restrict__ gaps, int B, double* __restrict__ stripes, int vb) {
+__device__ void fold_role(GapDev* __restrict__ gaps, int B, unsigned long long* __restrict__ stripes,
+                          int vb) {
   const int pair = vb * (kBlock / kStripes) + (int)threadIdx.x / kStripes;
   const int st = (int)threadIdx.x % kStripes;
-  unsigned long long bits = 0;
+  const int a = pair & 3;
+  const int nl = a < 2 ? 4 : 1;  // energy limbs, or one count
+  unsigned long long v[4] = {0, 0, 0, 0};
   if (pair < 4 * B) {
-    gptr<unsigned long long> slot = glb<unsigned long long>((void*)stripe_slot(stripes, pair >> 2, pair & 3, st));
-    bits = *slot;
-    *slot = 0ull;
+    gptr<unsigned long long> slot = glb<unsigned long long>((void*)stripe_slot(stripes, pair >> 2, a, st));
+    for (int k = 0; k < nl; ++k) {
+      v[k] = slot[k];
+      slot[k] = 0ull;
+    }
   }
-  double dv = __longlong_as_double((long long)bits);
-  unsigned long long uv = bits;
 #pragma unroll
-  for (int d = kStripes / 2; d >= 1; d >>= 1) {  // within each group of kStripes lanes
-    dv += __shfl_xor(dv, d, 64);
-    uv += __shfl_xor(uv, d, 64);
-  }
+  for (int d = kStripes / 2; d >= 1; d >>= 1)  // within each group of kStripes lanes
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] += __shfl_xor(v[k], d, 64);
   if (st != 0 || pair >= 4 * B) return;
   GapDev* __restrict__ G = gaps + (pair >> 2);
-  switch (pair & 3) {
-    case 0: if (dv != 0.0) atomicAdd(&G->ke_acc, dv); break;
-    case 1: if (dv != 0.0) atomicAdd(&G->lost_energy, dv); break;
-    default:
-      if (uv) {
-        const int s = (pair & 3) - 2;
-        atomicAdd(&G->absorbed[s], uv);
-        atomicAdd(&G->dead[s], uv);
-      }
+  if (a < 2) {
+    unsigned long long* acc = a == 0 ? G->ke_limb : G->lost_limb;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (v[k]) atomicAdd(acc + k, v[k]);
+  } else if (v[0]) {
+    const int s = a - 2;
+    atomicAdd(&G->absorbed[s], v[0]);
+    atomicAdd(&G->dead[s], v[0]);
   }
 }
 
@@ -1371,7 +1437,7 @@ __global__ __launch_bounds__(kBlock) void k_post(GapDev* __restrict__ gaps,
                                                  const int32_t* __restrict__ emit_cnt,
                                                  const uint32_t* __restrict__ emit_ent,
                                                  const uint32_t* __restrict__ wg_emit,
-                                                 double* __restrict__ stripes) {
+                                                 unsigned long long* __restrict__ stripes) {
   __shared__ double s_red[8];
   __shared__ unsigned long long s_wave[kBlock / 64];
   __shared__ unsigned long long s_base[1];

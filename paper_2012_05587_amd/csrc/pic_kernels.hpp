@@ -20,7 +20,7 @@ struct StepLaunch {
   int32_t* emit_cnt;   // emitters per chunk of the current plan (device)
   uint32_t* emit_ent;  // kChunk entries per chunk (device)
   uint32_t* wg_emit;   // emitters listed by each push workgroup, kPushGrid entries (device)
-  double* stripes;     // striped push tallies, B x 4 x kStripes x kStripeStride (device)
+  unsigned long long* stripes;  // striped push tallies, B x 4 x kStripes x kStripeStride (device)
   hipStream_t stream;
   bool spread;         // some gap draws per-lepton thresholds (gamma_thr_spread > 0)
   bool spline;         // the batch's leptons have the quadratic-spline shape

@@ -79,6 +79,10 @@ std::vector<uint32_t> build_table(const pic_gap_params& p) {
 
 int hist_rows_of(const pic_gap_params& p) { return p.history_rows > 0 ? p.history_rows : kDefaultHist; }
 
+// Lepton slots per species: the capacity (live leptons) plus a reserve for
+// the slots absorbed leptons hold until the next re-sort.
+int64_t slots_of(const pic_gap_params& p) { return p.capacity + p.capacity / 8 + 2048; }
+
 pic_status validate(const pic_gap_params* p) {
   if (!p) return PIC_ERR_ARG;
   if (p->n_cells < 2 || p->n_cells > (1 << 22)) return PIC_ERR_ARG;
@@ -99,7 +103,7 @@ pic_status validate(const pic_gap_params* p) {
   if (p->gamma_thr_spread > 0.0 && std::isfinite(p->gamma_thr) &&
       !((1.0 - p->f - p->gamma_thr_spread) * p->gamma_thr >= 1.0))
     return PIC_ERR_ARG;
-  if (p->capacity < 1 || p->capacity >= (int64_t)1 << 31) return PIC_ERR_ARG;
+  if (p->capacity < 1 || slots_of(*p) >= (int64_t)1 << 31) return PIC_ERR_ARG;
   if (p->photon_capacity < 0 || p->photon_capacity >= (int64_t)1 << 31) return PIC_ERR_ARG;
   if (p->l_gamma > 0.0 && p->photon_capacity < 1) return PIC_ERR_ARG;
   if (p->precision != PIC_FP64 && p->precision != PIC_MIXED) return PIC_ERR_ARG;
@@ -121,7 +125,7 @@ pic_status validate(const pic_gap_params* p) {
 // 32-bit, so a batch holds fewer than 2^32.
 bool batch_slots_ok(const pic_gap_params* prm, int B) {
   unsigned long long slots = 0;
-  for (int i = 0; i < B; ++i) slots += 2ull * (unsigned long long)prm[i].capacity;
+  for (int i = 0; i < B; ++i) slots += 2ull * (unsigned long long)slots_of(prm[i]);
   return slots < (1ull << 32);
 }
 
@@ -139,13 +143,13 @@ Layout make_layout(const pic_gap_params* prm, int B) {
   L.max_chunks = 0;
   L.max_ph_chunks = 0;
   for (int i = 0; i < B; ++i) {
-    L.max_chunks += 2 * ((prm[i].capacity + pic::kChunk - 1) / pic::kChunk);
+    L.max_chunks += 2 * ((slots_of(prm[i]) + pic::kChunk - 1) / pic::kChunk);
     L.max_ph_chunks += (prm[i].photon_capacity + pic::kPhChunk - 1) / pic::kPhChunk;
   }
   L.emit_cnt = o; o = align_up(o + sizeof(int32_t) * (size_t)L.max_chunks);
   L.emit_ent = o; o = align_up(o + sizeof(uint32_t) * (size_t)L.max_chunks * pic::kChunk);
   L.wg_emit = o; o = align_up(o + sizeof(uint32_t) * (size_t)pic::kPushGrid);
-  L.stripes = o; o = align_up(o + sizeof(double) * (size_t)B * 4 * pic::kStripes * pic::kStripeStride);
+  L.stripes = o; o = align_up(o + sizeof(unsigned long long) * (size_t)B * 4 * pic::kStripes * pic::kStripeStride);
   const int prec = prm[0].precision;
   const size_t tb = prec == PIC_MIXED ? 4 : 8;
   const int hist = hist_rows_of(prm[0]);
@@ -153,7 +157,7 @@ Layout make_layout(const pic_gap_params* prm, int B) {
   for (int i = 0; i < B; ++i) {
     const pic_gap_params& p = prm[i];
     GapLayout& G = L.g[(size_t)i];
-    const size_t nc = (size_t)p.n_cells, cap = (size_t)p.capacity, pc = (size_t)p.photon_capacity;
+    const size_t nc = (size_t)p.n_cells, cap = (size_t)slots_of(p), pc = (size_t)p.photon_capacity;
     G.E = o; o = align_up(o + 8 * nc);
     G.Ef = o; o = align_up(o + 4 * nc);
     G.F = o; o = align_up(o + 8 * nc);
@@ -196,7 +200,8 @@ void fill_precision_constants(GapDev& G, const pic_gap_params& p) {
   G.thr_lo = (double)(T)(p.gamma_thr * (1.0 + p.gamma_thr_spread * -1.0));
   G.gpair = (double)gpair;
   G.pchild = (double)pchild;
-  G.child_gamma64 = (double)std::sqrt((T)1 + pchild * pchild);
+  // a child's energy for the diagnostics, in binary64 from its momentum
+  G.child_gamma64 = std::sqrt(1.0 + (double)pchild * (double)pchild);
 }
 
 }  // namespace
@@ -262,6 +267,7 @@ struct pic_batch {
   pic::StepLaunch launch{};
   long long host_step = 0;
   bool started = false;
+  bool seed_sort = false;  // leptons were seeded since the last sort: sort them before stepping
   hipGraphExec_t graph = nullptr;
   hipGraph_t graph_tmpl = nullptr;
   bool graph_failed = false;
@@ -350,6 +356,7 @@ pic_status create_batch(const pic_gap_params* params, int n_gaps, void* d_ws, si
     G.domain = (int64_t)p.n_cells * G.one;
     G.photon_step = (int64_t)std::rint(std::ldexp(p.dt / p.dx, G.K));
     G.cap = p.capacity;
+    G.slots = slots_of(p);
     G.ph_cap = p.photon_capacity;
     G.dt = p.dt;
     G.dx = p.dx;
@@ -424,7 +431,7 @@ pic_status create_batch(const pic_gap_params* params, int n_gaps, void* d_ws, si
   b->launch.emit_cnt = reinterpret_cast<int32_t*>(ws + L.emit_cnt);
   b->launch.emit_ent = reinterpret_cast<uint32_t*>(ws + L.emit_ent);
   b->launch.wg_emit = reinterpret_cast<uint32_t*>(ws + L.wg_emit);
-  b->launch.stripes = reinterpret_cast<double*>(ws + L.stripes);
+  b->launch.stripes = reinterpret_cast<unsigned long long*>(ws + L.stripes);
   b->launch.stream = b->stream;
   b->launch.spline = params[0].shape == PIC_SHAPE_QUADRATIC;
   b->launch.spread = false;
@@ -434,8 +441,8 @@ pic_status create_batch(const pic_gap_params* params, int n_gaps, void* d_ws, si
   if (st == PIC_OK &&
       hipMemcpy(b->launch.cwi, cwi.data(), sizeof(long long) * cwi.size(), hipMemcpyHostToDevice) != hipSuccess)
     st = PIC_ERR_DEVICE;
-  const std::vector<double> zs((size_t)n_gaps * 4 * pic::kStripes * pic::kStripeStride, 0.0);
-  if (st == PIC_OK && hipMemcpy(b->launch.stripes, zs.data(), sizeof(double) * zs.size(),
+  const std::vector<unsigned long long> zs((size_t)n_gaps * 4 * pic::kStripes * pic::kStripeStride, 0ull);
+  if (st == PIC_OK && hipMemcpy(b->launch.stripes, zs.data(), sizeof(unsigned long long) * zs.size(),
                                 hipMemcpyHostToDevice) != hipSuccess)
     st = PIC_ERR_DEVICE;
   if (st == PIC_OK && pic::launch_plan(b->launch) != hipSuccess) st = PIC_ERR_DEVICE;
@@ -605,7 +612,44 @@ int tune_pick(Tuner& t, int& round) {
   return t.cur;
 }
 
+// The seed, written in the order it was drawn, is sorted by cell once before
+// the first step, so that its chunks deposit through the LDS tile from the
+// start (results do not depend on lepton order).
+pic_status sort_seed(pic_batch* b) {
+  if (!b->seed_sort) return PIC_OK;
+  if (pic::launch_sort(b->launch, b->precision == PIC_MIXED) != hipSuccess) return PIC_ERR_DEVICE;
+  b->seed_sort = false;
+  return PIC_OK;
+}
+
+// Captures (and uploads) every graph the step sequence can replay: the
+// candidate cadences of the tuner, or the one fixed cadence.
+pic_status prepare_graphs(pic_batch* b) {
+  if (b->stream == nullptr || b->profiling || b->graph_failed) return PIC_OK;
+  if (b->tune.on) {
+    for (int ci = 0; ci < kTuneN; ++ci) {
+      if (b->tgraph[ci]) continue;
+      if (!build_graph(b, kTuneCand[ci], &b->ttmpl[ci], &b->tgraph[ci])) {
+        b->graph_failed = true;
+        return PIC_OK;
+      }
+      if (hipGraphUpload(b->tgraph[ci], b->stream) != hipSuccess) return PIC_ERR_DEVICE;
+    }
+  } else if (!b->graph) {
+    if (!build_graph(b, b->sort_every, &b->graph_tmpl, &b->graph)) {
+      b->graph_failed = true;
+      return PIC_OK;
+    }
+    if (hipGraphUpload(b->graph, b->stream) != hipSuccess) return PIC_ERR_DEVICE;
+  }
+  return PIC_OK;
+}
+
 pic_status enqueue_steps(pic_batch* b, int64_t n_steps) {
+  if (n_steps > 0) {
+    const pic_status st = sort_seed(b);
+    if (st != PIC_OK) return st;
+  }
   // graphs need a capturable (non-null) stream and no per-launch events
   const bool graphs = b->stream != nullptr && !b->profiling && !b->graph_failed;
   Tuner& t = b->tune;
@@ -755,11 +799,15 @@ pic_status pic_seed_particles(pic_gap* g, int32_t mode, int64_t n_pairs, int32_t
   GapDev G;
   pic_status st = read_desc(b, g->idx, &G);
   if (st != PIC_OK) return st;
-  if ((long long)G.n[0] + N > G.cap || (long long)G.n[1] + N > G.cap) return PIC_ERR_CAPACITY;
+  // seed ids start at 0: a gap that already holds leptons would get
+  // duplicate ids, and with them shared random streams
+  if (G.n[0] != 0 || G.n[1] != 0) return PIC_ERR_STATE;
+  if (N > G.cap) return PIC_ERR_CAPACITY;
   if (N == 0) return PIC_OK;
   if (pic::launch_seed(dgaps(b), g->idx, mode, N, p0_minus, p0_plus, (long long)G.n[0],
                        (long long)G.n[1], b->precision == PIC_MIXED, b->stream) != hipSuccess)
     return PIC_ERR_DEVICE;
+  b->seed_sort = true;
   return append_counts(b, g->idx, N, N);
 }
 
@@ -801,6 +849,7 @@ pic_status pic_seed_explicit(pic_gap* g, int32_t species, int64_t n, const int32
     if (e == hipSuccess) e = hipMemcpy((double*)G.p[bb][species] + base, pp.data(), 8 * (size_t)n, hipMemcpyHostToDevice);
   }
   if (e != hipSuccess) return PIC_ERR_DEVICE;
+  b->seed_sort = true;
   return append_counts(b, g->idx, species == 0 ? n : 0, species == 1 ? n : 0);
 }
 
@@ -821,6 +870,20 @@ pic_status pic_step_n(pic_gap* g, int64_t n_steps, pic_step_report* out) {
     out->pushes = (int64_t)G.pushes;
   }
   return PIC_OK;
+}
+
+pic_status pic_batch_prepare(pic_batch* b) {
+  if (!b) return PIC_ERR_ARG;
+  if (b->started) return PIC_ERR_STATE;
+  pic_status st = sort_seed(b);
+  if (st == PIC_OK) st = prepare_graphs(b);
+  if (st != PIC_OK) return st;
+  return hipStreamSynchronize(b->stream) == hipSuccess ? PIC_OK : PIC_ERR_DEVICE;
+}
+
+pic_status pic_prepare(pic_gap* g) {
+  if (!g || !g->standalone) return PIC_ERR_ARG;
+  return pic_batch_prepare(g->b);
 }
 
 pic_status pic_batch_step_n(pic_batch* b, int64_t n_steps, pic_status* per_gap) {
@@ -1115,6 +1178,7 @@ const char* pic_status_string(pic_status s) {
     case PIC_ERR_STATE: return "invalid call order or frozen gap";
     case PIC_ERR_NONFINITE: return "non-finite momentum";
     case PIC_ERR_EMISSION: return "more than 64 emissions in one step";
+    case PIC_ERR_SLOTS: return "lepton slots held by absorbed leptons exhausted before the next re-sort";
     default: return "unknown status";
   }
 }

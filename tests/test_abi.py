@@ -134,8 +134,10 @@ def test_workspace_grows_with_capacity_and_precision():
     m = P.pic_workspace_bytes(pc.gpu_params(c, precision=workloads.MIXED))
     assert 0 < a < b and m < a
     # per-slot bytes: 2 buffers x 2 species x (4 + 8 + 8 + 8) in binary64, plus a
-    # 4-byte emission-list entry per species
-    assert abs((b - a) - (2 * 2 * 28 + 8) * c["capacity"]) <= 16 * 1024
+    # 4-byte emission-list entry per species; capacity + capacity/8 + 2048 slots
+    slots = lambda cap: cap + cap // 8 + 2048  # noqa: E731
+    extra = slots(2 * c["capacity"]) - slots(c["capacity"])
+    assert abs((b - a) - (2 * 2 * 28 + 8) * extra) <= 16 * 1024
 
 
 def test_batch_plan_admits_under_budget():
@@ -149,9 +151,13 @@ def test_batch_plan_admits_under_budget():
 
 
 def test_batch_slot_limit():
-    """A batch holds fewer than 2^32 lepton slots (both species)."""
+    """A batch holds fewer than 2^32 lepton slots (both species); a species
+    fewer than 2^31 (capacity + capacity/8 + 2048)."""
     import paper_2012_05587_amd as P
-    big = pc.gpu_params(_valid(), capacity=(1 << 31) - 1, photon_capacity=1)
+    cmax = ((1 << 31) - 1 - 2048) * 8 // 9
+    assert P.pic_validate_params(pc.gpu_params(_valid(), capacity=cmax, photon_capacity=1)) == P.OK
+    assert P.pic_validate_params(pc.gpu_params(_valid(), capacity=cmax + 8, photon_capacity=1)) == P.ERR_ARG
+    big = pc.gpu_params(_valid(), capacity=cmax, photon_capacity=1)
     two = (P.GapParams * 2)(big, big)
     assert P.lib().pic_batch_workspace_bytes(two, 2) == 0
     assert P.lib().pic_batch_workspace_bytes((P.GapParams * 1)(big), 1) > 0
@@ -171,7 +177,7 @@ def test_create_rejects_bad_workspace_without_device():
 
 def test_status_strings():
     import paper_2012_05587_amd as P
-    for st in (0, -1, -2, -3, -4, -5, -6, -7):
+    for st in (0, -1, -2, -3, -4, -5, -6, -7, -8):
         assert P.status_string(st)
     assert "unknown" in P.status_string(-99)
 

@@ -292,3 +292,40 @@ def test_energy_diagnostics_are_binary64_in_mixed_precision():
     ke32 = sum(0.75 * float(np.sqrt(np.float32(1) + np.float32(pv) * np.float32(pv)))
                for s in (0, 1) for pv in g.particles(s)["p"])
     assert abs(ke32 - ke) > 1e-11 * ke
+
+
+@pytest.mark.parametrize("precision,p_exact", [(oracle.MIXED, 3.872983455657959),
+                                                (oracle.FP64, 3.872983346207417)])
+@pytest.mark.parametrize("l_gamma", [0.0, 5.0])
+def test_emitter_left_at_rest_keeps_its_direction(precision, p_exact, l_gamma):
+    """(1 - f) gamma_thr = 1 exactly (gamma_thr = 4, f = 3/4): a lepton at
+    gamma = 4 emits once and is left with gamma = 1, |p| = 0.  Its pair (or
+    photon) still moves along the direction it had (section 2: the pair
+    energy leaves in the emitter's direction), and the emitter's stored
+    momentum keeps that sign (+0 or -0)."""
+    prm = dict(n_cells=32, dx=1.0, dt=0.45, boundary=oracle.PERIODIC, e0=0.0, gamma_thr=4.0,
+               f=0.75, l_gamma=l_gamma, weight=0.0, seed=17, precision=precision)
+    g = oracle.OracleGap(**prm)
+    for s in (0, 1):
+        g.seed_explicit(s, [5, 9], [0.25, 0.75], [p_exact, -p_exact], [10 + s, 20 + s])
+    assert g.step(1) == oracle.OK
+    for s in (0, 1):
+        P = g.particles(s)
+        for i, want in ((10 + s, 1.0), (20 + s, -1.0)):
+            k = int(np.nonzero(P["id"] == i)[0][0])
+            assert P["p"][k] == 0.0 and math.copysign(1.0, P["p"][k]) == want
+    if l_gamma == 0.0:
+        kids = [g.particles(s) for s in (0, 1)]
+        moving = np.concatenate([k["p"][~np.isin(k["id"], [10, 11, 20, 21])] for k in kids])
+        cells = np.concatenate([k["cell"][~np.isin(k["id"], [10, 11, 20, 21])] for k in kids])
+        assert len(moving) == 8
+        # children at the emitter's cell, moving the emitter's way
+        assert np.all(moving[cells == 5] > 0) and np.all(moving[cells == 9] < 0)
+    else:
+        ph = g.photons()
+        assert len(ph["dir"]) == 4
+        start = ph["xq"] - ph["dir"] * (ph["conv_step"] - 0) * round(0.45 * 2**g.offset_bits)
+        assert sorted(ph["dir"].tolist()) == [-1, -1, 1, 1]
+        # each photon started at its emitter's position
+        cell0 = (start // 2**g.offset_bits) % 32
+        assert np.all((cell0 == 5) == (ph["dir"] == 1))
