@@ -253,6 +253,19 @@ pic_status pic_step_n(pic_gap* g, int64_t n_steps, pic_step_report* out);
  * so that E_c - E_{c-1} = rho_c) into host buffers.  Either may be NULL. */
 pic_status pic_read_fields(pic_gap* g, double* E, double* rho, int32_t n_cells);
 
+/* For callers that cannot allocate memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): pic_read_fields
+ * computing rho in a static device array of (2^20 + 1) int64 node
+ * accumulators, one per GPU, held from the first call on that GPU until the
+ * process ends, instead of the workspace's.  Same arguments and results
+ * (rho bit for bit), except that a gap of more than 2^20 cells gets
+ * PIC_ERR_ARG when rho is requested.  Allocates no device or host memory:
+ * the accumulators are copied into rho itself and converted in place.  The
+ * array is cleared by a fill kernel at the start of each call; calls that
+ * overlap on one GPU (several threads or streams) race on it and must be
+ * serialised by the caller. */
+pic_status pic_read_fields_noalloc(pic_gap* g, double* E, double* rho, int32_t n_cells);
+
 /* Copies the flux sum q*w*(offset change) of the last step per cell, in
  * int64 units of w * 2^-K (K = 40 binary64, 24 mixed), into n_cells values. */
 pic_status pic_read_flux(pic_gap* g, int64_t* flux, int32_t n_cells);

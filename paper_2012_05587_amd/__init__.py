@@ -34,6 +34,7 @@ EXPORTS = [
     "pic_batch_size", "pic_destroy_batch", "pic_profile_push", "pic_read_push_time",
     "pic_batch_profile_push", "pic_batch_read_push_time", "pic_batch_tuning", "pic_tuning",
     "pic_phase_space", "pic_event_map", "pic_prepare", "pic_batch_prepare",
+    "pic_read_fields_noalloc",
 ]
 
 
@@ -108,6 +109,7 @@ def lib():
     L.pic_prepare.argtypes = [vp]; L.pic_prepare.restype = i32
     L.pic_batch_prepare.argtypes = [vp]; L.pic_batch_prepare.restype = i32
     L.pic_read_fields.argtypes = [vp, vp, vp, i32]; L.pic_read_fields.restype = i32
+    L.pic_read_fields_noalloc.argtypes = [vp, vp, vp, i32]; L.pic_read_fields_noalloc.restype = i32
     L.pic_read_flux.argtypes = [vp, vp, i32]; L.pic_read_flux.restype = i32
     L.pic_read_moments.argtypes = [vp, P(Moments)]; L.pic_read_moments.restype = i32
     L.pic_read_history.argtypes = [vp, vp, i64, P(i64)]; L.pic_read_history.restype = i32

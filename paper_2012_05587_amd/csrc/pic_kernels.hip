@@ -26,6 +26,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "pic_device.hpp"
 #include "pic_kernels.hpp"
 
@@ -1948,7 +1950,8 @@ __global__ __launch_bounds__(kBlock) void k_seed(GapDev* __restrict__ gaps, int 
 
 // ------------------------------------------------------------- rho (diag)
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_rho(GapDev* __restrict__ gaps, int g) {
+__global__ __launch_bounds__(kBlock) void k_rho(GapDev* __restrict__ gaps, int g,
+                                                long long* __restrict__ acc) {
   GapDev* __restrict__ G = gaps + g;
   const int buf = G->buf;
   const T scale = (T)(double)G->one;
@@ -1973,12 +1976,12 @@ __global__ __launch_bounds__(kBlock) void k_rho(GapDev* __restrict__ gaps, int g
             node = node < 0 ? node + G->n_cells : (node >= G->n_cells ? node - G->n_cells : node);
           else if (node < 0 || node > G->n_cells)
             continue;  // beyond a wall node
-          atomicAdd((unsigned long long*)&G->rho_acc[node], as_u64(q * wk[k]));
+          atomicAdd((unsigned long long*)&acc[node], as_u64(q * wk[k]));
         }
         continue;
       }
-      atomicAdd((unsigned long long*)&G->rho_acc[c], as_u64(q * (G->one - oq)));
-      atomicAdd((unsigned long long*)&G->rho_acc[c + 1], as_u64(q * oq));
+      atomicAdd((unsigned long long*)&acc[c], as_u64(q * (G->one - oq)));
+      atomicAdd((unsigned long long*)&acc[c + 1], as_u64(q * oq));
     }
   }
 }
@@ -2143,9 +2146,41 @@ hipError_t launch_zero(long long* a, long long n, hipStream_t st) {
 hipError_t launch_rho(GapDev* gaps, int g, long long* rho_acc, long long n_nodes, bool mixed,
                       hipStream_t st) {
   hipLaunchKernelGGL(k_zero_ll, dim3(64), dim3(256), 0, st, rho_acc, n_nodes);
-  if (mixed) hipLaunchKernelGGL(k_rho<float>, dim3(1024), dim3(kBlock), 0, st, gaps, g);
-  else hipLaunchKernelGGL(k_rho<double>, dim3(1024), dim3(kBlock), 0, st, gaps, g);
+  if (mixed) hipLaunchKernelGGL(k_rho<float>, dim3(1024), dim3(kBlock), 0, st, gaps, g, rho_acc);
+  else hipLaunchKernelGGL(k_rho<double>, dim3(1024), dim3(kBlock), 0, st, gaps, g, rho_acc);
   return hipGetLastError();
+}
+
+// ------------------------------------------------- static node scratch
+// The node-charge accumulators of pic_read_fields_noalloc: one array per
+// GPU the library runs on, held until the process ends, shared by every
+// call on that GPU.  Host code never passes `scratch` itself to a kernel
+// (in host code the name stands for a host-side placeholder); it uses the
+// device address that hipGetSymbolAddress returns, looked up once per
+// device with that device current.
+__device__ __align__(256) long long scratch[kStaticNodes];
+
+hipError_t static_scratch(int device, long long** out) {
+  static std::mutex lock;
+  static long long* addr[kMaxDevices] = {};
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> guard(lock);
+  if (!addr[device]) {
+    int prev = 0;
+    hipError_t e = hipGetDevice(&prev);
+    if (e != hipSuccess) return e;
+    if (prev != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (prev != device) {
+      const hipError_t e2 = hipSetDevice(prev);
+      if (e == hipSuccess) e = e2;
+    }
+    if (e != hipSuccess) return e;
+    addr[device] = static_cast<long long*>(p);
+  }
+  *out = addr[device];
+  return hipSuccess;
 }
 
 }  // namespace pic

@@ -39,5 +39,10 @@ hipError_t launch_phase(GapDev* gaps, int g, int s, int x_bins, int p_bins, doub
 hipError_t launch_zero(long long* a, long long n, hipStream_t st);
 hipError_t launch_rho(GapDev* gaps, int g, long long* rho_acc, long long n_nodes, bool mixed,
                       hipStream_t st);
+// Static node scratch (kStaticNodes int64 per GPU): its device address on
+// `device`, looked up on first use.
+constexpr long long kStaticNodes = (1 << 20) + 1;
+constexpr int kMaxDevices = 64;
+hipError_t static_scratch(int device, long long** out);
 
 }  // namespace pic

@@ -929,6 +929,43 @@ pic_status pic_read_fields(pic_gap* g, double* E, double* rho, int32_t n_cells) 
   return hipStreamSynchronize(b->stream) == hipSuccess ? PIC_OK : PIC_ERR_DEVICE;
 }
 
+pic_status pic_read_fields_noalloc(pic_gap* g, double* E, double* rho, int32_t n_cells) {
+  if (!g) return PIC_ERR_ARG;
+  pic_batch* b = g->b;
+  GapDev G;
+  pic_status st = read_desc(b, g->idx, &G);
+  if (st != PIC_OK) return st;
+  if (n_cells != G.n_cells) return PIC_ERR_ARG;
+  if (rho && (long long)n_cells + 1 > pic::kStaticNodes) return PIC_ERR_ARG;
+  if (E && copy_to_host(b, E, G.E, 8 * (size_t)n_cells) != PIC_OK) return PIC_ERR_DEVICE;
+  if (rho) {
+    // the GPU that holds this gap, whose copy of the static scratch is used
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, b->ws) != hipSuccess) return PIC_ERR_DEVICE;
+    long long* acc = nullptr;
+    if (pic::static_scratch(attr.device, &acc) != hipSuccess) return PIC_ERR_DEVICE;
+    if (pic::launch_rho(dgaps(b), g->idx, acc, n_cells + 1, b->precision == PIC_MIXED, b->stream) !=
+        hipSuccess)
+      return PIC_ERR_DEVICE;
+    // the int64 accumulators land in the caller's buffer (same size) and are
+    // turned into charges in place
+    if (copy_to_host(b, rho, acc, 8 * ((size_t)n_cells + 1)) != PIC_OK) return PIC_ERR_DEVICE;
+    if (hipStreamSynchronize(b->stream) != hipSuccess) return PIC_ERR_DEVICE;
+    int64_t first = 0, last = 0;
+    std::memcpy(&first, rho, 8);
+    std::memcpy(&last, rho + n_cells, 8);
+    if (G.boundary == PIC_BC_PERIODIC) first = last = first + last;
+    for (int32_t c = 0; c <= n_cells; ++c) {
+      int64_t v;
+      std::memcpy(&v, rho + c, 8);
+      if (c == 0) v = first;
+      if (c == n_cells) v = last;
+      rho[c] = G.wq * (double)v;
+    }
+  }
+  return hipStreamSynchronize(b->stream) == hipSuccess ? PIC_OK : PIC_ERR_DEVICE;
+}
+
 pic_status pic_phase_space(pic_gap* g, int32_t species, int32_t x_bins, int32_t p_bins, double p_min,
                            double p_max, int64_t* d_counts) {
   if (!g || !d_counts || species < 0 || species > 1 || x_bins < 1 || p_bins < 1) return PIC_ERR_ARG;
