@@ -48,16 +48,19 @@ __device__ __forceinline__ int conv_steps(const uint32_t* __restrict__ table, in
     k = (int)ceilf(est);
   }
   k = k < 1 ? 1 : (k > len - 1 ? len - 1 : k);
-  // walk to the exact answer; the estimate is within a step or two
-  for (int it = 0; it < 4; ++it) {
-    if (u >= table[k]) {
-      if (k > 1 && u >= table[k - 1]) { --k; continue; }
-      return k;
-    }
-    ++k;
-  }
-  // fall back to bisection (not reached for tables built by the runtime)
+  // the estimate is within a step of the answer: the entries around it are
+  // requested together (T_{len-1} = 0, so some k answers)
+  const uint32_t tm = table[k - 1 > 0 ? k - 1 : 0], t0 = table[k];
+  const uint32_t tp = table[k + 1 < len ? k + 1 : len - 1];
   int lo = 1, hi = len - 1;
+  if (u >= t0) {
+    if (k == 1 || u < tm) return k;
+    hi = k - 1;  // the answer lies below k - 1 + 1
+  } else {
+    if (k + 1 <= len - 1 && u >= tp) return k + 1;
+    lo = k + 1 < len - 1 ? k + 1 : len - 1;
+  }
+  // bisection over the rest (not reached for tables built by the runtime)
   while (lo < hi) {
     const int mid = (lo + hi) >> 1;
     if (u >= table[mid]) hi = mid; else lo = mid + 1;
@@ -676,12 +679,6 @@ __global__ __launch_bounds__(kBlock, kSpread ? PushCfg<T>::spread_waves : PushCf
 // ------------------------------------------------------------------ emit
 // Chunk x of the current plan lists its emitters in emit_ent[x * kChunk ..]
 // (chunk-local index << 8 | number of emissions k).
-__device__ __forceinline__ void chunk_origin(const GapDev* G, long long local, int& s,
-                                             long long& i0) {
-  const long long chunks0 = ((long long)G->n[0] + kChunk - 1) / kChunk;
-  s = local < chunks0 ? 0 : 1;
-  i0 = (s == 0 ? local : local - chunks0) * kChunk;
-}
 
 // Per-wave shares of a workgroup's total: s_wave[v] holds wave v's count on
 // entry; returns the block total and sets `pre` to the counts of the waves
@@ -733,68 +730,115 @@ __device__ __forceinline__ int block_excl_scan(int x, int* s_tmp, int& total) {
   return off + incl - x;
 }
 
+// What the emission of one gap reads, loaded from its descriptor once per
+// gap segment rather than per emitter.
+template <typename T>
+struct EmitGap {
+  GapDev* G;
+  gptr<int32_t> cell[2];
+  gptr<T> off[2], p[2];
+  gptr<uint64_t> id[2];
+  gptr<long long> phx;
+  gptr<int32_t> phs;
+  gptr<uint64_t> phc;
+  const uint32_t* table;
+  int table_len, K;
+  float inv_lnq;
+  long long domain, photon_step;
+  unsigned long long ph_cap, slots, n0, n1;
+  uint64_t step, seed;
+  T pchild, inv_scale, scale;
+  bool absorbing, in_place, evmap;
+};
+
+template <typename T>
+__device__ __forceinline__ EmitGap<T> emit_gap(GapDev* __restrict__ G) {
+  EmitGap<T> E;
+  E.G = G;
+  const int buf = G->buf, pb = G->phbuf;
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    E.cell[s] = glb(G->cell[buf][s]);
+    E.off[s] = glb<T>(G->off[buf][s]);
+    E.p[s] = glb<T>(G->p[buf][s]);
+    E.id[s] = glb(G->id[buf][s]);
+  }
+  E.phx = glb(G->ph_x[pb]);
+  E.phs = glb(G->ph_step[pb]);
+  E.phc = glb(G->ph_child[pb]);
+  E.table = G->table;
+  E.table_len = G->table_len;
+  E.K = G->K;
+  E.inv_lnq = G->inv_lnq;
+  E.domain = G->domain;
+  E.photon_step = G->photon_step;
+  E.ph_cap = (unsigned long long)G->ph_cap;
+  E.slots = (unsigned long long)G->slots;
+  E.n0 = G->n[0];
+  E.n1 = G->n[1];
+  E.step = (uint64_t)G->step;
+  E.seed = G->seed;
+  E.pchild = (T)G->pchild;
+  E.scale = (T)(double)G->one;
+  E.inv_scale = (T)(1.0 / (double)G->one);
+  E.absorbing = G->boundary == PIC_BC_ABSORBING;
+  E.in_place = G->table_len == 0;
+  E.evmap = G->evmap != nullptr;
+  return E;
+}
+
 // The k photons (or in-place pairs) of emitter i of species s, written at
 // photon slots slot0 .. slot0 + k - 1 (pair slots n[0] + slot, n[1] + slot).
 // Returns the number of photons that left the domain.
 template <typename T>
-__device__ __forceinline__ unsigned emit_one(GapDev* __restrict__ G, int s, long long i, int k,
-                                             unsigned long long slot0, bool in_place) {
-  const int buf = G->buf;
-  const long long ONE = G->one;
-  const T scale = (T)(double)ONE;
-  const int c = G->cell[buf][s][i];
-  const long long oq = (long long)(((const T*)G->off[buf][s])[i] * scale);
-  const T pv = ((const T*)G->p[buf][s])[i];
-  const uint64_t id = G->id[buf][s][i];
-  const uint64_t stepn = (uint64_t)G->step;
-  const uint64_t seed = G->seed;
+__device__ __forceinline__ unsigned emit_one(const EmitGap<T>& E, int s, long long i, int k,
+                                             unsigned long long slot0) {
+  // the emitter's species, by selects (no indexed array of pointers)
+  const gptr<int32_t> cA = s == 0 ? E.cell[0] : E.cell[1];
+  const gptr<T> oA = s == 0 ? E.off[0] : E.off[1];
+  const gptr<T> pA = s == 0 ? E.p[0] : E.p[1];
+  const gptr<uint64_t> iA = s == 0 ? E.id[0] : E.id[1];
+  const int c = cA[i];
+  const long long oq = (long long)(oA[i] * E.scale);
+  const T pv = pA[i];
+  const uint64_t id = iA[i];
   // the direction of the emitter before its recoil: the push stores +|p| or
   // -|p|, so the sign bit holds it also when the recoil leaves |p| = 0
   const int dir = signbit(pv) ? -1 : 1;
   unsigned esc = 0;
-  if (in_place) {
+  if (E.in_place) {
     // pair made in place (the paper's zero mean free path)
-    const T pchild = (T)G->pchild;
-    const T pc = dir > 0 ? pchild : -pchild;
-    const T offn = (T)oq * ((T)1 / scale);
-    const unsigned long long cap = (unsigned long long)G->slots;
-    const unsigned long long ne0 = G->n[0], ne1 = G->n[1];
+    const T pc = dir > 0 ? E.pchild : -E.pchild;
+    const T offn = (T)oq * E.inv_scale;
     for (int jj = 0; jj < k; ++jj) {
-      const U64x4 u = philox4x64_10(stepn, (uint64_t)jj, kTagPhoton, 0, id, seed);
+      const U64x4 u = philox4x64_10(E.step, (uint64_t)jj, kTagPhoton, 0, id, E.seed);
       const uint64_t child = u.v[1] & ~(uint64_t)1;
-      const unsigned long long se = ne0 + slot0 + jj, sp = ne1 + slot0 + jj;
-      if (se < cap) {
-        G->cell[buf][0][se] = c; ((T*)G->off[buf][0])[se] = offn;
-        ((T*)G->p[buf][0])[se] = pc; G->id[buf][0][se] = child;
-      }
-      if (sp < cap) {
-        G->cell[buf][1][sp] = c; ((T*)G->off[buf][1])[sp] = offn;
-        ((T*)G->p[buf][1])[sp] = pc; G->id[buf][1][sp] = child | 1u;
+      const unsigned long long se = E.n0 + slot0 + jj, sp = E.n1 + slot0 + jj;
+      if (se < E.slots) { E.cell[0][se] = c; E.off[0][se] = offn; E.p[0][se] = pc; E.id[0][se] = child; }
+      if (sp < E.slots) {
+        E.cell[1][sp] = c; E.off[1][sp] = offn; E.p[1][sp] = pc; E.id[1][sp] = child | 1u;
       }
     }
-    if (G->evmap) count_pairs(G, (long long)stepn, c, (unsigned long long)k);
+    if (E.evmap) count_pairs(E.G, (long long)E.step, c, (unsigned long long)k);
   } else {
-    const bool absorbing = G->boundary == PIC_BC_ABSORBING;
-    const unsigned long long ph_cap = (unsigned long long)G->ph_cap;
-    const int pb = G->phbuf;
-    const long long X0 = (long long)c * ONE + oq;
+    const long long X0 = ((long long)c << E.K) + oq;
     for (int jj = 0; jj < k; ++jj) {
-      const U64x4 u = philox4x64_10(stepn, (uint64_t)jj, kTagPhoton, 0, id, seed);
+      const U64x4 u = philox4x64_10(E.step, (uint64_t)jj, kTagPhoton, 0, id, E.seed);
       const uint64_t child = u.v[1] & ~(uint64_t)1;
-      const int ncv = conv_steps(G->table, G->table_len, (uint32_t)(u.v[0] >> 32), G->inv_lnq);
-      long long X = X0 + (long long)dir * (long long)ncv * G->photon_step;
-      int cstep = (int)((long long)stepn + ncv);
-      if (absorbing) {
-        if (X < 0 || X >= G->domain) { cstep = INT32_MIN; ++esc; }
-      } else {
-        X %= G->domain;
-        if (X < 0) X += G->domain;
+      const int ncv = conv_steps(E.table, E.table_len, (uint32_t)(u.v[0] >> 32), E.inv_lnq);
+      long long X = X0 + (long long)dir * (long long)ncv * E.photon_step;
+      int cstep = (int)((long long)E.step + ncv);
+      if (E.absorbing) {
+        if (X < 0 || X >= E.domain) { cstep = INT32_MIN; ++esc; }
+      } else if (X < 0 || X >= E.domain) {
+        X %= E.domain;
+        if (X < 0) X += E.domain;
       }
       const unsigned long long slot = slot0 + jj;
-      if (slot < ph_cap) {
-        G->ph_x[pb][slot] = X;
-        G->ph_step[pb][slot] = cstep;
-        G->ph_child[pb][slot] = child | (dir > 0 ? 1u : 0u);
+      if (slot < E.ph_cap) {
+        E.phx[slot] = X;
+        E.phs[slot] = cstep;
+        E.phc[slot] = child | (dir > 0 ? 1u : 0u);
       }
     }
   }
@@ -802,21 +846,20 @@ __device__ __forceinline__ unsigned emit_one(GapDev* __restrict__ G, int s, long
 }
 
 // Walks the emitters with flattened indices [qa, qb) (chunk order, then list
-// order within a chunk) among chunks [x, xend) of gap G, whose first emitter
-// has flattened index Q.  Windows of kBlock chunks are scanned for their
-// emitter counts; each round hands one emitter to each thread.  With
-// `write` false it returns the photons of the walked emitters (every thread
-// gets the sum); with `write` true it emits them at slots base + running
-// offset.  On return x and Q point past the last window walked.
+// order within a chunk) among chunks [x, xend) of gap E.G, whose first
+// emitter has flattened index Q, and emits their photons (or in-place
+// pairs).  Windows of kBlock chunks are scanned for their emitter counts;
+// each round hands one emitter to each thread, a block scan of the emitters'
+// photon counts gives each its place, and the round's slots are reserved
+// with one atomic.  On return x and Q point past the last window walked.
 template <typename T>
-__device__ unsigned long long emit_walk(GapDev* __restrict__ G, long long& x, long long xend,
-                                        unsigned long long& Q, unsigned long long qa,
-                                        unsigned long long qb, long long wg0, bool write,
-                                        unsigned long long base, unsigned& esc,
-                                        gptr<const uint32_t> cntA, gptr<const uint32_t> entA,
-                                        int* s_nb, int* s_tmp) {
-  const bool in_place = G->table_len == 0;
-  unsigned long long run = 0;
+__device__ __forceinline__ void emit_walk(const EmitGap<T>& E, long long& x, long long xend,
+                                          unsigned long long& Q, unsigned long long qa,
+                                          unsigned long long qb, long long wg0, unsigned& esc,
+                                          gptr<const uint32_t> cntA, gptr<const uint32_t> entA,
+                                          int* s_nb, int* s_tmp, unsigned long long* s_base) {
+  // electron chunks come first in the gap's items
+  const long long chunks0 = ((long long)E.n0 + kChunk - 1) / kChunk;
   while (x < xend && Q < qb) {
     const long long xc0 = x + threadIdx.x;
     const int ne = xc0 < xend ? (int)cntA[xc0] : 0;
@@ -841,27 +884,37 @@ __device__ unsigned long long emit_walk(GapDev* __restrict__ G, long long& x, lo
         const long long xc = x + a;
         const uint32_t en = entA[xc * kChunk + (ql - s_nb[a])];
         k = (int)(en & 255u);
-        long long i0;
-        chunk_origin(G, xc - wg0, s, i0);
-        i = i0 + (long long)(en >> 8);
+        const long long local = xc - wg0;
+        s = local < chunks0 ? 0 : 1;
+        i = (s == 0 ? local : local - chunks0) * kChunk + (long long)(en >> 8);
       }
       int kt;
-      const int ex = block_excl_scan(k, s_tmp, kt);
-      if (write && k > 0) esc += emit_one<T>(G, s, i, k, base + run + (unsigned long long)ex, in_place);
-      run += (unsigned long long)kt;
+      const int ex = block_excl_scan(k, s_tmp, kt);  // ends with a barrier
+      if (kt == 0) continue;                          // uniform
+      if (threadIdx.x == 0) {
+        if (E.in_place) {
+          s_base[0] = reserve_pairs(E.G, (unsigned long long)kt);
+        } else {
+          const unsigned long long b0 = atomicAdd(&E.G->n_ph_next, (unsigned long long)kt);
+          if (b0 + (unsigned long long)kt > E.ph_cap) E.G->overflow = 1;
+          s_base[0] = b0;
+        }
+      }
+      __syncthreads();
+      const unsigned long long base = s_base[0];
+      if (k > 0) esc += emit_one<T>(E, s, i, k, base + (unsigned long long)ex);
+      __syncthreads();  // s_base is rewritten by the next round
     }
     x = x + kBlock < xend ? x + kBlock : xend;
     Q += (unsigned long long)nwin;
     __syncthreads();  // s_nb is rewritten by the next window
   }
-  return run;
 }
 
 // Emission is balanced by emitters, not by chunks: the push left the number
 // of emitters of each of its workgroups (in chunk order), so every
 // workgroup here scans those counts, takes an equal share of the flattened
-// emitter list, and walks it gap by gap: one pass for the photon count of
-// the share, one slot reservation, one pass that writes.
+// emitter list, and walks it gap by gap in one pass.
 template <typename T>
 __device__ void emit_role(GapDev* __restrict__ gaps, const long long* __restrict__ wi, int B,
                           const int32_t* __restrict__ emit_cnt,
@@ -884,12 +937,12 @@ __device__ void emit_role(GapDev* __restrict__ gaps, const long long* __restrict
   __syncthreads();
   if (lane_id() == 63) s_tmp[threadIdx.x >> 6] = (int)incl;
   __syncthreads();
-  uint32_t off = 0, E = 0;
+  uint32_t off = 0, Etot = 0;
 #pragma unroll
   for (int k = 0; k < kBlock / 64; ++k) {
     const uint32_t t = (uint32_t)s_tmp[k];
     if (k < (int)(threadIdx.x >> 6)) off += t;
-    E += t;
+    Etot += t;
   }
   off += incl - loc;
 #pragma unroll
@@ -898,11 +951,11 @@ __device__ void emit_role(GapDev* __restrict__ gaps, const long long* __restrict
     off += v[j];
   }
   __syncthreads();
-  if (E == 0) return;
-  const unsigned long long share = ((unsigned long long)E + nvb - 1) / nvb;
+  if (Etot == 0) return;
+  const unsigned long long share = ((unsigned long long)Etot + nvb - 1) / nvb;
   const unsigned long long q0 = (unsigned long long)vb * share;
-  if (q0 >= E) return;
-  const unsigned long long q1 = q0 + share < E ? q0 + share : E;
+  if (q0 >= Etot) return;
+  const unsigned long long q1 = q0 + share < Etot ? q0 + share : Etot;
   // the push workgroup holding emitter q0: last lb with s_pre[lb] <= q0
   int a = 0, b = kPushGrid - 1;
   while (a < b) {
@@ -919,33 +972,13 @@ __device__ void emit_role(GapDev* __restrict__ gaps, const long long* __restrict
     GapDev* __restrict__ G = gaps + g;
     const long long xend = wi[g + 1];
     const long long wg0 = wi[g];
-    // pass 1: photons of the share within this gap
-    long long x1 = x;
-    unsigned long long Q1 = Q;
+    const EmitGap<T> E = emit_gap<T>(G);
     unsigned esc = 0;
-    const unsigned long long tot =
-        emit_walk<T>(G, x1, xend, Q1, q0, q1, wg0, false, 0, esc, cntA, entA, s_nb, s_tmp);
-    if (tot > 0) {
-      if (threadIdx.x == 0) {
-        if (G->table_len == 0) {
-          s_base[0] = reserve_pairs(G, tot);
-        } else {
-          const unsigned long long b0 = atomicAdd(&G->n_ph_next, tot);
-          if (b0 + tot > (unsigned long long)G->ph_cap) G->overflow = 1;
-          s_base[0] = b0;
-        }
-      }
-      __syncthreads();
-      const unsigned long long base = s_base[0];
-      emit_walk<T>(G, x, xend, Q, q0, q1, wg0, true, base, esc, cntA, entA, s_nb, s_tmp);
-      __syncthreads();  // s_base is reused by the next gap
-      if (G->boundary == PIC_BC_ABSORBING) {
-        const unsigned long long esc_w = wave_sum((unsigned long long)esc);
-        if (lane_id() == 0 && esc_w > 0) atomicAdd(&G->esc_next, esc_w);
-      }
+    emit_walk<T>(E, x, xend, Q, q0, q1, wg0, esc, cntA, entA, s_nb, s_tmp, s_base);
+    if (E.absorbing && !E.in_place) {
+      const unsigned long long esc_w = wave_sum((unsigned long long)esc);
+      if (lane_id() == 0 && esc_w > 0) atomicAdd(&G->esc_next, esc_w);
     }
-    x = x1;
-    Q = Q1;
   }
 }
 
@@ -1016,16 +1049,19 @@ __device__ __forceinline__ void convert_item(long long b0, long long b1, long lo
   }
 }
 
+constexpr int kConvGroup = 4;  // conversion items whose keys a workgroup holds at once
+
 template <typename T>
 __device__ void convert_role(GapDev* __restrict__ gaps, const long long* __restrict__ pwi, int B,
                              int vb, int nvb, unsigned long long* s_wave,
-                             unsigned long long* s_base) {
+                             unsigned long long* s_base, uint32_t* s_due) {
   // An item holds kPhChunk = 16 runs of 64 photons; wave v takes runs v, v + 4, v + 8, v + 12.
   constexpr int kWaves = kBlock / 64;
   constexpr int kRuns = kPhChunk / 64 / kWaves;
-  constexpr int kConvGroup = 4;  // items whose keys are held at once
+  constexpr int kDueCap = kConvGroup * kRuns * 64;  // due photons a wave can list per group
   const int lane = lane_id();
   const int v = threadIdx.x >> 6;
+  uint32_t* due = s_due + v * kDueCap;
   const long long total = pwi[B];
   long long w0, w1;
   xcd_range(total, w0, w1, vb, nvb);
@@ -1040,16 +1076,24 @@ __device__ void convert_role(GapDev* __restrict__ gaps, const long long* __restr
     long long rb0, rb1, rt0, rt1;  // the gap's due ranges, read once
     photon_ranges(G, rb0, rb1, rt0, rt1);
     gptr<const int32_t> phs = glb<const int32_t>((void*)G->ph_step[pb]);
+    gptr<const long long> phx = glb<const long long>((void*)G->ph_x[pb]);
+    gptr<const uint64_t> phc = glb<const uint64_t>((void*)G->ph_child[pb]);
+    gptr<int32_t> cell0 = glb(G->cell[buf][0]), cell1 = glb(G->cell[buf][1]);
+    gptr<T> off0 = glb<T>(G->off[buf][0]), off1 = glb<T>(G->off[buf][1]);
+    gptr<T> p0 = glb<T>(G->p[buf][0]), p1 = glb<T>(G->p[buf][1]);
+    gptr<uint64_t> id0 = glb(G->id[buf][0]), id1 = glb(G->id[buf][1]);
     const unsigned long long ne0 = G->n[0], ne1 = G->n[1];
     const unsigned long long cap = (unsigned long long)G->slots;
-    const long long ONE = G->one;
-    const T inv_scale = (T)(1.0 / (double)ONE);
+    const int K = G->K;
+    const long long mask = G->one - 1;
+    const T inv_scale = (T)(1.0 / (double)G->one);
     const T pchild = (T)G->pchild;
     const bool evmap = G->evmap != nullptr;
     // Groups of kConvGroup items: every key of the group is requested at
-    // once and kept in registers; the due photons are counted with ballots,
-    // the workgroup reserves their pair slots with one atomic, and the same
-    // ballots give each due photon its slot.
+    // once and kept in registers.  Each wave lists its due photons in LDS
+    // (ballots give the positions), the workgroup reserves their pair slots
+    // with one atomic, and the wave's lanes then convert its list one photon
+    // per lane.
     for (long long x = w; x < wend; x += kConvGroup) {
       int st[kConvGroup][kRuns];
 #pragma unroll
@@ -1062,12 +1106,21 @@ __device__ void convert_role(GapDev* __restrict__ gaps, const long long* __restr
           st[it][t] = i < i1 ? phs[i] : INT32_MIN;
         }
       }
-      unsigned long long cnt = 0;
+      __syncthreads();  // the previous group's list, s_wave and s_base are consumed
+      uint32_t cnt = 0;
 #pragma unroll
       for (int it = 0; it < kConvGroup; ++it)
 #pragma unroll
-        for (int t = 0; t < kRuns; ++t) cnt += (unsigned long long)__popcll(__ballot(st[it][t] == stepn));
-      __syncthreads();  // s_wave and s_base of the previous group are consumed
+        for (int t = 0; t < kRuns; ++t) {
+          const bool d = st[it][t] == stepn;
+          const unsigned long long m = __ballot(d);
+          if (d) {
+            // photon index within the group: item it, run (v + 4 t), lane
+            due[cnt + (uint32_t)__popcll(m & lanes_below())] =
+                (uint32_t)(it * kPhChunk + (v + kWaves * t) * 64 + lane);
+          }
+          cnt += (uint32_t)__popcll(m);
+        }
       if (lane == 0) s_wave[v] = cnt;
       __syncthreads();
       unsigned long long pre;
@@ -1076,37 +1129,21 @@ __device__ void convert_role(GapDev* __restrict__ gaps, const long long* __restr
       if (threadIdx.x == 0) s_base[0] = reserve_pairs(G, tot);
       __syncthreads();
       const unsigned long long base = s_base[0] + pre;
-      unsigned long long run = 0;
-#pragma unroll
-      for (int it = 0; it < kConvGroup; ++it) {
-        long long i0 = 0, i1 = 0;
-        if (x + it < wend) convert_item(rb0, rb1, rt0, rt1, x + it - wg0, i0, i1);
-#pragma unroll
-        for (int t = 0; t < kRuns; ++t) {
-          const bool due = st[it][t] == stepn;
-          const unsigned long long m = __ballot(due);
-          if (m == 0) continue;  // uniform
-          const unsigned long long ex = run + (unsigned long long)__popcll(m & lanes_below());
-          run += (unsigned long long)__popcll(m);
-          if (!due) continue;
-          const long long i = i0 + (long long)(v + kWaves * t) * 64 + lane;
-          const long long X = G->ph_x[pb][i];
-          const uint64_t ch = G->ph_child[pb][i];
-          const int c = (int)(X / ONE);
-          const T offn = (T)(X % ONE) * inv_scale;
-          const T pc = (ch & 1u) ? pchild : -pchild;
-          const uint64_t child = ch & ~(uint64_t)1;
-          const unsigned long long se = ne0 + base + ex, sp = ne1 + base + ex;
-          if (se < cap) {
-            G->cell[buf][0][se] = c; ((T*)G->off[buf][0])[se] = offn;
-            ((T*)G->p[buf][0])[se] = pc; G->id[buf][0][se] = child;
-          }
-          if (sp < cap) {
-            G->cell[buf][1][sp] = c; ((T*)G->off[buf][1])[sp] = offn;
-            ((T*)G->p[buf][1])[sp] = pc; G->id[buf][1][sp] = child | 1u;
-          }
-          if (evmap) count_pairs(G, (long long)stepn, c, 1ull);
-        }
+      for (uint32_t q = (uint32_t)lane; q < cnt; q += 64) {
+        const uint32_t e = due[q];
+        long long i0, i1;
+        convert_item(rb0, rb1, rt0, rt1, x + (long long)(e / kPhChunk) - wg0, i0, i1);
+        const long long i = i0 + (long long)(e % kPhChunk);
+        const long long X = phx[i];
+        const uint64_t ch = phc[i];
+        const int c = (int)(X >> K);
+        const T offn = (T)(X & mask) * inv_scale;
+        const T pc = (ch & 1u) ? pchild : -pchild;
+        const uint64_t child = ch & ~(uint64_t)1;
+        const unsigned long long se = ne0 + base + q, sp = ne1 + base + q;
+        if (se < cap) { cell0[se] = c; off0[se] = offn; p0[se] = pc; id0[se] = child; }
+        if (sp < cap) { cell1[sp] = c; off1[sp] = offn; p1[sp] = pc; id1[sp] = child | 1u; }
+        if (evmap) count_pairs(G, (long long)stepn, c, 1ull);
       }
     }
     w = wend;
@@ -1445,14 +1482,17 @@ __global__ __launch_bounds__(kBlock) void k_post(GapDev* __restrict__ gaps,
   __shared__ unsigned long long s_base[1];
   __shared__ int s_nb[kBlock];
   __shared__ int s_tmp[kBlock / 64];
-  __shared__ uint32_t s_pre[kPushGrid];
+  // the emission role's prefix of the push workgroups' emitters, or the
+  // conversion role's lists of due photons (a block takes one role)
+  __shared__ uint32_t s_buf[kPushGrid];
+  static_assert(kPushGrid >= kConvGroup * kPhChunk, "the due lists of a conversion group fit s_buf");
   const int b = blockIdx.x;
   if (b < n_field) field_role(gaps, cwi, B, b, s_red);
   else if (b < n_field + n_emit)
-    emit_role<T>(gaps, wi, B, emit_cnt, emit_ent, wg_emit, b - n_field, n_emit, s_pre, s_base, s_nb,
+    emit_role<T>(gaps, wi, B, emit_cnt, emit_ent, wg_emit, b - n_field, n_emit, s_buf, s_base, s_nb,
                  s_tmp);
   else if (b < n_field + n_emit + n_conv)
-    convert_role<T>(gaps, pwi, B, b - n_field - n_emit, n_conv, s_wave, s_base);
+    convert_role<T>(gaps, pwi, B, b - n_field - n_emit, n_conv, s_wave, s_base, s_buf);
   else fold_role(gaps, B, stripes, b - n_field - n_emit - n_conv);
 }
 
