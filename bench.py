@@ -320,127 +320,156 @@ def _profile_name(workload, precision):
 
 def stored_traffic(workload, precision, steps):
     """HBM bytes per push launch from the committed counter summary of this
-    workload, or None when it is missing or stale."""
+    workload and step count, or None when it is missing or the kernel
+    sources changed since the counters were taken."""
     path = os.path.join(PROFILE_DIR, _profile_name(workload, precision) + ".json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         prof = json.load(f)
+    pmc = prof.get("pmc", {})
     if (prof.get("source_sha256") != kernel_source_hash() or prof.get("workload") != workload
-            or prof.get("steps") != steps or not prof.get("pmc", {}).get("traffic_bytes_per_launch")):
+            or pmc.get("steps") != steps or not pmc.get("traffic_bytes_per_launch")):
         return None
-    return prof["pmc"]
+    return pmc
 
 
-def _db_rows(db, sql, args=()):
-    import sqlite3
-    con = sqlite3.connect(db)
-    try:
-        return con.execute(sql, args).fetchall()
-    finally:
-        con.close()
+def _csv_rows(path):
+    import csv
+    with open(path) as f:
+        return list(csv.DictReader(f))
 
 
-def _pmc_per_dispatch(db, counter, match):
-    """Per-dispatch counter values (summed over instances) of kernels whose
-    name contains `match`, in dispatch order."""
-    rows = _db_rows(db, "select dispatch_id, kernel_name, value from counters_collection "
-                        "where counter_name = ? order by dispatch_id", (counter,))
+def _col(row, *names):
+    low = {k.lower(): k for k in row}
+    for n in names:
+        if n.lower() in low:
+            return row[low[n.lower()]]
+    raise KeyError(names)
+
+
+def _counter_per_dispatch(path, counter, match):
+    """Per-dispatch values (summed over instances) of `counter` for kernels
+    whose name contains `match`, in dispatch order."""
     acc = {}
-    for d, name, v in rows:
-        if match in name:
-            acc[d] = acc.get(d, 0.0) + float(v)
+    for r in _csv_rows(path):
+        if _col(r, "Counter_Name") != counter or match not in _col(r, "Kernel_Name"):
+            continue
+        d = int(_col(r, "Dispatch_Id"))
+        acc[d] = acc.get(d, 0.0) + float(_col(r, "Counter_Value"))
     return [acc[d] for d in sorted(acc)]
 
 
 def summarize(args):
-    """Writes profiles/<kernel>_<workload>.{md,json} from rocprofv3 output of
-    the bench command (kernel trace, FETCH_SIZE and WRITE_SIZE passes) and of
-    the copy probe (the same two counters over a 1 GiB device copy)."""
+    """Writes profiles/<kernel>_<workload>.{md,json} from rocprofv3 CSV output:
+    the kernel trace and stats of the benchmark command (with its printed
+    JSON line), and, when given, counter passes (FETCH_SIZE, WRITE_SIZE, the
+    LDS counters) over the bounded counter-pass run of the same workload and
+    steps, calibrated by the same counters over 1 GiB device copies."""
     import numpy as np
     with open(args.bench_json) as f:
-        bench = json.loads(f.read().strip().splitlines()[-1])
+        bench = json.loads([ln for ln in f.read().splitlines() if ln.startswith("{")][-1])
     workload = bench["config"]["workload"]
     prec = workloads.MIXED if bench["dtype"] != "f64" else workloads.FP64
-    # the push instantiation without per-lepton thresholds and with the linear
-    # shape (the benchmark's)
     kname = ("k_push<float, false, false>" if prec == workloads.MIXED
              else "k_push<double, false, false>")
-    n = 2 * bench["steps"]  # the timed graph run and the evented run of the same steps
-    rows = _db_rows(args.trace_db, "select name, start, end from kernels order by start")
+    trace = _csv_rows(args.trace_csv)
     per = {}
-    for name, t0, t1 in rows:
-        per.setdefault(name.split("(")[0], []).append((t1 - t0) / 1e3)
-    push = [d for name, d in ((r[0], (r[2] - r[1]) / 1e3) for r in rows) if kname in name][-n:]
+    push = []
+    for r in trace:
+        name = _col(r, "Kernel_Name")
+        d = (int(_col(r, "End_Timestamp")) - int(_col(r, "Start_Timestamp"))) / 1e3
+        per.setdefault(name.split("(")[0], []).append(d)
+        if kname in name:
+            push.append(d)
+    # the command's push dispatches in order: the warm-up, `reps` timed runs
+    # and the evented run, each of `steps` steps (the warm-up of `warmup`)
+    reps = bench["config"].get("timed_runs", {}).get("reps", 1)
+    nstep, nwarm = bench["steps"], bench["warmup"]
+    timed = push[nwarm:nwarm + reps * nstep]
+    evented = push[nwarm + reps * nstep:nwarm + (reps + 1) * nstep]
     total = sum(sum(v) for v in per.values())
     table = sorted(((k, len(v), float(np.mean(v)), sum(v) / 1e3, 100 * sum(v) / total)
                     for k, v in per.items()), key=lambda r: -r[3])
     ev_avg_us = bench["roofline"]["kernel_ms"] * 1e3 / bench["roofline"]["launches"]
-    alg = bench["roofline"]["bytes_per_push"] * bench["config"]["pushes"] / bench["steps"]
+    alg = bench["roofline"]["alg_bytes_per_launch"]
+    prof = {"kernel": kname, "workload": workload, "steps": bench["steps"],
+            "source_sha256": kernel_source_hash(), "commands": args.command, "notes": args.note,
+            "trace": {"dispatches": len(push), "avg_us": float(np.mean(push)),
+                      "timed_runs_avg_us": float(np.mean(timed)) if timed else None,
+                      "evented_run_avg_us": float(np.mean(evented)) if evented else None,
+                      "bench_event_avg_us": ev_avg_us,
+                      "kernels": [dict(name=k, n=c, mean_us=m, total_ms=t, pct=p)
+                                  for k, c, m, t, p in table]},
+            "bench": {k: bench[k] for k in ("value", "ms_per_step", "steps")},
+            "pmc": {}}
+    lines = [f"# {kname} on {workload} ({bench['steps']} timed steps)", "",
+             "Commands (from the repository root; rocprofv3 after `cd /tmp && export TMPDIR=/tmp`,",
+             "with the repository path for `$R`):", ""]
+    lines += [f"    {c}" for c in args.command]
+    lines += ["", f"Kernel sources sha256: `{prof['source_sha256']}`", "",
+              f"## Kernel trace ({len(push)} dispatches of {kname} in the command)", "",
+              f"- rocprofv3 average duration of {kname}, all {len(push)} dispatches: "
+              f"{prof['trace']['avg_us']:.2f} us",
+              f"- rocprofv3 average over the {len(timed)} dispatches of the {reps} timed runs: "
+              f"{np.mean(timed):.2f} us; over the {len(evented)} of the evented run: {np.mean(evented):.2f} us",
+              f"- the bench's dispatch-event average over its evented run (the roofline's time): "
+              f"{ev_avg_us:.2f} us ({100 * (ev_avg_us / np.mean(evented) - 1):+.1f}% against rocprofv3 "
+              "on the same dispatches)", "",
+              f"Benchmark line of the same command: {bench['value']:.4g} pushes/s, "
+              f"{bench['ms_per_step']:.4f} ms per step, roofline frac {bench['roofline']['frac']:.4f}.", "",
+              "| kernel | dispatches | mean us | total ms | % |", "|---|---|---|---|---|"]
+    lines += [f"| {k} | {c} | {m:.2f} | {t:.2f} | {p:.1f} |" for k, c, m, t, p in table[:20]]
+    if args.fetch_csv and args.write_csv and args.copy_fetch_csv and args.copy_write_csv:
+        with open(args.pmc_json) as f:
+            cp = json.loads([ln for ln in f.read().splitlines() if ln.startswith("{")][-1])
+        pushes = np.array(cp["pushes_per_step"], dtype=float)
+        bpp = BYTES_PER_PUSH[prec]
 
-    def copy_factor(db, counter):
-        v = _pmc_per_dispatch(db, counter, "copyBuffer")
-        big = [x for x in v if x > 0.25 * (1 << 20)]  # KiB: the 1 GiB copies
-        return (1 << 20) / float(np.mean(big)), len(big)
+        def factor(path, counter):
+            v = [x for x in _counter_per_dispatch(path, counter, "copyBuffer") if x > 0.25 * (1 << 20)]
+            return (1 << 20) / float(np.mean(v)), len(v)  # KiB expected per 1 GiB copy
 
-    # the counter passes run the graph-replayed steps only (--timed-only);
-    # a pass that did not complete leaves its half of the traffic unknown
-    ff, nf = copy_factor(args.copy_fetch_db, "FETCH_SIZE") if args.copy_fetch_db else (None, 0)
-    wf, nw = copy_factor(args.copy_write_db, "WRITE_SIZE") if args.copy_write_db else (None, 0)
-    fetch = _pmc_per_dispatch(args.fetch_db, "FETCH_SIZE", kname)[-bench["steps"]:] if args.fetch_db else []
-    write = _pmc_per_dispatch(args.write_db, "WRITE_SIZE", kname)[-bench["steps"]:] if args.write_db else []
-    fkib = float(np.mean(fetch)) if fetch and ff else None
-    wkib = float(np.mean(write)) if write and wf else None
-    traffic = (fkib * ff + wkib * wf) * 1024.0 if fkib is not None and wkib is not None else None
-    alg_read = alg / 2.0  # the push reads and writes the same lepton state
-    prof = {
-        "kernel": kname, "workload": workload, "steps": bench["steps"],
-        "source_sha256": kernel_source_hash(),
-        "commands": args.command,
-        "notes": args.note,
-        "trace": {"dispatches": len(push), "avg_us": float(np.mean(push)),
-                  "bench_event_avg_us": ev_avg_us,
-                  "kernels": [dict(name=k, n=c, mean_us=m, total_ms=t, pct=p) for k, c, m, t, p in table]},
-        "pmc": {"dispatches": [len(fetch), len(write)], "fetch_kib_per_dispatch": fkib,
-                "write_kib_per_dispatch": wkib, "fetch_factor": ff, "write_factor": wf,
-                "copy_dispatches": [nf, nw],
-                "fetch_bytes_per_launch": fkib * ff * 1024.0 if fkib is not None else None,
-                "alg_read_bytes_per_launch": alg_read,
-                "traffic_bytes_per_launch": traffic, "alg_bytes_per_launch": alg,
-                "traffic_over_alg": traffic / alg if traffic is not None else None},
-        "bench": {k: bench[k] for k in ("value", "ms_per_step", "steps")},
-    }
+        ff, nf = factor(args.copy_fetch_csv, "FETCH_SIZE")
+        wf, nw = factor(args.copy_write_csv, "WRITE_SIZE")
+        fetch = np.array(_counter_per_dispatch(args.fetch_csv, "FETCH_SIZE", kname))
+        write = np.array(_counter_per_dispatch(args.write_csv, "WRITE_SIZE", kname))
+        assert len(fetch) == len(write) == len(pushes), (len(fetch), len(write), len(pushes))
+        fb = fetch * ff * 1024.0
+        wb = write * wf * 1024.0
+        alg_step = pushes * bpp
+        traffic = float(np.mean(fb + wb))
+        prof["pmc"] = {"steps": int(len(pushes)), "fetch_factor": ff, "write_factor": wf,
+                       "copy_dispatches": [nf, nw],
+                       "fetch_bytes_per_launch": float(np.mean(fb)),
+                       "write_bytes_per_launch": float(np.mean(wb)),
+                       "traffic_bytes_per_launch": traffic,
+                       "alg_bytes_per_launch": float(np.mean(alg_step)),
+                       "traffic_over_alg": traffic / float(np.mean(alg_step)),
+                       "per_step_ratio": [float(x) for x in (fb + wb) / alg_step]}
+        lines += ["", f"## HBM traffic of {kname} (counter passes over the first {len(pushes)} steps, "
+                      "one counter per run)", "",
+                  f"- calibration: 1 GiB device copies read FETCH_SIZE {1024 * 1024 / ff:.0f} KiB and "
+                  f"write WRITE_SIZE {1024 * 1024 / wf:.0f} KiB each (factors {ff:.3f}, {wf:.3f})",
+                  f"- per launch, averaged over the {len(pushes)} steps: read {np.mean(fb) / 1e6:.2f} MB, "
+                  f"written {np.mean(wb) / 1e6:.2f} MB, total {traffic / 1e6:.2f} MB against "
+                  f"{np.mean(alg_step) / 1e6:.2f} MB algorithmic ({bpp} B per push): ratio "
+                  f"{traffic / np.mean(alg_step):.3f}", "",
+                  "| step | leptons pushed | read MB | written MB | traffic / algorithmic |",
+                  "|---|---|---|---|---|"]
+        lines += [f"| {k + 1} | {int(pushes[k])} | {fb[k] / 1e6:.2f} | {wb[k] / 1e6:.2f} | "
+                  f"{(fb[k] + wb[k]) / alg_step[k]:.3f} |" for k in range(len(pushes))]
+    if args.lds_csv:
+        conf = np.array(_counter_per_dispatch(args.lds_csv, "SQ_LDS_BANK_CONFLICT", kname))
+        insts = np.array(_counter_per_dispatch(args.lds_csv, "SQ_INSTS_LDS", kname))
+        prof["pmc"]["lds_bank_conflict_cycles_per_lds_inst"] = float(conf.sum() / max(insts.sum(), 1))
+        lines += ["", "## LDS (flux tile, emitter list)", "",
+                  f"- SQ_LDS_BANK_CONFLICT {conf.sum():.0f} cycles over SQ_INSTS_LDS {insts.sum():.0f} "
+                  f"instructions: {conf.sum() / max(insts.sum(), 1):.3f} conflict cycles per LDS instruction"]
     base = os.path.join(PROFILE_DIR, _profile_name(workload, prec))
     os.makedirs(PROFILE_DIR, exist_ok=True)
     with open(base + ".json", "w") as f:
         json.dump(prof, f, indent=1)
-    lines = [f"# {kname} on {workload} ({bench['steps']} steps)", "",
-             "Commands (run from the repository root; rocprofv3 after `cd /tmp && export TMPDIR=/tmp`,",
-             "with the repository path for `$R`):", ""]
-    lines += [f"    {c}" for c in args.command]
-    lines += ["", f"Kernel sources sha256: `{prof['source_sha256']}`", "",
-              f"## Kernel trace ({len(push)} dispatches of {kname} in the two runs of the workload)", "",
-              f"- rocprofv3 average duration: {prof['trace']['avg_us']:.2f} us",
-              f"- bench HIP-event average over the evented run: {ev_avg_us:.2f} us", "",
-              "| kernel | dispatches | mean us | total ms | % |", "|---|---|---|---|---|"]
-    lines += [f"| {k} | {c} | {m:.2f} | {t:.1f} | {p:.1f} |" for k, c, m, t, p in table[:14]]
-    lines += ["", "## HBM traffic per launch (PMC, one counter per run, the graph-replayed "
-              f"steps: {len(fetch)} / {len(write)} dispatches)", ""]
-    if fkib is not None:
-        lines += [f"- FETCH_SIZE {fkib:.0f} KiB/dispatch x calibration {ff:.3f} = "
-                  f"{fkib * ff * 1024 / 1e9:.3f} GB read per launch vs algorithmic "
-                  f"{alg_read / 1e9:.3f} GB (ratio {fkib * ff * 1024 / alg_read:.3f})",
-                  f"- calibration: a 1 GiB device copy reads FETCH_SIZE {1024 * 1024 / ff:.0f} KiB per copy"]
-    else:
-        lines += ["- FETCH_SIZE: no completed pass"]
-    if wkib is not None:
-        lines += [f"- WRITE_SIZE {wkib:.0f} KiB/dispatch x calibration {wf:.3f}",
-                  f"- calibration: a 1 GiB device copy writes WRITE_SIZE {1024 * 1024 / wf:.0f} KiB per copy"]
-    else:
-        lines += ["- WRITE_SIZE: no completed pass, so the total traffic is not reported"]
-    if traffic is not None:
-        lines += [f"- traffic {traffic / 1e9:.3f} GB/launch vs algorithmic {alg / 1e9:.3f} GB/launch "
-                  f"(ratio {traffic / alg:.3f})"]
     lines += [""] + [f"Note: {n}" for n in args.note] + ([""] if args.note else [])
     with open(base + ".md", "w") as f:
         f.write("\n".join(lines))
@@ -495,13 +524,15 @@ def main():
     ap.add_argument("--timed-only", action="store_true",
                     help="skip the evented rerun (counter passes: same push dispatches, graph-replayed)")
     ap.add_argument("--summarize", action="store_true",
-                    help="write the profiles/ summary from rocprofv3 databases (no GPU)")
+                    help="write the profiles/ summary from rocprofv3 CSV output (no GPU)")
     ap.add_argument("--bench-json")
-    ap.add_argument("--trace-db")
-    ap.add_argument("--fetch-db")
-    ap.add_argument("--write-db")
-    ap.add_argument("--copy-fetch-db")
-    ap.add_argument("--copy-write-db")
+    ap.add_argument("--trace-csv")
+    ap.add_argument("--pmc-json", help="output of the --counter-pass run")
+    ap.add_argument("--fetch-csv")
+    ap.add_argument("--write-csv")
+    ap.add_argument("--lds-csv")
+    ap.add_argument("--copy-fetch-csv")
+    ap.add_argument("--copy-write-csv")
     ap.add_argument("--command", action="append", default=[])
     ap.add_argument("--note", action="append", default=[])
     args = ap.parse_args()

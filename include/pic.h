@@ -327,8 +327,9 @@ pic_status pic_destroy(pic_gap* g);
 const char* pic_status_string(pic_status s);
 
 /* Kernel timing.  While enabled, every launch of the push kernel (gather,
- * push, move, current deposit and emission) is bracketed by HIP events on
- * the gap's stream.  pic_read_push_time synchronises the stream and
+ * push, move, current deposit and emission) carries HIP start and stop
+ * events recorded by its dispatch on the gap's stream (steps are then
+ * launched one by one, without graphs).  pic_read_push_time synchronises the stream and
  * returns the summed event time in milliseconds and the number of
  * launches timed since enabling; disabling clears the record. */
 pic_status pic_profile_push(pic_gap* g, int32_t enable);

@@ -22,6 +22,7 @@
 // particles, photons or cells, numbered across gaps by prefix arrays that
 // the device itself maintains, so a sequence of steps needs no host
 // synchronisation and can be captured in a graph.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -2077,26 +2078,34 @@ static int grid_for(long long want, int cap) {
   return (int)(want < 1 ? 1 : (want < cap ? want : cap));
 }
 
+// With events, they are recorded by the dispatch itself (its start and end),
+// so that the timed span is the kernel's own.
 template <typename T, bool kSpread, bool kSpline>
-static void push_kernel(const StepLaunch& L) {
+static void push_kernel(const StepLaunch& L, hipEvent_t start, hipEvent_t stop) {
+  if (start) {
+    hipExtLaunchKernelGGL((k_push<T, kSpread, kSpline>), dim3(kPushGrid), dim3(kBlock), 0, L.stream,
+                          start, stop, 0, L.gaps, L.wi, L.B, L.emit_cnt, L.emit_ent, L.wg_emit,
+                          L.stripes);
+    return;
+  }
   hipLaunchKernelGGL((k_push<T, kSpread, kSpline>), dim3(kPushGrid), dim3(kBlock), 0, L.stream,
                      L.gaps, L.wi, L.B, L.emit_cnt, L.emit_ent, L.wg_emit, L.stripes);
 }
 
 template <typename T>
-static void push_for(const StepLaunch& L) {
+static void push_for(const StepLaunch& L, hipEvent_t start, hipEvent_t stop) {
   if (L.spline) {
-    if (L.spread) push_kernel<T, true, true>(L);
-    else push_kernel<T, false, true>(L);
+    if (L.spread) push_kernel<T, true, true>(L, start, stop);
+    else push_kernel<T, false, true>(L, start, stop);
   } else {
-    if (L.spread) push_kernel<T, true, false>(L);
-    else push_kernel<T, false, false>(L);
+    if (L.spread) push_kernel<T, true, false>(L, start, stop);
+    else push_kernel<T, false, false>(L, start, stop);
   }
 }
 
-hipError_t launch_push(const StepLaunch& L, bool mixed) {
-  if (mixed) push_for<float>(L);
-  else push_for<double>(L);
+hipError_t launch_push(const StepLaunch& L, bool mixed, hipEvent_t start, hipEvent_t stop) {
+  if (mixed) push_for<float>(L, start, stop);
+  else push_for<double>(L, start, stop);
   return hipGetLastError();
 }
 
@@ -2117,7 +2126,7 @@ hipError_t launch_step_after_push(const StepLaunch& L, bool mixed) {
 }
 
 hipError_t launch_step(const StepLaunch& L, bool mixed) {
-  hipError_t e = launch_push(L, mixed);
+  hipError_t e = launch_push(L, mixed, nullptr, nullptr);
   if (e != hipSuccess) return e;
   return launch_step_after_push(L, mixed);
 }

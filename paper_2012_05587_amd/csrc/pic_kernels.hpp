@@ -27,7 +27,8 @@ struct StepLaunch {
 };
 
 hipError_t launch_step(const StepLaunch& L, bool mixed);
-hipError_t launch_push(const StepLaunch& L, bool mixed);
+// start/stop (both or neither): events recorded by the push dispatch itself
+hipError_t launch_push(const StepLaunch& L, bool mixed, hipEvent_t start, hipEvent_t stop);
 hipError_t launch_step_after_push(const StepLaunch& L, bool mixed);
 hipError_t launch_sort(const StepLaunch& L, bool mixed);
 hipError_t launch_tail_sort(const StepLaunch& L, bool mixed);

@@ -501,9 +501,8 @@ pic_status eager_step(pic_batch* b) {
         }
       }
     }
-    if (hipEventRecord(b->ev[b->ev_used], b->stream) != hipSuccess) return PIC_ERR_DEVICE;
-    if (pic::launch_push(b->launch, mixed) != hipSuccess) return PIC_ERR_DEVICE;
-    if (hipEventRecord(b->ev[b->ev_used + 1], b->stream) != hipSuccess) return PIC_ERR_DEVICE;
+    if (pic::launch_push(b->launch, mixed, b->ev[b->ev_used], b->ev[b->ev_used + 1]) != hipSuccess)
+      return PIC_ERR_DEVICE;
     b->ev_used += 2;
     if (pic::launch_step_after_push(b->launch, mixed) != hipSuccess) return PIC_ERR_DEVICE;
   } else if (pic::launch_step(b->launch, mixed) != hipSuccess) {
