@@ -44,6 +44,20 @@ struct SortPer { static constexpr int value = PASS == 0 ? 4 : 2; };
 constexpr int kPhUnroll = 4;          // photons per thread per iteration of the photon sort
 constexpr int kTailEvery = 5;         // steps between sorts of the appended leptons
 constexpr int kPhBins = 8192;         // conversion steps of the LDS histogram of the photon sort
+constexpr int kFarKey = 255;          // tail key of a photon not due within 254 steps of the last sort
+constexpr int kKeyRun = 16;           // tail keys a lane reads at once (one 16-byte load)
+constexpr int kPhAgeMax = 160;        // photon sorts at most this many steps apart (with re-sorts
+                                      // at most 80 steps apart, tail keys stay below kFarKey)
+
+// Whether a particle re-sort at this state also sorts the photon store: once
+// the tail has grown for the gap's age, or when the store is half full (the
+// sort reclaims converted and escaped photons).
+__host__ __device__ __forceinline__ bool photon_sort_due(int table_len, long long step,
+                                                         long long ph_base, int age,
+                                                         unsigned long long n_ph,
+                                                         long long ph_cap) {
+  return table_len > 0 && (step - ph_base >= age || 2 * (long long)n_ph >= ph_cap);
+}
 constexpr int32_t kDead = INT32_MIN;  // cell of an absorbed lepton until re-sort
 constexpr int kMaxEmit = 64;
 constexpr int kPushGrid = 4096;       // workgroups of the push kernel
@@ -106,8 +120,10 @@ struct GapDev {
   int32_t* ph_step[2];
   uint64_t* ph_child[2];  // electron id with bit 0 = (direction > 0)
   int32_t* ph_bucket;     // photon store sorted by conversion step: end of each bucket
+  uint8_t* ph_key;        // per slot of the unsorted tail: conversion step - ph_base when
+                          // below kFarKey, else kFarKey (escaped photons too)
   float inv_lnq;          // 1 / ln q of the photon path, q = exp(-dt / (l_gamma dx))
-  int32_t pad3;
+  int32_t ph_age;         // steps the photon tail may grow before a re-sort sorts the store
   unsigned long long* evmap;  // pair-event map (caller's device buffer), or null
   int32_t ev_x, ev_steps, ev_rows, pad5;
 
@@ -135,7 +151,8 @@ struct GapDev {
   unsigned long long ph_body_n;  // photons in the sorted body of the store
   long long ph_base;             // conversion step of bucket 0 of the sorted body
   long long step;
-  int32_t status, buf, phbuf, pad2;
+  int32_t status, buf, phbuf;
+  int32_t ph_due;                // the current re-sort also sorts the photon store
   int32_t overflow, nonfinite, emit_err, slot_overflow;
   double lost_energy;  // cumulative, a binary64 sum over steps in step order
   pic_history_row last;

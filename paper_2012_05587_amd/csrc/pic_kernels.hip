@@ -742,10 +742,11 @@ struct EmitGap {
   gptr<long long> phx;
   gptr<int32_t> phs;
   gptr<uint64_t> phc;
+  gptr<uint8_t> phk;
   const uint32_t* table;
   int table_len, K;
   float inv_lnq;
-  long long domain, photon_step;
+  long long domain, photon_step, ph_base;
   unsigned long long ph_cap, slots, n0, n1;
   uint64_t step, seed;
   T pchild, inv_scale, scale;
@@ -767,6 +768,8 @@ __device__ __forceinline__ EmitGap<T> emit_gap(GapDev* __restrict__ G) {
   E.phx = glb(G->ph_x[pb]);
   E.phs = glb(G->ph_step[pb]);
   E.phc = glb(G->ph_child[pb]);
+  E.phk = glb(G->ph_key);
+  E.ph_base = G->ph_base;
   E.table = G->table;
   E.table_len = G->table_len;
   E.K = G->K;
@@ -840,6 +843,9 @@ __device__ __forceinline__ unsigned emit_one(const EmitGap<T>& E, int s, long lo
         E.phx[slot] = X;
         E.phs[slot] = cstep;
         E.phc[slot] = child | (dir > 0 ? 1u : 0u);
+        // the tail key: steps from the last sort to the conversion (>= 1)
+        const long long rel = (long long)cstep - E.ph_base;
+        E.phk[slot] = (uint8_t)(cstep != INT32_MIN && rel < kFarKey ? rel : kFarKey);
       }
     }
   }
@@ -1036,30 +1042,52 @@ __device__ __forceinline__ void photon_ranges(const GapDev* G, long long& b0, lo
   t1 = (long long)G->n_ph;
 }
 
-// Photons [i0, i1) of due-photon item `local` of a gap whose due ranges are
-// [b0, b1) (sorted body) and [t0, t1) (unsorted tail).
-__device__ __forceinline__ void convert_item(long long b0, long long b1, long long t0, long long t1,
-                                             long long local, long long& i0, long long& i1) {
-  const long long nb = (b1 - b0 + kPhChunk - 1) / kPhChunk;
-  if (local < nb) {
-    i0 = b0 + local * kPhChunk;
-    i1 = i0 + kPhChunk < b1 ? i0 + kPhChunk : b1;
-  } else {
-    i0 = t0 + (local - nb) * kPhChunk;
-    i1 = i0 + kPhChunk < t1 ? i0 + kPhChunk : t1;
-  }
+// Conversion items of a gap: chunks of kPhChunk photons of the due bucket,
+// then of the tail, whose chunks start on kKeyRun boundaries (the first one
+// at or below the tail's start) so that keys are read with aligned loads.
+__device__ __forceinline__ long long tail_items(long long t0, long long t1) {
+  return t1 > t0 ? (t1 - (t0 & ~(long long)(kKeyRun - 1)) + kPhChunk - 1) / kPhChunk : 0;
 }
 
-constexpr int kConvGroup = 4;  // conversion items whose keys a workgroup holds at once
+// Item `local` of a gap whose due ranges are [b0, b1) (sorted body) and
+// [t0, t1) (unsorted tail): photons [i0, i1) of the item starting at slot
+// ib.  Returns whether it is a tail item.
+__device__ __forceinline__ bool convert_item(long long b0, long long b1, long long t0, long long t1,
+                                             long long local, long long& ib, long long& i0,
+                                             long long& i1) {
+  const long long nb = (b1 - b0 + kPhChunk - 1) / kPhChunk;
+  if (local < nb) {
+    ib = i0 = b0 + local * kPhChunk;
+    i1 = i0 + kPhChunk < b1 ? i0 + kPhChunk : b1;
+    return false;
+  }
+  ib = (t0 & ~(long long)(kKeyRun - 1)) + (local - nb) * kPhChunk;
+  i0 = ib > t0 ? ib : t0;
+  i1 = ib + kPhChunk < t1 ? ib + kPhChunk : t1;
+  return true;
+}
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// Bit 4q + j set where byte j of word q of a 16-byte key run equals key.
+__device__ __forceinline__ uint32_t key_matches(u32x4 kv, uint32_t key) {
+  const uint32_t w[4] = {kv.x, kv.y, kv.z, kv.w};
+  uint32_t m = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) m |= (((w[q] >> (8 * j)) & 0xFFu) == key ? 1u : 0u) << (4 * q + j);
+  return m;
+}
+
+constexpr int kConvGroup = kBlock / 64;  // conversion items of a workgroup at once: one per wave
 
 template <typename T>
 __device__ void convert_role(GapDev* __restrict__ gaps, const long long* __restrict__ pwi, int B,
                              int vb, int nvb, unsigned long long* s_wave,
                              unsigned long long* s_base, uint32_t* s_due) {
-  // An item holds kPhChunk = 16 runs of 64 photons; wave v takes runs v, v + 4, v + 8, v + 12.
-  constexpr int kWaves = kBlock / 64;
-  constexpr int kRuns = kPhChunk / 64 / kWaves;
-  constexpr int kDueCap = kConvGroup * kRuns * 64;  // due photons a wave can list per group
+  static_assert(kPhChunk == 64 * kKeyRun, "an item is one key run per lane");
+  constexpr int kDueCap = kPhChunk;  // due photons a wave can list (its item)
   const int lane = lane_id();
   const int v = threadIdx.x >> 6;
   uint32_t* due = s_due + v * kDueCap;
@@ -1076,6 +1104,11 @@ __device__ void convert_role(GapDev* __restrict__ gaps, const long long* __restr
     const long long wg0 = pwi[g];
     long long rb0, rb1, rt0, rt1;  // the gap's due ranges, read once
     photon_ranges(G, rb0, rb1, rt0, rt1);
+    // tail photons are found by their one-byte keys while the step is within
+    // kFarKey - 1 steps of the last sort, else by their conversion steps
+    const long long kstep = G->step - G->ph_base;
+    const bool keyed = kstep < kFarKey;
+    gptr<const uint8_t> phk = glb<const uint8_t>((void*)G->ph_key);
     gptr<const int32_t> phs = glb<const int32_t>((void*)G->ph_step[pb]);
     gptr<const long long> phx = glb<const long long>((void*)G->ph_x[pb]);
     gptr<const uint64_t> phc = glb<const uint64_t>((void*)G->ph_child[pb]);
@@ -1090,38 +1123,48 @@ __device__ void convert_role(GapDev* __restrict__ gaps, const long long* __restr
     const T inv_scale = (T)(1.0 / (double)G->one);
     const T pchild = (T)G->pchild;
     const bool evmap = G->evmap != nullptr;
-    // Groups of kConvGroup items: every key of the group is requested at
-    // once and kept in registers.  Each wave lists its due photons in LDS
-    // (ballots give the positions), the workgroup reserves their pair slots
-    // with one atomic, and the wave's lanes then convert its list one photon
-    // per lane.
+    // Groups of kConvGroup items, one per wave: each lane tests kKeyRun
+    // consecutive photons of its wave's item, the wave lists its due photons
+    // in LDS (a wave scan of the lanes' counts gives the positions), the
+    // workgroup reserves their pair slots with one atomic, and the wave's
+    // lanes then convert its list one photon per lane.
     for (long long x = w; x < wend; x += kConvGroup) {
-      int st[kConvGroup][kRuns];
+      const long long xi = x + v;
+      long long ib = 0;
+      uint32_t m = 0;  // due photons among the lane's kKeyRun
+      if (xi < wend) {
+        long long i0, i1;
+        const bool tail = convert_item(rb0, rb1, rt0, rt1, xi - wg0, ib, i0, i1);
+        const long long s0 = ib + (long long)lane * kKeyRun;
+        const long long lo = i0 - s0, hi = i1 - s0;
+        const int a = lo < 0 ? 0 : (lo > kKeyRun ? kKeyRun : (int)lo);
+        const int e = hi < 0 ? 0 : (hi > kKeyRun ? kKeyRun : (int)hi);
+        const uint32_t in = ((1u << e) - 1u) & ~((1u << a) - 1u);
+        if (!tail) {
+          m = in;  // the bucket of this step: all due
+        } else if (in != 0u) {
+          if (keyed) {
+            // s0 is a multiple of kKeyRun below the tail's end: the run lies
+            // in the key array (sized up to a multiple of kKeyRun)
+            const u32x4 kv = *(gptr<const u32x4>)(phk + s0);
+            m = key_matches(kv, (uint32_t)kstep) & in;
+          } else {
 #pragma unroll
-      for (int it = 0; it < kConvGroup; ++it) {
-        long long i0 = 0, i1 = 0;
-        if (x + it < wend) convert_item(rb0, rb1, rt0, rt1, x + it - wg0, i0, i1);
-#pragma unroll
-        for (int t = 0; t < kRuns; ++t) {
-          const long long i = i0 + (long long)(v + kWaves * t) * 64 + lane;
-          st[it][t] = i < i1 ? phs[i] : INT32_MIN;
+            for (int b = 0; b < kKeyRun; ++b)
+              if ((in >> b) & 1u) m |= (phs[s0 + b] == stepn ? 1u : 0u) << b;
+          }
         }
       }
-      __syncthreads();  // the previous group's list, s_wave and s_base are consumed
-      uint32_t cnt = 0;
-#pragma unroll
-      for (int it = 0; it < kConvGroup; ++it)
-#pragma unroll
-        for (int t = 0; t < kRuns; ++t) {
-          const bool d = st[it][t] == stepn;
-          const unsigned long long m = __ballot(d);
-          if (d) {
-            // photon index within the group: item it, run (v + 4 t), lane
-            due[cnt + (uint32_t)__popcll(m & lanes_below())] =
-                (uint32_t)(it * kPhChunk + (v + kWaves * t) * 64 + lane);
-          }
-          cnt += (uint32_t)__popcll(m);
-        }
+      __syncthreads();  // the previous group's lists, s_wave and s_base are consumed
+      const uint32_t c = (uint32_t)__popc(m);
+      const uint32_t incl = wave_incl_scan(c);
+      uint32_t pos = incl - c;
+      while (m) {
+        const int b = __ffs(m) - 1;
+        m &= m - 1u;
+        due[pos++] = (uint32_t)(lane * kKeyRun + b);
+      }
+      const uint32_t cnt = (uint32_t)__shfl((int)incl, 63, 64);
       if (lane == 0) s_wave[v] = cnt;
       __syncthreads();
       unsigned long long pre;
@@ -1131,10 +1174,7 @@ __device__ void convert_role(GapDev* __restrict__ gaps, const long long* __restr
       __syncthreads();
       const unsigned long long base = s_base[0] + pre;
       for (uint32_t q = (uint32_t)lane; q < cnt; q += 64) {
-        const uint32_t e = due[q];
-        long long i0, i1;
-        convert_item(rb0, rb1, rt0, rt1, x + (long long)(e / kPhChunk) - wg0, i0, i1);
-        const long long i = i0 + (long long)(e % kPhChunk);
+        const long long i = ib + (long long)due[q];
         const long long X = phx[i];
         const uint64_t ch = phc[i];
         const int c = (int)(X >> K);
@@ -1157,9 +1197,9 @@ __device__ void convert_role(GapDev* __restrict__ gaps, const long long* __restr
 // (for its re-sort); frozen gaps get none.
 struct PlanIn {
   bool ok;
-  int table_len;
+  int table_len, ph_age;
   unsigned long long n0, n1, n_ph, body_n;
-  long long step, ph_base;
+  long long step, ph_base, ph_cap;
   const int32_t* bucket;
 };
 
@@ -1173,6 +1213,8 @@ __device__ __forceinline__ PlanIn plan_in(const GapDev* G) {
   p.body_n = G->ph_body_n;
   p.step = G->step;
   p.ph_base = G->ph_base;
+  p.ph_age = G->ph_age;
+  p.ph_cap = G->ph_cap;
   p.bucket = G->ph_bucket;
   return p;
 }
@@ -1187,8 +1229,9 @@ __device__ __forceinline__ void plan_items(const PlanIn& p, long long& a, long l
     b0 = k == 0 ? 0 : (long long)p.bucket[k - 1];
     b1 = (long long)p.bucket[k];
   }
-  b = (b1 - b0 + kPhChunk - 1) / kPhChunk + ((long long)(p.n_ph - p.body_n) + kPhChunk - 1) / kPhChunk;
-  if (p.table_len > 0) c = ((long long)p.n_ph + kPhChunk - 1) / kPhChunk;
+  b = (b1 - b0 + kPhChunk - 1) / kPhChunk + tail_items((long long)p.body_n, (long long)p.n_ph);
+  if (photon_sort_due(p.table_len, p.step, p.ph_base, p.ph_age, p.n_ph, p.ph_cap))
+    c = ((long long)p.n_ph + kPhChunk - 1) / kPhChunk;
 }
 
 // Exclusive prefix sums of three values over a block of up to 1024 threads
@@ -1308,6 +1351,8 @@ __device__ __forceinline__ PlanIn finalize_gap(GapDev* __restrict__ G) {
   out.table_len = table_len;
   out.body_n = body_n;
   out.ph_base = ph_base;
+  out.ph_age = G->ph_age;
+  out.ph_cap = G->ph_cap;
   out.bucket = bucket;
   if (status != PIC_OK) return out;
   // what this step appended: dp pairs (in place or converted), dph photons
@@ -1798,10 +1843,19 @@ __global__ __launch_bounds__(kBlock) void k_tail_copy(GapDev* __restrict__ gaps,
 
 // ---- photon store: counting sort by conversion step, dropping the photons
 // that converted or escaped.
+// The photon store is sorted by a re-sort only when photon_sort_due says so
+// (the plan of the step gave its chunks to the sort on the same condition).
 __global__ __launch_bounds__(kBlock) void k_ph_zero(GapDev* __restrict__ gaps, int B) {
   GapDev* __restrict__ G = gaps + blockIdx.x;
+  const bool due = G->status == PIC_OK &&
+                   photon_sort_due(G->table_len, G->step, G->ph_base, G->ph_age, G->n_ph, G->ph_cap);
+  __syncthreads();  // every thread has read the state before thread 0 writes the flag
+  if (threadIdx.x == 0) {
+    G->ph_due = due ? 1 : 0;
+    G->ph_sorted = 0;
+  }
+  if (!due) return;
   for (int k = threadIdx.x; k <= G->table_len; k += kBlock) G->ph_bucket[k] = 0;
-  if (threadIdx.x == 0) G->ph_sorted = 0;
 }
 
 // Counting sort of the photon store by conversion step (key = step - now),
@@ -1825,7 +1879,7 @@ __global__ __launch_bounds__(kBlock) void k_ph_pass(GapDev* __restrict__ gaps,
     const long long p0 = (w - qwi[g]) * kPhChunk;
     const long long p1 = (wend - qwi[g]) * kPhChunk < nP ? (wend - qwi[g]) * kPhChunk : nP;
     w = wend;
-    if (G->status != PIC_OK || G->table_len == 0) continue;
+    if (G->status != PIC_OK || G->table_len == 0 || !G->ph_due) continue;
     const int pb = G->phbuf;
     const long long stepn = G->step;
     const int L = G->table_len;
@@ -1926,7 +1980,7 @@ __global__ __launch_bounds__(kBlock) void k_ph_pass(GapDev* __restrict__ gaps,
 __global__ __launch_bounds__(1024) void k_ph_scan(GapDev* __restrict__ gaps, int B) {
   __shared__ long long s_sum[1024];
   GapDev* __restrict__ G = gaps + blockIdx.x;
-  if (G->status != PIC_OK || G->table_len == 0) return;
+  if (G->status != PIC_OK || G->table_len == 0 || !G->ph_due) return;
   const long long tot = block_scan_counts(G->ph_bucket, G->table_len, s_sum);
   if (threadIdx.x == blockDim.x - 1) G->ph_sorted = (unsigned long long)tot;
 }
@@ -1945,7 +1999,7 @@ __global__ __launch_bounds__(1024) void k_sort_finish(GapDev* __restrict__ gaps,
       G->dead[s] = 0;
     }
     G->buf ^= 1;
-    if (G->table_len > 0) {
+    if (G->ph_due) {
       G->n_ph = G->ph_sorted;
       G->n_ph_next = G->ph_sorted;
       G->ph_body_n = G->ph_sorted;

@@ -36,7 +36,7 @@ struct GapLayout {
   size_t E, Ef, F, F_last, rho, table, sort_cnt[2], hist;
   size_t cell[2][2], off[2][2], p[2][2], id[2][2];
   size_t ph_x[2], ph_step[2], ph_child[2];
-  size_t ph_bucket;
+  size_t ph_bucket, ph_key;
   size_t end;
   int64_t table_len;
 };
@@ -54,6 +54,20 @@ int grid_for_items(long long want) {
 }
 
 int offset_bits(int precision) { return precision == PIC_MIXED ? 24 : 40; }
+
+// Steps the unsorted photon tail may grow before a re-sort sorts the store.
+// Each step scans one key byte per tail photon, a sort moves about 64 bytes
+// per stored photon, and photons stay about m = 1 / (1 - q) steps in the
+// store (q = exp(-dt / (l_gamma dx))): scanning a tail of R a photons over a
+// steps against sorting R (m + a) photons every a steps costs least near
+// a = sqrt(128 m).
+int photon_sort_age(const pic_gap_params& p) {
+  if (!(p.l_gamma > 0.0)) return pic::kPhAgeMax;
+  const double q = std::exp(-p.dt / (p.l_gamma * p.dx));
+  const double m = 1.0 / (1.0 - q);
+  const double a = std::sqrt(128.0 * m);
+  return a >= (double)pic::kPhAgeMax ? pic::kPhAgeMax : (a < 1.0 ? 1 : (int)a);
+}
 
 // Photon conversion table T_k = floor(exp(-k dt / (l_gamma dx)) 2^32), until 0.
 int64_t table_length(const pic_gap_params& p) {
@@ -181,6 +195,8 @@ Layout make_layout(const pic_gap_params* prm, int B) {
       G.ph_child[b] = o; o = align_up(o + 8 * pc);
     }
     G.ph_bucket = o; o = align_up(o + 4 * ((size_t)G.table_len + 1));
+    // tail keys, read 16 at a time from 16-byte boundaries below the store's end
+    G.ph_key = o; o = align_up(o + (pc + 15) / 16 * 16);
     G.end = o;
     L.cell_items += ((long long)p.n_cells + pic::kCellChunk - 1) / pic::kCellChunk;
   }
@@ -391,7 +407,9 @@ pic_status create_batch(const pic_gap_params* params, int n_gaps, void* d_ws, si
       G.ph_child[bb] = reinterpret_cast<uint64_t*>(ws + GL.ph_child[bb]);
     }
     G.ph_bucket = reinterpret_cast<int32_t*>(ws + GL.ph_bucket);
+    G.ph_key = reinterpret_cast<uint8_t*>(ws + GL.ph_key);
     G.inv_lnq = p.l_gamma > 0.0 ? (float)(-p.l_gamma * p.dx / p.dt) : 0.0f;
+    G.ph_age = photon_sort_age(p);
     cwi[(size_t)i + 1] = cwi[(size_t)i] + ((long long)p.n_cells + pic::kCellChunk - 1) / pic::kCellChunk;
 
     // initial field and zeroed flux; conversion table
@@ -495,8 +513,11 @@ pic_status eager_step(pic_batch* b) {
         if (st != PIC_OK) return st;
       } else {
         for (int e = 0; e < 2; ++e) {
+          // timing only: no system-scope fence (and its cache write-back)
+          // when the push completes, which would be counted in its time
           hipEvent_t h;
-          if (hipEventCreate(&h) != hipSuccess) return PIC_ERR_DEVICE;
+          if (hipEventCreateWithFlags(&h, hipEventDisableSystemFence) != hipSuccess)
+            return PIC_ERR_DEVICE;
           b->ev.push_back(h);
         }
       }

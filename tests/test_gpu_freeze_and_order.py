@@ -172,3 +172,30 @@ def test_diagnostics_do_not_depend_on_lepton_order(precision):
     # the energies are binary64 re-evaluations from the stored momenta
     ho = go.history()
     assert np.max(np.abs(runs[0]["kinetic"] - ho["kinetic"]) / ho["kinetic"]) < 1e-12
+
+
+@pytest.mark.parametrize("precision", [workloads.FP64, workloads.MIXED])
+def test_photon_tail_past_the_key_horizon(precision):
+    """Re-sorts 300 steps apart: between steps 255 and 300 after a sort the
+    unsorted photons are found by their stored conversion steps instead of
+    their one-byte keys.  History and photons in flight stay the oracle's
+    across that range and across the sorts."""
+    cfg = workloads.config("c1_fp64_reference_gap")
+    cfg.update(precision=precision, history_rows=800)
+    go = pc.make_oracle(cfg)
+    gg = pc.make_gpu(cfg, sort_every=300)
+    done = 0
+    for n in (250, 10, 40, 5, 295, 50):  # ends of steps 249, 259, 299, 304, 599, 649
+        assert go.step(n) == 0
+        gg.step_n(n)
+        done += n
+        a, b = gg.read_photons(), go.photons()
+        key = lambda d: np.lexsort((d["child"], d["dir"], d["conv_step"], d["xq"]))  # noqa: E731
+        ka, kb = key(a), key(b)
+        assert len(ka) == len(kb), (done, len(ka), len(kb))
+        for k in ("xq", "conv_step", "dir", "child"):
+            assert np.array_equal(np.asarray(a[k])[ka], np.asarray(b[k])[kb]), (done, k)
+    h = gg.read_history()
+    pc.compare_history(h, go.history())
+    # photons converted in the range the keys do not cover
+    assert h["pairs_created"][298] > h["pairs_created"][256]

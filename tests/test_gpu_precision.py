@@ -1,0 +1,242 @@
+"""Error of the mixed-precision path against the binary64 oracle, per result
+(needs a GPU).
+
+The mixed path pushes in binary32 (momentum, offset on a 2^-24 grid) and
+keeps the current exact, E and every diagnostic in binary64.  Its results are
+compared here with the binary64 oracle on the same seeded inputs, not with
+the binary32-emulating oracle mode the parity tests use:
+
+  - configuration 3 (mixed) against configuration 1 run by the binary64
+    oracle, step by step: counts, and at checkpoints the momenta joined by
+    id, E and total energy, up to the first step at which a count differs
+    (an emission or absorption decided one step apart: from there the two
+    are different trajectories of the same physics), measured against the
+    binary64 oracle's own sensitivity to a binary32-sized perturbation;
+  - the large gap (65536 cells) in mixed precision against the stored
+    binary64 oracle history of its first 200 steps (energy conservation);
+  - the binary64 single gap (8192 cells) against the stored binary64 oracle
+    statistics of its first 3000 steps: growth rate (section 3), screening,
+    amplitude and frequency of the <E> oscillation (section 5); exact in
+    binary64, within stated tolerances in mixed precision.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import workloads
+from tests import cascade_stats as cs
+from tests import pic_cases as pc
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+CHECKPOINTS = (1, 5, 10, 20, 50, 100, 200, 300, 500, 1000, 2000)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2012_05587_amd as P
+    P.lib()
+    yield
+
+
+def _total_energy(h):
+    return h["kinetic"] + h["field"] + h["photon_energy"] + h["lost_energy"]
+
+
+def _join(a, b):
+    """Momenta and positions of the leptons present in both, joined by id."""
+    ia, ib = np.argsort(a["id"]), np.argsort(b["id"])
+    ida, idb = a["id"][ia], b["id"][ib]
+    common, ja, jb = np.intersect1d(ida, idb, assume_unique=True, return_indices=True)
+    pa, pb = a["p"][ia][ja], b["p"][ib][jb]
+    xa = a["cell"][ia][ja] + a["off"][ia][ja]
+    xb = b["cell"][ib][jb] + b["off"][ib][jb]
+    return common.size, pa, pb, xa, xb
+
+
+def _first_count_difference(ha, hb):
+    first = None
+    for k in pc.HIST_INT:
+        n = min(len(ha), len(hb))
+        bad = np.nonzero(ha[k][:n] != hb[k][:n])[0]
+        if bad.size:
+            d = int(ha["step"][bad[0]])
+            first = d if first is None else min(first, d)
+    return first
+
+
+def _difference(read_a, read_b, fields_a, fields_b):
+    """Normwise differences of two runs: max |dp| over the largest |p|, and
+    max |dE| over max |E|; leptons joined by id."""
+    dp, pmax, n_common = 0.0, 0.0, 0
+    for s in (0, 1):
+        n, pa, pb, _, _ = _join(read_a(s), read_b(s))
+        n_common += n
+        if n:
+            dp = max(dp, float(np.max(np.abs(pa - pb))))
+            pmax = max(pmax, float(np.max(np.abs(pb))))
+    Ea, Eb = fields_a(), fields_b()
+    return dp / max(pmax, 1.0), float(np.max(np.abs(Ea - Eb)) / np.max(np.abs(Eb))), n_common
+
+
+def _perturbed_oracle(cfg, reference, seed=5):
+    """The binary64 oracle gap of cfg with every seeded offset moved by one
+    step of the binary32 grid (2^-24 cells, random sign), same ids."""
+    import oracle
+    g = oracle.OracleGap(**pc.gap_kwargs(cfg), capacity=0)
+    for s in (0, 1):
+        P = reference.particles(s)
+        rng = np.random.default_rng(seed + s)
+        off = P["off"] + rng.choice([-1.0, 1.0], P["off"].size) * 2.0 ** -24
+        off = np.clip(off, 0.0, 1.0 - 2.0 ** -40)
+        g.seed_explicit(s, P["cell"], off, P["p"], P["id"])
+    return g
+
+
+def test_mixed_gpu_against_binary64_oracle_configuration_1():
+    """Configuration 3 on the GPU (mixed) against configuration 1 in the
+    binary64 oracle, with the oracle's own sensitivity beside it: a second
+    binary64 run whose seeds sit one binary32 grid step (2^-24 cells) away.
+
+    The cascade amplifies any difference exponentially (the perturbed
+    binary64 run leaves the first one as fast), so no fixed tolerance holds
+    over the run.  The mixed path rounds momentum (relative u = 2^-24) and
+    position (2^-24 cells) once per step; each rounding grows at most as the
+    seed perturbation does, and after n steps there are n of them.  While
+    the counts agree the test asserts, for the momenta (normwise: max |dp|
+    over the largest |p|, since a lepton at its turning point has |p| far
+    below the impulse it has taken) and for E (max |dE| over max |E|):
+
+        difference(n) <= 8 n u + n * perturbed difference(n),
+
+    and that the counts of the mixed run part from the oracle's no earlier
+    than four fifths of the step at which the perturbed run's do."""
+    c1 = workloads.config("c1_fp64_reference_gap")
+    c3 = workloads.config("c3_mixed_single_gap")
+    assert {k: v for k, v in c1.items() if k != "precision"} == \
+        {k: v for k, v in c3.items() if k != "precision"}
+    go = pc.make_oracle(c1)
+    gp = _perturbed_oracle(c1, go)
+    gg = pc.make_gpu(c3, history_rows=c3["steps"] + 8)
+    done, rows, diverged, diverged_p = 0, [], None, None
+    for cp in CHECKPOINTS:
+        assert go.step(cp - done) == 0 and gp.step(cp - done) == 0
+        gg.step_n(cp - done)
+        done = cp
+        ho, hg, hp = go.history(), gg.read_history(), gp.history()
+        if diverged is None:
+            diverged = _first_count_difference(hg, ho)
+        if diverged_p is None:
+            diverged_p = _first_count_difference(hp, ho)
+        dp, dE, n_common = _difference(gg.read_particles, go.particles,
+                                       lambda: gg.read_fields(rho=False)["E"],
+                                       lambda: go.fields()["E"])
+        dp_p, dE_p, _ = _difference(gp.particles, go.particles,
+                                    lambda: gp.fields()["E"], lambda: go.fields()["E"])
+        Wg, Wo = _total_energy(hg), _total_energy(ho)
+        cons_g, cons_o = float(Wg[-1] / Wg[0] - 1), float(Wo[-1] / Wo[0] - 1)
+        rows.append((cp, diverged is None, n_common, dp, dp_p, dE, dE_p, cons_g, cons_o))
+    print("\nstep  counts-agree  joined  dp mixed  dp perturbed  dE mixed  dE perturbed  "
+          "W/W0-1 mixed  W/W0-1 binary64")
+    for r in rows:
+        print(f"{r[0]:5d}  {str(r[1]):5s}  {r[2]:7d}  {r[3]:.3e}  {r[4]:.3e}  {r[5]:.3e}  {r[6]:.3e}"
+              f"  {r[7]:+.4e}  {r[8]:+.4e}")
+    print("first step with a different count: mixed", diverged, "perturbed binary64", diverged_p,
+          flush=True)
+    u = 2.0 ** -24
+    for r in rows:
+        if r[1]:
+            n = r[0]
+            assert r[3] <= 8 * n * u + n * r[4], r
+            assert r[5] <= 8 * n * u + n * r[6], r
+    assert diverged_p is not None
+    assert diverged is None or diverged >= 0.8 * diverged_p, (diverged, diverged_p)
+
+
+def _load_rows(path):
+    names = None
+    data = []
+    with open(path) as f:
+        for line in f:
+            if line.startswith("#"):
+                names = line[1:].split()
+                continue
+            data.append([float(x) for x in line.split()])
+    arr = np.array(data)
+    return {n: arr[:, i] for i, n in enumerate(names)}
+
+
+def test_large_gap_mixed_energy_against_binary64_oracle():
+    """The large gap (65536 cells, E0 = 1000, 16384 seed pairs) in mixed
+    precision against the stored binary64 oracle history of its first 200
+    steps: energy conservation W(n)/W(0) - 1 within 1e-4 of the oracle's at
+    every step, and lepton counts within 1%."""
+    golden = _load_rows(os.path.join(GOLDEN, "c5_fp64_oracle_200_steps.txt"))
+    cfg = workloads.config("c5_large_mixed")
+    print("[case] large gap mixed, 200 steps", flush=True)
+    gg = pc.make_gpu(cfg, history_rows=256)
+    gg.step_n(200)
+    h = gg.read_history()
+    assert len(h) == 200 and np.array_equal(h["step"], golden["step"].astype(np.int64))
+    Wg = _total_energy(h)
+    Wo = golden["kinetic"] + golden["field"] + golden["photon_energy"] + golden["lost_energy"]
+    err_g, err_o = Wg / Wg[0] - 1.0, Wo / Wo[0] - 1.0
+    worst = float(np.max(np.abs(err_g - err_o)))
+    nl = h["n_minus"] + h["n_plus"]
+    no = golden["n_minus"] + golden["n_plus"]
+    dn = float(np.max(np.abs(nl - no) / no))
+    print(f"energy error at step 200: mixed {err_g[-1]:+.5e}, binary64 oracle {err_o[-1]:+.5e}; "
+          f"largest difference {worst:.3e}; largest relative count difference {dn:.3e}")
+    assert worst <= 1e-4
+    assert dn <= 1e-2
+
+
+def _golden_stats():
+    out = {}
+    with open(os.path.join(GOLDEN, "c2_fp64_oracle_statistics.txt")) as f:
+        for line in f:
+            if line.startswith("#"):
+                continue
+            k, *v = line.split()
+            out[k] = v
+    return out
+
+
+@pytest.mark.parametrize("precision", [workloads.FP64, workloads.MIXED])
+def test_single_gap_statistics_against_binary64_oracle(precision):
+    """The single gap (8192 cells) over 3000 steps against the stored binary64
+    oracle statistics: in binary64 the history is the oracle's bit for bit, so
+    the statistics agree to rounding; in mixed precision the growth rate
+    agrees within 2%, the screening step within 3 steps, and the amplitude and
+    frequency of the <E> oscillation within 5% and 2%."""
+    gold = _golden_stats()
+    cfg = workloads.config("c2_fp64_single_gap")
+    cfg["precision"] = precision
+    print(f"[case] single gap statistics prec={precision}", flush=True)
+    gg = pc.make_gpu(cfg, history_rows=3008)
+    gg.step_n(3000)
+    h = gg.read_history()
+    dt = cfg["dt"]
+    n0 = cfg["n_pairs"] * cfg["macro_per_pair"]
+    rate, a, b = cs.growth_rate(h["n_minus"], dt, n0)
+    ts = cs.screening_step(h["e_mean"])
+    omega, amp, _ = cs.oscillation(h["e_mean"], dt, ts)
+    g_rate, g_ts = float(gold["growth_rate"][0]), int(gold["screening_step"][0])
+    g_omega, g_amp = float(gold["omega"][0]), float(gold["amplitude"][0])
+    print(f"growth {rate:.6f} (oracle {g_rate:.6f}), screening {ts} ({g_ts}), "
+          f"omega {omega:.6f} ({g_omega:.6f}), amplitude {amp:.5f} ({g_amp:.5f})")
+    if precision == workloads.FP64:
+        assert np.array_equal(h["n_minus"][:g_ts + 1],
+                              np.array([int(x) for x in gold["n_minus"]], dtype=np.int64))
+        assert abs(rate / g_rate - 1) < 1e-9 and ts == g_ts
+        assert abs(omega / g_omega - 1) < 1e-9 and abs(amp / g_amp - 1) < 1e-9
+    else:
+        assert abs(rate / g_rate - 1) < 0.02
+        assert abs(ts - g_ts) <= 3
+        assert abs(omega / g_omega - 1) < 0.02
+        assert abs(amp / g_amp - 1) < 0.05
