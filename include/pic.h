@@ -42,8 +42,11 @@
  *    absorbed leptons keep their slots until the next re-sort, and a step
  *    whose appends do not fit the slots although the live leptons stay
  *    within capacity freezes the gap the same way with PIC_ERR_SLOTS.  The
- *    photon store has `photon_capacity` slots, reclaimed at re-sorts; a step
- *    that overflows it freezes with PIC_ERR_CAPACITY.
+ *    photon store has `photon_capacity` slots; converted and escaped photons
+ *    keep theirs until the store is re-sorted, which a particle re-sort does
+ *    once the store has gone unsorted for sqrt(128 m) steps (m the mean
+ *    number of steps to conversion, at most 160) or is half full.  A step
+ *    that overflows the store freezes with PIC_ERR_CAPACITY.
  *  - Non-finite momenta freeze the gap with PIC_ERR_NONFINITE the same way.
  */
 #ifndef PIC_H
@@ -99,7 +102,7 @@ enum { PIC_ELECTRON = 0, PIC_POSITRON = 1 };
  *            gap freezes, see Capacity above); below 2^31 with its slot
  *            reserve.
  *  photon_capacity  slots of the photon store (l_gamma > 0); converted and
- *            escaped photons are reclaimed at re-sorts.
+ *            escaped photons are reclaimed when the store is re-sorted.
  *  seed      key of the Philox4x64-10 streams of this gap.
  *  precision PIC_FP64: per-particle arithmetic in binary64, offsets on a
  *            2^-40 cell grid.  PIC_MIXED: binary32 push, offset (2^-24 grid)
