@@ -33,6 +33,24 @@ import workloads  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_PUSH = {workloads.FP64: 40, workloads.MIXED: 24}
+# The push kernel also emits: a stored photon writes x 8 + conversion step 4
+# + child 8 + tail key 1 bytes; an in-place pair writes two leptons (cell 4 +
+# offset + momentum + id 8 each).
+BYTES_PER_PHOTON = 21
+BYTES_PER_CHILD = {workloads.FP64: 28, workloads.MIXED: 20}
+
+
+def push_alg_bytes(views, gaps, precision):
+    """Algorithmic bytes the push kernel moved over a run of these gaps:
+    24 (40) B per push, plus each emission's writes (the emitters' id reads
+    are not counted)."""
+    total = 0
+    for v, c in zip(views, gaps):
+        m = v.read_moments()
+        emitted = int(m.last.photons_emitted)
+        per = BYTES_PER_PHOTON if c["l_gamma"] > 0 else 2 * BYTES_PER_CHILD[precision]
+        total += BYTES_PER_PUSH[precision] * int(m.pushes) + per * emitted
+    return total
 DTYPE = {workloads.FP64: "f64", workloads.MIXED: "f32/f64"}
 METRIC = "particle-pushes/sec + % HBM roofline, mixed-batched vs plain FP64, 1 MI355X"
 # Timed steps when --steps is not given.  The single gap of 8192 cells at
@@ -203,6 +221,8 @@ def run_gpu(gaps, steps, warmup=0, reps=5, profile=True, dump=None):
         # the evented run repeats the same steps and pushes the same leptons
         again = sum(int(x.read_moments().pushes) for x in views)
         out.update(push_ms=push_ms, push_launches=launches, evented_pushes=again,
+                   evented_bytes=push_alg_bytes(views, gaps, gaps[0]["precision"]),
+                   evented_photons=sum(int(x.read_moments().last.photons_emitted) for x in views),
                    evented_tuning=g.tuning())
         g.close()
         del g, views
@@ -215,7 +235,8 @@ def run_counter_pass(gaps, steps):
     """A bounded run for hardware-counter passes: the workload's first
     `steps` steps launched directly (no graphs), one step at a time, printing
     a line after each, so that a profiler serialising every dispatch still
-    shows progress.  Prints a JSON line with the leptons pushed per step."""
+    shows progress.  Prints a JSON line with the leptons pushed and the push
+    kernel's algorithmic bytes per step."""
     import torch
     import paper_2012_05587_amd as P
     P.lib()
@@ -223,15 +244,19 @@ def run_counter_pass(gaps, steps):
     g, views = _make(P, gaps, None)
     g.prepare()
     torch.cuda.synchronize()
-    per_step = []
+    per_step, bytes_step = [], []
+    prec = gaps[0]["precision"]
     for k in range(steps):
         before = sum(int(v.read_moments().pushes) for v in views)
+        b0 = push_alg_bytes(views, gaps, prec)
         g.step_n(1)
         torch.cuda.synchronize()
         after = sum(int(v.read_moments().pushes) for v in views)
         per_step.append(after - before)
+        bytes_step.append(push_alg_bytes(views, gaps, prec) - b0)
         print(f"[pmc] step {k + 1}/{steps}: {after - before} leptons pushed", flush=True)
-    print(json.dumps({"counter_pass": True, "steps": steps, "pushes_per_step": per_step}), flush=True)
+    print(json.dumps({"counter_pass": True, "steps": steps, "pushes_per_step": per_step,
+                      "alg_bytes_per_step": bytes_step}), flush=True)
     g.close()
 
 
@@ -437,7 +462,8 @@ def summarize(args):
         assert len(fetch) == len(write) == len(pushes), (len(fetch), len(write), len(pushes))
         fb = fetch * ff * 1024.0
         wb = write * wf * 1024.0
-        alg_step = pushes * bpp
+        alg_step = (np.array(cp["alg_bytes_per_step"], dtype=float) if "alg_bytes_per_step" in cp
+                    else pushes * bpp)
         traffic = float(np.mean(fb + wb))
         prof["pmc"] = {"steps": int(len(pushes)), "fetch_factor": ff, "write_factor": wf,
                        "copy_dispatches": [nf, nw],
@@ -453,7 +479,7 @@ def summarize(args):
                   f"write WRITE_SIZE {1024 * 1024 / wf:.0f} KiB each (factors {ff:.3f}, {wf:.3f})",
                   f"- per launch, averaged over the {len(pushes)} steps: read {np.mean(fb) / 1e6:.2f} MB, "
                   f"written {np.mean(wb) / 1e6:.2f} MB, total {traffic / 1e6:.2f} MB against "
-                  f"{np.mean(alg_step) / 1e6:.2f} MB algorithmic ({bpp} B per push): ratio "
+                  f"{np.mean(alg_step) / 1e6:.2f} MB algorithmic ({bpp} B per push, {BYTES_PER_PHOTON} B per photon emitted): ratio "
                   f"{traffic / np.mean(alg_step):.3f}", "",
                   "| step | leptons pushed | read MB | written MB | traffic / algorithmic |",
                   "|---|---|---|---|---|"]
@@ -489,12 +515,11 @@ def host_cpu_model():
 
 
 def _leg(r, precision):
-    bpp = BYTES_PER_PUSH[precision]
     leg = dict(value=r["pushes"] / r["seconds"], unit="pushes/s", pushes=r["pushes"],
                seconds=r["seconds"], steps=r["steps"], frozen_gaps=r["frozen"],
                run_seconds=r["run_seconds"])
     if r["push_ms"]:
-        leg["push_kernel_GBs"] = r["evented_pushes"] * bpp / (r["push_ms"] * 1e-3) / 1e9
+        leg["push_kernel_GBs"] = r["evented_bytes"] / (r["push_ms"] * 1e-3) / 1e9
     return leg
 
 
@@ -584,7 +609,7 @@ def main():
         print(json.dumps({"timed_only": True, "workload": args.workload, "steps": main_run["steps"],
                           "pushes": main_run["pushes"], "value": value}), flush=True)
         return
-    achieved = main_run["evented_pushes"] * bpp / (main_run["push_ms"] * 1e-3) / 1e9
+    achieved = main_run["evented_bytes"] / (main_run["push_ms"] * 1e-3) / 1e9
 
     extra = {}
     if not args.no_compare:
@@ -652,12 +677,13 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": pmc["traffic_bytes_per_launch"] if pmc else None,
                      "traffic_unit": "B/launch",
-                     "alg_bytes_per_launch": main_run["evented_pushes"] * bpp / max(main_run["push_launches"], 1),
+                     "alg_bytes_per_launch": main_run["evented_bytes"] / max(main_run["push_launches"], 1),
                      "evented_run": {"pushes": main_run["evented_pushes"],
+                                     "photons_emitted": main_run["evented_photons"],
                                      "sort_every": main_run["evented_tuning"]["sort_every"],
                                      "switches": main_run["evented_tuning"]["switches"]},
                      "copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs,
-                     "kernel": "k_push", "bytes_per_push": bpp,
+                     "kernel": "k_push", "bytes_per_push": bpp, "bytes_per_photon": BYTES_PER_PHOTON,
                      "kernel_ms": main_run["push_ms"], "launches": main_run["push_launches"]},
         "cpu_baseline": cpu,
     }

@@ -190,7 +190,9 @@ __device__ __forceinline__ U64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_
                                                uint64_t c3, uint64_t k0, uint64_t k1) {
   const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
   const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
-#pragma unroll
+  // rounds kept as a loop: unrolled, the scheduler interleaves them and
+  // holds far more registers than one round needs
+#pragma unroll 1
   for (int r = 0; r < 10; ++r) {
     if (r > 0) { k0 += W0; k1 += W1; }
     uint64_t hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
@@ -349,6 +351,23 @@ __device__ __forceinline__ I wave_incl_scan(I x) {
     I y = __shfl_up(x, d, 64);
     if (l >= d) x += y;
   }
+  return x;
+}
+
+// Inclusive prefix sum of ints over the 64 lanes of a wave with DPP moves
+// (rows of 16 lanes by shifts of 1, 2, 4 and 8, then the row totals
+// broadcast to the rows above): no lane masks or shuffle addresses, which a
+// caller's loop would otherwise keep in registers throughout.
+__device__ __forceinline__ int wave_incl_scan_dpp(int x) {
+  // dpp_ctrl row_shr:n = 0x110 + n; lanes shifted in from below the row read 0
+  x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);
+  x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);
+  x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);
+  x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);
+  // row_bcast:15 (0x142) adds lane 15's total to row 1 and lane 47's to row 3;
+  // row_bcast:31 (0x143) adds lane 31's to rows 2 and 3
+  x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);
+  x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);
   return x;
 }
 

@@ -4,15 +4,15 @@
 //   k_push     gather E at each lepton, relativistic push, move with an exact
 //              integer charge-conserving flux (per-workgroup LDS tile reduced
 //              into the global int64 grid), absorb/wrap, and the threshold
-//              test: the emitter loses k * gamma_pair and is listed;
-//              instantiated with the linear or quadratic-spline shape and
-//              with or without per-lepton thresholds;
-//   k_post     four roles on disjoint block ranges of one launch: Ampere's
-//              law E -= w 2^-K F (Eq. 4 in normalised units; plus j_m dt in
-//              the co-rotating frame) with the field diagnostics; the listed
+//              test: the emitter loses k * gamma_pair, and each chunk's
 //              emitters draw their photons (or in-place pairs) from Philox
-//              and append them; photons due this step become pairs; the
-//              striped push tallies are folded;
+//              and append them; instantiated with the linear or
+//              quadratic-spline shape and with or without per-lepton
+//              thresholds;
+//   k_post     three roles on disjoint block ranges of one launch: Ampere's
+//              law E -= w 2^-K F (Eq. 4 in normalised units; plus j_m dt in
+//              the co-rotating frame) with the field diagnostics; photons due
+//              this step become pairs; the striped push tallies are folded;
 //   k_finalize counters, history row and the work plan of the next step.
 // Every S steps the leptons are re-sorted by cell and the photon store by
 // conversion step (counting sorts), which drops absorbed leptons and
@@ -39,8 +39,7 @@ __device__ __forceinline__ unsigned long long as_u64(long long v) { return (unsi
 // n_conv = min{k >= 1 : u >= T_k} over the decreasing integer table T
 // (T_{len-1} = 0).  T_k ~ q^k 2^32, so k ~ ln(u 2^-32) / ln q; the estimate
 // only picks where to look: the answer is decided by the table entries.
-__device__ __forceinline__ int conv_steps(const uint32_t* __restrict__ table, int len, uint32_t u,
-                                         float inv_lnq) {
+__device__ __forceinline__ int conv_estimate(int len, uint32_t u, float inv_lnq) {
   int k;
   if (u == 0u) {
     k = len - 1;
@@ -48,11 +47,13 @@ __device__ __forceinline__ int conv_steps(const uint32_t* __restrict__ table, in
     const float est = __logf((float)u * 2.3283064365386963e-10f) * inv_lnq;
     k = (int)ceilf(est);
   }
-  k = k < 1 ? 1 : (k > len - 1 ? len - 1 : k);
-  // the estimate is within a step of the answer: the entries around it are
-  // requested together (T_{len-1} = 0, so some k answers)
-  const uint32_t tm = table[k - 1 > 0 ? k - 1 : 0], t0 = table[k];
-  const uint32_t tp = table[k + 1 < len ? k + 1 : len - 1];
+  return k < 1 ? 1 : (k > len - 1 ? len - 1 : k);
+}
+
+// The answer from the estimate k and the entries T_{k-1}, T_k, T_{k+1}
+// around it (clamped to the table), which the caller requested together.
+__device__ __forceinline__ int conv_decide(const uint32_t* __restrict__ table, int len, uint32_t u,
+                                          int k, uint32_t tm, uint32_t t0, uint32_t tp) {
   int lo = 1, hi = len - 1;
   if (u >= t0) {
     if (k == 1 || u < tm) return k;
@@ -67,6 +68,29 @@ __device__ __forceinline__ int conv_steps(const uint32_t* __restrict__ table, in
     if (u >= table[mid]) hi = mid; else lo = mid + 1;
   }
   return lo;
+}
+
+__device__ __forceinline__ int conv_steps(const uint32_t* __restrict__ table, int len, uint32_t u,
+                                         float inv_lnq) {
+  const int k = conv_estimate(len, u, inv_lnq);
+  // the estimate is within a step of the answer: the entries around it are
+  // requested together (T_{len-1} = 0, so some k answers)
+  const uint32_t tm = table[k - 1 > 0 ? k - 1 : 0], t0 = table[k];
+  const uint32_t tp = table[k + 1 < len ? k + 1 : len - 1];
+  return conv_decide(table, len, u, k, tm, t0, tp);
+}
+
+// X modulo the domain length D, in [0, D), for |X| < 2^62 and D >= 2^24
+// (a photon's conversion point in a periodic gap): the quotient taken in
+// binary64 is within one of the true floor (its magnitude is below 2^38, so
+// its rounding error is far below one), and the remainder is then brought
+// into range exactly in integers.
+__device__ __forceinline__ long long wrap_periodic(long long X, long long D) {
+  const long long q = (long long)floor((double)X / (double)D);
+  X -= q * D;
+  if (X < 0) X += D;
+  else if (X >= D) X -= D;
+  return X;
 }
 
 // Block-wide min and max of ints; every thread gets the result.
@@ -101,6 +125,225 @@ __device__ __forceinline__ void block_minmax_pp(int& mn, int& mx, int (*s_red)[8
   __syncthreads();
   mn = min(min(r[0], r[1]), min(r[2], r[3]));
   mx = max(max(r[4], r[5]), max(r[6], r[7]));
+}
+
+// Per-wave shares of a workgroup's total: s_wave[v] holds wave v's count on
+// entry; returns the block total and sets `pre` to the counts of the waves
+// before this one.  Every thread must call it.
+__device__ __forceinline__ unsigned long long wave_shares(const unsigned long long* s_wave,
+                                                          unsigned long long& pre) {
+  const int v = threadIdx.x >> 6;
+  unsigned long long t = 0;
+  pre = 0;
+#pragma unroll
+  for (int k = 0; k < kBlock / 64; ++k) {
+    if (k < v) pre += s_wave[k];
+    t += s_wave[k];
+  }
+  return t;
+}
+
+// Lanes below this one in the wave.
+__device__ __forceinline__ unsigned long long lanes_below() {
+  return (1ull << lane_id()) - 1ull;
+}
+
+// Pairs of a step share one slot cursor: the workgroup reserves `tot` pairs
+// (electron slots from n[0], positron slots from n[1]).  Appends beyond the
+// slots are not written and freeze the gap; the capacity itself (live
+// leptons) is checked by the finalize.
+__device__ __forceinline__ unsigned long long reserve_pairs(GapDev* G, unsigned long long tot) {
+  const unsigned long long b = atomicAdd(&G->pair_next, tot);
+  const unsigned long long slots = (unsigned long long)G->slots;
+  if (G->n[0] + b + tot > slots || G->n[1] + b + tot > slots) G->slot_overflow = 1;
+  return b;
+}
+
+// Block-wide exclusive prefix sum of ints (256 threads); `total` gets the sum.
+__device__ __forceinline__ int block_excl_scan(int x, int* s_tmp, int& total) {
+  const int incl = wave_incl_scan_dpp(x);
+  // the wave's index, uniform: its LDS slot and the compares below are scalar
+  const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  __syncthreads();
+  if (lane_id() == 63) s_tmp[w] = incl;
+  __syncthreads();
+  int off = 0, t = 0;
+#pragma unroll
+  for (int k = 0; k < kBlock / 64; ++k) {
+    const int v = s_tmp[k];
+    if (k < w) off += v;
+    t += v;
+  }
+  total = t;
+  return off + incl - x;
+}
+
+// ------------------------------------------------------------------ emit
+// Emission of one pushed chunk of species s (section 2: a lepton that reaches
+// gamma_thr emits; with a finite photon path the photon is stored and converts
+// later, else the pair is made in place).  The push lists the chunk's ne
+// emitters in LDS: entry (chunk-local index << 8 | k, the k emissions of this
+// step) and the position after the move on the 2^-K grid (<< 1 | forward).
+// Each thread takes the emitters tid, tid + kBlock, ...: their ids are
+// requested together and kept in LDS, an LDS atomic gives each thread its
+// place among the chunk's photons (any order serves: results do not depend
+// on slots), and the chunk's slots are reserved with one global atomic.
+// Emission j of an emitter at step n draws Philox4x64-10 with counter
+// (n, j, 2, 0) and key (id, seed): the child electron id is word 1 with bit
+// 0 cleared (the positron's has it set), and the photon's path in steps,
+// n_conv = min{k >= 1 : u >= T_k} for u the top 32 bits of word 0, comes
+// from the gap's conversion table.  The gap's emission constants are read
+// here, where they are used, not held in registers through the push.
+template <typename T>
+__device__ __forceinline__ void emit_chunk(GapDev* __restrict__ G, int s, long long i0, int ne,
+                                           uint32_t* s_emit, const long long* s_emx,
+                                           uint64_t* s_emid, int* s_scan,
+                                           unsigned long long* s_slot) {
+  const int tid = threadIdx.x;
+  const int buf = G->buf;
+  const bool in_place = G->table_len == 0;
+  int kt;
+  {
+    // thread t owns the entries 4t .. 4t + 3 (list order): their ids, and a
+    // block scan of their photon counts gives each its first photon; the
+    // entry's slot in s_emit then holds that prefix
+    gptr<const uint64_t> idA = glb<const uint64_t>((void*)G->id[buf][s]);
+    uint32_t e[4];
+    uint64_t idv[4];
+    int mine = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int q = 4 * tid + j;
+      e[j] = q < ne ? s_emit[q] : 0u;
+      idv[j] = q < ne ? idA[i0 + (long long)(e[j] >> 8)] : 0ull;
+      mine += (int)(e[j] & 255u);
+    }
+    int ex = block_excl_scan(mine, s_scan, kt);  // ends with a barrier
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int q = 4 * tid + j;
+      if (q < ne) {
+        s_emit[q] = (uint32_t)ex;
+        s_emid[q] = idv[j];
+      }
+      ex += (int)(e[j] & 255u);
+    }
+    if (tid == 0) {
+      if (in_place) {
+        *s_slot = reserve_pairs(G, (unsigned long long)kt);
+      } else {
+        const unsigned long long b0 = atomicAdd(&G->n_ph_next, (unsigned long long)kt);
+        if (b0 + (unsigned long long)kt > (unsigned long long)G->ph_cap) G->overflow = 1;
+        *s_slot = b0;
+      }
+    }
+  }
+  __syncthreads();
+  const unsigned long long base = *s_slot;
+  const uint64_t step = (uint64_t)G->step, seed = G->seed;
+  const int K = G->K;
+  // the emitter of the chunk's photon p: the last entry whose first photon is at most p
+  auto emitter_of = [&](int p) {
+    int lo = 0, hi = ne - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if ((int)s_emit[mid] <= p) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+  };
+  if (in_place) {
+    // pairs made in place (the paper's zero mean free path), both children
+    // at the emitter's position moving along its direction
+    const unsigned long long n0 = G->n[0], n1 = G->n[1], slots = (unsigned long long)G->slots;
+    const long long mask = G->one - 1;
+    const T inv_scale = (T)(1.0 / (double)G->one), pchild = (T)G->pchild;
+    const bool evmap = G->evmap != nullptr;
+    gptr<int32_t> c0 = glb(G->cell[buf][0]), c1 = glb(G->cell[buf][1]);
+    gptr<T> o0 = glb<T>(G->off[buf][0]), o1 = glb<T>(G->off[buf][1]);
+    gptr<T> p0 = glb<T>(G->p[buf][0]), p1 = glb<T>(G->p[buf][1]);
+    gptr<uint64_t> d0 = glb(G->id[buf][0]), d1 = glb(G->id[buf][1]);
+#pragma unroll 1
+    for (int p = tid; p < kt; p += kBlock) {
+      const int q = emitter_of(p);
+      const int jj = p - (int)s_emit[q];
+      const long long xe = s_emx[q];
+      const long long X0 = xe >> 1;
+      const int c = (int)(X0 >> K);
+      const T offn = (T)(X0 & mask) * inv_scale;
+      const T pc = (xe & 1) ? pchild : -pchild;
+      const U64x4 u = philox4x64_10(step, (uint64_t)jj, kTagPhoton, 0, s_emid[q], seed);
+      const uint64_t child = u.v[1] & ~(uint64_t)1;
+      const unsigned long long se = n0 + base + p, sp = n1 + base + p;
+      if (se < slots) { c0[se] = c; o0[se] = offn; p0[se] = pc; d0[se] = child; }
+      if (sp < slots) { c1[sp] = c; o1[sp] = offn; p1[sp] = pc; d1[sp] = child | 1u; }
+      if (evmap) count_pairs(G, (long long)step, c, 1ull);
+    }
+    return;
+  }
+  const int pb = G->phbuf;
+  gptr<long long> phx = glb(G->ph_x[pb]);
+  gptr<int32_t> phs = glb(G->ph_step[pb]);
+  gptr<uint64_t> phc = glb(G->ph_child[pb]);
+  gptr<uint8_t> phk = glb(G->ph_key);
+  const uint32_t* table = G->table;
+  gptr<const uint32_t> tab = glb<const uint32_t>((void*)G->table);
+  const int len = G->table_len;
+  const float inv_lnq = G->inv_lnq;
+  const long long domain = G->domain, photon_step = G->photon_step, ph_base = G->ph_base;
+  const unsigned long long ph_cap = (unsigned long long)G->ph_cap;
+  const bool absorbing = G->boundary == PIC_BC_ABSORBING;
+  unsigned esc = 0;
+  // two photons per iteration, so that their table entries are requested together
+#pragma unroll 1
+  for (int p = tid; p < kt; p += 2 * kBlock) {
+    uint32_t uu[2], tm[2], t0[2], tp[2];
+    uint64_t ch[2];
+    int kk[2], qe[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int ph = p + h * kBlock < kt ? p + h * kBlock : p;
+      const int q = emitter_of(ph);
+      qe[h] = q;
+      const U64x4 u = philox4x64_10(step, (uint64_t)(ph - (int)s_emit[q]), kTagPhoton, 0, s_emid[q], seed);
+      ch[h] = u.v[1] & ~(uint64_t)1;
+      uu[h] = (uint32_t)(u.v[0] >> 32);
+      kk[h] = conv_estimate(len, uu[h], inv_lnq);
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      tm[h] = tab[kk[h] - 1 > 0 ? kk[h] - 1 : 0];
+      t0[h] = tab[kk[h]];
+      tp[h] = tab[kk[h] + 1 < len ? kk[h] + 1 : len - 1];
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int ph = p + h * kBlock;
+      if (ph >= kt) break;
+      const int ncv = conv_decide(table, len, uu[h], kk[h], tm[h], t0[h], tp[h]);
+      const long long xe = s_emx[qe[h]];
+      const long long dirq = (xe & 1) ? photon_step : -photon_step;
+      long long X = (xe >> 1) + (long long)ncv * dirq;
+      int cstep = (int)((long long)step + ncv);
+      if (absorbing) {
+        if (X < 0 || X >= domain) { cstep = INT32_MIN; ++esc; }
+      } else if (X < 0 || X >= domain) {
+        X = wrap_periodic(X, domain);
+      }
+      const unsigned long long sl = base + (unsigned long long)ph;
+      if (sl < ph_cap) {
+        phx[sl] = X;
+        phs[sl] = cstep;
+        phc[sl] = ch[h] | (uint64_t)(xe & 1);
+        // the tail key: steps from the last sort to the conversion (>= 1)
+        const long long rel = (long long)cstep - ph_base;
+        phk[sl] = (uint8_t)(cstep != INT32_MIN && rel < kFarKey ? rel : kFarKey);
+      }
+    }
+  }
+  if (absorbing) {
+    const unsigned long long esc_w = wave_sum((unsigned long long)esc);
+    if (lane_id() == 0 && esc_w > 0) atomicAdd(&G->esc_next, esc_w);
+  }
 }
 
 // ------------------------------------------------------------------ push
@@ -269,13 +512,14 @@ __device__ __forceinline__ void push_item(long long local, long long chunks0, lo
 template <typename T, bool kSpread, bool kSpline>
 __global__ __launch_bounds__(kBlock, kSpread ? PushCfg<T>::spread_waves : PushCfg<T>::waves) void k_push(GapDev* __restrict__ gaps,
                                                  const long long* __restrict__ wi, int B,
-                                                 int32_t* __restrict__ emit_cnt,
-                                                 uint32_t* __restrict__ emit_ent,
-                                                 uint32_t* __restrict__ wg_emit,
                                                  unsigned long long* __restrict__ stripes) {
   using I = typename Fixed<T>::I;
   __shared__ long long s_flux[kTile];
   __shared__ uint32_t s_emit[kChunk];  // chunk-local index << 8 | k
+  __shared__ long long s_emx[kChunk];  // the emitter's position after the move << 1 | forward
+  __shared__ uint64_t s_emid[kChunk];  // the emitter's id
+  __shared__ int s_scan[kBlock / 64];
+  __shared__ unsigned long long s_slot;  // the chunk's first photon (or pair) slot
   __shared__ int s_red[2][8];
   __shared__ __int128 s_e[4];
   __shared__ unsigned long long s_abs[6];
@@ -298,7 +542,6 @@ __global__ __launch_bounds__(kBlock, kSpread ? PushCfg<T>::spread_waves : PushCf
   const int tid = threadIdx.x;
   const int lane = lane_id();
   __int128 ke_t = 0;  // this thread's kinetic energy terms (diagnosed steps)
-  uint32_t my_emitters = 0;  // emitters listed by this workgroup (thread 0)
 
   // constants of the current gap
   int g = -1;
@@ -312,7 +555,7 @@ __global__ __launch_bounds__(kBlock, kSpread ? PushCfg<T>::spread_waves : PushCf
   I ONE = 0;
   T scale = 0, inv_scale = 0, dt_t = 0, dtdx = 0, gthr = 0, gpair = 0, thr_lo = 0;
   double sigma = 0.0, gthr64 = 0.0;
-  int Kb = 0;  // offset grid bits (the spline's weights)
+  int Kb = 0;  // offset grid bits (the spline's weights, the emitters' positions)
   uint64_t kseed = 0;
   gptr<uint64_t> idS[2] = {nullptr, nullptr};
   GapDev* __restrict__ G = gaps;
@@ -352,7 +595,7 @@ __global__ __launch_bounds__(kBlock, kSpread ? PushCfg<T>::spread_waves : PushCf
       dtdx = (T)G->dtdx;
       gthr = (T)G->gthr;
       gpair = (T)G->gpair;
-      if constexpr (kSpline) Kb = G->K;
+      Kb = G->K;
       if constexpr (kSpread) {
         sigma = G->sigma;
         gthr64 = G->gthr64;
@@ -361,7 +604,6 @@ __global__ __launch_bounds__(kBlock, kSpread ? PushCfg<T>::spread_waves : PushCf
       }
       have = false;
     }
-    if (tid == 0) emit_cnt[w] = 0;
     if (!gap_ok) continue;
     int s;
     long long i0, i1;
@@ -615,6 +857,10 @@ __global__ __launch_bounds__(kBlock, kSpread ? PushCfg<T>::spread_waves : PushCf
             pn = pn > (T)0 ? mag : -mag;
             const int pos = atomicAdd(&s_emit_n, 1);
             s_emit[pos] = ((uint32_t)(i - i0) << 8) | (uint32_t)k;
+            // its photons (or pairs) start at its position after the move,
+            // along the stored momentum's sign
+            const long long X0 = ((long long)c2 << Kb) + (long long)nq;
+            s_emx[pos] = (X0 << 1) | (signbit(pn) ? 0ll : 1ll);
           }
           __builtin_nontemporal_store(pn, &pA[i]);
           __builtin_nontemporal_store((T)nq * inv_scale, &offA[i]);
@@ -654,16 +900,9 @@ __global__ __launch_bounds__(kBlock, kSpread ? PushCfg<T>::spread_waves : PushCf
           }
         }
       }
-      // ---- emitters of this chunk, in the chunk's own slice of the list
+      // ---- the photons (or in-place pairs) of this chunk's emitters
       const int ne = s_emit_n;
-      if (ne > 0) {
-        if (tid == 0) {
-          emit_cnt[w] = ne;
-          my_emitters += (uint32_t)ne;
-        }
-        gptr<uint32_t> el = glb(emit_ent + w * (long long)kChunk);
-        for (int k = tid; k < ne; k += kBlock) el[k] = s_emit[k];
-      }
+      if (ne > 0) emit_chunk<T>(G, s, i0, ne, s_emit, s_emx, s_emid, s_scan, &s_slot);
       __syncthreads();
     }
     if constexpr (PushCfg<T>::prefetch) {
@@ -673,320 +912,6 @@ __global__ __launch_bounds__(kBlock, kSpread ? PushCfg<T>::spread_waves : PushCf
     have = pre;
   }
   if (g >= 0) flush_tally(stripes, g, ke_t, diag, s_e, s_abs);
-  // emitters of this workgroup's chunk range, indexed in chunk order
-  if (tid == 0) wg_emit[xcd_logical((int)blockIdx.x, (int)gridDim.x)] = my_emitters;
-}
-
-// ------------------------------------------------------------------ emit
-// Chunk x of the current plan lists its emitters in emit_ent[x * kChunk ..]
-// (chunk-local index << 8 | number of emissions k).
-
-// Per-wave shares of a workgroup's total: s_wave[v] holds wave v's count on
-// entry; returns the block total and sets `pre` to the counts of the waves
-// before this one.  Every thread must call it.
-__device__ __forceinline__ unsigned long long wave_shares(const unsigned long long* s_wave,
-                                                          unsigned long long& pre) {
-  const int v = threadIdx.x >> 6;
-  unsigned long long t = 0;
-  pre = 0;
-#pragma unroll
-  for (int k = 0; k < kBlock / 64; ++k) {
-    if (k < v) pre += s_wave[k];
-    t += s_wave[k];
-  }
-  return t;
-}
-
-// Lanes below this one in the wave.
-__device__ __forceinline__ unsigned long long lanes_below() {
-  return (1ull << lane_id()) - 1ull;
-}
-
-// Pairs of a step share one slot cursor: the workgroup reserves `tot` pairs
-// (electron slots from n[0], positron slots from n[1]).  Appends beyond the
-// slots are not written and freeze the gap; the capacity itself (live
-// leptons) is checked by the finalize.
-__device__ __forceinline__ unsigned long long reserve_pairs(GapDev* G, unsigned long long tot) {
-  const unsigned long long b = atomicAdd(&G->pair_next, tot);
-  const unsigned long long slots = (unsigned long long)G->slots;
-  if (G->n[0] + b + tot > slots || G->n[1] + b + tot > slots) G->slot_overflow = 1;
-  return b;
-}
-
-// Block-wide exclusive prefix sum of ints (256 threads); `total` gets the sum.
-__device__ __forceinline__ int block_excl_scan(int x, int* s_tmp, int& total) {
-  const int incl = wave_incl_scan(x);
-  const int w = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane_id() == 63) s_tmp[w] = incl;
-  __syncthreads();
-  int off = 0, t = 0;
-#pragma unroll
-  for (int k = 0; k < kBlock / 64; ++k) {
-    const int v = s_tmp[k];
-    if (k < w) off += v;
-    t += v;
-  }
-  total = t;
-  return off + incl - x;
-}
-
-// What the emission of one gap reads, loaded from its descriptor once per
-// gap segment rather than per emitter.
-template <typename T>
-struct EmitGap {
-  GapDev* G;
-  gptr<int32_t> cell[2];
-  gptr<T> off[2], p[2];
-  gptr<uint64_t> id[2];
-  gptr<long long> phx;
-  gptr<int32_t> phs;
-  gptr<uint64_t> phc;
-  gptr<uint8_t> phk;
-  const uint32_t* table;
-  int table_len, K;
-  float inv_lnq;
-  long long domain, photon_step, ph_base;
-  unsigned long long ph_cap, slots, n0, n1;
-  uint64_t step, seed;
-  T pchild, inv_scale, scale;
-  bool absorbing, in_place, evmap;
-};
-
-template <typename T>
-__device__ __forceinline__ EmitGap<T> emit_gap(GapDev* __restrict__ G) {
-  EmitGap<T> E;
-  E.G = G;
-  const int buf = G->buf, pb = G->phbuf;
-#pragma unroll
-  for (int s = 0; s < 2; ++s) {
-    E.cell[s] = glb(G->cell[buf][s]);
-    E.off[s] = glb<T>(G->off[buf][s]);
-    E.p[s] = glb<T>(G->p[buf][s]);
-    E.id[s] = glb(G->id[buf][s]);
-  }
-  E.phx = glb(G->ph_x[pb]);
-  E.phs = glb(G->ph_step[pb]);
-  E.phc = glb(G->ph_child[pb]);
-  E.phk = glb(G->ph_key);
-  E.ph_base = G->ph_base;
-  E.table = G->table;
-  E.table_len = G->table_len;
-  E.K = G->K;
-  E.inv_lnq = G->inv_lnq;
-  E.domain = G->domain;
-  E.photon_step = G->photon_step;
-  E.ph_cap = (unsigned long long)G->ph_cap;
-  E.slots = (unsigned long long)G->slots;
-  E.n0 = G->n[0];
-  E.n1 = G->n[1];
-  E.step = (uint64_t)G->step;
-  E.seed = G->seed;
-  E.pchild = (T)G->pchild;
-  E.scale = (T)(double)G->one;
-  E.inv_scale = (T)(1.0 / (double)G->one);
-  E.absorbing = G->boundary == PIC_BC_ABSORBING;
-  E.in_place = G->table_len == 0;
-  E.evmap = G->evmap != nullptr;
-  return E;
-}
-
-// The k photons (or in-place pairs) of emitter i of species s, written at
-// photon slots slot0 .. slot0 + k - 1 (pair slots n[0] + slot, n[1] + slot).
-// Returns the number of photons that left the domain.
-template <typename T>
-__device__ __forceinline__ unsigned emit_one(const EmitGap<T>& E, int s, long long i, int k,
-                                             unsigned long long slot0) {
-  // the emitter's species, by selects (no indexed array of pointers)
-  const gptr<int32_t> cA = s == 0 ? E.cell[0] : E.cell[1];
-  const gptr<T> oA = s == 0 ? E.off[0] : E.off[1];
-  const gptr<T> pA = s == 0 ? E.p[0] : E.p[1];
-  const gptr<uint64_t> iA = s == 0 ? E.id[0] : E.id[1];
-  const int c = cA[i];
-  const long long oq = (long long)(oA[i] * E.scale);
-  const T pv = pA[i];
-  const uint64_t id = iA[i];
-  // the direction of the emitter before its recoil: the push stores +|p| or
-  // -|p|, so the sign bit holds it also when the recoil leaves |p| = 0
-  const int dir = signbit(pv) ? -1 : 1;
-  unsigned esc = 0;
-  if (E.in_place) {
-    // pair made in place (the paper's zero mean free path)
-    const T pc = dir > 0 ? E.pchild : -E.pchild;
-    const T offn = (T)oq * E.inv_scale;
-    for (int jj = 0; jj < k; ++jj) {
-      const U64x4 u = philox4x64_10(E.step, (uint64_t)jj, kTagPhoton, 0, id, E.seed);
-      const uint64_t child = u.v[1] & ~(uint64_t)1;
-      const unsigned long long se = E.n0 + slot0 + jj, sp = E.n1 + slot0 + jj;
-      if (se < E.slots) { E.cell[0][se] = c; E.off[0][se] = offn; E.p[0][se] = pc; E.id[0][se] = child; }
-      if (sp < E.slots) {
-        E.cell[1][sp] = c; E.off[1][sp] = offn; E.p[1][sp] = pc; E.id[1][sp] = child | 1u;
-      }
-    }
-    if (E.evmap) count_pairs(E.G, (long long)E.step, c, (unsigned long long)k);
-  } else {
-    const long long X0 = ((long long)c << E.K) + oq;
-    for (int jj = 0; jj < k; ++jj) {
-      const U64x4 u = philox4x64_10(E.step, (uint64_t)jj, kTagPhoton, 0, id, E.seed);
-      const uint64_t child = u.v[1] & ~(uint64_t)1;
-      const int ncv = conv_steps(E.table, E.table_len, (uint32_t)(u.v[0] >> 32), E.inv_lnq);
-      long long X = X0 + (long long)dir * (long long)ncv * E.photon_step;
-      int cstep = (int)((long long)E.step + ncv);
-      if (E.absorbing) {
-        if (X < 0 || X >= E.domain) { cstep = INT32_MIN; ++esc; }
-      } else if (X < 0 || X >= E.domain) {
-        X %= E.domain;
-        if (X < 0) X += E.domain;
-      }
-      const unsigned long long slot = slot0 + jj;
-      if (slot < E.ph_cap) {
-        E.phx[slot] = X;
-        E.phs[slot] = cstep;
-        E.phc[slot] = child | (dir > 0 ? 1u : 0u);
-        // the tail key: steps from the last sort to the conversion (>= 1)
-        const long long rel = (long long)cstep - E.ph_base;
-        E.phk[slot] = (uint8_t)(cstep != INT32_MIN && rel < kFarKey ? rel : kFarKey);
-      }
-    }
-  }
-  return esc;
-}
-
-// Walks the emitters with flattened indices [qa, qb) (chunk order, then list
-// order within a chunk) among chunks [x, xend) of gap E.G, whose first
-// emitter has flattened index Q, and emits their photons (or in-place
-// pairs).  Windows of kBlock chunks are scanned for their emitter counts;
-// each round hands one emitter to each thread, a block scan of the emitters'
-// photon counts gives each its place, and the round's slots are reserved
-// with one atomic.  On return x and Q point past the last window walked.
-template <typename T>
-__device__ __forceinline__ void emit_walk(const EmitGap<T>& E, long long& x, long long xend,
-                                          unsigned long long& Q, unsigned long long qa,
-                                          unsigned long long qb, long long wg0, unsigned& esc,
-                                          gptr<const uint32_t> cntA, gptr<const uint32_t> entA,
-                                          int* s_nb, int* s_tmp, unsigned long long* s_base) {
-  // electron chunks come first in the gap's items
-  const long long chunks0 = ((long long)E.n0 + kChunk - 1) / kChunk;
-  while (x < xend && Q < qb) {
-    const long long xc0 = x + threadIdx.x;
-    const int ne = xc0 < xend ? (int)cntA[xc0] : 0;
-    int nwin;
-    const int nb = block_excl_scan(ne, s_tmp, nwin);
-    s_nb[threadIdx.x] = nb;
-    __syncthreads();
-    const unsigned long long lo = qa > Q ? qa : Q;
-    const unsigned long long hi = qb < Q + (unsigned long long)nwin ? qb : Q + (unsigned long long)nwin;
-    for (unsigned long long r = lo; r < hi; r += kBlock) {
-      const unsigned long long q = r + threadIdx.x;
-      int k = 0, s = 0;
-      long long i = 0;
-      if (q < hi) {
-        const int ql = (int)(q - Q);
-        // the chunk holding emitter ql of the window: last t with s_nb[t] <= ql
-        int a = 0, b = kBlock - 1;
-        while (a < b) {
-          const int mid = (a + b + 1) >> 1;
-          if (s_nb[mid] <= ql) a = mid; else b = mid - 1;
-        }
-        const long long xc = x + a;
-        const uint32_t en = entA[xc * kChunk + (ql - s_nb[a])];
-        k = (int)(en & 255u);
-        const long long local = xc - wg0;
-        s = local < chunks0 ? 0 : 1;
-        i = (s == 0 ? local : local - chunks0) * kChunk + (long long)(en >> 8);
-      }
-      int kt;
-      const int ex = block_excl_scan(k, s_tmp, kt);  // ends with a barrier
-      if (kt == 0) continue;                          // uniform
-      if (threadIdx.x == 0) {
-        if (E.in_place) {
-          s_base[0] = reserve_pairs(E.G, (unsigned long long)kt);
-        } else {
-          const unsigned long long b0 = atomicAdd(&E.G->n_ph_next, (unsigned long long)kt);
-          if (b0 + (unsigned long long)kt > E.ph_cap) E.G->overflow = 1;
-          s_base[0] = b0;
-        }
-      }
-      __syncthreads();
-      const unsigned long long base = s_base[0];
-      if (k > 0) esc += emit_one<T>(E, s, i, k, base + (unsigned long long)ex);
-      __syncthreads();  // s_base is rewritten by the next round
-    }
-    x = x + kBlock < xend ? x + kBlock : xend;
-    Q += (unsigned long long)nwin;
-    __syncthreads();  // s_nb is rewritten by the next window
-  }
-}
-
-// Emission is balanced by emitters, not by chunks: the push left the number
-// of emitters of each of its workgroups (in chunk order), so every
-// workgroup here scans those counts, takes an equal share of the flattened
-// emitter list, and walks it gap by gap in one pass.
-template <typename T>
-__device__ void emit_role(GapDev* __restrict__ gaps, const long long* __restrict__ wi, int B,
-                          const int32_t* __restrict__ emit_cnt,
-                          const uint32_t* __restrict__ emit_ent,
-                          const uint32_t* __restrict__ wg_emit, int vb, int nvb,
-                          uint32_t* s_pre, unsigned long long* s_base, int* s_nb, int* s_tmp) {
-  constexpr int kPer = kPushGrid / kBlock;
-  const long long total = wi[B];
-  if (total == 0) return;
-  // exclusive prefix of the push workgroups' emitter counts
-  uint32_t v[kPer];
-  uint32_t loc = 0;
-#pragma unroll
-  for (int j = 0; j < kPer; ++j) {
-    v[j] = glb<const uint32_t>((void*)wg_emit)[threadIdx.x * kPer + j];
-    loc += v[j];
-  }
-  // block scan of the per-thread sums (a batch holds fewer than 2^32 lepton slots)
-  const uint32_t incl = wave_incl_scan(loc);
-  __syncthreads();
-  if (lane_id() == 63) s_tmp[threadIdx.x >> 6] = (int)incl;
-  __syncthreads();
-  uint32_t off = 0, Etot = 0;
-#pragma unroll
-  for (int k = 0; k < kBlock / 64; ++k) {
-    const uint32_t t = (uint32_t)s_tmp[k];
-    if (k < (int)(threadIdx.x >> 6)) off += t;
-    Etot += t;
-  }
-  off += incl - loc;
-#pragma unroll
-  for (int j = 0; j < kPer; ++j) {
-    s_pre[threadIdx.x * kPer + j] = off;
-    off += v[j];
-  }
-  __syncthreads();
-  if (Etot == 0) return;
-  const unsigned long long share = ((unsigned long long)Etot + nvb - 1) / nvb;
-  const unsigned long long q0 = (unsigned long long)vb * share;
-  if (q0 >= Etot) return;
-  const unsigned long long q1 = q0 + share < Etot ? q0 + share : Etot;
-  // the push workgroup holding emitter q0: last lb with s_pre[lb] <= q0
-  int a = 0, b = kPushGrid - 1;
-  while (a < b) {
-    const int mid = (a + b + 1) >> 1;
-    if (s_pre[mid] <= q0) a = mid; else b = mid - 1;
-  }
-  long long x, xa_end;
-  share_range(total, a, kPushGrid, x, xa_end);
-  unsigned long long Q = s_pre[a];
-  gptr<const uint32_t> cntA = glb<const uint32_t>((void*)emit_cnt);
-  gptr<const uint32_t> entA = glb<const uint32_t>((void*)emit_ent);
-  while (x < total && Q < q1) {
-    const int g = find_gap(wi, B, x);
-    GapDev* __restrict__ G = gaps + g;
-    const long long xend = wi[g + 1];
-    const long long wg0 = wi[g];
-    const EmitGap<T> E = emit_gap<T>(G);
-    unsigned esc = 0;
-    emit_walk<T>(E, x, xend, Q, q0, q1, wg0, esc, cntA, entA, s_nb, s_tmp, s_base);
-    if (E.absorbing && !E.in_place) {
-      const unsigned long long esc_w = wave_sum((unsigned long long)esc);
-      if (lane_id() == 0 && esc_w > 0) atomicAdd(&G->esc_next, esc_w);
-    }
-  }
 }
 
 // ----------------------------------------------------------------- field
@@ -1509,37 +1434,26 @@ __device__ void fold_role(GapDev* __restrict__ gaps, int B, unsigned long long* 
   }
 }
 
-// Everything of a step between the push and the finalize: the Ampere update
-// (blocks [0, n_field)), the emission draws (next n_emit blocks), the
-// conversions (next n_conv blocks) and the fold of the push tallies (the
-// rest) are independent of each other.
+// Everything of a step between the push (which also emits) and the
+// finalize: the Ampere update (blocks [0, n_field)), the conversions (next
+// n_conv blocks) and the fold of the push tallies (the rest) are independent
+// of each other.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_post(GapDev* __restrict__ gaps,
                                                  const long long* __restrict__ cwi,
-                                                 const long long* __restrict__ wi,
                                                  const long long* __restrict__ pwi, int B,
-                                                 int n_field, int n_emit, int n_conv,
-                                                 const int32_t* __restrict__ emit_cnt,
-                                                 const uint32_t* __restrict__ emit_ent,
-                                                 const uint32_t* __restrict__ wg_emit,
+                                                 int n_field, int n_conv,
                                                  unsigned long long* __restrict__ stripes) {
   __shared__ double s_red[8];
   __shared__ unsigned long long s_wave[kBlock / 64];
   __shared__ unsigned long long s_base[1];
-  __shared__ int s_nb[kBlock];
-  __shared__ int s_tmp[kBlock / 64];
-  // the emission role's prefix of the push workgroups' emitters, or the
-  // conversion role's lists of due photons (a block takes one role)
-  __shared__ uint32_t s_buf[kPushGrid];
-  static_assert(kPushGrid >= kConvGroup * kPhChunk, "the due lists of a conversion group fit s_buf");
+  // the conversion role's lists of due photons
+  __shared__ uint32_t s_buf[kConvGroup * kPhChunk];
   const int b = blockIdx.x;
   if (b < n_field) field_role(gaps, cwi, B, b, s_red);
-  else if (b < n_field + n_emit)
-    emit_role<T>(gaps, wi, B, emit_cnt, emit_ent, wg_emit, b - n_field, n_emit, s_buf, s_base, s_nb,
-                 s_tmp);
-  else if (b < n_field + n_emit + n_conv)
-    convert_role<T>(gaps, pwi, B, b - n_field - n_emit, n_conv, s_wave, s_base, s_buf);
-  else fold_role(gaps, B, stripes, b - n_field - n_emit - n_conv);
+  else if (b < n_field + n_conv)
+    convert_role<T>(gaps, pwi, B, b - n_field, n_conv, s_wave, s_base, s_buf);
+  else fold_role(gaps, B, stripes, b - n_field - n_conv);
 }
 
 __global__ __launch_bounds__(1024) void k_finalize(GapDev* __restrict__ gaps, int B,
@@ -2138,12 +2052,11 @@ template <typename T, bool kSpread, bool kSpline>
 static void push_kernel(const StepLaunch& L, hipEvent_t start, hipEvent_t stop) {
   if (start) {
     hipExtLaunchKernelGGL((k_push<T, kSpread, kSpline>), dim3(kPushGrid), dim3(kBlock), 0, L.stream,
-                          start, stop, 0, L.gaps, L.wi, L.B, L.emit_cnt, L.emit_ent, L.wg_emit,
-                          L.stripes);
+                          start, stop, 0, L.gaps, L.wi, L.B, L.stripes);
     return;
   }
   hipLaunchKernelGGL((k_push<T, kSpread, kSpline>), dim3(kPushGrid), dim3(kBlock), 0, L.stream,
-                     L.gaps, L.wi, L.B, L.emit_cnt, L.emit_ent, L.wg_emit, L.stripes);
+                     L.gaps, L.wi, L.B, L.stripes);
 }
 
 template <typename T>
@@ -2166,15 +2079,13 @@ hipError_t launch_push(const StepLaunch& L, bool mixed, hipEvent_t start, hipEve
 hipError_t launch_step_after_push(const StepLaunch& L, bool mixed) {
   const int nf = grid_for(L.cell_items, 1 << 30);
   const int nfold = (4 * L.B * kStripes + kBlock - 1) / kBlock;
-  const int grid = nf + L.emit_grid + L.conv_grid + nfold;
+  const int grid = nf + L.conv_grid + nfold;
   if (mixed)
-    hipLaunchKernelGGL(k_post<float>, dim3(grid), dim3(kBlock), 0, L.stream, L.gaps, L.cwi, L.wi,
-                       L.pwi, L.B, nf, L.emit_grid, L.conv_grid, L.emit_cnt, L.emit_ent, L.wg_emit,
-                       L.stripes);
+    hipLaunchKernelGGL(k_post<float>, dim3(grid), dim3(kBlock), 0, L.stream, L.gaps, L.cwi, L.pwi,
+                       L.B, nf, L.conv_grid, L.stripes);
   else
-    hipLaunchKernelGGL(k_post<double>, dim3(grid), dim3(kBlock), 0, L.stream, L.gaps, L.cwi, L.wi,
-                       L.pwi, L.B, nf, L.emit_grid, L.conv_grid, L.emit_cnt, L.emit_ent, L.wg_emit,
-                       L.stripes);
+    hipLaunchKernelGGL(k_post<double>, dim3(grid), dim3(kBlock), 0, L.stream, L.gaps, L.cwi, L.pwi,
+                       L.B, nf, L.conv_grid, L.stripes);
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, L.stream, L.gaps, L.B, L.wi, L.pwi, L.qwi);
   return hipGetLastError();
 }
