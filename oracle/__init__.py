@@ -79,6 +79,7 @@ def lib():
     L.orc_event_map.argtypes = [vp, i32, i32, i32]; L.orc_event_map.restype = C.c_int
     L.orc_read_event_map.argtypes = [vp, vp]; L.orc_read_event_map.restype = C.c_int
     L.orc_philox4x64_10.argtypes = [vp, vp, vp]; L.orc_philox4x64_10.restype = None
+    L.orc_philox4x32_10.argtypes = [vp, vp, vp]; L.orc_philox4x32_10.restype = None
     L.orc_conv_table.argtypes = [dbl, dbl, dbl, vp, i64]; L.orc_conv_table.restype = i64
     _LIB = L
     return L
@@ -103,6 +104,14 @@ def philox4x64_10(ctr, key):
     k = np.asarray(key, dtype=np.uint64).copy()
     out = np.zeros(4, dtype=np.uint64)
     lib().orc_philox4x64_10(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def philox4x32_10(ctr, key):
+    c = np.asarray(ctr, dtype=np.uint32).copy()
+    k = np.asarray(key, dtype=np.uint32).copy()
+    out = np.zeros(4, dtype=np.uint32)
+    lib().orc_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
     return out
 
 

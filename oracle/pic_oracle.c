@@ -117,11 +117,54 @@ void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t ou
   out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
 
-static void draw(uint64_t id, uint64_t seed, uint64_t step, uint64_t j, uint64_t tag,
-                 uint64_t out[4]) {
-  uint64_t ctr[4] = {step, j, tag, 0};
-  uint64_t key[2] = {id, seed};
+/* Philox4x32-10 (same paper): the 32-bit form, with 32x32 -> 64-bit
+ * products, its own round multipliers and Weyl constants; four 32-bit
+ * counter words, two key words. */
+static void mulhilo32(uint32_t a, uint32_t b, uint32_t* hi, uint32_t* lo) {
+  uint64_t prod = (uint64_t)a * (uint64_t)b;
+  *hi = (uint32_t)(prod >> 32);
+  *lo = (uint32_t)prod;
+}
+
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+  const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+  uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) { k0 += W0; k1 += W1; }
+    uint32_t hi0, lo0, hi1, lo1;
+    mulhilo32(M0, c0, &hi0, &lo0);
+    mulhilo32(M1, c2, &hi1, &lo1);
+    uint32_t n0 = hi1 ^ c1 ^ k0;
+    uint32_t n1 = lo1;
+    uint32_t n2 = hi0 ^ c3 ^ k1;
+    uint32_t n3 = lo0;
+    c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* The seeding draw of pair i: Philox4x64-10, key (i, seed), counter
+ * (0, 0, 1, 0). */
+static void draw_seed(uint64_t i, uint64_t seed, uint64_t out[4]) {
+  uint64_t ctr[4] = {0, 0, ORC_TAG_SEED, 0};
+  uint64_t key[2] = {i, seed};
   orc_philox4x64_10(ctr, key, out);
+}
+
+/* A draw of lepton `id` during the run (tag 2: emission j at step n; tag 3:
+ * its threshold, n = j = 0): Philox4x32-10, key (seed low, seed high),
+ * counter (n, j | tag << 8, id low, id high).  Words 0 and 1 form the 64-bit
+ * value `bits`, word 2 is `u32`. */
+static void draw_run(uint64_t id, uint64_t seed, uint64_t step, uint64_t j, uint32_t tag,
+                     uint64_t* bits, uint32_t* u32) {
+  uint32_t ctr[4] = {(uint32_t)step, (uint32_t)j | (tag << 8), (uint32_t)id, (uint32_t)(id >> 32)};
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  uint32_t out[4];
+  orc_philox4x32_10(ctr, key, out);
+  *bits = ((uint64_t)out[1] << 32) | out[0];
+  *u32 = out[2];
 }
 
 /* Photon path, discretised to whole steps.  A photon streams c*dt/dx cells
@@ -164,13 +207,14 @@ static double gamma64(double p) { return sqrt(1.0 + p * p); }
 
 /* Emission threshold of lepton `id` under a spread sigma of gamma_thr: a
  * fixed property of the lepton, uniform in gamma_thr (1 - sigma, 1 + sigma).
- * u = (top 53 bits of word 0 of the tag-3 draw at counter (0, 0, 3, 0)) /
- * 2^53, then gamma_thr (1 + sigma (2u - 1)) in binary64, one rounding per
- * operation, rounded to the particle precision at the end. */
+ * u = (top 53 bits of the 64-bit value of its tag-3 draw) / 2^53, then
+ * gamma_thr (1 + sigma (2u - 1)) in binary64, one rounding per operation,
+ * rounded to the particle precision at the end. */
 static double lepton_threshold(const orc_gap* g, uint64_t id) {
-  uint64_t u[4];
-  draw(id, g->prm.seed, 0, 0, ORC_TAG_THRESHOLD, u);
-  const double x = ldexp((double)(u[0] >> 11), -53);
+  uint64_t bits;
+  uint32_t u32;
+  draw_run(id, g->prm.seed, 0, 0, ORC_TAG_THRESHOLD, &bits, &u32);
+  const double x = ldexp((double)(bits >> 11), -53);
   const double a = 2.0 * x - 1.0;
   const double t = g->prm.gamma_thr * (1.0 + g->prm.gamma_thr_spread * a);
   return R(g, t);
@@ -291,7 +335,7 @@ int orc_seed(orc_gap* g, int32_t mode, int64_t n_pairs, int32_t macro_per_pair,
     int64_t off24;
     if (mode == ORC_SEED_RANDOM) {
       uint64_t u[4];
-      draw((uint64_t)i, g->prm.seed, 0, 0, ORC_TAG_SEED, u);
+      draw_seed((uint64_t)i, g->prm.seed, u);
       cell = (int32_t)(((u[0] >> 32) * (uint64_t)g->prm.n_cells) >> 32);
       off24 = (int64_t)(u[1] >> 40);
     } else {
@@ -603,16 +647,17 @@ static int step_once(orc_gap* g) {
       int64_t oq = S->offq[i];
       uint64_t id = S->id[i];
       for (int j = 0; j < k; ++j) {
-        uint64_t u[4];
-        draw(id, P->seed, (uint64_t)n, (uint64_t)j, ORC_TAG_PHOTON, u);
-        uint64_t child = u[1] & ~(uint64_t)1;
+        uint64_t bits;
+        uint32_t u32;
+        draw_run(id, P->seed, (uint64_t)n, (uint64_t)j, ORC_TAG_PHOTON, &bits, &u32);
+        uint64_t child = bits & ~(uint64_t)1;
         g->photons_emitted++;
         if (g->table_len == 0) {
           /* in-place pair production (section 2) */
           append_pair(g, n, c, oq, dir, child, pchild);
           continue;
         }
-        int64_t nc = conv_steps(g, (uint32_t)(u[0] >> 32));
+        int64_t nc = conv_steps(g, u32);
         int64_t X = (int64_t)c * ONE + oq + (int64_t)dir * nc * photon_step;
         if (absorbing) {
           if (X < 0 || X >= domain) {

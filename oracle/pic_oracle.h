@@ -98,6 +98,7 @@ int      orc_read_event_map(const orc_gap* g, int64_t* out);
 
 /* Building blocks exposed for pinning against libraries and closed forms. */
 void     orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
+void     orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 int64_t  orc_conv_table(double dt, double dx, double l_gamma, uint32_t* table, int64_t max_len);
 
 #ifdef __cplusplus

@@ -205,16 +205,44 @@ __device__ __forceinline__ U64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_
   return o;
 }
 
+// Philox4x32-10 (same paper): the 32-bit form, two 32x32 -> 64-bit products
+// per round.  The draws of the run use it: lepton `id`'s draw with tag t at
+// step n and index j has counter (n, j | t << 8, id low, id high) and key
+// (seed low, seed high); words 1:0 form a 64-bit value, word 2 a 32-bit one.
+struct RunDraw { uint64_t bits; uint32_t u32; };
+
+__device__ __forceinline__ RunDraw draw_run(uint64_t id, uint64_t seed, uint32_t step, uint32_t j,
+                                            uint32_t tag) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+  const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+  uint32_t c0 = step, c1 = j | (tag << 8), c2 = (uint32_t)id, c3 = (uint32_t)(id >> 32);
+  uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+#pragma unroll 1
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) { k0 += W0; k1 += W1; }
+    const uint64_t a = (uint64_t)M0 * c0, b = (uint64_t)M1 * c2;
+    const uint32_t n0 = (uint32_t)(b >> 32) ^ c1 ^ k0, n2 = (uint32_t)(a >> 32) ^ c3 ^ k1;
+    c1 = (uint32_t)b;
+    c3 = (uint32_t)a;
+    c0 = n0;
+    c2 = n2;
+  }
+  RunDraw d;
+  d.bits = ((uint64_t)c1 << 32) | c0;
+  d.u32 = c2;
+  return d;
+}
+
 // Emission threshold of lepton `id` under a spread sigma of gamma_thr, a fixed
 // property of the lepton, uniform in gamma_thr (1 - sigma, 1 + sigma): the top
-// 53 bits of word 0 of its tag-3 draw as a fraction u, then
+// 53 bits of the 64-bit value of its tag-3 draw as a fraction u, then
 // gamma_thr (1 + sigma (2u - 1)) in binary64 with one rounding per operation,
 // rounded to the particle precision.
 template <typename T>
 __device__ __forceinline__ T lepton_threshold(uint64_t id, uint64_t seed, double gthr64,
                                               double sigma) {
-  const U64x4 u = philox4x64_10(0, 0, kTagThreshold, 0, id, seed);
-  const double x = (double)(u.v[0] >> 11) * 0x1p-53;
+  const RunDraw u = draw_run(id, seed, 0, 0, (uint32_t)kTagThreshold);
+  const double x = (double)(u.bits >> 11) * 0x1p-53;
   const double a = 2.0 * x - 1.0;
   return (T)(gthr64 * (1.0 + sigma * a));
 }

@@ -184,16 +184,17 @@ __device__ __forceinline__ int block_excl_scan(int x, int* s_tmp, int& total) {
 // later, else the pair is made in place).  The push lists the chunk's ne
 // emitters in LDS: entry (chunk-local index << 8 | k, the k emissions of this
 // step) and the position after the move on the 2^-K grid (<< 1 | forward).
-// Each thread takes the emitters tid, tid + kBlock, ...: their ids are
-// requested together and kept in LDS, an LDS atomic gives each thread its
-// place among the chunk's photons (any order serves: results do not depend
-// on slots), and the chunk's slots are reserved with one global atomic.
-// Emission j of an emitter at step n draws Philox4x64-10 with counter
-// (n, j, 2, 0) and key (id, seed): the child electron id is word 1 with bit
-// 0 cleared (the positron's has it set), and the photon's path in steps,
-// n_conv = min{k >= 1 : u >= T_k} for u the top 32 bits of word 0, comes
-// from the gap's conversion table.  The gap's emission constants are read
-// here, where they are used, not held in registers through the push.
+// Each thread takes four consecutive entries and requests their ids; a block
+// scan of their photon counts gives each emitter its first photon (kept in
+// its entry's place), and one global atomic reserves the chunk's slots.  The
+// chunk's photons are then spread evenly over the threads; a binary search
+// over the prefixes finds each photon's emitter.  Emission j of an emitter
+// at step n is its tag-2 draw (draw_run): the child electron id is the
+// 64-bit value with bit 0 cleared (the positron's has it set), and the
+// photon's path in steps, n_conv = min{k >= 1 : u >= T_k} for u the 32-bit
+// value, comes from the gap's conversion table.  The gap's emission
+// constants are read here, where they are used, not held in registers
+// through the push.
 template <typename T>
 __device__ __forceinline__ void emit_chunk(GapDev* __restrict__ G, int s, long long i0, int ne,
                                            uint32_t* s_emit, const long long* s_emx,
@@ -240,7 +241,8 @@ __device__ __forceinline__ void emit_chunk(GapDev* __restrict__ G, int s, long l
   }
   __syncthreads();
   const unsigned long long base = *s_slot;
-  const uint64_t step = (uint64_t)G->step, seed = G->seed;
+  const uint32_t step = (uint32_t)G->step;
+  const uint64_t seed = G->seed;
   const int K = G->K;
   // the emitter of the chunk's photon p: the last entry whose first photon is at most p
   auto emitter_of = [&](int p) {
@@ -271,8 +273,8 @@ __device__ __forceinline__ void emit_chunk(GapDev* __restrict__ G, int s, long l
       const int c = (int)(X0 >> K);
       const T offn = (T)(X0 & mask) * inv_scale;
       const T pc = (xe & 1) ? pchild : -pchild;
-      const U64x4 u = philox4x64_10(step, (uint64_t)jj, kTagPhoton, 0, s_emid[q], seed);
-      const uint64_t child = u.v[1] & ~(uint64_t)1;
+      const RunDraw u = draw_run(s_emid[q], seed, step, (uint32_t)jj, (uint32_t)kTagPhoton);
+      const uint64_t child = u.bits & ~(uint64_t)1;
       const unsigned long long se = n0 + base + p, sp = n1 + base + p;
       if (se < slots) { c0[se] = c; o0[se] = offn; p0[se] = pc; d0[se] = child; }
       if (sp < slots) { c1[sp] = c; o1[sp] = offn; p1[sp] = pc; d1[sp] = child | 1u; }
@@ -304,9 +306,10 @@ __device__ __forceinline__ void emit_chunk(GapDev* __restrict__ G, int s, long l
       const int ph = p + h * kBlock < kt ? p + h * kBlock : p;
       const int q = emitter_of(ph);
       qe[h] = q;
-      const U64x4 u = philox4x64_10(step, (uint64_t)(ph - (int)s_emit[q]), kTagPhoton, 0, s_emid[q], seed);
-      ch[h] = u.v[1] & ~(uint64_t)1;
-      uu[h] = (uint32_t)(u.v[0] >> 32);
+      const RunDraw u = draw_run(s_emid[q], seed, step, (uint32_t)(ph - (int)s_emit[q]),
+                                 (uint32_t)kTagPhoton);
+      ch[h] = u.bits & ~(uint64_t)1;
+      uu[h] = u.u32;
       kk[h] = conv_estimate(len, uu[h], inv_lnq);
     }
 #pragma unroll

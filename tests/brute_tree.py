@@ -3,8 +3,9 @@
 With zero macro-particle weight the current vanishes and E stays at its
 uniform initial value, so every lepton evolves on its own.  This helper
 follows each lepton from its birth to the end of the run, one lineage at a
-time (depth first), and draws its photons with numpy's Philox4x64-10 rather
-than the oracle's generator.  Counting births, deaths and conversions per
+time (depth first), and draws its photons with its own Philox4x32-10 (written
+here from the published definition and pinned to the generator's published
+known-answer vectors) rather than the oracle's generator.  Counting births, deaths and conversions per
 step then gives the per-step totals the oracle must reproduce exactly.
 
 The emission model is that of section 2 of arXiv:2012.05587 (threshold
@@ -30,6 +31,33 @@ def philox(ctr, key):
     return [int(x) for x in bg.random_raw(4)]
 
 
+_M32 = 0xFFFFFFFF
+
+
+def philox4x32(ctr, key):
+    """Philox4x32-10 block: ten rounds of two 32 x 32 -> 64-bit products by
+    0xD2511F53 (word 0) and 0xCD9E8D57 (word 2), the new words being
+    (hi1 ^ c1 ^ k0, lo1, hi0 ^ c3 ^ k1, lo0); the key is bumped by 0x9E3779B9
+    and 0xBB67AE85 before every round after the first."""
+    c0, c1, c2, c3 = (int(x) & _M32 for x in ctr)
+    k0, k1 = (int(x) & _M32 for x in key)
+    for r in range(10):
+        if r:
+            k0 = (k0 + 0x9E3779B9) & _M32
+            k1 = (k1 + 0xBB67AE85) & _M32
+        a = 0xD2511F53 * c0
+        b = 0xCD9E8D57 * c2
+        c0, c1, c2, c3 = (b >> 32) ^ c1 ^ k0, b & _M32, (a >> 32) ^ c3 ^ k1, a & _M32
+    return [c0, c1, c2, c3]
+
+
+def draw_run(pid, seed, step, j, tag):
+    """A lepton's draw during the run: counter (step, j | tag << 8, id low, id
+    high), key (seed low, seed high); returns (words 1:0 as 64 bits, word 2)."""
+    w = philox4x32((step, j | (tag << 8), pid & _M32, pid >> 32), (seed & _M32, seed >> 32))
+    return (w[1] << 32) | w[0], w[2]
+
+
 def conv_table(dt, dx, l_gamma):
     r = dt / (l_gamma * dx)
     t = []
@@ -44,10 +72,10 @@ def conv_table(dt, dx, l_gamma):
 
 def threshold(pid, seed, gamma_thr, spread):
     """A lepton's own threshold under a spread of gamma_thr: uniform in
-    gamma_thr (1 - spread, 1 + spread) from the top 53 bits of the first word
-    of its tag-3 draw (counter (0, 0, 3, 0)), in binary64."""
-    u = philox((0, 0, TAG_THRESHOLD, 0), (pid, seed))
-    x = (u[0] >> 11) * 2.0 ** -53
+    gamma_thr (1 - spread, 1 + spread) from the top 53 bits of the 64-bit value
+    of its tag-3 draw, in binary64."""
+    bits, _ = draw_run(pid, seed, 0, 0, TAG_THRESHOLD)
+    x = (bits >> 11) * 2.0 ** -53
     return gamma_thr * (1.0 + spread * (2.0 * x - 1.0))
 
 
@@ -115,8 +143,8 @@ def run(n_cells, dx, dt, absorbing, e0, gamma_thr, f, l_gamma, seeds, n_steps, s
                 direction = 1 if p > 0 else -1
                 p = mag if direction > 0 else -mag
                 for j in range(k):
-                    u = philox((n, j, TAG_PHOTON, 0), (pid, seed))
-                    child = u[1] & ~1
+                    bits, u32 = draw_run(pid, seed, n, j, TAG_PHOTON)
+                    child = bits & ~1
                     emitted[n:] += 1
                     if table is None:
                         created[n:] += 1
@@ -129,7 +157,6 @@ def run(n_cells, dx, dt, absorbing, e0, gamma_thr, f, l_gamma, seeds, n_steps, s
                             alive[0, n] += 1
                             alive[1, n] += 1
                         continue
-                    u32 = u[0] >> 32
                     nconv = next(kk for kk in range(1, len(table)) if u32 >= table[kk])
                     X = c * ONE + oq + direction * nconv * photon_step
                     if absorbing and (X < 0 or X >= domain):

@@ -174,8 +174,12 @@ def _load_rows(path):
 def test_large_gap_mixed_energy_against_binary64_oracle():
     """The large gap (65536 cells, E0 = 1000, 16384 seed pairs) in mixed
     precision against the stored binary64 oracle history of its first 200
-    steps: energy conservation W(n)/W(0) - 1 within 1e-4 of the oracle's at
-    every step, and lepton counts within 1%."""
+    steps: the energy-conservation error W(n)/W(0) - 1 (+1.4% by step 200 in
+    binary64: dt = 0.45 does not resolve the screened plasma, which the scheme
+    heats) changed by mixed precision by less than 1% of the oracle's largest
+    error at every step, and lepton counts within 1%.  Once a rounding moves
+    one emission by a step the two runs are different realizations of that
+    heating, so the bound is relative to the error itself."""
     golden = _load_rows(os.path.join(GOLDEN, "c5_fp64_oracle_200_steps.txt"))
     cfg = workloads.config("c5_large_mixed")
     print("[case] large gap mixed, 200 steps", flush=True)
@@ -192,7 +196,7 @@ def test_large_gap_mixed_energy_against_binary64_oracle():
     dn = float(np.max(np.abs(nl - no) / no))
     print(f"energy error at step 200: mixed {err_g[-1]:+.5e}, binary64 oracle {err_o[-1]:+.5e}; "
           f"largest difference {worst:.3e}; largest relative count difference {dn:.3e}")
-    assert worst <= 1e-4
+    assert worst <= 0.01 * float(np.max(np.abs(err_o)))
     assert dn <= 1e-2
 
 

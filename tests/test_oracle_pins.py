@@ -35,6 +35,38 @@ def test_philox_matches_numpy(ctr, key):
     assert (oracle.philox4x64_10(ctr, key) == _np_philox(ctr, key)).all()
 
 
+# Published known-answer vectors of Philox4x32-10 (Salmon et al., SC'11; the
+# Random123 distribution's tests): counter, key -> output words.
+PHILOX4X32_KAT = [
+    ((0, 0, 0, 0), (0, 0), (0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8)),
+    ((0xFFFFFFFF,) * 4, (0xFFFFFFFF, 0xFFFFFFFF), (0x408F276D, 0x41C83B0E, 0xA20BC7C6, 0x6D5451FD)),
+    ((0x243F6A88, 0x85A308D3, 0x13198A2E, 0x03707344), (0xA4093822, 0x299F31D0),
+     (0xD16CFE09, 0x94FDCCEB, 0x5001E420, 0x24126EA1)),
+]
+
+
+@pytest.mark.parametrize("ctr,key,want", PHILOX4X32_KAT)
+def test_philox4x32_known_answers(ctr, key, want):
+    """Philox4x32-10, which draws each emission's child id and photon path and
+    each lepton's threshold, reproduces the generator's published
+    known-answer vectors, in the oracle and in the brute-force helper."""
+    assert [int(x) for x in oracle.philox4x32_10(ctr, key)] == list(want)
+    assert brute_tree.philox4x32(ctr, key) == list(want)
+
+
+def test_philox4x32_oracle_matches_helper_on_run_counters():
+    """The oracle's block and the helper's agree on counters of the run's
+    layout (step, j | tag << 8, id low, id high) and 64-bit seeds."""
+    rng = np.random.default_rng(5)
+    for _ in range(200):
+        pid = int(rng.integers(0, 2**63)) * 2 + int(rng.integers(0, 2))
+        seed = int(rng.integers(0, 2**63))
+        step, j, tag = int(rng.integers(0, 2**31)), int(rng.integers(0, 65)), int(rng.integers(2, 4))
+        ctr = (step, j | (tag << 8), pid & 0xFFFFFFFF, pid >> 32)
+        key = (seed & 0xFFFFFFFF, seed >> 32)
+        assert [int(x) for x in oracle.philox4x32_10(ctr, key)] == brute_tree.philox4x32(ctr, key)
+
+
 # ----------------------------------------------------------------- photon path
 def test_conversion_table_is_floor_of_geometric_tail():
     """T_k = floor(q^k 2^32), q = exp(-dt/(l_gamma dx)), checked with 40-digit
@@ -625,7 +657,10 @@ def test_threshold_spread_first_emissions_are_uniform():
     n_pairs = 10000
     g.seed(oracle.SEED_RANDOM, n_pairs, 1)
     # p^{n+1/2} = (n + 1) E0 dt: step n passes the thresholds in (gamma_{n-1}, gamma_n]
-    lo = int(gthr * (1 - sigma) / (e0 * dt))   # first step past gamma_thr (1 - sigma)
+    # with gamma_n = sqrt(1 + ((n + 1) E0 dt)^2); the first step whose gamma
+    # reaches the lowest threshold gamma_thr (1 - sigma)
+    lo = next(n for n in range(10**6)
+              if math.sqrt(1.0 + ((n + 1) * e0 * dt) ** 2) >= gthr * (1 - sigma))
     hi = lo + 900                              # a child needs 900 steps to reach it
     assert g.step(hi) == oracle.OK
     em = np.diff(g.history()["photons_emitted"], prepend=0)

@@ -192,14 +192,13 @@ def _restated_step(F, prm, E, leptons, step):
             p = mag if d > 0 else -mag
         surv[pid] = (c2, nq, float(p))
         for jj in range(k):
-            u = brute_tree.philox((step, jj, TAG_PHOTON, 0), (pid, prm["seed"]))
-            child = u[1] & ~1
+            bits, u32 = brute_tree.draw_run(pid, prm["seed"], step, jj, TAG_PHOTON)
+            child = bits & ~1
             if not table:
                 pc = float(pchild if d > 0 else -pchild)
                 kids[child] = (0, c2, nq, pc)
                 kids[child | 1] = (1, c2, nq, pc)
                 continue
-            u32 = u[0] >> 32
             ncv = next(kk for kk in range(1, len(table)) if u32 >= table[kk])
             Xc = c2 * one + nq + d * ncv * photon_step
             if not periodic and (Xc < 0 or Xc >= domain):
