@@ -127,27 +127,6 @@ __device__ __forceinline__ void block_minmax_pp(int& mn, int& mx, int (*s_red)[8
   mx = max(max(r[4], r[5]), max(r[6], r[7]));
 }
 
-// Per-wave shares of a workgroup's total: s_wave[v] holds wave v's count on
-// entry; returns the block total and sets `pre` to the counts of the waves
-// before this one.  Every thread must call it.
-__device__ __forceinline__ unsigned long long wave_shares(const unsigned long long* s_wave,
-                                                          unsigned long long& pre) {
-  const int v = threadIdx.x >> 6;
-  unsigned long long t = 0;
-  pre = 0;
-#pragma unroll
-  for (int k = 0; k < kBlock / 64; ++k) {
-    if (k < v) pre += s_wave[k];
-    t += s_wave[k];
-  }
-  return t;
-}
-
-// Lanes below this one in the wave.
-__device__ __forceinline__ unsigned long long lanes_below() {
-  return (1ull << lane_id()) - 1ull;
-}
-
 // Pairs of a step share one slot cursor: the workgroup reserves `tot` pairs
 // (electron slots from n[0], positron slots from n[1]).  Appends beyond the
 // slots are not written and freeze the gap; the capacity itself (live
@@ -1008,21 +987,57 @@ __device__ __forceinline__ uint32_t key_matches(u32x4 kv, uint32_t key) {
   return m;
 }
 
-constexpr int kConvGroup = kBlock / 64;  // conversion items of a workgroup at once: one per wave
+constexpr int kConvGroup = kBlock / 64;  // waves of a conversion workgroup, each with its own list
 
+// The due mask of one lane's kKeyRun photons of conversion item `local` of a
+// gap whose due ranges are [rb0, rb1) and [rt0, rt1): bit b set when photon
+// ib + 16 lane + b converts this step.  Bucket items are all due; tail
+// photons are found by their one-byte keys while the step is within
+// kFarKey - 1 steps of the last sort (keyed), else by their conversion steps.
+struct ConvRun {
+  long long ib;  // first slot of the item
+  uint32_t in;   // the lane's photons inside the item's range
+  bool tail;
+};
+
+__device__ __forceinline__ ConvRun conv_run(long long rb0, long long rb1, long long rt0, long long rt1,
+                                            long long local, int lane) {
+  ConvRun r;
+  long long i0, i1;
+  r.tail = convert_item(rb0, rb1, rt0, rt1, local, r.ib, i0, i1);
+  const long long s0 = r.ib + (long long)lane * kKeyRun;
+  const long long lo = i0 - s0, hi = i1 - s0;
+  const int a = lo < 0 ? 0 : (lo > kKeyRun ? kKeyRun : (int)lo);
+  const int e = hi < 0 ? 0 : (hi > kKeyRun ? kKeyRun : (int)hi);
+  r.in = ((1u << e) - 1u) & ~((1u << a) - 1u);
+  return r;
+}
+
+// Photons due at the end of the step become pairs at their conversion
+// points, moving along the photon (section 2).  Each wave works apart: it
+// takes a contiguous range of the plan's conversion items (its workgroup's
+// range cut in four); for each item every lane tests kKeyRun consecutive
+// photons (one 16-byte load of keys), a wave scan of the lanes' counts places
+// the item's due photons in the wave's LDS list, lane 0 reserves their pair
+// slots with one atomic, and the lanes convert the list one photon each.
+// The keys of the wave's next item of the same gap are requested before the
+// current item's photons are converted.  No workgroup barrier.
 template <typename T>
 __device__ void convert_role(GapDev* __restrict__ gaps, const long long* __restrict__ pwi, int B,
-                             int vb, int nvb, unsigned long long* s_wave,
-                             unsigned long long* s_base, uint32_t* s_due) {
+                             int vb, int nvb, uint32_t* s_due) {
   static_assert(kPhChunk == 64 * kKeyRun, "an item is one key run per lane");
-  constexpr int kDueCap = kPhChunk;  // due photons a wave can list (its item)
   const int lane = lane_id();
-  const int v = threadIdx.x >> 6;
-  uint32_t* due = s_due + v * kDueCap;
+  // the wave's index, uniform
+  const int v = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  uint32_t* due = s_due + v * kPhChunk;
   const long long total = pwi[B];
-  long long w0, w1;
-  xcd_range(total, w0, w1, vb, nvb);
-  for (long long w = w0; w < w1;) {
+  long long x0, x1;
+  xcd_range(total, x0, x1, vb, nvb);
+  const long long per = (x1 - x0 + kConvGroup - 1) / kConvGroup;
+  long long w = x0 + (long long)v * per;
+  w = w < x1 ? w : x1;
+  const long long w1 = w + per < x1 ? w + per : x1;
+  while (w < w1) {
     const int g = find_gap(pwi, B, w);
     const long long wend = pwi[g + 1] < w1 ? pwi[g + 1] : w1;
     GapDev* __restrict__ G = gaps + g;
@@ -1032,8 +1047,6 @@ __device__ void convert_role(GapDev* __restrict__ gaps, const long long* __restr
     const long long wg0 = pwi[g];
     long long rb0, rb1, rt0, rt1;  // the gap's due ranges, read once
     photon_ranges(G, rb0, rb1, rt0, rt1);
-    // tail photons are found by their one-byte keys while the step is within
-    // kFarKey - 1 steps of the last sort, else by their conversion steps
     const long long kstep = G->step - G->ph_base;
     const bool keyed = kstep < kFarKey;
     gptr<const uint8_t> phk = glb<const uint8_t>((void*)G->ph_key);
@@ -1051,69 +1064,62 @@ __device__ void convert_role(GapDev* __restrict__ gaps, const long long* __restr
     const T inv_scale = (T)(1.0 / (double)G->one);
     const T pchild = (T)G->pchild;
     const bool evmap = G->evmap != nullptr;
-    // Groups of kConvGroup items, one per wave: each lane tests kKeyRun
-    // consecutive photons of its wave's item, the wave lists its due photons
-    // in LDS (a wave scan of the lanes' counts gives the positions), the
-    // workgroup reserves their pair slots with one atomic, and the wave's
-    // lanes then convert its list one photon per lane.
-    for (long long x = w; x < wend; x += kConvGroup) {
-      const long long xi = x + v;
-      long long ib = 0;
-      uint32_t m = 0;  // due photons among the lane's kKeyRun
-      if (xi < wend) {
-        long long i0, i1;
-        const bool tail = convert_item(rb0, rb1, rt0, rt1, xi - wg0, ib, i0, i1);
-        const long long s0 = ib + (long long)lane * kKeyRun;
-        const long long lo = i0 - s0, hi = i1 - s0;
-        const int a = lo < 0 ? 0 : (lo > kKeyRun ? kKeyRun : (int)lo);
-        const int e = hi < 0 ? 0 : (hi > kKeyRun ? kKeyRun : (int)hi);
-        const uint32_t in = ((1u << e) - 1u) & ~((1u << a) - 1u);
-        if (!tail) {
-          m = in;  // the bucket of this step: all due
-        } else if (in != 0u) {
-          if (keyed) {
-            // s0 is a multiple of kKeyRun below the tail's end: the run lies
-            // in the key array (sized up to a multiple of kKeyRun)
-            const u32x4 kv = *(gptr<const u32x4>)(phk + s0);
-            m = key_matches(kv, (uint32_t)kstep) & in;
-          } else {
+    // the keys of a tail item's lane run (s0 is a multiple of kKeyRun below
+    // the tail's end: the run lies in the key array, sized up to a multiple of
+    // kKeyRun); zero for bucket items and unkeyed tails
+    auto keys_of = [&](const ConvRun& r) {
+      u32x4 kv = {0u, 0u, 0u, 0u};
+      if (r.tail && keyed && r.in != 0u) kv = *(gptr<const u32x4>)(phk + r.ib + (long long)lane * kKeyRun);
+      return kv;
+    };
+    ConvRun r = conv_run(rb0, rb1, rt0, rt1, w - wg0, lane);
+    u32x4 kv = keys_of(r);
+    for (long long x = w; x < wend; ++x) {
+      // this item's due photons
+      uint32_t m;
+      if (!r.tail) m = r.in;  // the bucket of this step: all due
+      else if (keyed) m = key_matches(kv, (uint32_t)kstep) & r.in;
+      else {
+        m = 0u;
+        const long long s0 = r.ib + (long long)lane * kKeyRun;
 #pragma unroll
-            for (int b = 0; b < kKeyRun; ++b)
-              if ((in >> b) & 1u) m |= (phs[s0 + b] == stepn ? 1u : 0u) << b;
-          }
-        }
+        for (int b = 0; b < kKeyRun; ++b)
+          if ((r.in >> b) & 1u) m |= (phs[s0 + b] == stepn ? 1u : 0u) << b;
       }
-      __syncthreads();  // the previous group's lists, s_wave and s_base are consumed
+      const long long ib = r.ib;
+      // the next item's keys, requested now
+      if (x + 1 < wend) {
+        r = conv_run(rb0, rb1, rt0, rt1, x + 1 - wg0, lane);
+        kv = keys_of(r);
+      }
       const uint32_t c = (uint32_t)__popc(m);
-      const uint32_t incl = wave_incl_scan(c);
+      const uint32_t incl = (uint32_t)wave_incl_scan_dpp((int)c);
+      const uint32_t cnt = (uint32_t)__builtin_amdgcn_readfirstlane(__shfl((int)incl, 63, 64));
+      if (cnt == 0) continue;  // uniform
       uint32_t pos = incl - c;
       while (m) {
         const int b = __ffs(m) - 1;
         m &= m - 1u;
         due[pos++] = (uint32_t)(lane * kKeyRun + b);
       }
-      const uint32_t cnt = (uint32_t)__shfl((int)incl, 63, 64);
-      if (lane == 0) s_wave[v] = cnt;
-      __syncthreads();
-      unsigned long long pre;
-      const unsigned long long tot = wave_shares(s_wave, pre);
-      if (tot == 0) continue;  // uniform
-      if (threadIdx.x == 0) s_base[0] = reserve_pairs(G, tot);
-      __syncthreads();
-      const unsigned long long base = s_base[0] + pre;
+      __builtin_amdgcn_wave_barrier();  // the list is complete before any lane reads it
+      unsigned long long base = 0;
+      if (lane == 0) base = reserve_pairs(G, cnt);
+      base = __shfl(base, 0, 64);
       for (uint32_t q = (uint32_t)lane; q < cnt; q += 64) {
         const long long i = ib + (long long)due[q];
         const long long X = phx[i];
         const uint64_t ch = phc[i];
-        const int c = (int)(X >> K);
+        const int cc = (int)(X >> K);
         const T offn = (T)(X & mask) * inv_scale;
         const T pc = (ch & 1u) ? pchild : -pchild;
         const uint64_t child = ch & ~(uint64_t)1;
         const unsigned long long se = ne0 + base + q, sp = ne1 + base + q;
-        if (se < cap) { cell0[se] = c; off0[se] = offn; p0[se] = pc; id0[se] = child; }
-        if (sp < cap) { cell1[sp] = c; off1[sp] = offn; p1[sp] = pc; id1[sp] = child | 1u; }
-        if (evmap) count_pairs(G, (long long)stepn, c, 1ull);
+        if (se < cap) { cell0[se] = cc; off0[se] = offn; p0[se] = pc; id0[se] = child; }
+        if (sp < cap) { cell1[sp] = cc; off1[sp] = offn; p1[sp] = pc; id1[sp] = child | 1u; }
+        if (evmap) count_pairs(G, (long long)stepn, cc, 1ull);
       }
+      __builtin_amdgcn_wave_barrier();  // the list is read before the next item rewrites it
     }
     w = wend;
   }
@@ -1448,14 +1454,12 @@ __global__ __launch_bounds__(kBlock) void k_post(GapDev* __restrict__ gaps,
                                                  int n_field, int n_conv,
                                                  unsigned long long* __restrict__ stripes) {
   __shared__ double s_red[8];
-  __shared__ unsigned long long s_wave[kBlock / 64];
-  __shared__ unsigned long long s_base[1];
-  // the conversion role's lists of due photons
+  // the conversion role's lists of due photons, one per wave
   __shared__ uint32_t s_buf[kConvGroup * kPhChunk];
   const int b = blockIdx.x;
   if (b < n_field) field_role(gaps, cwi, B, b, s_red);
   else if (b < n_field + n_conv)
-    convert_role<T>(gaps, pwi, B, b - n_field, n_conv, s_wave, s_base, s_buf);
+    convert_role<T>(gaps, pwi, B, b - n_field, n_conv, s_buf);
   else fold_role(gaps, B, stripes, b - n_field - n_conv);
 }
 
