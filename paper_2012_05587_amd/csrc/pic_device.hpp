@@ -125,6 +125,9 @@ struct GapDev {
   float inv_lnq;          // 1 / ln q of the photon path, q = exp(-dt / (l_gamma dx))
   int32_t ph_age;         // steps the photon tail may grow before a re-sort sorts the store
   unsigned long long* evmap;  // pair-event map (caller's device buffer), or null
+  int32_t* emit_cnt;          // the batch's emitters per chunk (same in every gap)
+  uint32_t* emit_ent;         // the batch's emitter lists, kChunk entries per chunk
+  uint32_t* wg_emit;          // the batch's emitters per push workgroup
   int32_t ev_x, ev_steps, ev_rows, pad5;
 
   // ---- counters (device-updated)

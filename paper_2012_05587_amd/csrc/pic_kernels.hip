@@ -158,174 +158,132 @@ __device__ __forceinline__ int block_excl_scan(int x, int* s_tmp, int& total) {
 }
 
 // ------------------------------------------------------------------ emit
-// Emission of one pushed chunk of species s (section 2: a lepton that reaches
-// gamma_thr emits; with a finite photon path the photon is stored and converts
-// later, else the pair is made in place).  The push lists the chunk's ne
-// emitters in LDS: entry (chunk-local index << 8 | k, the k emissions of this
-// step) and the position after the move on the 2^-K grid (<< 1 | forward).
-// Each thread takes four consecutive entries and requests their ids; a block
-// scan of their photon counts gives each emitter its first photon (kept in
-// its entry's place), and one global atomic reserves the chunk's slots.  The
-// chunk's photons are then spread evenly over the threads; a binary search
-// over the prefixes finds each photon's emitter.  Emission j of an emitter
-// at step n is its tag-2 draw (draw_run): the child electron id is the
-// 64-bit value with bit 0 cleared (the positron's has it set), and the
-// photon's path in steps, n_conv = min{k >= 1 : u >= T_k} for u the 32-bit
-// value, comes from the gap's conversion table.  The gap's emission
-// constants are read here, where they are used, not held in registers
-// through the push.
+// The push lists each chunk's emitters (chunk-local index << 8 | k) in the
+// chunk's slice of emit_ent, with their count in emit_cnt and each push
+// workgroup's total in wg_emit; the emission role of k_post draws their
+// photons (or in-place pairs).
+
+// What the emission of one gap needs, read from its descriptor once per gap
+// segment of a wave.
 template <typename T>
-__device__ __forceinline__ void emit_chunk(GapDev* __restrict__ G, int s, long long i0, int ne,
-                                           uint32_t* s_emit, const long long* s_emx,
-                                           uint64_t* s_emid, int* s_scan,
-                                           unsigned long long* s_slot) {
-  const int tid = threadIdx.x;
-  const int buf = G->buf;
-  const bool in_place = G->table_len == 0;
-  int kt;
-  {
-    // thread t owns the entries 4t .. 4t + 3 (list order): their ids, and a
-    // block scan of their photon counts gives each its first photon; the
-    // entry's slot in s_emit then holds that prefix
-    gptr<const uint64_t> idA = glb<const uint64_t>((void*)G->id[buf][s]);
-    uint32_t e[4];
-    uint64_t idv[4];
-    int mine = 0;
+struct EmitGap {
+  GapDev* G;
+  gptr<int32_t> cell[2];
+  gptr<T> off[2], p[2];
+  gptr<uint64_t> id[2];
+  gptr<long long> phx;
+  gptr<int32_t> phs;
+  gptr<uint64_t> phc;
+  gptr<uint8_t> phk;
+  const uint32_t* table;
+  int table_len, K;
+  float inv_lnq;
+  long long domain, photon_step, ph_base;
+  unsigned long long ph_cap, slots, n0, n1;
+  uint32_t step;
+  uint64_t seed;
+  T pchild, inv_scale, scale;
+  bool absorbing, in_place, evmap;
+};
+
+template <typename T>
+__device__ __forceinline__ EmitGap<T> emit_gap(GapDev* __restrict__ G) {
+  EmitGap<T> E;
+  E.G = G;
+  const int buf = G->buf, pb = G->phbuf;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int q = 4 * tid + j;
-      e[j] = q < ne ? s_emit[q] : 0u;
-      idv[j] = q < ne ? idA[i0 + (long long)(e[j] >> 8)] : 0ull;
-      mine += (int)(e[j] & 255u);
-    }
-    int ex = block_excl_scan(mine, s_scan, kt);  // ends with a barrier
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int q = 4 * tid + j;
-      if (q < ne) {
-        s_emit[q] = (uint32_t)ex;
-        s_emid[q] = idv[j];
-      }
-      ex += (int)(e[j] & 255u);
-    }
-    if (tid == 0) {
-      if (in_place) {
-        *s_slot = reserve_pairs(G, (unsigned long long)kt);
-      } else {
-        const unsigned long long b0 = atomicAdd(&G->n_ph_next, (unsigned long long)kt);
-        if (b0 + (unsigned long long)kt > (unsigned long long)G->ph_cap) G->overflow = 1;
-        *s_slot = b0;
-      }
-    }
+  for (int s = 0; s < 2; ++s) {
+    E.cell[s] = glb(G->cell[buf][s]);
+    E.off[s] = glb<T>(G->off[buf][s]);
+    E.p[s] = glb<T>(G->p[buf][s]);
+    E.id[s] = glb(G->id[buf][s]);
   }
-  __syncthreads();
-  const unsigned long long base = *s_slot;
-  const uint32_t step = (uint32_t)G->step;
-  const uint64_t seed = G->seed;
-  const int K = G->K;
-  // the emitter of the chunk's photon p: the last entry whose first photon is at most p
-  auto emitter_of = [&](int p) {
-    int lo = 0, hi = ne - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if ((int)s_emit[mid] <= p) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-  };
-  if (in_place) {
-    // pairs made in place (the paper's zero mean free path), both children
-    // at the emitter's position moving along its direction
-    const unsigned long long n0 = G->n[0], n1 = G->n[1], slots = (unsigned long long)G->slots;
-    const long long mask = G->one - 1;
-    const T inv_scale = (T)(1.0 / (double)G->one), pchild = (T)G->pchild;
-    const bool evmap = G->evmap != nullptr;
-    gptr<int32_t> c0 = glb(G->cell[buf][0]), c1 = glb(G->cell[buf][1]);
-    gptr<T> o0 = glb<T>(G->off[buf][0]), o1 = glb<T>(G->off[buf][1]);
-    gptr<T> p0 = glb<T>(G->p[buf][0]), p1 = glb<T>(G->p[buf][1]);
-    gptr<uint64_t> d0 = glb(G->id[buf][0]), d1 = glb(G->id[buf][1]);
-#pragma unroll 1
-    for (int p = tid; p < kt; p += kBlock) {
-      const int q = emitter_of(p);
-      const int jj = p - (int)s_emit[q];
-      const long long xe = s_emx[q];
-      const long long X0 = xe >> 1;
-      const int c = (int)(X0 >> K);
-      const T offn = (T)(X0 & mask) * inv_scale;
-      const T pc = (xe & 1) ? pchild : -pchild;
-      const RunDraw u = draw_run(s_emid[q], seed, step, (uint32_t)jj, (uint32_t)kTagPhoton);
-      const uint64_t child = u.bits & ~(uint64_t)1;
-      const unsigned long long se = n0 + base + p, sp = n1 + base + p;
-      if (se < slots) { c0[se] = c; o0[se] = offn; p0[se] = pc; d0[se] = child; }
-      if (sp < slots) { c1[sp] = c; o1[sp] = offn; p1[sp] = pc; d1[sp] = child | 1u; }
-      if (evmap) count_pairs(G, (long long)step, c, 1ull);
-    }
-    return;
-  }
-  const int pb = G->phbuf;
-  gptr<long long> phx = glb(G->ph_x[pb]);
-  gptr<int32_t> phs = glb(G->ph_step[pb]);
-  gptr<uint64_t> phc = glb(G->ph_child[pb]);
-  gptr<uint8_t> phk = glb(G->ph_key);
-  const uint32_t* table = G->table;
-  gptr<const uint32_t> tab = glb<const uint32_t>((void*)G->table);
-  const int len = G->table_len;
-  const float inv_lnq = G->inv_lnq;
-  const long long domain = G->domain, photon_step = G->photon_step, ph_base = G->ph_base;
-  const unsigned long long ph_cap = (unsigned long long)G->ph_cap;
-  const bool absorbing = G->boundary == PIC_BC_ABSORBING;
+  E.phx = glb(G->ph_x[pb]);
+  E.phs = glb(G->ph_step[pb]);
+  E.phc = glb(G->ph_child[pb]);
+  E.phk = glb(G->ph_key);
+  E.ph_base = G->ph_base;
+  E.table = G->table;
+  E.table_len = G->table_len;
+  E.K = G->K;
+  E.inv_lnq = G->inv_lnq;
+  E.domain = G->domain;
+  E.photon_step = G->photon_step;
+  E.ph_cap = (unsigned long long)G->ph_cap;
+  E.slots = (unsigned long long)G->slots;
+  E.n0 = G->n[0];
+  E.n1 = G->n[1];
+  E.step = (uint32_t)G->step;
+  E.seed = G->seed;
+  E.pchild = (T)G->pchild;
+  E.scale = (T)(double)G->one;
+  E.inv_scale = (T)(1.0 / (double)G->one);
+  E.absorbing = G->boundary == PIC_BC_ABSORBING;
+  E.in_place = G->table_len == 0;
+  E.evmap = G->evmap != nullptr;
+  return E;
+}
+
+// The k photons (or in-place pairs) of listed emitter i of species s, from
+// its stored state after the push (position, the momentum's sign for the
+// direction, id), written at slots slot0 .. slot0 + k - 1 (pair slots
+// n[0] + slot, n[1] + slot).  Emission j of an emitter at step n is its
+// tag-2 draw (draw_run): the child electron id is the 64-bit value with bit
+// 0 cleared (the positron's has it set), and the photon's path in steps,
+// n_conv = min{k >= 1 : u >= T_k} for u the 32-bit value, comes from the
+// gap's conversion table.  Returns the number of photons that left the
+// domain.
+template <typename T>
+__device__ __forceinline__ unsigned emit_listed(const EmitGap<T>& E, int s, long long i, int k,
+                                                unsigned long long slot0) {
+  const gptr<int32_t> cA = s == 0 ? E.cell[0] : E.cell[1];
+  const gptr<T> oA = s == 0 ? E.off[0] : E.off[1];
+  const gptr<T> pA = s == 0 ? E.p[0] : E.p[1];
+  const gptr<uint64_t> iA = s == 0 ? E.id[0] : E.id[1];
+  const int c = cA[i];
+  const long long oq = (long long)(oA[i] * E.scale);
+  const T pv = pA[i];
+  const uint64_t id = iA[i];
+  const int dir = signbit(pv) ? -1 : 1;
   unsigned esc = 0;
-  // two photons per iteration, so that their table entries are requested together
-#pragma unroll 1
-  for (int p = tid; p < kt; p += 2 * kBlock) {
-    uint32_t uu[2], tm[2], t0[2], tp[2];
-    uint64_t ch[2];
-    int kk[2], qe[2];
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int ph = p + h * kBlock < kt ? p + h * kBlock : p;
-      const int q = emitter_of(ph);
-      qe[h] = q;
-      const RunDraw u = draw_run(s_emid[q], seed, step, (uint32_t)(ph - (int)s_emit[q]),
-                                 (uint32_t)kTagPhoton);
-      ch[h] = u.bits & ~(uint64_t)1;
-      uu[h] = u.u32;
-      kk[h] = conv_estimate(len, uu[h], inv_lnq);
-    }
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      tm[h] = tab[kk[h] - 1 > 0 ? kk[h] - 1 : 0];
-      t0[h] = tab[kk[h]];
-      tp[h] = tab[kk[h] + 1 < len ? kk[h] + 1 : len - 1];
-    }
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int ph = p + h * kBlock;
-      if (ph >= kt) break;
-      const int ncv = conv_decide(table, len, uu[h], kk[h], tm[h], t0[h], tp[h]);
-      const long long xe = s_emx[qe[h]];
-      const long long dirq = (xe & 1) ? photon_step : -photon_step;
-      long long X = (xe >> 1) + (long long)ncv * dirq;
-      int cstep = (int)((long long)step + ncv);
-      if (absorbing) {
-        if (X < 0 || X >= domain) { cstep = INT32_MIN; ++esc; }
-      } else if (X < 0 || X >= domain) {
-        X = wrap_periodic(X, domain);
-      }
-      const unsigned long long sl = base + (unsigned long long)ph;
-      if (sl < ph_cap) {
-        phx[sl] = X;
-        phs[sl] = cstep;
-        phc[sl] = ch[h] | (uint64_t)(xe & 1);
-        // the tail key: steps from the last sort to the conversion (>= 1)
-        const long long rel = (long long)cstep - ph_base;
-        phk[sl] = (uint8_t)(cstep != INT32_MIN && rel < kFarKey ? rel : kFarKey);
+  if (E.in_place) {
+    const T pc = dir > 0 ? E.pchild : -E.pchild;
+    const T offn = (T)oq * E.inv_scale;
+    for (int jj = 0; jj < k; ++jj) {
+      const RunDraw u = draw_run(id, E.seed, E.step, (uint32_t)jj, (uint32_t)kTagPhoton);
+      const uint64_t child = u.bits & ~(uint64_t)1;
+      const unsigned long long se = E.n0 + slot0 + jj, sp = E.n1 + slot0 + jj;
+      if (se < E.slots) { E.cell[0][se] = c; E.off[0][se] = offn; E.p[0][se] = pc; E.id[0][se] = child; }
+      if (sp < E.slots) {
+        E.cell[1][sp] = c; E.off[1][sp] = offn; E.p[1][sp] = pc; E.id[1][sp] = child | 1u;
       }
     }
+    if (E.evmap) count_pairs(E.G, (long long)E.step, c, (unsigned long long)k);
+    return 0;
   }
-  if (absorbing) {
-    const unsigned long long esc_w = wave_sum((unsigned long long)esc);
-    if (lane_id() == 0 && esc_w > 0) atomicAdd(&G->esc_next, esc_w);
+  const long long X0 = ((long long)c << E.K) + oq;
+  for (int jj = 0; jj < k; ++jj) {
+    const RunDraw u = draw_run(id, E.seed, E.step, (uint32_t)jj, (uint32_t)kTagPhoton);
+    const uint64_t child = u.bits & ~(uint64_t)1;
+    const int ncv = conv_steps(E.table, E.table_len, u.u32, E.inv_lnq);
+    long long X = X0 + (long long)dir * (long long)ncv * E.photon_step;
+    int cstep = (int)((long long)E.step + ncv);
+    if (E.absorbing) {
+      if (X < 0 || X >= E.domain) { cstep = INT32_MIN; ++esc; }
+    } else if (X < 0 || X >= E.domain) {
+      X = wrap_periodic(X, E.domain);
+    }
+    const unsigned long long slot = slot0 + jj;
+    if (slot < E.ph_cap) {
+      E.phx[slot] = X;
+      E.phs[slot] = cstep;
+      E.phc[slot] = child | (dir > 0 ? 1u : 0u);
+      // the tail key: steps from the last sort to the conversion (>= 1)
+      const long long rel = (long long)cstep - E.ph_base;
+      E.phk[slot] = (uint8_t)(cstep != INT32_MIN && rel < kFarKey ? rel : kFarKey);
+    }
   }
+  return esc;
 }
 
 // ------------------------------------------------------------------ push
@@ -498,10 +456,6 @@ __global__ __launch_bounds__(kBlock, kSpread ? PushCfg<T>::spread_waves : PushCf
   using I = typename Fixed<T>::I;
   __shared__ long long s_flux[kTile];
   __shared__ uint32_t s_emit[kChunk];  // chunk-local index << 8 | k
-  __shared__ long long s_emx[kChunk];  // the emitter's position after the move << 1 | forward
-  __shared__ uint64_t s_emid[kChunk];  // the emitter's id
-  __shared__ int s_scan[kBlock / 64];
-  __shared__ unsigned long long s_slot;  // the chunk's first photon (or pair) slot
   __shared__ int s_red[2][8];
   __shared__ __int128 s_e[4];
   __shared__ unsigned long long s_abs[6];
@@ -524,6 +478,7 @@ __global__ __launch_bounds__(kBlock, kSpread ? PushCfg<T>::spread_waves : PushCf
   const int tid = threadIdx.x;
   const int lane = lane_id();
   __int128 ke_t = 0;  // this thread's kinetic energy terms (diagnosed steps)
+  uint32_t my_emitters = 0;  // emitters listed by this workgroup (thread 0)
 
   // constants of the current gap
   int g = -1;
@@ -537,7 +492,7 @@ __global__ __launch_bounds__(kBlock, kSpread ? PushCfg<T>::spread_waves : PushCf
   I ONE = 0;
   T scale = 0, inv_scale = 0, dt_t = 0, dtdx = 0, gthr = 0, gpair = 0, thr_lo = 0;
   double sigma = 0.0, gthr64 = 0.0;
-  int Kb = 0;  // offset grid bits (the spline's weights, the emitters' positions)
+  int Kb = 0;  // offset grid bits (the spline's weights)
   uint64_t kseed = 0;
   gptr<uint64_t> idS[2] = {nullptr, nullptr};
   GapDev* __restrict__ G = gaps;
@@ -577,7 +532,7 @@ __global__ __launch_bounds__(kBlock, kSpread ? PushCfg<T>::spread_waves : PushCf
       dtdx = (T)G->dtdx;
       gthr = (T)G->gthr;
       gpair = (T)G->gpair;
-      Kb = G->K;
+      if constexpr (kSpline) Kb = G->K;
       if constexpr (kSpread) {
         sigma = G->sigma;
         gthr64 = G->gthr64;
@@ -587,6 +542,7 @@ __global__ __launch_bounds__(kBlock, kSpread ? PushCfg<T>::spread_waves : PushCf
       have = false;
     }
     if (!gap_ok) continue;
+    int listed = 0;  // emitters of this chunk
     int s;
     long long i0, i1;
     push_item(w - gbeg, chunks0, n0, n1, s, i0, i1);
@@ -839,10 +795,6 @@ __global__ __launch_bounds__(kBlock, kSpread ? PushCfg<T>::spread_waves : PushCf
             pn = pn > (T)0 ? mag : -mag;
             const int pos = atomicAdd(&s_emit_n, 1);
             s_emit[pos] = ((uint32_t)(i - i0) << 8) | (uint32_t)k;
-            // its photons (or pairs) start at its position after the move,
-            // along the stored momentum's sign
-            const long long X0 = ((long long)c2 << Kb) + (long long)nq;
-            s_emx[pos] = (X0 << 1) | (signbit(pn) ? 0ll : 1ll);
           }
           __builtin_nontemporal_store(pn, &pA[i]);
           __builtin_nontemporal_store((T)nq * inv_scale, &offA[i]);
@@ -882,10 +834,18 @@ __global__ __launch_bounds__(kBlock, kSpread ? PushCfg<T>::spread_waves : PushCf
           }
         }
       }
-      // ---- the photons (or in-place pairs) of this chunk's emitters
-      const int ne = s_emit_n;
-      if (ne > 0) emit_chunk<T>(G, s, i0, ne, s_emit, s_emx, s_emid, s_scan, &s_slot);
+      // ---- emitters of this chunk, in the chunk's own slice of the list
+      const int ne = __builtin_amdgcn_readfirstlane(s_emit_n);
+      if (ne > 0) {
+        listed = ne;
+        gptr<uint32_t> el = glb(G->emit_ent + w * (long long)kChunk);
+        for (int k = tid; k < ne; k += kBlock) el[k] = s_emit[k];
+      }
       __syncthreads();
+    }
+    if (tid == 0) {
+      glb(G->emit_cnt)[w] = listed;
+      my_emitters += (uint32_t)listed;
     }
     if constexpr (PushCfg<T>::prefetch) {
 #pragma unroll
@@ -894,6 +854,147 @@ __global__ __launch_bounds__(kBlock, kSpread ? PushCfg<T>::spread_waves : PushCf
     have = pre;
   }
   if (g >= 0) flush_tally(stripes, g, ke_t, diag, s_e, s_abs);
+  // emitters of this workgroup's chunk range, indexed in chunk order (every
+  // descriptor holds the batch's array)
+  if (tid == 0) glb(gaps->wg_emit)[xcd_logical((int)blockIdx.x, (int)gridDim.x)] = my_emitters;
+}
+
+// ------------------------------------------------------- emission role
+// Walks the emitters with flattened indices [qa, qb) (chunk order, then list
+// order within a chunk) among chunks [x, xend) of gap E.G, whose first
+// emitter has flattened index Q, and emits their photons (or in-place
+// pairs).  Windows of kBlock chunks are scanned for their emitter counts;
+// each round hands one emitter to each thread, a block scan of the emitters'
+// photon counts gives each its place, and the round's slots are reserved
+// with one atomic.  On return x and Q point past the last window walked.
+template <typename T>
+__device__ __forceinline__ void emit_walk(const EmitGap<T>& E, long long& x, long long xend,
+                                          unsigned long long& Q, unsigned long long qa,
+                                          unsigned long long qb, long long wg0, unsigned& esc,
+                                          gptr<const uint32_t> cntA, gptr<const uint32_t> entA,
+                                          int* s_nb, int* s_tmp, unsigned long long* s_base) {
+  // electron chunks come first in the gap's items
+  const long long chunks0 = ((long long)E.n0 + kChunk - 1) / kChunk;
+  while (x < xend && Q < qb) {
+    const long long xc0 = x + threadIdx.x;
+    const int ne = xc0 < xend ? (int)cntA[xc0] : 0;
+    int nwin;
+    const int nb = block_excl_scan(ne, s_tmp, nwin);
+    s_nb[threadIdx.x] = nb;
+    __syncthreads();
+    const unsigned long long lo = qa > Q ? qa : Q;
+    const unsigned long long hi = qb < Q + (unsigned long long)nwin ? qb : Q + (unsigned long long)nwin;
+    for (unsigned long long r = lo; r < hi; r += kBlock) {
+      const unsigned long long q = r + threadIdx.x;
+      int k = 0, s = 0;
+      long long i = 0;
+      if (q < hi) {
+        const int ql = (int)(q - Q);
+        // the chunk holding emitter ql of the window: last t with s_nb[t] <= ql
+        int a = 0, b = kBlock - 1;
+        while (a < b) {
+          const int mid = (a + b + 1) >> 1;
+          if (s_nb[mid] <= ql) a = mid; else b = mid - 1;
+        }
+        const long long xc = x + a;
+        const uint32_t en = entA[xc * kChunk + (ql - s_nb[a])];
+        k = (int)(en & 255u);
+        const long long local = xc - wg0;
+        s = local < chunks0 ? 0 : 1;
+        i = (s == 0 ? local : local - chunks0) * kChunk + (long long)(en >> 8);
+      }
+      int kt;
+      const int ex = block_excl_scan(k, s_tmp, kt);  // ends with a barrier
+      if (kt == 0) continue;                          // uniform
+      if (threadIdx.x == 0) {
+        if (E.in_place) {
+          s_base[0] = reserve_pairs(E.G, (unsigned long long)kt);
+        } else {
+          const unsigned long long b0 = atomicAdd(&E.G->n_ph_next, (unsigned long long)kt);
+          if (b0 + (unsigned long long)kt > E.ph_cap) E.G->overflow = 1;
+          s_base[0] = b0;
+        }
+      }
+      __syncthreads();
+      const unsigned long long base = s_base[0];
+      if (k > 0) esc += emit_listed<T>(E, s, i, k, base + (unsigned long long)ex);
+      __syncthreads();  // s_base is rewritten by the next round
+    }
+    x = x + kBlock < xend ? x + kBlock : xend;
+    Q += (unsigned long long)nwin;
+    __syncthreads();  // s_nb is rewritten by the next window
+  }
+}
+
+// Emission is balanced by emitters, not by chunks: the push left the number
+// of emitters of each of its workgroups (in chunk order), so every
+// workgroup here scans those counts, takes an equal share of the flattened
+// emitter list, and walks it gap by gap in one pass.
+template <typename T>
+__device__ void emit_role(GapDev* __restrict__ gaps, const long long* __restrict__ wi, int B,
+                          const int32_t* __restrict__ emit_cnt,
+                          const uint32_t* __restrict__ emit_ent,
+                          const uint32_t* __restrict__ wg_emit, int vb, int nvb,
+                          uint32_t* s_pre, unsigned long long* s_base, int* s_nb, int* s_tmp) {
+  constexpr int kPer = kPushGrid / kBlock;
+  const long long total = wi[B];
+  if (total == 0) return;
+  // exclusive prefix of the push workgroups' emitter counts
+  uint32_t v[kPer];
+  uint32_t loc = 0;
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    v[j] = glb<const uint32_t>((void*)wg_emit)[threadIdx.x * kPer + j];
+    loc += v[j];
+  }
+  // block scan of the per-thread sums (a batch holds fewer than 2^32 lepton slots)
+  const uint32_t incl = wave_incl_scan(loc);
+  __syncthreads();
+  if (lane_id() == 63) s_tmp[threadIdx.x >> 6] = (int)incl;
+  __syncthreads();
+  uint32_t off = 0, Etot = 0;
+#pragma unroll
+  for (int k = 0; k < kBlock / 64; ++k) {
+    const uint32_t t = (uint32_t)s_tmp[k];
+    if (k < (int)(threadIdx.x >> 6)) off += t;
+    Etot += t;
+  }
+  off += incl - loc;
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    s_pre[threadIdx.x * kPer + j] = off;
+    off += v[j];
+  }
+  __syncthreads();
+  if (Etot == 0) return;
+  const unsigned long long share = ((unsigned long long)Etot + nvb - 1) / nvb;
+  const unsigned long long q0 = (unsigned long long)vb * share;
+  if (q0 >= Etot) return;
+  const unsigned long long q1 = q0 + share < Etot ? q0 + share : Etot;
+  // the push workgroup holding emitter q0: last lb with s_pre[lb] <= q0
+  int a = 0, b = kPushGrid - 1;
+  while (a < b) {
+    const int mid = (a + b + 1) >> 1;
+    if (s_pre[mid] <= q0) a = mid; else b = mid - 1;
+  }
+  long long x, xa_end;
+  share_range(total, a, kPushGrid, x, xa_end);
+  unsigned long long Q = s_pre[a];
+  gptr<const uint32_t> cntA = glb<const uint32_t>((void*)emit_cnt);
+  gptr<const uint32_t> entA = glb<const uint32_t>((void*)emit_ent);
+  while (x < total && Q < q1) {
+    const int g = find_gap(wi, B, x);
+    GapDev* __restrict__ G = gaps + g;
+    const long long xend = wi[g + 1];
+    const long long wg0 = wi[g];
+    const EmitGap<T> E = emit_gap<T>(G);
+    unsigned esc = 0;
+    emit_walk<T>(E, x, xend, Q, q0, q1, wg0, esc, cntA, entA, s_nb, s_tmp, s_base);
+    if (E.absorbing && !E.in_place) {
+      const unsigned long long esc_w = wave_sum((unsigned long long)esc);
+      if (lane_id() == 0 && esc_w > 0) atomicAdd(&G->esc_next, esc_w);
+    }
+  }
 }
 
 // ----------------------------------------------------------------- field
@@ -1443,24 +1544,35 @@ __device__ void fold_role(GapDev* __restrict__ gaps, int B, unsigned long long* 
   }
 }
 
-// Everything of a step between the push (which also emits) and the
-// finalize: the Ampere update (blocks [0, n_field)), the conversions (next
-// n_conv blocks) and the fold of the push tallies (the rest) are independent
-// of each other.
+// Everything of a step between the push and the finalize: the Ampere
+// update (blocks [0, n_field)), the emission of the listed chunks (next
+// n_emit blocks), the conversions (next n_conv blocks) and the fold of the
+// push tallies (the rest) are independent of each other.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_post(GapDev* __restrict__ gaps,
                                                  const long long* __restrict__ cwi,
+                                                 const long long* __restrict__ wi,
                                                  const long long* __restrict__ pwi, int B,
-                                                 int n_field, int n_conv,
+                                                 int n_field, int n_emit, int n_conv,
+                                                 const int32_t* __restrict__ emit_cnt,
+                                                 const uint32_t* __restrict__ emit_ent,
+                                                 const uint32_t* __restrict__ wg_emit,
                                                  unsigned long long* __restrict__ stripes) {
   __shared__ double s_red[8];
-  // the conversion role's lists of due photons, one per wave
-  __shared__ uint32_t s_buf[kConvGroup * kPhChunk];
+  __shared__ unsigned long long s_base[1];
+  __shared__ int s_nb[kBlock];
+  __shared__ int s_tmp[kBlock / 64];
+  // the emission role's prefix of the push workgroups' emitters, or the
+  // conversion role's lists of due photons, one per wave (a block takes one role)
+  __shared__ uint32_t s_buf[kPushGrid > kConvGroup * kPhChunk ? kPushGrid : kConvGroup * kPhChunk];
   const int b = blockIdx.x;
   if (b < n_field) field_role(gaps, cwi, B, b, s_red);
-  else if (b < n_field + n_conv)
-    convert_role<T>(gaps, pwi, B, b - n_field, n_conv, s_buf);
-  else fold_role(gaps, B, stripes, b - n_field - n_conv);
+  else if (b < n_field + n_emit)
+    emit_role<T>(gaps, wi, B, emit_cnt, emit_ent, wg_emit, b - n_field, n_emit, s_buf, s_base, s_nb,
+                 s_tmp);
+  else if (b < n_field + n_emit + n_conv)
+    convert_role<T>(gaps, pwi, B, b - n_field - n_emit, n_conv, s_buf);
+  else fold_role(gaps, B, stripes, b - n_field - n_emit - n_conv);
 }
 
 __global__ __launch_bounds__(1024) void k_finalize(GapDev* __restrict__ gaps, int B,
@@ -2086,13 +2198,15 @@ hipError_t launch_push(const StepLaunch& L, bool mixed, hipEvent_t start, hipEve
 hipError_t launch_step_after_push(const StepLaunch& L, bool mixed) {
   const int nf = grid_for(L.cell_items, 1 << 30);
   const int nfold = (4 * L.B * kStripes + kBlock - 1) / kBlock;
-  const int grid = nf + L.conv_grid + nfold;
+  const int grid = nf + L.emit_grid + L.conv_grid + nfold;
   if (mixed)
-    hipLaunchKernelGGL(k_post<float>, dim3(grid), dim3(kBlock), 0, L.stream, L.gaps, L.cwi, L.pwi,
-                       L.B, nf, L.conv_grid, L.stripes);
+    hipLaunchKernelGGL(k_post<float>, dim3(grid), dim3(kBlock), 0, L.stream, L.gaps, L.cwi, L.wi,
+                       L.pwi, L.B, nf, L.emit_grid, L.conv_grid, L.emit_cnt, L.emit_ent, L.wg_emit,
+                       L.stripes);
   else
-    hipLaunchKernelGGL(k_post<double>, dim3(grid), dim3(kBlock), 0, L.stream, L.gaps, L.cwi, L.pwi,
-                       L.B, nf, L.conv_grid, L.stripes);
+    hipLaunchKernelGGL(k_post<double>, dim3(grid), dim3(kBlock), 0, L.stream, L.gaps, L.cwi, L.wi,
+                       L.pwi, L.B, nf, L.emit_grid, L.conv_grid, L.emit_cnt, L.emit_ent, L.wg_emit,
+                       L.stripes);
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, L.stream, L.gaps, L.B, L.wi, L.pwi, L.qwi);
   return hipGetLastError();
 }

@@ -16,7 +16,10 @@ struct StepLaunch {
   long long* cwi;      // cell work-item prefix, B + 1 entries (device, static)
   long long cell_items;
   int B;
-  int push_grid, conv_grid, ph_sort_grid;
+  int push_grid, conv_grid, emit_grid, ph_sort_grid;
+  int32_t* emit_cnt;   // emitters per chunk of the current plan (device)
+  uint32_t* emit_ent;  // kChunk entries per chunk (device)
+  uint32_t* wg_emit;   // emitters listed by each push workgroup, kPushGrid entries (device)
   unsigned long long* stripes;  // striped push tallies, B x 4 x kStripes x kStripeStride (device)
   hipStream_t stream;
   bool spread;         // some gap draws per-lepton thresholds (gamma_thr_spread > 0)

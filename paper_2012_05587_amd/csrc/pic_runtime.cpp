@@ -42,8 +42,8 @@ struct GapLayout {
 };
 
 struct Layout {
-  size_t gaps, wi, pwi, qwi, twi, cwi, stripes, total;
-  long long max_ph_chunks;
+  size_t gaps, wi, pwi, qwi, twi, cwi, emit_cnt, emit_ent, wg_emit, stripes, total;
+  long long max_chunks, max_ph_chunks;
   std::vector<GapLayout> g;
   long long cell_items;
 };
@@ -153,9 +153,16 @@ Layout make_layout(const pic_gap_params* prm, int B) {
   L.twi = o; o = align_up(o + sizeof(long long) * (size_t)(B + 1));
   L.cwi = o; o = align_up(o + sizeof(long long) * (size_t)(B + 1));
   L.cell_items = 0;
+  // one emission slice per particle chunk the plan can hold
+  L.max_chunks = 0;
   L.max_ph_chunks = 0;
-  for (int i = 0; i < B; ++i)
+  for (int i = 0; i < B; ++i) {
+    L.max_chunks += 2 * ((slots_of(prm[i]) + pic::kChunk - 1) / pic::kChunk);
     L.max_ph_chunks += (prm[i].photon_capacity + pic::kPhChunk - 1) / pic::kPhChunk;
+  }
+  L.emit_cnt = o; o = align_up(o + sizeof(int32_t) * (size_t)L.max_chunks);
+  L.emit_ent = o; o = align_up(o + sizeof(uint32_t) * (size_t)L.max_chunks * pic::kChunk);
+  L.wg_emit = o; o = align_up(o + sizeof(uint32_t) * (size_t)pic::kPushGrid);
   L.stripes = o; o = align_up(o + sizeof(unsigned long long) * (size_t)B * 4 * pic::kStripes * pic::kStripeStride);
   const int prec = prm[0].precision;
   const size_t tb = prec == PIC_MIXED ? 4 : 8;
@@ -366,6 +373,9 @@ pic_status create_batch(const pic_gap_params* params, int n_gaps, void* d_ws, si
     G.photon_step = (int64_t)std::rint(std::ldexp(p.dt / p.dx, G.K));
     G.cap = p.capacity;
     G.slots = slots_of(p);
+    G.emit_cnt = reinterpret_cast<int32_t*>(ws + L.emit_cnt);
+    G.emit_ent = reinterpret_cast<uint32_t*>(ws + L.emit_ent);
+    G.wg_emit = reinterpret_cast<uint32_t*>(ws + L.wg_emit);
     G.ph_cap = p.photon_capacity;
     G.dt = p.dt;
     G.dx = p.dx;
@@ -432,12 +442,16 @@ pic_status create_batch(const pic_gap_params* params, int n_gaps, void* d_ws, si
   b->launch.cwi = reinterpret_cast<long long*>(ws + L.cwi);
   b->launch.cell_items = L.cell_items;
   b->launch.B = n_gaps;
-  // Conversion and the photon re-sort get grids sized to what the batch can
-  // hold (about 16 chunks per workgroup when full), in whole multiples of
-  // the 8 XCDs.
+  // Emission, conversion and the photon re-sort get grids sized to what the
+  // batch can hold (about 16 chunks per workgroup when full), in whole
+  // multiples of the 8 XCDs.
   b->launch.push_grid = pic::kPushGrid;
+  b->launch.emit_grid = grid_for_items(L.max_chunks / 16);
   b->launch.conv_grid = grid_for_items(L.max_ph_chunks / 16);
   b->launch.ph_sort_grid = grid_for_items(L.max_ph_chunks / 16);
+  b->launch.emit_cnt = reinterpret_cast<int32_t*>(ws + L.emit_cnt);
+  b->launch.emit_ent = reinterpret_cast<uint32_t*>(ws + L.emit_ent);
+  b->launch.wg_emit = reinterpret_cast<uint32_t*>(ws + L.wg_emit);
   b->launch.stripes = reinterpret_cast<unsigned long long*>(ws + L.stripes);
   b->launch.stream = b->stream;
   b->launch.spline = params[0].shape == PIC_SHAPE_QUADRATIC;

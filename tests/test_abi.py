@@ -133,12 +133,11 @@ def test_workspace_grows_with_capacity_and_precision():
     b = P.pic_workspace_bytes(pc.gpu_params(c, capacity=2 * c["capacity"]))
     m = P.pic_workspace_bytes(pc.gpu_params(c, precision=workloads.MIXED))
     assert 0 < a < b and m < a
-    # per-slot bytes: 2 buffers x 2 species x (4 + 8 + 8 + 8) in binary64 (the
-    # emitters of a chunk are listed in the push's LDS, not in the workspace);
-    # capacity + capacity/8 + 2048 slots
+    # per-slot bytes: 2 buffers x 2 species x (4 + 8 + 8 + 8) in binary64, plus a
+    # 4-byte emission-list entry per species; capacity + capacity/8 + 2048 slots
     slots = lambda cap: cap + cap // 8 + 2048  # noqa: E731
     extra = slots(2 * c["capacity"]) - slots(c["capacity"])
-    assert abs((b - a) - (2 * 2 * 28) * extra) <= 16 * 1024
+    assert abs((b - a) - (2 * 2 * 28 + 8) * extra) <= 16 * 1024
 
 
 def test_batch_plan_admits_under_budget():
