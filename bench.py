@@ -33,23 +33,23 @@ import workloads  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_PUSH = {workloads.FP64: 40, workloads.MIXED: 24}
-# The push kernel also emits: a stored photon writes x 8 + conversion step 4
-# + child 8 + tail key 1 bytes; an in-place pair writes two leptons (cell 4 +
-# offset + momentum + id 8 each).
+# In steps small enough for it, the push kernel also emits: a stored photon
+# writes x 8 + conversion step 4 + child 8 + tail key 1 bytes; an in-place
+# pair writes two leptons (cell 4 + offset + momentum + id 8 each).
 BYTES_PER_PHOTON = 21
 BYTES_PER_CHILD = {workloads.FP64: 28, workloads.MIXED: 20}
 
 
 def push_alg_bytes(views, gaps, precision):
     """Algorithmic bytes the push kernel moved over a run of these gaps:
-    24 (40) B per push, plus each emission's writes (the emitters' id reads
-    are not counted)."""
+    24 (40) B per push, plus the writes of the emissions it drew itself (in
+    steps small enough for it to emit; the emitters' id reads are not
+    counted)."""
     total = 0
     for v, c in zip(views, gaps):
         m = v.read_moments()
-        emitted = int(m.last.photons_emitted)
         per = BYTES_PER_PHOTON if c["l_gamma"] > 0 else 2 * BYTES_PER_CHILD[precision]
-        total += BYTES_PER_PUSH[precision] * int(m.pushes) + per * emitted
+        total += BYTES_PER_PUSH[precision] * int(m.pushes) + per * int(m.push_emissions)
     return total
 DTYPE = {workloads.FP64: "f64", workloads.MIXED: "f32/f64"}
 METRIC = "particle-pushes/sec + % HBM roofline, mixed-batched vs plain FP64, 1 MI355X"
@@ -222,7 +222,7 @@ def run_gpu(gaps, steps, warmup=0, reps=5, profile=True, dump=None):
         again = sum(int(x.read_moments().pushes) for x in views)
         out.update(push_ms=push_ms, push_launches=launches, evented_pushes=again,
                    evented_bytes=push_alg_bytes(views, gaps, gaps[0]["precision"]),
-                   evented_photons=sum(int(x.read_moments().last.photons_emitted) for x in views),
+                   evented_photons=sum(int(x.read_moments().push_emissions) for x in views),
                    evented_tuning=g.tuning())
         g.close()
         del g, views
@@ -679,7 +679,7 @@ def main():
                      "traffic_unit": "B/launch",
                      "alg_bytes_per_launch": main_run["evented_bytes"] / max(main_run["push_launches"], 1),
                      "evented_run": {"pushes": main_run["evented_pushes"],
-                                     "photons_emitted": main_run["evented_photons"],
+                                     "push_emissions": main_run["evented_photons"],
                                      "sort_every": main_run["evented_tuning"]["sort_every"],
                                      "switches": main_run["evented_tuning"]["switches"]},
                      "copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs,

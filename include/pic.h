@@ -189,6 +189,9 @@ typedef struct {
   int64_t slots_minus, slots_plus, photon_slots; /* occupied slots (live + not yet reclaimed) */
   int64_t pushes;           /* cumulative leptons pushed */
   pic_history_row last;     /* the last history row written (zero before any step) */
+  int64_t push_emissions;   /* cumulative photons (or in-place pairs) drawn by the push kernel
+                               itself, in steps whose plan is small enough for it; the rest
+                               are drawn by a later kernel of the step */
 } pic_moments;
 
 typedef struct pic_gap pic_gap;
@@ -375,6 +378,18 @@ pic_status pic_batch_prepare(pic_batch* b);
 pic_status pic_batch_tuning(pic_batch* b, int32_t* sort_every, int32_t* autotuned,
                             int64_t* replays, int32_t* switches);
 /* The same for a single gap. */
+/* Where a step's emissions are drawn (section 2's emission: the photons, or
+ * the pairs made in place, of the leptons that reached the threshold).  Not
+ * part of the method: both kernels draw the same photons; only the cost
+ * differs.  A step whose plan holds fewer than max_push_chunks lepton chunks
+ * (1024 leptons of one species of one gap each) draws them inside the push
+ * kernel, after each chunk; a larger step lists the emitters and a later
+ * kernel of the step draws them, balanced by emitters.  Default 32768; 0
+ * sends every step to the later kernel.  Applies to the whole batch from
+ * the next step on.  Errors: PIC_ERR_ARG (null, max_push_chunks < 0),
+ * PIC_ERR_DEVICE. */
+pic_status pic_batch_emission_split(pic_batch* b, int64_t max_push_chunks);
+pic_status pic_emission_split(pic_gap* g, int64_t max_push_chunks);
 pic_status pic_tuning(pic_gap* g, int32_t* sort_every, int32_t* autotuned, int64_t* replays,
                       int32_t* switches);
 

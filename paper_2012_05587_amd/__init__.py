@@ -34,7 +34,7 @@ EXPORTS = [
     "pic_batch_size", "pic_destroy_batch", "pic_profile_push", "pic_read_push_time",
     "pic_batch_profile_push", "pic_batch_read_push_time", "pic_batch_tuning", "pic_tuning",
     "pic_phase_space", "pic_event_map", "pic_prepare", "pic_batch_prepare",
-    "pic_read_fields_noalloc",
+    "pic_read_fields_noalloc", "pic_emission_split", "pic_batch_emission_split",
 ]
 
 
@@ -77,7 +77,7 @@ class Moments(C.Structure):
         ("steps_done", C.c_int64), ("status", C.c_int32), ("n_minus", C.c_int64),
         ("n_plus", C.c_int64), ("n_photons", C.c_int64), ("slots_minus", C.c_int64),
         ("slots_plus", C.c_int64), ("photon_slots", C.c_int64), ("pushes", C.c_int64),
-        ("last", HistoryRow),
+        ("last", HistoryRow), ("push_emissions", C.c_int64),
     ]
 
 
@@ -137,6 +137,8 @@ def lib():
     L.pic_event_map.argtypes = [vp, vp, i32, i32, i32]; L.pic_event_map.restype = i32
     for name in ("pic_tuning", "pic_batch_tuning"):
         getattr(L, name).argtypes = [vp, P(i32), P(i32), P(i64), P(i32)]; getattr(L, name).restype = i32
+    for name in ("pic_emission_split", "pic_batch_emission_split"):
+        getattr(L, name).argtypes = [vp, i64]; getattr(L, name).restype = i32
     _lib = L
     return L
 
@@ -345,6 +347,10 @@ class Gap(_GapView):
     def tuning(self):
         return _tuning("pic_tuning", self._h)
 
+    def emission_split(self, max_push_chunks):
+        """Steps whose plan holds fewer lepton chunks draw their emissions in the push."""
+        _check("pic_emission_split", lib().pic_emission_split(self._h, int(max_push_chunks)))
+
     def close(self):
         """Frees the handle and drops this object's reference to the workspace."""
         if self._h:
@@ -399,6 +405,10 @@ class Batch:
 
     def tuning(self):
         return _tuning("pic_batch_tuning", self._h)
+
+    def emission_split(self, max_push_chunks):
+        """Steps whose plan holds fewer lepton chunks draw their emissions in the push."""
+        _check("pic_batch_emission_split", lib().pic_batch_emission_split(self._h, int(max_push_chunks)))
 
     def close(self):
         """Frees the handle and drops this object's reference to the workspace;

@@ -25,7 +25,7 @@
 #define PIC_PUSH_D_EGROUP 4
 #endif
 #ifndef PIC_PUSH_D_WAVES
-#define PIC_PUSH_D_WAVES 1
+#define PIC_PUSH_D_WAVES 3
 #endif
 
 namespace pic {
@@ -76,13 +76,16 @@ struct PushCfg<float> {
   // spill store writes only the active lanes and the others later reloaded
   // stale values, so they get 168 VGPRs (3 waves per SIMD) and spill nothing
   static constexpr int spread_waves = 3;
+  static constexpr int spline_waves = PIC_PUSH_F_WAVES;
 };
 template <>
 struct PushCfg<double> {
   static constexpr bool prefetch = PIC_PUSH_D_PREFETCH;
   static constexpr int e_group = PIC_PUSH_D_EGROUP;
   static constexpr int waves = PIC_PUSH_D_WAVES;
-  static constexpr int spread_waves = PIC_PUSH_D_WAVES;
+  // the binary64 spline and spread instantiations take the registers they need
+  static constexpr int spread_waves = 1;
+  static constexpr int spline_waves = 1;
 };
 constexpr int kStripes = 32;          // striped per-gap accumulators of the push kernel
 constexpr int kStripeStride = 16;     // doubles between stripes (one 128-byte line each)
@@ -128,6 +131,7 @@ struct GapDev {
   int32_t* emit_cnt;          // the batch's emitters per chunk (same in every gap)
   uint32_t* emit_ent;         // the batch's emitter lists, kChunk entries per chunk
   uint32_t* wg_emit;          // the batch's emitters per push workgroup
+  long long emit_split;       // steps whose plan holds fewer lepton chunks emit in the push
   int32_t ev_x, ev_steps, ev_rows, pad5;
 
   // ---- counters (device-updated)
@@ -140,6 +144,7 @@ struct GapDev {
   unsigned long long n_ph, n_ph_next, inflight;  // photon slots at step start, append cursor
   unsigned long long pairs_created, photons_emitted, photons_escaped, absorbed[2];
   unsigned long long pushes;
+  unsigned long long push_emitted;  // emissions drawn inside the push kernel (cumulative)
   unsigned long long hist_count;
   // order-independent sums of the step, cleared by the finalize: the sum of
   // the Lorentz factors of the leptons pushed this step and of those

@@ -158,10 +158,16 @@ __device__ __forceinline__ int block_excl_scan(int x, int* s_tmp, int& total) {
 }
 
 // ------------------------------------------------------------------ emit
-// The push lists each chunk's emitters (chunk-local index << 8 | k) in the
-// chunk's slice of emit_ent, with their count in emit_cnt and each push
-// workgroup's total in wg_emit; the emission role of k_post draws their
-// photons (or in-place pairs).
+// Where a step's emission runs depends on its size.  A step whose plan holds
+// fewer than kEmitInPushChunks lepton chunks emits inside the push, right
+// after each chunk (emit_chunk): there the emission role's own chain of
+// dependent loads would dominate the step.  A larger step lists each
+// chunk's emitters (chunk-local index << 8 | k) in the chunk's slice of
+// emit_ent, with their count in emit_cnt and each push workgroup's total in
+// wg_emit, and the emission role of k_post draws them, balanced by emitters
+// across its workgroups: there a per-chunk emission phase would put its
+// round trips into the push's streaming loop for every one of ~1e5 chunks.
+// The split (emit_split, the same in every descriptor) is set by the host.
 
 // What the emission of one gap needs, read from its descriptor once per gap
 // segment of a wave.
@@ -284,6 +290,178 @@ __device__ __forceinline__ unsigned emit_listed(const EmitGap<T>& E, int s, long
     }
   }
   return esc;
+}
+
+// ------------------------------------------------------- emission in the push
+// Emission of one pushed chunk of species s (section 2: a lepton that reaches
+// gamma_thr emits; with a finite photon path the photon is stored and converts
+// later, else the pair is made in place).  The push lists the chunk's ne
+// emitters in LDS: entry (chunk-local index << 8 | k, the k emissions of this
+// step) and the position after the move on the 2^-K grid (<< 1 | forward).
+// Each thread takes four consecutive entries and requests their ids; a block
+// scan of their photon counts gives each emitter its first photon (kept in
+// its entry's place), and one global atomic reserves the chunk's slots.  The
+// chunk's photons are then spread evenly over the threads; a binary search
+// over the prefixes finds each photon's emitter.  Emission j of an emitter
+// at step n is its tag-2 draw (draw_run): the child electron id is the
+// 64-bit value with bit 0 cleared (the positron's has it set), and the
+// photon's path in steps, n_conv = min{k >= 1 : u >= T_k} for u the 32-bit
+// value, comes from the gap's conversion table.  The gap's emission
+// constants are read here, where they are used, not held in registers
+// through the push.
+template <typename T, int kPhBatch>
+__device__ __forceinline__ void emit_chunk(GapDev* __restrict__ G, int s, long long i0, int ne,
+                                           uint32_t* s_emit, const long long* s_emx,
+                                           uint64_t* s_emid, int* s_scan,
+                                           unsigned long long* s_slot) {
+  const int tid = threadIdx.x;
+  const int buf = G->buf;
+  const bool in_place = G->table_len == 0;
+  int kt;
+  {
+    // thread t owns the entries 4t .. 4t + 3 (list order): their ids, and a
+    // block scan of their photon counts gives each its first photon; the
+    // entry's slot in s_emit then holds that prefix
+    gptr<const uint64_t> idA = glb<const uint64_t>((void*)G->id[buf][s]);
+    uint32_t e[4];
+    uint64_t idv[4];
+    int mine = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int q = 4 * tid + j;
+      e[j] = q < ne ? s_emit[q] : 0u;
+      idv[j] = q < ne ? idA[i0 + (long long)(e[j] >> 8)] : 0ull;
+      mine += (int)(e[j] & 255u);
+    }
+    int ex = block_excl_scan(mine, s_scan, kt);  // ends with a barrier
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int q = 4 * tid + j;
+      if (q < ne) {
+        s_emit[q] = (uint32_t)ex;
+        s_emid[q] = idv[j];
+      }
+      ex += (int)(e[j] & 255u);
+    }
+    if (tid == 0) {
+      if (in_place) {
+        *s_slot = reserve_pairs(G, (unsigned long long)kt);
+      } else {
+        const unsigned long long b0 = atomicAdd(&G->n_ph_next, (unsigned long long)kt);
+        if (b0 + (unsigned long long)kt > (unsigned long long)G->ph_cap) G->overflow = 1;
+        *s_slot = b0;
+      }
+    }
+  }
+  __syncthreads();
+  const unsigned long long base = *s_slot;
+  const uint32_t step = (uint32_t)G->step;
+  const uint64_t seed = G->seed;
+  const int K = G->K;
+  // the emitter of the chunk's photon p: the last entry whose first photon is at most p
+  auto emitter_of = [&](int p) {
+    int lo = 0, hi = ne - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if ((int)s_emit[mid] <= p) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+  };
+  if (in_place) {
+    // pairs made in place (the paper's zero mean free path), both children
+    // at the emitter's position moving along its direction
+    const unsigned long long n0 = G->n[0], n1 = G->n[1], slots = (unsigned long long)G->slots;
+    const long long mask = G->one - 1;
+    const T inv_scale = (T)(1.0 / (double)G->one), pchild = (T)G->pchild;
+    const bool evmap = G->evmap != nullptr;
+    gptr<int32_t> c0 = glb(G->cell[buf][0]), c1 = glb(G->cell[buf][1]);
+    gptr<T> o0 = glb<T>(G->off[buf][0]), o1 = glb<T>(G->off[buf][1]);
+    gptr<T> p0 = glb<T>(G->p[buf][0]), p1 = glb<T>(G->p[buf][1]);
+    gptr<uint64_t> d0 = glb(G->id[buf][0]), d1 = glb(G->id[buf][1]);
+#pragma unroll 1
+    for (int p = tid; p < kt; p += kBlock) {
+      const int q = emitter_of(p);
+      const int jj = p - (int)s_emit[q];
+      const long long xe = s_emx[q];
+      const long long X0 = xe >> 1;
+      const int c = (int)(X0 >> K);
+      const T offn = (T)(X0 & mask) * inv_scale;
+      const T pc = (xe & 1) ? pchild : -pchild;
+      const RunDraw u = draw_run(s_emid[q], seed, step, (uint32_t)jj, (uint32_t)kTagPhoton);
+      const uint64_t child = u.bits & ~(uint64_t)1;
+      const unsigned long long se = n0 + base + p, sp = n1 + base + p;
+      if (se < slots) { c0[se] = c; o0[se] = offn; p0[se] = pc; d0[se] = child; }
+      if (sp < slots) { c1[sp] = c; o1[sp] = offn; p1[sp] = pc; d1[sp] = child | 1u; }
+      if (evmap) count_pairs(G, (long long)step, c, 1ull);
+    }
+    return;
+  }
+  const int pb = G->phbuf;
+  gptr<long long> phx = glb(G->ph_x[pb]);
+  gptr<int32_t> phs = glb(G->ph_step[pb]);
+  gptr<uint64_t> phc = glb(G->ph_child[pb]);
+  gptr<uint8_t> phk = glb(G->ph_key);
+  const uint32_t* table = G->table;
+  gptr<const uint32_t> tab = glb<const uint32_t>((void*)G->table);
+  const int len = G->table_len;
+  const float inv_lnq = G->inv_lnq;
+  const long long domain = G->domain, photon_step = G->photon_step, ph_base = G->ph_base;
+  const unsigned long long ph_cap = (unsigned long long)G->ph_cap;
+  const bool absorbing = G->boundary == PIC_BC_ABSORBING;
+  unsigned esc = 0;
+  // kPhBatch photons per iteration, so that their table entries are requested
+  // together (the spline's push has registers for one)
+#pragma unroll 1
+  for (int p = tid; p < kt; p += kPhBatch * kBlock) {
+    uint32_t uu[kPhBatch], tm[kPhBatch], t0[kPhBatch], tp[kPhBatch];
+    uint64_t ch[kPhBatch];
+    int kk[kPhBatch], qe[kPhBatch];
+#pragma unroll
+    for (int h = 0; h < kPhBatch; ++h) {
+      const int ph = p + h * kBlock < kt ? p + h * kBlock : p;
+      const int q = emitter_of(ph);
+      qe[h] = q;
+      const RunDraw u = draw_run(s_emid[q], seed, step, (uint32_t)(ph - (int)s_emit[q]),
+                                 (uint32_t)kTagPhoton);
+      ch[h] = u.bits & ~(uint64_t)1;
+      uu[h] = u.u32;
+      kk[h] = conv_estimate(len, uu[h], inv_lnq);
+    }
+#pragma unroll
+    for (int h = 0; h < kPhBatch; ++h) {
+      tm[h] = tab[kk[h] - 1 > 0 ? kk[h] - 1 : 0];
+      t0[h] = tab[kk[h]];
+      tp[h] = tab[kk[h] + 1 < len ? kk[h] + 1 : len - 1];
+    }
+#pragma unroll
+    for (int h = 0; h < kPhBatch; ++h) {
+      const int ph = p + h * kBlock;
+      if (ph >= kt) break;
+      const int ncv = conv_decide(table, len, uu[h], kk[h], tm[h], t0[h], tp[h]);
+      const long long xe = s_emx[qe[h]];
+      const long long dirq = (xe & 1) ? photon_step : -photon_step;
+      long long X = (xe >> 1) + (long long)ncv * dirq;
+      int cstep = (int)((long long)step + ncv);
+      if (absorbing) {
+        if (X < 0 || X >= domain) { cstep = INT32_MIN; ++esc; }
+      } else if (X < 0 || X >= domain) {
+        X = wrap_periodic(X, domain);
+      }
+      const unsigned long long sl = base + (unsigned long long)ph;
+      if (sl < ph_cap) {
+        phx[sl] = X;
+        phs[sl] = cstep;
+        phc[sl] = ch[h] | (uint64_t)(xe & 1);
+        // the tail key: steps from the last sort to the conversion (>= 1)
+        const long long rel = (long long)cstep - ph_base;
+        phk[sl] = (uint8_t)(cstep != INT32_MIN && rel < kFarKey ? rel : kFarKey);
+      }
+    }
+  }
+  if (absorbing) {
+    const unsigned long long esc_w = wave_sum((unsigned long long)esc);
+    if (lane_id() == 0 && esc_w > 0) atomicAdd(&G->esc_next, esc_w);
+  }
 }
 
 // ------------------------------------------------------------------ push
@@ -450,12 +628,17 @@ __device__ __forceinline__ void push_item(long long local, long long chunks0, lo
 // the quadratic-spline shape; batches without them run the
 // kernel without that code.
 template <typename T, bool kSpread, bool kSpline>
-__global__ __launch_bounds__(kBlock, kSpread ? PushCfg<T>::spread_waves : PushCfg<T>::waves) void k_push(GapDev* __restrict__ gaps,
+__global__ __launch_bounds__(kBlock, kSpread ? PushCfg<T>::spread_waves
+                                     : (kSpline ? PushCfg<T>::spline_waves : PushCfg<T>::waves)) void k_push(GapDev* __restrict__ gaps,
                                                  const long long* __restrict__ wi, int B,
                                                  unsigned long long* __restrict__ stripes) {
   using I = typename Fixed<T>::I;
   __shared__ long long s_flux[kTile];
   __shared__ uint32_t s_emit[kChunk];  // chunk-local index << 8 | k
+  __shared__ long long s_emx[kChunk];  // the emitter's position after the move << 1 | forward
+  __shared__ uint64_t s_emid[kChunk];  // the emitter's id (emission in the push)
+  __shared__ int s_scan[kBlock / 64];
+  __shared__ unsigned long long s_slot;  // the chunk's first photon (or pair) slot
   __shared__ int s_red[2][8];
   __shared__ __int128 s_e[4];
   __shared__ unsigned long long s_abs[6];
@@ -476,6 +659,7 @@ __global__ __launch_bounds__(kBlock, kSpread ? PushCfg<T>::spread_waves : PushCf
   long long w0, w1;
   xcd_range(total, w0, w1);
   const int tid = threadIdx.x;
+  const bool in_push = total < gaps->emit_split;  // this step emits in the push
   const int lane = lane_id();
   __int128 ke_t = 0;  // this thread's kinetic energy terms (diagnosed steps)
   uint32_t my_emitters = 0;  // emitters listed by this workgroup (thread 0)
@@ -492,7 +676,7 @@ __global__ __launch_bounds__(kBlock, kSpread ? PushCfg<T>::spread_waves : PushCf
   I ONE = 0;
   T scale = 0, inv_scale = 0, dt_t = 0, dtdx = 0, gthr = 0, gpair = 0, thr_lo = 0;
   double sigma = 0.0, gthr64 = 0.0;
-  int Kb = 0;  // offset grid bits (the spline's weights)
+  int Kb = 0;  // offset grid bits (the spline's weights, the emitters' positions)
   uint64_t kseed = 0;
   gptr<uint64_t> idS[2] = {nullptr, nullptr};
   GapDev* __restrict__ G = gaps;
@@ -532,7 +716,7 @@ __global__ __launch_bounds__(kBlock, kSpread ? PushCfg<T>::spread_waves : PushCf
       dtdx = (T)G->dtdx;
       gthr = (T)G->gthr;
       gpair = (T)G->gpair;
-      if constexpr (kSpline) Kb = G->K;
+      Kb = G->K;
       if constexpr (kSpread) {
         sigma = G->sigma;
         gthr64 = G->gthr64;
@@ -795,6 +979,10 @@ __global__ __launch_bounds__(kBlock, kSpread ? PushCfg<T>::spread_waves : PushCf
             pn = pn > (T)0 ? mag : -mag;
             const int pos = atomicAdd(&s_emit_n, 1);
             s_emit[pos] = ((uint32_t)(i - i0) << 8) | (uint32_t)k;
+            // its photons (or pairs) start at its position after the move,
+            // along the stored momentum's sign
+            const long long X0 = ((long long)c2 << Kb) + (long long)nq;
+            s_emx[pos] = (X0 << 1) | (signbit(pn) ? 0ll : 1ll);
           }
           __builtin_nontemporal_store(pn, &pA[i]);
           __builtin_nontemporal_store((T)nq * inv_scale, &offA[i]);
@@ -834,9 +1022,12 @@ __global__ __launch_bounds__(kBlock, kSpread ? PushCfg<T>::spread_waves : PushCf
           }
         }
       }
-      // ---- emitters of this chunk, in the chunk's own slice of the list
+      // ---- this chunk's emitters: their photons (or in-place pairs) now, or
+      // listed in the chunk's own slice of the list for the emission role
       const int ne = __builtin_amdgcn_readfirstlane(s_emit_n);
-      if (ne > 0) {
+      if (ne > 0 && in_push) {
+        emit_chunk<T, 1>(G, s, i0, ne, s_emit, s_emx, s_emid, s_scan, &s_slot);
+      } else if (ne > 0) {
         listed = ne;
         gptr<uint32_t> el = glb(G->emit_ent + w * (long long)kChunk);
         for (int k = tid; k < ne; k += kBlock) el[k] = s_emit[k];
@@ -938,7 +1129,7 @@ __device__ void emit_role(GapDev* __restrict__ gaps, const long long* __restrict
                           uint32_t* s_pre, unsigned long long* s_base, int* s_nb, int* s_tmp) {
   constexpr int kPer = kPushGrid / kBlock;
   const long long total = wi[B];
-  if (total == 0) return;
+  if (total < gaps->emit_split) return;  // this step emitted in the push
   // exclusive prefix of the push workgroups' emitter counts
   uint32_t v[kPer];
   uint32_t loc = 0;
@@ -1357,9 +1548,9 @@ __global__ __launch_bounds__(1024) void k_plan(GapDev* __restrict__ gaps, int B,
 // history row, and plan the next step.
 
 // One gap's end of step (the push tallies are already folded into the
-// descriptor).  Every field is read before any is written, so the reads go
-// out together.
-__device__ __forceinline__ PlanIn finalize_gap(GapDev* __restrict__ G) {
+// descriptor); in_push: the step's emissions were drawn by the push kernel.
+// Every field is read before any is written, so the reads go out together.
+__device__ __forceinline__ PlanIn finalize_gap(GapDev* __restrict__ G, bool in_push) {
   const int status = G->status, nonfinite = G->nonfinite, overflow = G->overflow;
   const int slot_overflow = G->slot_overflow;
   const int emit_err = G->emit_err, table_len = G->table_len, diag_every = G->diag_every;
@@ -1371,6 +1562,7 @@ __device__ __forceinline__ PlanIn finalize_gap(GapDev* __restrict__ G) {
   const unsigned long long absorbed0 = G->absorbed[0], absorbed1 = G->absorbed[1];
   const unsigned long long inflight0 = G->inflight, created0 = G->pairs_created;
   const unsigned long long emitted0 = G->photons_emitted, escaped0 = G->photons_escaped;
+  const unsigned long long push_emitted0 = G->push_emitted;
   const unsigned long long hist_count = G->hist_count, body_n = G->ph_body_n;
   const long long done = G->step, ph_base = G->ph_base;
   const int32_t* bucket = G->ph_bucket;
@@ -1418,6 +1610,7 @@ __device__ __forceinline__ PlanIn finalize_gap(GapDev* __restrict__ G) {
   if (diag && dp) ke += (double)dp * 2.0 * weight * child_gamma64;
   G->pairs_created = created;
   G->photons_emitted = emitted;
+  if (in_push) G->push_emitted = push_emitted0 + (emitted - emitted0);
   G->photons_escaped = escaped;
   G->inflight = inflight;
   G->lost_energy = lost;
@@ -1486,6 +1679,8 @@ __device__ __forceinline__ void diag_values(GapDev* __restrict__ G) {
 __device__ void finalize_body(GapDev* __restrict__ gaps, int B, long long* __restrict__ wi,
                               long long* __restrict__ pwi, long long* __restrict__ qwi) {
   const int per = (B + (int)blockDim.x - 1) / (int)blockDim.x;
+  // the step's plan, read before this kernel writes the next one
+  const bool in_push = wi[B] < gaps->emit_split;
   // each thread converts the sums of the gaps it ends below
 #pragma unroll 1
   for (int g = threadIdx.x * per; g < (int)(threadIdx.x + 1) * per && g < B; ++g) diag_values(gaps + g);
@@ -1497,12 +1692,12 @@ __device__ void finalize_body(GapDev* __restrict__ gaps, int B, long long* __res
     for (int k = 0; k < kPlanPer; ++k) {
       a[k] = b[k] = c[k] = 0;
       const int g = threadIdx.x * per + k;
-      if (k < per && g < B) plan_items(finalize_gap(gaps + g), a[k], b[k], c[k]);
+      if (k < per && g < B) plan_items(finalize_gap(gaps + g, in_push), a[k], b[k], c[k]);
     }
     plan_write(B, per, a, b, c, wi, pwi, qwi);
     return;
   }
-  for (int g = threadIdx.x; g < B; g += blockDim.x) finalize_gap(gaps + g);
+  for (int g = threadIdx.x; g < B; g += blockDim.x) finalize_gap(gaps + g, in_push);
   __syncthreads();
   compute_plans(gaps, B, wi, pwi, qwi);
 }

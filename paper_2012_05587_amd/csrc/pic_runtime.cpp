@@ -28,6 +28,11 @@ constexpr int kDefaultSort = 20;
 // Steps a gap may run in total: conversion steps of photons are 32-bit and a
 // photon converts at most 2^28 steps after its emission (the table limit).
 constexpr int64_t kMaxSteps = ((int64_t)1 << 31) - ((int64_t)1 << 28) - 1;
+// Steps whose plan holds fewer lepton chunks than this draw their emissions
+// inside the push (measured on the 256-gap batch: the push emitting was 11%
+// faster over the first 20 steps, about 1.4e4 chunks, and the emission
+// kernel 16% faster over 200 steps, whose cascade peaks near 1e5 chunks).
+constexpr int64_t kDefaultEmitSplit = 32768;
 constexpr int kDefaultHist = 4096;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -376,6 +381,7 @@ pic_status create_batch(const pic_gap_params* params, int n_gaps, void* d_ws, si
     G.emit_cnt = reinterpret_cast<int32_t*>(ws + L.emit_cnt);
     G.emit_ent = reinterpret_cast<uint32_t*>(ws + L.emit_ent);
     G.wg_emit = reinterpret_cast<uint32_t*>(ws + L.wg_emit);
+    G.emit_split = kDefaultEmitSplit;
     G.ph_cap = p.photon_capacity;
     G.dt = p.dt;
     G.dx = p.dx;
@@ -1047,6 +1053,7 @@ pic_status pic_read_moments(pic_gap* g, pic_moments* out) {
   out->photon_slots = (int64_t)G.n_ph;
   out->pushes = (int64_t)G.pushes;
   out->last = G.last;
+  out->push_emissions = (int64_t)G.push_emitted;
   return PIC_OK;
 }
 
@@ -1201,6 +1208,25 @@ pic_status pic_batch_tuning(pic_batch* b, int32_t* sort_every, int32_t* autotune
   if (replays) *replays = b->tune.launches;
   if (switches) *switches = b->tune.switches;
   return PIC_OK;
+}
+
+pic_status pic_batch_emission_split(pic_batch* b, int64_t max_push_chunks) {
+  if (!b || max_push_chunks < 0) return PIC_ERR_ARG;
+  if (hipStreamSynchronize(b->stream) != hipSuccess) return PIC_ERR_DEVICE;
+  for (int i = 0; i < b->B; ++i) {
+    GapDev G;
+    pic_status st = read_desc(b, i, &G);
+    if (st != PIC_OK) return st;
+    G.emit_split = max_push_chunks;
+    st = write_desc(b, i, &G);
+    if (st != PIC_OK) return st;
+  }
+  return PIC_OK;
+}
+
+pic_status pic_emission_split(pic_gap* g, int64_t max_push_chunks) {
+  if (!g) return PIC_ERR_ARG;
+  return pic_batch_emission_split(g->b, max_push_chunks);
 }
 
 pic_status pic_tuning(pic_gap* g, int32_t* sort_every, int32_t* autotuned, int64_t* replays,

@@ -175,6 +175,12 @@ def test_create_rejects_bad_workspace_without_device():
                                   C.byref(h)) == P.ERR_WORKSPACE
 
 
+def test_emission_split_rejects_null_handles():
+    import paper_2012_05587_amd as P
+    assert P.lib().pic_emission_split(None, 0) == P.ERR_ARG
+    assert P.lib().pic_batch_emission_split(None, 32768) == P.ERR_ARG
+
+
 def test_status_strings():
     import paper_2012_05587_amd as P
     for st in (0, -1, -2, -3, -4, -5, -6, -7, -8):

@@ -586,10 +586,55 @@ def test_invalid_workspace_rejected():
     assert P.lib().pic_create_gap(C.byref(prm), None, 0, None, C.byref(h)) == P.ERR_WORKSPACE
 
 
+# --------------------------------------------------- where emissions are drawn
+# A step draws its emissions inside the push while its plan is small, else in
+# the emission kernel balanced by emitters (pic_emission_split); the parity
+# cases are small, so these force each path in turn.
+SPLIT_KERNEL, SPLIT_PUSH = 0, 1 << 40
+
+
+@pytest.mark.parametrize("split", [SPLIT_KERNEL, SPLIT_PUSH])
+@pytest.mark.parametrize("case", ["c1", "c3", "in_place", "spread"])
+def test_emission_in_push_and_in_kernel_match_oracle(case, split):
+    """Configuration 1 (binary64) and 3 (mixed) with stored photons, the
+    in-place pairs of a periodic gap and a spread of gamma_thr, over 400
+    steps, with every step's emissions drawn by the push or by the emission
+    kernel: history, leptons and photons equal the oracle's, and the count
+    of emissions drawn by the push is all or none of them."""
+    cfg = workloads.config("c3_mixed_single_gap" if case == "c3" else "c1_fp64_reference_gap")
+    if case == "in_place":
+        cfg.update(l_gamma=0.0, photon_capacity=0, boundary=workloads.PERIODIC)
+    if case == "spread":
+        cfg.update(gamma_thr_spread=0.25)
+    steps = 400
+    cfg["history_rows"] = steps + 8
+    print(f"[case] emission {case} split={split}", flush=True)
+    go = pc.make_oracle(cfg)
+    assert go.step(steps) == 0
+    gg = pc.make_gpu(cfg)
+    gg.emission_split(split)
+    gg.step_n(steps)
+    _check_all(gg, go, cfg["precision"])
+    if cfg["l_gamma"] > 0:
+        a, b = gg.read_photons(), go.photons()
+        key = lambda d: np.lexsort((d["child"], d["dir"], d["conv_step"], d["xq"]))  # noqa: E731
+        ka, kb = key(a), key(b)
+        assert len(ka) == len(kb)
+        for k in ("xq", "conv_step", "dir", "child"):
+            assert np.array_equal(np.asarray(a[k])[ka], np.asarray(b[k])[kb]), k
+    m = gg.read_moments()
+    emitted = int(go.history()["photons_emitted"][-1])
+    assert emitted > 1000
+    assert m.push_emissions == (emitted if split == SPLIT_PUSH else 0)
+
+
 # ------------------------------------------------------------------- batch
-def test_batch_matches_oracle_per_gap():
+@pytest.mark.parametrize("split", [SPLIT_KERNEL, None])
+def test_batch_matches_oracle_per_gap(split):
     """Gaps of different size and physics in one batch, each against its own
-    oracle run."""
+    oracle run; with the default split (emission in the push at this size)
+    and with every step's emissions drawn by the emission kernel, whose
+    emitter-balanced shares then span the gaps."""
     import paper_2012_05587_amd as P
     gaps = workloads.batched_scan(n_gaps=6, precision=workloads.FP64, steps=150)
     for c in gaps:
@@ -597,6 +642,8 @@ def test_batch_matches_oracle_per_gap():
                  e0=min(c["e0"], 120.0), gamma_thr=max(c["gamma_thr"], 150.0),
                  capacity=1_000_000, photon_capacity=1_000_000, history_rows=200)
     b = P.Batch([pc.gpu_params(c) for c in gaps])
+    if split is not None:
+        b.emission_split(split)
     for view, c in zip(b.gaps, gaps):
         view.seed_particles(0, c["n_pairs"], 1)
     st = b.step_n(150, statuses=True)
@@ -636,7 +683,8 @@ def test_large_batch_plans_in_two_passes():
     b.close()
 
 
-def test_batch_mixed_matches_single_gaps():
+@pytest.mark.parametrize("split", [SPLIT_KERNEL, None])
+def test_batch_mixed_matches_single_gaps(split):
     import paper_2012_05587_amd as P
     gaps = workloads.batched_scan(n_gaps=4, precision=workloads.MIXED, steps=100)
     for c in gaps:
@@ -644,6 +692,8 @@ def test_batch_mixed_matches_single_gaps():
                  e0=min(c["e0"], 120.0), gamma_thr=max(c["gamma_thr"], 150.0),
                  capacity=1_000_000, photon_capacity=1_000_000, history_rows=200)
     b = P.Batch([pc.gpu_params(c) for c in gaps])
+    if split is not None:
+        b.emission_split(split)
     for view, c in zip(b.gaps, gaps):
         view.seed_particles(0, c["n_pairs"], 1)
     st = b.step_n(100, statuses=True)
