@@ -13,7 +13,8 @@
 //              law E -= w 2^-K F (Eq. 4 in normalised units; plus j_m dt in
 //              the co-rotating frame) with the field diagnostics; photons due
 //              this step become pairs; the striped push tallies are folded;
-//   k_finalize counters, history row and the work plan of the next step.
+//   k_finalize counters, history row and the work items of the next step,
+//              one gap per wave; k_plan_scan their prefixes (one block).
 // Every S steps the leptons are re-sorted by cell and the photon store by
 // conversion step (counting sorts), which drops absorbed leptons and
 // converted photons.
@@ -1676,30 +1677,42 @@ __device__ __forceinline__ void diag_values(GapDev* __restrict__ G) {
   G->es_step = es;
 }
 
-__device__ void finalize_body(GapDev* __restrict__ gaps, int B, long long* __restrict__ wi,
-                              long long* __restrict__ pwi, long long* __restrict__ qwi) {
-  const int per = (B + (int)blockDim.x - 1) / (int)blockDim.x;
-  // the step's plan, read before this kernel writes the next one
-  const bool in_push = wi[B] < gaps->emit_split;
-  // each thread converts the sums of the gaps it ends below
-#pragma unroll 1
-  for (int g = threadIdx.x * per; g < (int)(threadIdx.x + 1) * per && g < B; ++g) diag_values(gaps + g);
-  __syncthreads();
+// The work-item prefixes of the next step from the per-gap item counts the
+// finalize left in `items` (a: lepton chunks, b: due-photon chunks, c:
+// photon-store chunks, B each), one block.
+__device__ void plan_from_items(int B, const long long* __restrict__ items, long long* __restrict__ wi,
+                                long long* __restrict__ pwi, long long* __restrict__ qwi) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int per = (B + nt - 1) / nt;
   if (per <= kPlanPer) {
-    // each thread ends its own gaps and plans them from the values in hand
     long long a[kPlanPer], b[kPlanPer], c[kPlanPer];
 #pragma unroll
     for (int k = 0; k < kPlanPer; ++k) {
-      a[k] = b[k] = c[k] = 0;
-      const int g = threadIdx.x * per + k;
-      if (k < per && g < B) plan_items(finalize_gap(gaps + g, in_push), a[k], b[k], c[k]);
+      const int g = tid * per + k;
+      const bool in = k < per && g < B;
+      a[k] = in ? items[g] : 0;
+      b[k] = in ? items[B + g] : 0;
+      c[k] = in ? items[2 * B + g] : 0;
     }
     plan_write(B, per, a, b, c, wi, pwi, qwi);
     return;
   }
-  for (int g = threadIdx.x; g < B; g += blockDim.x) finalize_gap(gaps + g, in_push);
-  __syncthreads();
-  compute_plans(gaps, B, wi, pwi, qwi);
+  // very large batches: two passes over the counts
+  long long sa = 0, sb = 0, sc = 0;
+  for (int g = tid * per; g < (tid + 1) * per && g < B; ++g) {
+    sa += items[g];
+    sb += items[B + g];
+    sc += items[2 * B + g];
+  }
+  long long ta, tb, tc;
+  block_scan3(sa, sb, sc, ta, tb, tc);
+  for (int g = tid * per; g < (tid + 1) * per && g < B; ++g) {
+    wi[g] = sa; pwi[g] = sb; qwi[g] = sc;
+    sa += items[g];
+    sb += items[B + g];
+    sc += items[2 * B + g];
+  }
+  if (tid == 0) { wi[B] = ta; pwi[B] = tb; qwi[B] = tc; }
 }
 
 // ------------------------------------------------------------------ fold
@@ -1770,11 +1783,32 @@ __global__ __launch_bounds__(kBlock) void k_post(GapDev* __restrict__ gaps,
   else fold_role(gaps, B, stripes, b - n_field - n_emit - n_conv);
 }
 
-__global__ __launch_bounds__(1024) void k_finalize(GapDev* __restrict__ gaps, int B,
-                                                   long long* __restrict__ wi,
-                                                   long long* __restrict__ pwi,
-                                                   long long* __restrict__ qwi) {
-  finalize_body(gaps, B, wi, pwi, qwi);
+// The end of a step, one gap per wave: the wave's gap index is uniform, so
+// the descriptor's fields are read with scalar loads, and the gaps are ended
+// on as many compute units as there are gaps / 4 (one workgroup ending every
+// gap was bound by one unit's scattered loads).  Each gap's item counts of
+// the next step go to `items`; k_plan_scan turns them into the prefixes.
+__global__ __launch_bounds__(kBlock) void k_finalize(GapDev* __restrict__ gaps, int B,
+                                                     const long long* __restrict__ wi,
+                                                     long long* __restrict__ items) {
+  const int g = __builtin_amdgcn_readfirstlane((int)blockIdx.x * (kBlock / 64) + ((int)threadIdx.x >> 6));
+  if (g >= B || lane_id() != 0) return;
+  // the step's plan, read before k_plan_scan writes the next one
+  const bool in_push = wi[B] < gaps->emit_split;
+  GapDev* __restrict__ G = gaps + g;
+  diag_values(G);
+  long long a, b, c;
+  plan_items(finalize_gap(G, in_push), a, b, c);
+  items[g] = a;
+  items[B + g] = b;
+  items[2 * B + g] = c;
+}
+
+__global__ __launch_bounds__(1024) void k_plan_scan(int B, const long long* __restrict__ items,
+                                                    long long* __restrict__ wi,
+                                                    long long* __restrict__ pwi,
+                                                    long long* __restrict__ qwi) {
+  plan_from_items(B, items, wi, pwi, qwi);
 }
 
 // ------------------------------------------------------------------ sort
@@ -2402,7 +2436,9 @@ hipError_t launch_step_after_push(const StepLaunch& L, bool mixed) {
     hipLaunchKernelGGL(k_post<double>, dim3(grid), dim3(kBlock), 0, L.stream, L.gaps, L.cwi, L.wi,
                        L.pwi, L.B, nf, L.emit_grid, L.conv_grid, L.emit_cnt, L.emit_ent, L.wg_emit,
                        L.stripes);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, L.stream, L.gaps, L.B, L.wi, L.pwi, L.qwi);
+  hipLaunchKernelGGL(k_finalize, dim3((L.B + kBlock / 64 - 1) / (kBlock / 64)), dim3(kBlock), 0, L.stream,
+                     L.gaps, L.B, L.wi, L.items);
+  hipLaunchKernelGGL(k_plan_scan, dim3(1), dim3(1024), 0, L.stream, L.B, L.items, L.wi, L.pwi, L.qwi);
   return hipGetLastError();
 }
 

@@ -14,6 +14,7 @@ struct StepLaunch {
   long long* qwi;      // photon-store work-item prefix (re-sort), B + 1 entries (device)
   long long* twi;      // work-item prefix of the tail sort, B + 1 entries (device)
   long long* cwi;      // cell work-item prefix, B + 1 entries (device, static)
+  long long* items;    // the finalize's per-gap item counts of the next step, 3 x B (device)
   long long cell_items;
   int B;
   int push_grid, conv_grid, emit_grid, ph_sort_grid;

@@ -47,7 +47,7 @@ struct GapLayout {
 };
 
 struct Layout {
-  size_t gaps, wi, pwi, qwi, twi, cwi, emit_cnt, emit_ent, wg_emit, stripes, total;
+  size_t gaps, wi, pwi, qwi, twi, cwi, items, emit_cnt, emit_ent, wg_emit, stripes, total;
   long long max_chunks, max_ph_chunks;
   std::vector<GapLayout> g;
   long long cell_items;
@@ -157,6 +157,7 @@ Layout make_layout(const pic_gap_params* prm, int B) {
   L.qwi = o; o = align_up(o + sizeof(long long) * (size_t)(B + 1));
   L.twi = o; o = align_up(o + sizeof(long long) * (size_t)(B + 1));
   L.cwi = o; o = align_up(o + sizeof(long long) * (size_t)(B + 1));
+  L.items = o; o = align_up(o + sizeof(long long) * 3 * (size_t)B);
   L.cell_items = 0;
   // one emission slice per particle chunk the plan can hold
   L.max_chunks = 0;
@@ -446,6 +447,7 @@ pic_status create_batch(const pic_gap_params* params, int n_gaps, void* d_ws, si
   b->launch.qwi = reinterpret_cast<long long*>(ws + L.qwi);
   b->launch.twi = reinterpret_cast<long long*>(ws + L.twi);
   b->launch.cwi = reinterpret_cast<long long*>(ws + L.cwi);
+  b->launch.items = reinterpret_cast<long long*>(ws + L.items);
   b->launch.cell_items = L.cell_items;
   b->launch.B = n_gaps;
   // Emission, conversion and the photon re-sort get grids sized to what the
