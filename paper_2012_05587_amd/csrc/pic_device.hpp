@@ -35,7 +35,7 @@ constexpr int kItems = 4;             // particles per thread per work item
 constexpr int kChunk = kBlock * kItems;
 constexpr int kTile = 2048;           // cells of the per-workgroup LDS current tile
 constexpr int kPhChunk = kBlock * 4;  // photons per convert work item
-constexpr int kCellChunk = kBlock * 4;
+constexpr int kCellChunk = kBlock * 8;  // cells per work item of the field role (and the sorts' counts)
 constexpr int kSortTile = 8192;       // cells of the LDS histogram of the lepton sort
 // lepton chunks per iteration of the lepton sort: counting holds only the
 // cells, moving holds the whole lepton state

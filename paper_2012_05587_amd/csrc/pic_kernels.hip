@@ -1198,17 +1198,34 @@ __device__ void field_role(GapDev* __restrict__ gaps, const long long* __restric
   const long long c0 = (vb - cwi[g]) * (long long)kCellChunk;
   const int nc = G->n_cells;
   const double wq = G->wq, dxh = G->dx, jmdt = G->jmdt;
+  gptr<long long> F = glb(G->F);
+  gptr<double> E = glb(G->E);
+  gptr<float> Ef = glb(G->Ef);
+  gptr<long long> Fl = glb(G->F_last);
+  // the thread's cells c0 + tid + j kBlock: every load is requested before
+  // any cell is updated
+  constexpr int kPer = kCellChunk / kBlock;
+  long long fv[kPer];
+  double ev[kPer];
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    const long long c = c0 + threadIdx.x + (long long)j * kBlock;
+    const long long cc = c < nc ? c : 0;
+    fv[j] = F[cc];
+    ev[j] = E[cc];
+  }
   double fe = 0.0, es = 0.0;
-  for (int k = threadIdx.x; k < kCellChunk; k += kBlock) {
-    const long long c = c0 + k;
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    const long long c = c0 + threadIdx.x + (long long)j * kBlock;
     if (c >= nc) break;
-    const long long f = G->F[c];
-    double e = G->E[c] - wq * (double)f;
+    const long long f = fv[j];
+    double e = ev[j] - wq * (double)f;
     if (jmdt != 0.0) e = e + jmdt;  // imposed current of the co-rotating frame
-    G->E[c] = e;
-    G->Ef[c] = (float)e;
-    G->F_last[c] = f;
-    G->F[c] = 0;
+    E[c] = e;
+    Ef[c] = (float)e;
+    Fl[c] = f;
+    F[c] = 0;
     fe += e * e * dxh * 0.5;
     es += e;
   }
@@ -2042,25 +2059,60 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(GapDev* __restrict__ gaps,
 
 // Exclusive scan of n int32 counts in place by one 1024-thread block; returns the total.
 __device__ long long block_scan_counts(int32_t* __restrict__ cnt, int n, long long* s_sum) {
+  // thread t takes a contiguous run of entries, a multiple of 4 long, read
+  // and written as 16-byte vectors where a whole vector lies below n (the
+  // rest one by one); runs are added up within waves (DPP-free shuffles
+  // suffice here) and across the block through LDS
+  typedef int i32x4 __attribute__((ext_vector_type(4)));
   const int tid = threadIdx.x, nt = blockDim.x;
-  const int per = (n + nt - 1) / nt;
+  const int per = (((n + nt - 1) / nt) + 3) & ~3;
+  const int c0 = tid * per;
+  const int c1 = c0 + per < n ? c0 + per : n;
   long long loc = 0;
-  for (int c = tid * per; c < (tid + 1) * per && c < n; ++c) loc += cnt[c];
-  s_sum[tid] = loc;
+  for (int c = c0; c < c1; c += 16) {
+    i32x4 v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int cq = c + 4 * q;
+      v[q] = cq + 4 <= c1 ? *(const i32x4*)(cnt + cq) : i32x4{0, 0, 0, 0};
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int cq = c + 4 * q;
+      if (cq + 4 <= c1) loc += (long long)v[q].x + v[q].y + v[q].z + v[q].w;
+      else
+        for (int e = cq; e < c1 && e < cq + 4; ++e) loc += cnt[e];
+    }
+  }
+  const long long incl = wave_incl_scan(loc);
+  const int w = tid >> 6, nw = nt >> 6;
+  if (lane_id() == 63) s_sum[w] = incl;
   __syncthreads();
-  for (int d = 1; d < nt; d <<= 1) {
-    long long y = tid >= d ? s_sum[tid - d] : 0;
-    __syncthreads();
-    s_sum[tid] += y;
-    __syncthreads();
+  long long pre = 0, tot = 0;
+  for (int k = 0; k < nw; ++k) {
+    const long long t = s_sum[k];
+    if (k < w) pre += t;
+    tot += t;
   }
-  long long run = s_sum[tid] - loc;
-  for (int c = tid * per; c < (tid + 1) * per && c < n; ++c) {
-    const int v = cnt[c];
-    cnt[c] = (int32_t)run;
-    run += v;
+  long long run = pre + incl - loc;
+  for (int c = c0; c < c1; c += 4) {
+    if (c + 4 <= c1) {
+      const i32x4 v = *(const i32x4*)(cnt + c);
+      i32x4 o;
+      o.x = (int32_t)run; run += v.x;
+      o.y = (int32_t)run; run += v.y;
+      o.z = (int32_t)run; run += v.z;
+      o.w = (int32_t)run; run += v.w;
+      *(i32x4*)(cnt + c) = o;
+    } else {
+      for (int e = c; e < c1; ++e) {
+        const int v = cnt[e];
+        cnt[e] = (int32_t)run;
+        run += v;
+      }
+    }
   }
-  return s_sum[nt - 1];
+  return tot;
 }
 
 // Exclusive scan of the per-cell counts of one (gap, species) in place (the
