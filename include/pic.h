@@ -103,7 +103,12 @@ enum { PIC_ELECTRON = 0, PIC_POSITRON = 1 };
  *            reserve.
  *  photon_capacity  slots of the photon store (l_gamma > 0); converted and
  *            escaped photons are reclaimed when the store is re-sorted.
- *  seed      key of the Philox4x64-10 streams of this gap.
+ *  seed      key of this gap's random draws: the seeding draws are
+ *            Philox4x64-10 blocks keyed by (pair index, seed); the draws of
+ *            the run (photon paths and child ids, per-lepton thresholds) are
+ *            Philox4x32-10 blocks at counter (step, j | tag << 8, id low 32
+ *            bits, id high 32 bits), key (seed low, seed high), whose 64-bit
+ *            value is word 1 << 32 | word 0 and whose 32-bit value is word 2.
  *  precision PIC_FP64: per-particle arithmetic in binary64, offsets on a
  *            2^-40 cell grid.  PIC_MIXED: binary32 push, offset (2^-24 grid)
  *            and momentum; the current, E and all diagnostics stay exact
@@ -122,9 +127,9 @@ enum { PIC_ELECTRON = 0, PIC_POSITRON = 1 };
  *  gamma_thr_spread  sigma in [0, 1): a spread of the threshold, which the
  *            paper's conclusion names as absent from its model.  Each lepton
  *            then emits at its own fixed threshold, uniform in
- *            gamma_thr (1 - sigma, 1 + sigma): u = (top 53 bits of word 0 of
- *            the Philox4x64-10 block at counter (0, 0, 3, 0), key (id, seed))
- *            / 2^53, threshold gamma_thr (1 + sigma (2u - 1)) in binary64,
+ *            gamma_thr (1 - sigma, 1 + sigma): u = (top 53 bits of the 64-bit
+ *            value of the lepton's draw at step 0, j 0, tag 3) / 2^53,
+ *            threshold gamma_thr (1 + sigma (2u - 1)) in binary64,
  *            rounded to the particle precision.  gamma_pair stays
  *            f * gamma_thr.  Requires (1 - f - sigma) gamma_thr >= 1.  0 is
  *            the paper's single threshold.

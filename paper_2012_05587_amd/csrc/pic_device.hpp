@@ -132,6 +132,9 @@ struct GapDev {
   uint32_t* emit_ent;         // the batch's emitter lists, kChunk entries per chunk
   uint32_t* wg_emit;          // the batch's emitters per push workgroup
   long long emit_split;       // steps whose plan holds fewer lepton chunks emit in the push
+  float conv_c;               // ln 2 l_gamma dx / dt (the photon path in steps per unit of
+                              // -log2 of the survival probability)
+  int32_t pad6;
   int32_t ev_x, ev_steps, ev_rows, pad5;
 
   // ---- counters (device-updated)

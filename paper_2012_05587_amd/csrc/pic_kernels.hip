@@ -76,9 +76,31 @@ __device__ __forceinline__ int conv_steps(const uint32_t* __restrict__ table, in
   const int k = conv_estimate(len, u, inv_lnq);
   // the estimate is within a step of the answer: the entries around it are
   // requested together (T_{len-1} = 0, so some k answers)
-  const uint32_t tm = table[k - 1 > 0 ? k - 1 : 0], t0 = table[k];
-  const uint32_t tp = table[k + 1 < len ? k + 1 : len - 1];
+  gptr<const uint32_t> tab = glb<const uint32_t>((void*)table);
+  const uint32_t tm = tab[k - 1 > 0 ? k - 1 : 0], t0 = tab[k];
+  const uint32_t tp = tab[k + 1 < len ? k + 1 : len - 1];
   return conv_decide(table, len, u, k, tm, t0, tp);
+}
+
+// n_conv without the table where the answer is clear.  T_k = floor(V_k) with
+// V_k = 2^32 q^k as the host evaluates it, so for an integer u, u >= T_k
+// exactly when V_k < u + 1, that is when k exceeds
+// x = (32 - log2(u + 1)) ln 2 / r (q = e^-r), and n_conv = floor(x) + 1.  In
+// binary32, u + 1 is rounded once (relative 2^-24), log2f is within one ulp
+// (4e-6 for results below 32), 32 - log2 is rounded once more (2e-6) and the
+// product with c = ln 2 / r, itself rounded, twice (1.2e-7 relative); the
+// host's V_k is within 3e-15 relative.  So x is off by less than
+// 6.1e-6 c + 1.3e-7 x, and tol = 2e-5 c + 5e-7 x + 1e-6 covers that three
+// times over: wherever x lies farther than tol from an integer the rule gives
+// the table's answer.  Near an integer, or at the table's end, the table
+// decides.
+__device__ __forceinline__ int conv_steps_direct(const uint32_t* __restrict__ table, int len,
+                                                 uint32_t u, float c, float inv_lnq) {
+  const float x = (32.0f - log2f((float)((uint64_t)u + 1u))) * c;
+  const float fl = floorf(x), fr = x - fl;
+  const float tol = 2e-5f * c + 5e-7f * x + 1e-6f;
+  if (fr > tol && fr < 1.0f - tol && fl + 1.0f < (float)len) return (int)fl + 1;
+  return conv_steps(table, len, u, inv_lnq);
 }
 
 // X modulo the domain length D, in [0, D), for |X| < 2^62 and D >= 2^24
@@ -184,7 +206,7 @@ struct EmitGap {
   gptr<uint8_t> phk;
   const uint32_t* table;
   int table_len, K;
-  float inv_lnq;
+  float inv_lnq, conv_c;
   long long domain, photon_step, ph_base;
   unsigned long long ph_cap, slots, n0, n1;
   uint32_t step;
@@ -214,6 +236,7 @@ __device__ __forceinline__ EmitGap<T> emit_gap(GapDev* __restrict__ G) {
   E.table_len = G->table_len;
   E.K = G->K;
   E.inv_lnq = G->inv_lnq;
+  E.conv_c = G->conv_c;
   E.domain = G->domain;
   E.photon_step = G->photon_step;
   E.ph_cap = (unsigned long long)G->ph_cap;
@@ -272,7 +295,7 @@ __device__ __forceinline__ unsigned emit_listed(const EmitGap<T>& E, int s, long
   for (int jj = 0; jj < k; ++jj) {
     const RunDraw u = draw_run(id, E.seed, E.step, (uint32_t)jj, (uint32_t)kTagPhoton);
     const uint64_t child = u.bits & ~(uint64_t)1;
-    const int ncv = conv_steps(E.table, E.table_len, u.u32, E.inv_lnq);
+    const int ncv = conv_steps_direct(E.table, E.table_len, u.u32, E.conv_c, E.inv_lnq);
     long long X = X0 + (long long)dir * (long long)ncv * E.photon_step;
     int cstep = (int)((long long)E.step + ncv);
     if (E.absorbing) {
@@ -302,19 +325,24 @@ __device__ __forceinline__ unsigned emit_listed(const EmitGap<T>& E, int s, long
 // Each thread takes four consecutive entries and requests their ids; a block
 // scan of their photon counts gives each emitter its first photon (kept in
 // its entry's place), and one global atomic reserves the chunk's slots.  The
-// chunk's photons are then spread evenly over the threads; a binary search
-// over the prefixes finds each photon's emitter.  Emission j of an emitter
-// at step n is its tag-2 draw (draw_run): the child electron id is the
-// 64-bit value with bit 0 cleared (the positron's has it set), and the
-// photon's path in steps, n_conv = min{k >= 1 : u >= T_k} for u the 32-bit
-// value, comes from the gap's conversion table.  The gap's emission
-// constants are read here, where they are used, not held in registers
-// through the push.
-template <typename T, int kPhBatch>
+// chunk's photons are then spread evenly over the threads.  Each emitter
+// writes its index at its photons' places in s_map (the flux tile, empty
+// between the flush and the next chunk, holds kMapPhotons of them), so a
+// photon finds its emitter with one LDS read; the thread that reads an entry
+// clears it, which leaves the tile zero again.  Photons past kMapPhotons
+// (more than eight per lepton of the chunk) search the prefixes instead.
+// Emission j of an emitter at step n is its tag-2 draw (draw_run): the child
+// electron id is the 64-bit value with bit 0 cleared (the positron's has it
+// set), and the photon's path in steps, n_conv = min{k >= 1 : u >= T_k} for u
+// the 32-bit value, comes from the gap's conversion table.  The gap's
+// emission constants are read here, where they are used, not held in
+// registers through the push.
+constexpr int kMapPhotons = kTile * 4;  // 16-bit entries in the flux tile
+template <typename T>
 __device__ __forceinline__ void emit_chunk(GapDev* __restrict__ G, int s, long long i0, int ne,
                                            uint32_t* s_emit, const long long* s_emx,
                                            uint64_t* s_emid, int* s_scan,
-                                           unsigned long long* s_slot) {
+                                           unsigned long long* s_slot, uint16_t* s_map) {
   const int tid = threadIdx.x;
   const int buf = G->buf;
   const bool in_place = G->table_len == 0;
@@ -334,7 +362,8 @@ __device__ __forceinline__ void emit_chunk(GapDev* __restrict__ G, int s, long l
       idv[j] = q < ne ? idA[i0 + (long long)(e[j] >> 8)] : 0ull;
       mine += (int)(e[j] & 255u);
     }
-    int ex = block_excl_scan(mine, s_scan, kt);  // ends with a barrier
+    const int ex0 = block_excl_scan(mine, s_scan, kt);  // ends with a barrier
+    int ex = ex0;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int q = 4 * tid + j;
@@ -343,6 +372,17 @@ __device__ __forceinline__ void emit_chunk(GapDev* __restrict__ G, int s, long l
         s_emid[q] = idv[j];
       }
       ex += (int)(e[j] & 255u);
+    }
+    // each emitter's index at its photons' places in the map (the thread's
+    // own entries, read back: the next entry's first photon ends the range)
+#pragma unroll 1
+    for (int j = 0; j < 4; ++j) {
+      const int q = 4 * tid + j;
+      if (q >= ne) break;
+      const int a = (int)s_emit[q];
+      const int b = j < 3 && q + 1 < ne ? (int)s_emit[q + 1] : ex0 + mine;
+      const int mend = b < kMapPhotons ? b : kMapPhotons;
+      for (int m = a; m < mend; ++m) s_map[m] = (uint16_t)q;
     }
     if (tid == 0) {
       if (in_place) {
@@ -359,8 +399,15 @@ __device__ __forceinline__ void emit_chunk(GapDev* __restrict__ G, int s, long l
   const uint32_t step = (uint32_t)G->step;
   const uint64_t seed = G->seed;
   const int K = G->K;
-  // the emitter of the chunk's photon p: the last entry whose first photon is at most p
+  // the emitter of the chunk's photon p (read once, by the thread that owns
+  // p): its map entry, or past the map the last entry whose first photon is
+  // at most p
   auto emitter_of = [&](int p) {
+    if (p < kMapPhotons) {
+      const int q = s_map[p];
+      s_map[p] = 0;
+      return q;
+    }
     int lo = 0, hi = ne - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
@@ -403,60 +450,36 @@ __device__ __forceinline__ void emit_chunk(GapDev* __restrict__ G, int s, long l
   gptr<uint64_t> phc = glb(G->ph_child[pb]);
   gptr<uint8_t> phk = glb(G->ph_key);
   const uint32_t* table = G->table;
-  gptr<const uint32_t> tab = glb<const uint32_t>((void*)G->table);
   const int len = G->table_len;
   const float inv_lnq = G->inv_lnq;
+  const float conv_c = G->conv_c;
   const long long domain = G->domain, photon_step = G->photon_step, ph_base = G->ph_base;
   const unsigned long long ph_cap = (unsigned long long)G->ph_cap;
   const bool absorbing = G->boundary == PIC_BC_ABSORBING;
   unsigned esc = 0;
-  // kPhBatch photons per iteration, so that their table entries are requested
-  // together (the spline's push has registers for one)
 #pragma unroll 1
-  for (int p = tid; p < kt; p += kPhBatch * kBlock) {
-    uint32_t uu[kPhBatch], tm[kPhBatch], t0[kPhBatch], tp[kPhBatch];
-    uint64_t ch[kPhBatch];
-    int kk[kPhBatch], qe[kPhBatch];
-#pragma unroll
-    for (int h = 0; h < kPhBatch; ++h) {
-      const int ph = p + h * kBlock < kt ? p + h * kBlock : p;
-      const int q = emitter_of(ph);
-      qe[h] = q;
-      const RunDraw u = draw_run(s_emid[q], seed, step, (uint32_t)(ph - (int)s_emit[q]),
-                                 (uint32_t)kTagPhoton);
-      ch[h] = u.bits & ~(uint64_t)1;
-      uu[h] = u.u32;
-      kk[h] = conv_estimate(len, uu[h], inv_lnq);
+  for (int p = tid; p < kt; p += kBlock) {
+    const int q = emitter_of(p);
+    const RunDraw u = draw_run(s_emid[q], seed, step, (uint32_t)(p - (int)s_emit[q]),
+                               (uint32_t)kTagPhoton);
+    const int ncv = conv_steps_direct(table, len, u.u32, conv_c, inv_lnq);
+    const long long xe = s_emx[q];
+    const long long dirq = (xe & 1) ? photon_step : -photon_step;
+    long long X = (xe >> 1) + (long long)ncv * dirq;
+    int cstep = (int)((long long)step + ncv);
+    if (absorbing) {
+      if (X < 0 || X >= domain) { cstep = INT32_MIN; ++esc; }
+    } else if (X < 0 || X >= domain) {
+      X = wrap_periodic(X, domain);
     }
-#pragma unroll
-    for (int h = 0; h < kPhBatch; ++h) {
-      tm[h] = tab[kk[h] - 1 > 0 ? kk[h] - 1 : 0];
-      t0[h] = tab[kk[h]];
-      tp[h] = tab[kk[h] + 1 < len ? kk[h] + 1 : len - 1];
-    }
-#pragma unroll
-    for (int h = 0; h < kPhBatch; ++h) {
-      const int ph = p + h * kBlock;
-      if (ph >= kt) break;
-      const int ncv = conv_decide(table, len, uu[h], kk[h], tm[h], t0[h], tp[h]);
-      const long long xe = s_emx[qe[h]];
-      const long long dirq = (xe & 1) ? photon_step : -photon_step;
-      long long X = (xe >> 1) + (long long)ncv * dirq;
-      int cstep = (int)((long long)step + ncv);
-      if (absorbing) {
-        if (X < 0 || X >= domain) { cstep = INT32_MIN; ++esc; }
-      } else if (X < 0 || X >= domain) {
-        X = wrap_periodic(X, domain);
-      }
-      const unsigned long long sl = base + (unsigned long long)ph;
-      if (sl < ph_cap) {
-        phx[sl] = X;
-        phs[sl] = cstep;
-        phc[sl] = ch[h] | (uint64_t)(xe & 1);
-        // the tail key: steps from the last sort to the conversion (>= 1)
-        const long long rel = (long long)cstep - ph_base;
-        phk[sl] = (uint8_t)(cstep != INT32_MIN && rel < kFarKey ? rel : kFarKey);
-      }
+    const unsigned long long sl = base + (unsigned long long)p;
+    if (sl < ph_cap) {
+      phx[sl] = X;
+      phs[sl] = cstep;
+      phc[sl] = (u.bits & ~(uint64_t)1) | (uint64_t)(xe & 1);
+      // the tail key: steps from the last sort to the conversion (>= 1)
+      const long long rel = (long long)cstep - ph_base;
+      phk[sl] = (uint8_t)(cstep != INT32_MIN && rel < kFarKey ? rel : kFarKey);
     }
   }
   if (absorbing) {
@@ -1027,7 +1050,8 @@ __global__ __launch_bounds__(kBlock, kSpread ? PushCfg<T>::spread_waves
       // listed in the chunk's own slice of the list for the emission role
       const int ne = __builtin_amdgcn_readfirstlane(s_emit_n);
       if (ne > 0 && in_push) {
-        emit_chunk<T, 1>(G, s, i0, ne, s_emit, s_emx, s_emid, s_scan, &s_slot);
+        emit_chunk<T>(G, s, i0, ne, s_emit, s_emx, s_emid, s_scan, &s_slot,
+                      reinterpret_cast<uint16_t*>(s_flux));
       } else if (ne > 0) {
         listed = ne;
         gptr<uint32_t> el = glb(G->emit_ent + w * (long long)kChunk);

@@ -419,6 +419,7 @@ pic_status create_batch(const pic_gap_params* params, int n_gaps, void* d_ws, si
     G.ph_bucket = reinterpret_cast<int32_t*>(ws + GL.ph_bucket);
     G.ph_key = reinterpret_cast<uint8_t*>(ws + GL.ph_key);
     G.inv_lnq = p.l_gamma > 0.0 ? (float)(-p.l_gamma * p.dx / p.dt) : 0.0f;
+    G.conv_c = p.l_gamma > 0.0 ? (float)(std::log(2.0) * p.l_gamma * p.dx / p.dt) : 0.0f;
     G.ph_age = photon_sort_age(p);
     cwi[(size_t)i + 1] = cwi[(size_t)i] + ((long long)p.n_cells + pic::kCellChunk - 1) / pic::kCellChunk;
 
