@@ -94,6 +94,15 @@ constexpr uint64_t kTagSeed = 1, kTagPhoton = 2, kTagThreshold = 3;
 // One gap, in device memory.  The host fills the constant part at creation;
 // kernels update the counters.  Particle and photon arrays are double
 // buffered; `buf` selects the live copy and flips at each re-sort.
+// A stored photon: its conversion point on the 2^-K grid and its child
+// electron id with bit 0 = (direction > 0).  The two are read together when
+// the photon converts, so they share one 16-byte record (one cache line per
+// photon where due photons are sparse in the store).
+struct __attribute__((aligned(16))) PhotonRec {
+  long long x;
+  uint64_t child;
+};
+
 struct GapDev {
   // ---- constants
   int32_t n_cells, boundary, K, table_len;
@@ -119,9 +128,8 @@ struct GapDev {
   void* off[2][2];
   void* p[2][2];
   uint64_t* id[2][2];
-  long long* ph_x[2];
+  PhotonRec* ph_rec[2];   // position (2^-K grid) and child id with the direction, one record
   int32_t* ph_step[2];
-  uint64_t* ph_child[2];  // electron id with bit 0 = (direction > 0)
   int32_t* ph_bucket;     // photon store sorted by conversion step: end of each bucket
   uint8_t* ph_key;        // per slot of the unsorted tail: conversion step - ph_base when
                           // below kFarKey, else kFarKey (escaped photons too)
@@ -178,6 +186,16 @@ template <class T>
 __device__ __forceinline__ gptr<T> glb(T* p) { return (gptr<T>)p; }
 template <class T>
 __device__ __forceinline__ gptr<T> glb(void* p) { return (gptr<T>)(T*)p; }
+
+// Photon records moved as one 16-byte vector (one load or store instruction).
+typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void put_photon(gptr<PhotonRec> a, long long i, long long x,
+                                           uint64_t child) {
+  *(gptr<u64x2>)(a + i) = u64x2{(unsigned long long)x, child};
+}
+__device__ __forceinline__ u64x2 get_photon(gptr<const PhotonRec> a, long long i) {
+  return *(gptr<const u64x2>)(a + i);
+}
 
 __device__ __forceinline__ void gadd(gptr<unsigned long long> p, unsigned long long v) {
   __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -200,9 +200,8 @@ struct EmitGap {
   gptr<int32_t> cell[2];
   gptr<T> off[2], p[2];
   gptr<uint64_t> id[2];
-  gptr<long long> phx;
+  gptr<PhotonRec> phr;
   gptr<int32_t> phs;
-  gptr<uint64_t> phc;
   gptr<uint8_t> phk;
   const uint32_t* table;
   int table_len, K;
@@ -227,9 +226,8 @@ __device__ __forceinline__ EmitGap<T> emit_gap(GapDev* __restrict__ G) {
     E.p[s] = glb<T>(G->p[buf][s]);
     E.id[s] = glb(G->id[buf][s]);
   }
-  E.phx = glb(G->ph_x[pb]);
+  E.phr = glb(G->ph_rec[pb]);
   E.phs = glb(G->ph_step[pb]);
-  E.phc = glb(G->ph_child[pb]);
   E.phk = glb(G->ph_key);
   E.ph_base = G->ph_base;
   E.table = G->table;
@@ -305,9 +303,8 @@ __device__ __forceinline__ unsigned emit_listed(const EmitGap<T>& E, int s, long
     }
     const unsigned long long slot = slot0 + jj;
     if (slot < E.ph_cap) {
-      E.phx[slot] = X;
+      put_photon(E.phr, (long long)slot, X, child | (dir > 0 ? 1u : 0u));
       E.phs[slot] = cstep;
-      E.phc[slot] = child | (dir > 0 ? 1u : 0u);
       // the tail key: steps from the last sort to the conversion (>= 1)
       const long long rel = (long long)cstep - E.ph_base;
       E.phk[slot] = (uint8_t)(cstep != INT32_MIN && rel < kFarKey ? rel : kFarKey);
@@ -445,9 +442,8 @@ __device__ __forceinline__ void emit_chunk(GapDev* __restrict__ G, int s, long l
     return;
   }
   const int pb = G->phbuf;
-  gptr<long long> phx = glb(G->ph_x[pb]);
+  gptr<PhotonRec> phr = glb(G->ph_rec[pb]);
   gptr<int32_t> phs = glb(G->ph_step[pb]);
-  gptr<uint64_t> phc = glb(G->ph_child[pb]);
   gptr<uint8_t> phk = glb(G->ph_key);
   const uint32_t* table = G->table;
   const int len = G->table_len;
@@ -474,9 +470,8 @@ __device__ __forceinline__ void emit_chunk(GapDev* __restrict__ G, int s, long l
     }
     const unsigned long long sl = base + (unsigned long long)p;
     if (sl < ph_cap) {
-      phx[sl] = X;
+      put_photon(phr, (long long)sl, X, (u.bits & ~(uint64_t)1) | (uint64_t)(xe & 1));
       phs[sl] = cstep;
-      phc[sl] = (u.bits & ~(uint64_t)1) | (uint64_t)(xe & 1);
       // the tail key: steps from the last sort to the conversion (>= 1)
       const long long rel = (long long)cstep - ph_base;
       phk[sl] = (uint8_t)(cstep != INT32_MIN && rel < kFarKey ? rel : kFarKey);
@@ -523,6 +518,39 @@ __device__ __forceinline__ void flush_tally(unsigned long long* __restrict__ str
 // Lorentz factor of a lepton of momentum p (the stored value, binary32 in
 // mixed precision) for the diagnostics: sqrt(1 + p^2) in binary64.
 __device__ __forceinline__ double lepton_gamma64(double p) { return sqrt(1.0 + p * p); }
+
+// The same for the per-step kinetic energy of the push, from the stored
+// momentum p and the push's own Lorentz factor g of it.  In binary64 it is
+// the square root above.  In binary32, g = sqrt(1 + p^2) rounded twice is
+// within 3e-7 of the true value, and one Newton step g + (1 + p^2 - g^2) / (2 g)
+// in binary64, with 1 / g from the binary32 reciprocal, leaves an error of
+// about the square of that, below 1e-13 relative: far below the binary64
+// sum's own tolerance, at a third of the cost of a correctly rounded root.
+template <typename T>
+__device__ __forceinline__ double diag_gamma(T p, T g);
+template <>
+__device__ __forceinline__ double diag_gamma<double>(double p, double) { return lepton_gamma64(p); }
+template <>
+__device__ __forceinline__ double diag_gamma<float>(float p, float g) {
+  const double pd = (double)p, gd = (double)g;
+  const double a = fma(pd, pd, 1.0);
+  const double r = fma(-gd, gd, a);
+  const double h = (double)(0.5f * __builtin_amdgcn_rcpf(g));
+  return fma(r, h, gd);
+}
+
+// fix64 of a Lorentz factor t: for t in [1, 2^51), t 2^64 = m 2^(e + 12)
+// (m the 53-bit significand, e >= 0 the exponent) is the integer part
+// m >> (52 - e) above 64 fraction bits m << (12 + e); other values take the
+// general conversion.
+__device__ __forceinline__ __int128 fix64_gamma(double t) {
+  if (!(t >= 1.0 && t < 0x1p51)) return fix64(t);
+  const unsigned long long bits = (unsigned long long)__double_as_longlong(t);
+  const int e = (int)(bits >> 52) - 1023;
+  const unsigned long long m = (bits & 0xFFFFFFFFFFFFFull) | (1ull << 52);
+  const unsigned long long hi = m >> (52 - e), lo = m << (12 + e);
+  return (__int128)(((unsigned __int128)hi << 64) | lo);
+}
 
 // E at the cells left of, at and right of cell cl (a dead slot reads cell 0),
 // with the boundary ghosts of the gather.  The binary32 push reads the
@@ -1012,7 +1040,7 @@ __global__ __launch_bounds__(kBlock, kSpread ? PushCfg<T>::spread_waves
           __builtin_nontemporal_store((T)nq * inv_scale, &offA[i]);
           if (c2 != c) __builtin_nontemporal_store(c2, &cellA[i]);
           // energy diagnostics in binary64 from the stored momentum
-          if (diag) ke_t += fix64(lepton_gamma64((double)pn));
+          if (diag) ke_t += fix64_gamma(diag_gamma<T>(pn, gm));
         } else {
           const unsigned __int128 u = (unsigned __int128)fix64(lepton_gamma64((double)pn));
 #pragma unroll
@@ -1385,8 +1413,7 @@ __device__ void convert_role(GapDev* __restrict__ gaps, const long long* __restr
     const bool keyed = kstep < kFarKey;
     gptr<const uint8_t> phk = glb<const uint8_t>((void*)G->ph_key);
     gptr<const int32_t> phs = glb<const int32_t>((void*)G->ph_step[pb]);
-    gptr<const long long> phx = glb<const long long>((void*)G->ph_x[pb]);
-    gptr<const uint64_t> phc = glb<const uint64_t>((void*)G->ph_child[pb]);
+    gptr<const PhotonRec> phr = glb<const PhotonRec>((void*)G->ph_rec[pb]);
     gptr<int32_t> cell0 = glb(G->cell[buf][0]), cell1 = glb(G->cell[buf][1]);
     gptr<T> off0 = glb<T>(G->off[buf][0]), off1 = glb<T>(G->off[buf][1]);
     gptr<T> p0 = glb<T>(G->p[buf][0]), p1 = glb<T>(G->p[buf][1]);
@@ -1442,8 +1469,9 @@ __device__ void convert_role(GapDev* __restrict__ gaps, const long long* __restr
       base = __shfl(base, 0, 64);
       for (uint32_t q = (uint32_t)lane; q < cnt; q += 64) {
         const long long i = ib + (long long)due[q];
-        const long long X = phx[i];
-        const uint64_t ch = phc[i];
+        const u64x2 pr = get_photon(phr, i);
+        const long long X = (long long)pr.x;
+        const uint64_t ch = pr.y;
         const int cc = (int)(X >> K);
         const T offn = (T)(X & mask) * inv_scale;
         const T pc = (ch & 1u) ? pchild : -pchild;
@@ -2256,8 +2284,7 @@ __global__ __launch_bounds__(kBlock) void k_ph_pass(GapDev* __restrict__ gaps,
         __syncthreads();
         for (long long r = p0; r < p1; r += kPhUnroll * kBlock) {
           int key[kPhUnroll];
-          long long xv[kPhUnroll];
-          uint64_t chv[kPhUnroll];
+          u64x2 rv[kPhUnroll];
 #pragma unroll
           for (int k = 0; k < kPhUnroll; ++k) {
             const long long i = r + threadIdx.x + (long long)k * kBlock;
@@ -2268,12 +2295,8 @@ __global__ __launch_bounds__(kBlock) void k_ph_pass(GapDev* __restrict__ gaps,
 #pragma unroll
           for (int k = 0; k < kPhUnroll; ++k) {
             const long long i = r + threadIdx.x + (long long)k * kBlock;
-            xv[k] = 0;
-            chv[k] = 0;
-            if (key[k] >= 0) {
-              xv[k] = G->ph_x[pb][i];
-              chv[k] = G->ph_child[pb][i];
-            }
+            rv[k] = u64x2{0ull, 0ull};
+            if (key[k] >= 0) rv[k] = get_photon(glb<const PhotonRec>((void*)G->ph_rec[pb]), i);
           }
 #pragma unroll
           for (int k = 0; k < kPhUnroll; ++k) {
@@ -2284,9 +2307,8 @@ __global__ __launch_bounds__(kBlock) void k_ph_pass(GapDev* __restrict__ gaps,
             b = __shfl(b, head_lane, 64);
             if (key[k] < 0) continue;
             const long long dst = (long long)b + (lane - head_lane);
-            G->ph_x[pb ^ 1][dst] = xv[k];
+            *(gptr<u64x2>)(glb(G->ph_rec[pb ^ 1]) + dst) = rv[k];
             G->ph_step[pb ^ 1][dst] = (int32_t)(stepn + key[k]);
-            G->ph_child[pb ^ 1][dst] = chv[k];
           }
         }
       }
@@ -2305,9 +2327,9 @@ __global__ __launch_bounds__(kBlock) void k_ph_pass(GapDev* __restrict__ gaps,
           b = __shfl(b, head_lane, 64);
           if (key >= 0) {
             const long long dst = (long long)b + (lane - head_lane);
-            G->ph_x[pb ^ 1][dst] = G->ph_x[pb][i];
+            *(gptr<u64x2>)(glb(G->ph_rec[pb ^ 1]) + dst) =
+                get_photon(glb<const PhotonRec>((void*)G->ph_rec[pb]), i);
             G->ph_step[pb ^ 1][dst] = (int32_t)cs;
-            G->ph_child[pb ^ 1][dst] = G->ph_child[pb][i];
           }
         }
       }

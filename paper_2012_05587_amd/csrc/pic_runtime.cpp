@@ -40,7 +40,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 struct GapLayout {
   size_t E, Ef, F, F_last, rho, table, sort_cnt[2], hist;
   size_t cell[2][2], off[2][2], p[2][2], id[2][2];
-  size_t ph_x[2], ph_step[2], ph_child[2];
+  size_t ph_rec[2], ph_step[2];
   size_t ph_bucket, ph_key;
   size_t end;
   int64_t table_len;
@@ -196,9 +196,8 @@ Layout make_layout(const pic_gap_params* prm, int B) {
         G.id[b][s] = o; o = align_up(o + 8 * cap);
       }
     for (int b = 0; b < 2; ++b) {
-      G.ph_x[b] = o; o = align_up(o + 8 * pc);
+      G.ph_rec[b] = o; o = align_up(o + 16 * pc);
       G.ph_step[b] = o; o = align_up(o + 4 * pc);
-      G.ph_child[b] = o; o = align_up(o + 8 * pc);
     }
     G.ph_bucket = o; o = align_up(o + 4 * ((size_t)G.table_len + 1));
     // tail keys, read 16 at a time from 16-byte boundaries below the store's end
@@ -412,9 +411,8 @@ pic_status create_batch(const pic_gap_params* params, int n_gaps, void* d_ws, si
         G.p[bb][s] = ws + GL.p[bb][s];
         G.id[bb][s] = reinterpret_cast<uint64_t*>(ws + GL.id[bb][s]);
       }
-      G.ph_x[bb] = reinterpret_cast<long long*>(ws + GL.ph_x[bb]);
+      G.ph_rec[bb] = reinterpret_cast<pic::PhotonRec*>(ws + GL.ph_rec[bb]);
       G.ph_step[bb] = reinterpret_cast<int32_t*>(ws + GL.ph_step[bb]);
-      G.ph_child[bb] = reinterpret_cast<uint64_t*>(ws + GL.ph_child[bb]);
     }
     G.ph_bucket = reinterpret_cast<int32_t*>(ws + GL.ph_bucket);
     G.ph_key = reinterpret_cast<uint8_t*>(ws + GL.ph_key);
@@ -1128,21 +1126,19 @@ pic_status pic_read_photons(pic_gap* g, int64_t max_n, int64_t* xq, int64_t* con
   if (st != PIC_OK) return st;
   const size_t n = (size_t)G.n_ph;
   const int pb = G.phbuf;
-  std::vector<long long> x(n);
+  std::vector<pic::PhotonRec> rec(n);
   std::vector<int32_t> cs(n);
-  std::vector<uint64_t> ch(n);
-  if (copy_to_host(b, x.data(), G.ph_x[pb], 8 * n) != PIC_OK) return PIC_ERR_DEVICE;
+  if (copy_to_host(b, rec.data(), G.ph_rec[pb], 16 * n) != PIC_OK) return PIC_ERR_DEVICE;
   if (copy_to_host(b, cs.data(), G.ph_step[pb], 4 * n) != PIC_OK) return PIC_ERR_DEVICE;
-  if (copy_to_host(b, ch.data(), G.ph_child[pb], 8 * n) != PIC_OK) return PIC_ERR_DEVICE;
   if (hipStreamSynchronize(b->stream) != hipSuccess) return PIC_ERR_DEVICE;
   int64_t k = 0;
   for (size_t i = 0; i < n; ++i) {
     if ((long long)cs[i] < G.step) continue;  // converted or escaped, not yet reclaimed
     if (k < max_n) {
-      if (xq) xq[k] = x[i];
+      if (xq) xq[k] = rec[i].x;
       if (conv_step) conv_step[k] = cs[i];
-      if (dir) dir[k] = (ch[i] & 1u) ? 1 : -1;
-      if (child) child[k] = ch[i] & ~(uint64_t)1;
+      if (dir) dir[k] = (rec[i].child & 1u) ? 1 : -1;
+      if (child) child[k] = rec[i].child & ~(uint64_t)1;
     }
     ++k;
   }
