@@ -1,6 +1,7 @@
 // Internal header of the MI355X pair-cascade PIC library: the per-gap
 // descriptor that lives in device memory, launch constants, and device
-// helpers (Philox4x64-10, wave-level scans).  Not part of the C-ABI.
+// helpers (Philox4x64-10 and Philox4x32-10, wave-level scans).  Not part of
+// the C-ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -260,6 +261,33 @@ __device__ __forceinline__ RunDraw draw_run(uint64_t id, uint64_t seed, uint32_t
   d.bits = ((uint64_t)c1 << 32) | c0;
   d.u32 = c2;
   return d;
+}
+
+// Two independent draws at once (two leptons' or emissions' counters under
+// one key), their rounds interleaved so that each hides the other's
+// multiply latency; the same values as two draw_run calls.
+__device__ __forceinline__ void draw_run2(uint64_t ida, uint64_t idb, uint64_t seed, uint32_t step,
+                                          uint32_t ja, uint32_t jb, uint32_t tag, RunDraw& da,
+                                          RunDraw& db) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+  const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+  uint32_t a0 = step, a1 = ja | (tag << 8), a2 = (uint32_t)ida, a3 = (uint32_t)(ida >> 32);
+  uint32_t b0 = step, b1 = jb | (tag << 8), b2 = (uint32_t)idb, b3 = (uint32_t)(idb >> 32);
+  uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+#pragma unroll 1
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) { k0 += W0; k1 += W1; }
+    const uint64_t pa = (uint64_t)M0 * a0, qa = (uint64_t)M1 * a2;
+    const uint64_t pb = (uint64_t)M0 * b0, qb = (uint64_t)M1 * b2;
+    const uint32_t na0 = (uint32_t)(qa >> 32) ^ a1 ^ k0, na2 = (uint32_t)(pa >> 32) ^ a3 ^ k1;
+    const uint32_t nb0 = (uint32_t)(qb >> 32) ^ b1 ^ k0, nb2 = (uint32_t)(pb >> 32) ^ b3 ^ k1;
+    a1 = (uint32_t)qa; a3 = (uint32_t)pa; a0 = na0; a2 = na2;
+    b1 = (uint32_t)qb; b3 = (uint32_t)pb; b0 = nb0; b2 = nb2;
+  }
+  da.bits = ((uint64_t)a1 << 32) | a0;
+  da.u32 = a2;
+  db.bits = ((uint64_t)b1 << 32) | b0;
+  db.u32 = b2;
 }
 
 // Emission threshold of lepton `id` under a spread sigma of gamma_thr, a fixed

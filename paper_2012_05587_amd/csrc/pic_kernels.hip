@@ -4,15 +4,16 @@
 //   k_push     gather E at each lepton, relativistic push, move with an exact
 //              integer charge-conserving flux (per-workgroup LDS tile reduced
 //              into the global int64 grid), absorb/wrap, and the threshold
-//              test: the emitter loses k * gamma_pair, and each chunk's
-//              emitters draw their photons (or in-place pairs) from Philox
-//              and append them; instantiated with the linear or
-//              quadratic-spline shape and with or without per-lepton
-//              thresholds;
-//   k_post     three roles on disjoint block ranges of one launch: Ampere's
+//              test: the emitter loses k * gamma_pair; in small steps each
+//              chunk's emitters then draw their photons (or in-place pairs)
+//              from Philox and append them, in large steps they are listed
+//              for k_post; instantiated with the linear or quadratic-spline
+//              shape and with or without per-lepton thresholds;
+//   k_post     four roles on disjoint block ranges of one launch: Ampere's
 //              law E -= w 2^-K F (Eq. 4 in normalised units; plus j_m dt in
-//              the co-rotating frame) with the field diagnostics; photons due
-//              this step become pairs; the striped push tallies are folded;
+//              the co-rotating frame) with the field diagnostics; the listed
+//              emitters' photons, balanced by emitter; photons due this step
+//              become pairs; the striped push tallies are folded;
 //   k_finalize counters, history row and the work items of the next step,
 //              one gap per wave; k_plan_scan their prefixes (one block).
 // Every S steps the leptons are re-sorted by cell and the photon store by
@@ -335,7 +336,7 @@ __device__ __forceinline__ unsigned emit_listed(const EmitGap<T>& E, int s, long
 // emission constants are read here, where they are used, not held in
 // registers through the push.
 constexpr int kMapPhotons = kTile * 4;  // 16-bit entries in the flux tile
-template <typename T>
+template <typename T, bool kTwo>
 __device__ __forceinline__ void emit_chunk(GapDev* __restrict__ G, int s, long long i0, int ne,
                                            uint32_t* s_emit, const long long* s_emx,
                                            uint64_t* s_emid, int* s_scan,
@@ -453,11 +454,8 @@ __device__ __forceinline__ void emit_chunk(GapDev* __restrict__ G, int s, long l
   const unsigned long long ph_cap = (unsigned long long)G->ph_cap;
   const bool absorbing = G->boundary == PIC_BC_ABSORBING;
   unsigned esc = 0;
-#pragma unroll 1
-  for (int p = tid; p < kt; p += kBlock) {
-    const int q = emitter_of(p);
-    const RunDraw u = draw_run(s_emid[q], seed, step, (uint32_t)(p - (int)s_emit[q]),
-                               (uint32_t)kTagPhoton);
+  // the photon p of emitter q with its draw u: conversion step and store
+  auto put = [&](int p, int q, const RunDraw& u) {
     const int ncv = conv_steps_direct(table, len, u.u32, conv_c, inv_lnq);
     const long long xe = s_emx[q];
     const long long dirq = (xe & 1) ? photon_step : -photon_step;
@@ -475,6 +473,28 @@ __device__ __forceinline__ void emit_chunk(GapDev* __restrict__ G, int s, long l
       // the tail key: steps from the last sort to the conversion (>= 1)
       const long long rel = (long long)cstep - ph_base;
       phk[sl] = (uint8_t)(cstep != INT32_MIN && rel < kFarKey ? rel : kFarKey);
+    }
+  };
+  if constexpr (kTwo) {
+    // two photons per thread and round, their draws interleaved
+#pragma unroll 1
+    for (int p = tid; p < kt; p += 2 * kBlock) {
+      const int p2 = p + kBlock;
+      const bool two = p2 < kt;
+      const int qa = emitter_of(p);
+      const int qb = two ? emitter_of(p2) : qa;
+      RunDraw ua, ub;
+      draw_run2(s_emid[qa], s_emid[qb], seed, step, (uint32_t)(p - (int)s_emit[qa]),
+                (uint32_t)((two ? p2 : p) - (int)s_emit[qb]), (uint32_t)kTagPhoton, ua, ub);
+      put(p, qa, ua);
+      if (two) put(p2, qb, ub);
+    }
+  } else {
+#pragma unroll 1
+    for (int p = tid; p < kt; p += kBlock) {
+      const int q = emitter_of(p);
+      put(p, q, draw_run(s_emid[q], seed, step, (uint32_t)(p - (int)s_emit[q]),
+                         (uint32_t)kTagPhoton));
     }
   }
   if (absorbing) {
@@ -1078,7 +1098,8 @@ __global__ __launch_bounds__(kBlock, kSpread ? PushCfg<T>::spread_waves
       // listed in the chunk's own slice of the list for the emission role
       const int ne = __builtin_amdgcn_readfirstlane(s_emit_n);
       if (ne > 0 && in_push) {
-        emit_chunk<T>(G, s, i0, ne, s_emit, s_emx, s_emid, s_scan, &s_slot,
+        emit_chunk<T, PushCfg<T>::prefetch && !kSpread && !kSpline>(G, s, i0, ne, s_emit, s_emx,
+                                                                      s_emid, s_scan, &s_slot,
                       reinterpret_cast<uint16_t*>(s_flux));
       } else if (ne > 0) {
         listed = ne;
