@@ -1843,9 +1843,11 @@ __device__ void fold_role(GapDev* __restrict__ gaps, int B, unsigned long long* 
 }
 
 // Everything of a step between the push and the finalize: the Ampere
-// update (blocks [0, n_field)), the emission of the listed chunks (next
-// n_emit blocks), the conversions (next n_conv blocks) and the fold of the
-// push tallies (the rest) are independent of each other.
+// update (blocks [0, n_field)), the conversions (next n_conv blocks), the
+// emission of the listed chunks (next n_emit blocks) and the fold of the
+// push tallies (the rest) are independent of each other.  Blocks start in
+// index order, so the emission role, idle in steps that emit inside the
+// push, comes after the conversions.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_post(GapDev* __restrict__ gaps,
                                                  const long long* __restrict__ cwi,
@@ -1865,12 +1867,12 @@ __global__ __launch_bounds__(kBlock) void k_post(GapDev* __restrict__ gaps,
   __shared__ uint32_t s_buf[kPushGrid > kConvGroup * kPhChunk ? kPushGrid : kConvGroup * kPhChunk];
   const int b = blockIdx.x;
   if (b < n_field) field_role(gaps, cwi, B, b, s_red);
-  else if (b < n_field + n_emit)
-    emit_role<T>(gaps, wi, B, emit_cnt, emit_ent, wg_emit, b - n_field, n_emit, s_buf, s_base, s_nb,
-                 s_tmp);
-  else if (b < n_field + n_emit + n_conv)
-    convert_role<T>(gaps, pwi, B, b - n_field - n_emit, n_conv, s_buf);
-  else fold_role(gaps, B, stripes, b - n_field - n_emit - n_conv);
+  else if (b < n_field + n_conv)
+    convert_role<T>(gaps, pwi, B, b - n_field, n_conv, s_buf);
+  else if (b < n_field + n_conv + n_emit)
+    emit_role<T>(gaps, wi, B, emit_cnt, emit_ent, wg_emit, b - n_field - n_conv, n_emit, s_buf,
+                 s_base, s_nb, s_tmp);
+  else fold_role(gaps, B, stripes, b - n_field - n_conv - n_emit);
 }
 
 // The end of a step, one gap per wave: the wave's gap index is uniform, so
