@@ -224,8 +224,9 @@ pic_status pic_create_gap(const pic_gap_params* p, void* d_ws, size_t ws_bytes,
  * cell = (u0 >> 32) * n_cells >> 32, offset = (u1 >> 40) * 2^-24.
  * PIC_SEED_LATTICE: x_i = (i + 1/2) n_cells / N on the 2^-24 grid.
  * Momenta are p0_minus / p0_plus (taken as p at t = -dt/2).
- * The seed is sorted by cell before the first step (by pic_prepare or the
- * first pic_step_n), so that its chunks deposit through the LDS tile.
+ * The seed is sorted by cell group (8 cells) before the first step (by
+ * pic_prepare or the first pic_step_n), so that its chunks deposit through
+ * the LDS tile.
  * Errors: PIC_ERR_ARG, PIC_ERR_STATE (after the first step, or when the gap
  * already holds leptons: the seed ids start at 0), PIC_ERR_CAPACITY (more
  * pairs than the capacity), PIC_ERR_DEVICE. */
@@ -239,7 +240,7 @@ pic_status pic_seed_explicit(pic_gap* g, int32_t species, int64_t n, const int32
                              const double* off, const double* p, const uint64_t* id);
 
 /* Makes a seeded gap ready to step: enqueues the sort of the seed by cell
- * and, on a non-NULL stream, captures and uploads the HIP graphs of the
+ * group and, on a non-NULL stream, captures and uploads the HIP graphs of the
  * step sequence (every candidate re-sort cadence when sort_every = 0), so
  * that pic_step_n only launches them.  Optional: pic_step_n does the same
  * work on first use.  Synchronises the stream.  Errors: PIC_ERR_STATE

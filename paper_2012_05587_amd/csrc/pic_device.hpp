@@ -37,7 +37,8 @@ constexpr int kChunk = kBlock * kItems;
 constexpr int kTile = 2048;           // cells of the per-workgroup LDS current tile
 constexpr int kPhChunk = kBlock * 4;  // photons per convert work item
 constexpr int kCellChunk = kBlock * 8;  // cells per work item of the field role (and the sorts' counts)
-constexpr int kSortTile = 8192;       // cells of the LDS histogram of the lepton sort
+constexpr int kSortTile = 8192;       // buckets of the LDS histogram of the lepton sort
+constexpr int kSortShift = 3;         // a lepton sort bucket is a group of 2^kSortShift cells
 // lepton chunks per iteration of the lepton sort: counting holds only the
 // cells, moving holds the whole lepton state
 template <int PASS>

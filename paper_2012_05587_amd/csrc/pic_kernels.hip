@@ -16,9 +16,9 @@
 //              become pairs; the striped push tallies are folded;
 //   k_finalize counters, history row and the work items of the next step,
 //              one gap per wave; k_plan_scan their prefixes (one block).
-// Every S steps the leptons are re-sorted by cell and the photon store by
-// conversion step (counting sorts), which drops absorbed leptons and
-// converted photons.
+// Every S steps the leptons are re-sorted by cell group (8 cells) and the
+// photon store by conversion step (counting sorts), which drops absorbed
+// leptons and converted photons.
 //
 // All kernels take the gaps of a batch at once: work items are chunks of
 // particles, photons or cells, numbered across gaps by prefix arrays that
@@ -681,8 +681,8 @@ __device__ __forceinline__ void push_item(long long local, long long chunks0, lo
 }
 
 // One work item is a chunk of kChunk leptons of one species of one gap.
-// Leptons are sorted by cell (between re-sorts they drift by a few cells),
-// so a chunk touches a short range of cells: its current is summed in a
+// Leptons are sorted by groups of 8 cells (between re-sorts they drift by a
+// few cells), so a chunk touches a short range of cells: its current is summed in a
 // per-workgroup LDS tile over that range and added to the grid with one
 // atomic per touched cell.  Chunks spread over more than kTile cells (the
 // sparse early cascade, unsorted appended leptons) add to the grid directly.
@@ -1918,14 +1918,24 @@ __device__ __forceinline__ void wave_runs(int cv, int& head_lane, int& run_len) 
   run_len = head ? next - lane : 0;
 }
 
+// Buckets of the lepton sort of a gap of nc cells: groups of 2^kSortShift
+// cells.  The push needs a chunk's leptons within a short span of cells, not
+// in cell order inside a group, and groups make each bucket's run of
+// destination slots 2^kSortShift times longer, so the scatter's stores
+// coalesce.
+__device__ __forceinline__ int sort_buckets(int nc) {
+  return (nc + (1 << kSortShift) - 1) >> kSortShift;
+}
+
 __global__ __launch_bounds__(kBlock) void k_sort_zero(GapDev* __restrict__ gaps,
                                                       const long long* __restrict__ cwi, int B) {
   const int g = find_gap(cwi, B, blockIdx.x);
   GapDev* __restrict__ G = gaps + g;
   const long long c0 = (blockIdx.x - cwi[g]) * (long long)kCellChunk;
+  const int nk = sort_buckets(G->n_cells);
   for (int k = threadIdx.x; k < kCellChunk; k += kBlock) {
     const long long c = c0 + k;
-    if (c >= G->n_cells) break;
+    if (c >= nk) break;
     G->sort_cnt[0][c] = 0;
     G->sort_cnt[1][c] = 0;
   }
@@ -1933,11 +1943,11 @@ __global__ __launch_bounds__(kBlock) void k_sort_zero(GapDev* __restrict__ gaps,
 }
 
 // Between full re-sorts, the leptons of a species appended since the last
-// one (slots body_n .. n) are sorted by cell among themselves every
+// one (slots body_n .. n) are sorted by cell group among themselves every
 // kTailEvery steps, where they are many: their chunks then fit the push's
 // LDS tile instead of depositing through global atomics.  Nothing moves
 // out of the tail and nothing is dropped; dead leptons keep their slots in
-// an extra bucket after the last cell.
+// an extra bucket after the last group.
 // A species' tail is sorted when its gap is wider than the push's tile (in
 // a narrower gap every chunk fits the tile anyway) and the tail holds at
 // least a chunk and a 32nd of the species.
@@ -1985,23 +1995,24 @@ __global__ __launch_bounds__(kBlock) void k_tail_zero(GapDev* __restrict__ gaps,
   const int g = find_gap(cwi, B, blockIdx.x);
   GapDev* __restrict__ G = gaps + g;
   const long long c0 = (blockIdx.x - cwi[g]) * (long long)kCellChunk;
-  const int nc = G->n_cells;
+  const int nk = sort_buckets(G->n_cells);
   for (int s = 0; s < 2; ++s) {
     if (!tail_sorted(G, s)) continue;
+    // the groups and, after them, the dead bucket
     for (int k = threadIdx.x; k < kCellChunk; k += kBlock) {
       const long long c = c0 + k;
-      if (c >= nc) break;
+      if (c > nk) break;
       G->sort_cnt[s][c] = 0;
     }
-    if (blockIdx.x == cwi[g] && threadIdx.x == 0) G->sort_cnt[s][nc] = 0;  // the dead bucket
   }
 }
 
-// Counting sort of the leptons by cell.  PASS 0 counts, PASS 1 (after the
-// scan turned the counts into bucket starts) moves each live lepton to the
-// other buffer.  A chunk whose cells span at most kSortTile counts in an LDS
-// histogram first and touches each global bucket once; wider chunks (leptons
-// appended since the last sort) use one global atomic per run of equal cells.
+// Counting sort of the leptons by cell group (sort_buckets).  PASS 0 counts,
+// PASS 1 (after the scan turned the counts into bucket starts) moves each
+// live lepton to the other buffer.  A chunk whose groups span at most
+// kSortTile counts in an LDS histogram first and touches each global bucket
+// once; wider chunks (leptons appended since the last sort) use one global
+// atomic per run of equal groups.
 // An iteration takes up to SortPer consecutive chunks of one (gap, species),
 // so the barriers and the round trip of the bucket atomics are shared.
 // TAIL sorts only the appended leptons of the species that have many
@@ -2042,6 +2053,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(GapDev* __restrict__ gaps,
     const long long i1 = i0 + nch * kChunk < nS ? i0 + nch * kChunk : nS;
     gptr<int32_t> cnt = glb(G->sort_cnt[s]);
     gptr<const int32_t> cin = glb<const int32_t>((void*)G->cell[buf][s]);
+    const int nk = sort_buckets(nc);
     // the whole lepton state is requested at once (slots past the end read
     // the first slot and are discarded), before any store of this chunk
     int cvs[kN];
@@ -2059,13 +2071,16 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(GapDev* __restrict__ gaps,
         idv[j] = glb<const uint64_t>((void*)G->id[buf][s])[ii];
       }
       // kDead marks what takes no part: slots outside the range and, in the
-      // full sort, dead leptons; the tail sort keeps those in bucket n_cells
+      // full sort, dead leptons; the tail sort keeps those in a bucket after
+      // the last group (cell n_cells)
       cvs[j] = in ? (TAIL && cv == kDead ? nc : cv) : kDead;
     }
+    // the bucket of a taking part lepton: its cell's group, or the dead bucket
+    auto key = [&](int cv) { return TAIL && cv == nc ? nk : cv >> kSortShift; };
     int mn = INT32_MAX, mx = INT32_MIN;
 #pragma unroll
     for (int j = 0; j < kN; ++j)
-      if (cvs[j] != kDead) { mn = min(mn, cvs[j]); mx = max(mx, cvs[j]); }
+      if (cvs[j] != kDead) { mn = min(mn, key(cvs[j])); mx = max(mx, key(cvs[j])); }
     block_minmax(mn, mx, s_red);
     if (mx < mn) continue;  // no live lepton in this chunk (uniform)
     long long dst[kN];
@@ -2078,11 +2093,11 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(GapDev* __restrict__ gaps,
       int rank[kN];
 #pragma unroll
       for (int j = 0; j < kN; ++j) {
-        const int cv = cvs[j];
+        const int kv = cvs[j] != kDead ? key(cvs[j]) : kDead;
         int head_lane, run_len;
-        wave_runs(cv, head_lane, run_len);
+        wave_runs(kv, head_lane, run_len);
         int r = 0;
-        if (run_len > 0 && cv != kDead) r = atomicAdd(&s_hist[cv - mn], run_len);
+        if (run_len > 0 && kv != kDead) r = atomicAdd(&s_hist[kv - mn], run_len);
         rank[j] = __shfl(r, head_lane, 64) + (lane - head_lane);
       }
       __syncthreads();
@@ -2098,16 +2113,16 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(GapDev* __restrict__ gaps,
       __syncthreads();
 #pragma unroll
       for (int j = 0; j < kN; ++j)
-        dst[j] = cvs[j] != kDead ? (long long)s_hist[cvs[j] - mn] + rank[j] : 0;
+        dst[j] = cvs[j] != kDead ? (long long)s_hist[key(cvs[j]) - mn] + rank[j] : 0;
     } else {
 #pragma unroll
       for (int j = 0; j < kN; ++j) {
-        const int cv = cvs[j];
+        const int kv = cvs[j] != kDead ? key(cvs[j]) : kDead;
         int head_lane, run_len;
-        wave_runs(cv, head_lane, run_len);
+        wave_runs(kv, head_lane, run_len);
         int b = 0;
-        if (run_len > 0 && cv != kDead)
-          b = __hip_atomic_fetch_add(cnt + cv, run_len, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (run_len > 0 && kv != kDead)
+          b = __hip_atomic_fetch_add(cnt + kv, run_len, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (PASS == 1) {
           b = __shfl(b, head_lane, 64);
           dst[j] = (long long)b + (lane - head_lane);
@@ -2199,7 +2214,7 @@ __global__ __launch_bounds__(1024) void k_sort_scan(GapDev* __restrict__ gaps, i
   GapDev* __restrict__ G = gaps + g;
   if (G->status != PIC_OK) return;
   if (TAIL && !tail_sorted(G, s)) return;  // (tail_sorted also requires PIC_OK)
-  const long long tot = block_scan_counts(G->sort_cnt[s], G->n_cells + (TAIL ? 1 : 0), s_sum);
+  const long long tot = block_scan_counts(G->sort_cnt[s], sort_buckets(G->n_cells) + (TAIL ? 1 : 0), s_sum);
   if (!TAIL && threadIdx.x == blockDim.x - 1) G->sorted_n[s] = (unsigned long long)tot;
 }
 

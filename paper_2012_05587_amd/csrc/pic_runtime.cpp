@@ -642,7 +642,7 @@ int tune_pick(Tuner& t, int& round) {
   return t.cur;
 }
 
-// The seed, written in the order it was drawn, is sorted by cell once before
+// The seed, written in the order it was drawn, is sorted by cell group once before
 // the first step, so that its chunks deposit through the LDS tile from the
 // start (results do not depend on lepton order).
 pic_status sort_seed(pic_batch* b) {
