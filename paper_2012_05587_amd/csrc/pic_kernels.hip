@@ -1400,11 +1400,13 @@ __device__ __forceinline__ ConvRun conv_run(long long rb0, long long rb1, long l
 // points, moving along the photon (section 2).  Each wave works apart: it
 // takes a contiguous range of the plan's conversion items (its workgroup's
 // range cut in four); for each item every lane tests kKeyRun consecutive
-// photons (one 16-byte load of keys), a wave scan of the lanes' counts places
-// the item's due photons in the wave's LDS list, lane 0 reserves their pair
-// slots with one atomic, and the lanes convert the list one photon each.
-// The keys of the wave's next item of the same gap are requested before the
-// current item's photons are converted.  No workgroup barrier.
+// photons (one 16-byte load of keys), and a wave scan of the lanes' counts
+// appends the item's due photons to the wave's LDS list (offsets from the
+// first listed item's slot).  Once the list holds a wave's worth, or the
+// next item might not fit, or the gap's items end, lane 0 reserves the
+// list's pair slots with one atomic and the lanes convert it one photon
+// each.  The keys of the wave's next item of the same gap are requested
+// before the current item is tested.  No workgroup barrier.
 template <typename T>
 __device__ void convert_role(GapDev* __restrict__ gaps, const long long* __restrict__ pwi, int B,
                              int vb, int nvb, uint32_t* s_due) {
@@ -1454,6 +1456,31 @@ __device__ void convert_role(GapDev* __restrict__ gaps, const long long* __restr
       if (r.tail && keyed && r.in != 0u) kv = *(gptr<const u32x4>)(phk + r.ib + (long long)lane * kKeyRun);
       return kv;
     };
+    // the wave's list: `pending` due photons at offsets from slot `lb`
+    uint32_t pending = 0;
+    long long lb = 0;
+    auto convert_list = [&]() {
+      __builtin_amdgcn_wave_barrier();  // the list is complete before any lane reads it
+      unsigned long long base = 0;
+      if (lane == 0) base = reserve_pairs(G, pending);
+      base = __shfl(base, 0, 64);
+      for (uint32_t q = (uint32_t)lane; q < pending; q += 64) {
+        const long long i = lb + (long long)due[q];
+        const u64x2 pr = get_photon(phr, i);
+        const long long X = (long long)pr.x;
+        const uint64_t ch = pr.y;
+        const int cc = (int)(X >> K);
+        const T offn = (T)(X & mask) * inv_scale;
+        const T pc = (ch & 1u) ? pchild : -pchild;
+        const uint64_t child = ch & ~(uint64_t)1;
+        const unsigned long long se = ne0 + base + q, sp = ne1 + base + q;
+        if (se < cap) { cell0[se] = cc; off0[se] = offn; p0[se] = pc; id0[se] = child; }
+        if (sp < cap) { cell1[sp] = cc; off1[sp] = offn; p1[sp] = pc; id1[sp] = child | 1u; }
+        if (evmap) count_pairs(G, (long long)stepn, cc, 1ull);
+      }
+      __builtin_amdgcn_wave_barrier();  // the list is read before it is rewritten
+      pending = 0;
+    };
     ConvRun r = conv_run(rb0, rb1, rt0, rt1, w - wg0, lane);
     u32x4 kv = keys_of(r);
     for (long long x = w; x < wend; ++x) {
@@ -1477,32 +1504,21 @@ __device__ void convert_role(GapDev* __restrict__ gaps, const long long* __restr
       const uint32_t c = (uint32_t)__popc(m);
       const uint32_t incl = (uint32_t)wave_incl_scan_dpp((int)c);
       const uint32_t cnt = (uint32_t)__builtin_amdgcn_readfirstlane(__shfl((int)incl, 63, 64));
-      if (cnt == 0) continue;  // uniform
-      uint32_t pos = incl - c;
-      while (m) {
-        const int b = __ffs(m) - 1;
-        m &= m - 1u;
-        due[pos++] = (uint32_t)(lane * kKeyRun + b);
+      if (cnt > 0) {  // uniform
+        if (pending + cnt > (uint32_t)kPhChunk) convert_list();  // the list holds kPhChunk
+        if (pending == 0) lb = ib;
+        uint32_t pos = pending + incl - c;
+        const uint32_t off = (uint32_t)(ib - lb);
+        while (m) {
+          const int b = __ffs(m) - 1;
+          m &= m - 1u;
+          due[pos++] = off + (uint32_t)(lane * kKeyRun + b);
+        }
+        pending += cnt;
       }
-      __builtin_amdgcn_wave_barrier();  // the list is complete before any lane reads it
-      unsigned long long base = 0;
-      if (lane == 0) base = reserve_pairs(G, cnt);
-      base = __shfl(base, 0, 64);
-      for (uint32_t q = (uint32_t)lane; q < cnt; q += 64) {
-        const long long i = ib + (long long)due[q];
-        const u64x2 pr = get_photon(phr, i);
-        const long long X = (long long)pr.x;
-        const uint64_t ch = pr.y;
-        const int cc = (int)(X >> K);
-        const T offn = (T)(X & mask) * inv_scale;
-        const T pc = (ch & 1u) ? pchild : -pchild;
-        const uint64_t child = ch & ~(uint64_t)1;
-        const unsigned long long se = ne0 + base + q, sp = ne1 + base + q;
-        if (se < cap) { cell0[se] = cc; off0[se] = offn; p0[se] = pc; id0[se] = child; }
-        if (sp < cap) { cell1[sp] = cc; off1[sp] = offn; p1[sp] = pc; id1[sp] = child | 1u; }
-        if (evmap) count_pairs(G, (long long)stepn, cc, 1ull);
-      }
-      __builtin_amdgcn_wave_barrier();  // the list is read before the next item rewrites it
+      // convert once the list holds a wave's worth, and at the end of the
+      // gap's items
+      if (pending >= 64u || (pending > 0u && x + 1 == wend)) convert_list();
     }
     w = wend;
   }
