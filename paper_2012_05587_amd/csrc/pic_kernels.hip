@@ -1402,9 +1402,9 @@ __device__ __forceinline__ ConvRun conv_run(long long rb0, long long rb1, long l
 // range cut in four); for each item every lane tests kKeyRun consecutive
 // photons (one 16-byte load of keys), and a wave scan of the lanes' counts
 // appends the item's due photons to the wave's LDS list (offsets from the
-// first listed item's slot).  Once the list holds a wave's worth, or the
-// next item might not fit, or the gap's items end, lane 0 reserves the
-// list's pair slots with one atomic and the lanes convert it one photon
+// first listed item's slot).  Once the list holds two rounds of the wave,
+// or the next item might not fit, or the gap's items end, lane 0 reserves
+// the list's pair slots with one atomic and the lanes convert it one photon
 // each.  The keys of the wave's next item of the same gap are requested
 // before the current item is tested.  No workgroup barrier.
 template <typename T>
@@ -1516,9 +1516,9 @@ __device__ void convert_role(GapDev* __restrict__ gaps, const long long* __restr
         }
         pending += cnt;
       }
-      // convert once the list holds a wave's worth, and at the end of the
-      // gap's items
-      if (pending >= 64u || (pending > 0u && x + 1 == wend)) convert_list();
+      // convert once the list holds two rounds of the wave, and at the end
+      // of the gap's items
+      if (pending >= 128u || (pending > 0u && x + 1 == wend)) convert_list();
     }
     w = wend;
   }
