@@ -1371,6 +1371,9 @@ __device__ __forceinline__ uint32_t key_matches(u32x4 kv, uint32_t key) {
 }
 
 constexpr int kConvGroup = kBlock / 64;  // waves of a conversion workgroup, each with its own list
+constexpr int kDueFlush = 128;           // listed due photons that start a conversion round
+constexpr int kDueList = 2 * kPhChunk;   // a wave's list: below kDueFlush, plus one item
+static_assert(kDueList >= kDueFlush - 1 + kPhChunk, "a wave's list holds a flush's worth and an item");
 
 // The due mask of one lane's kKeyRun photons of conversion item `local` of a
 // gap whose due ranges are [rb0, rb1) and [rt0, rt1): bit b set when photon
@@ -1402,11 +1405,12 @@ __device__ __forceinline__ ConvRun conv_run(long long rb0, long long rb1, long l
 // range cut in four); for each item every lane tests kKeyRun consecutive
 // photons (one 16-byte load of keys), and a wave scan of the lanes' counts
 // appends the item's due photons to the wave's LDS list (offsets from the
-// first listed item's slot).  Once the list holds two rounds of the wave,
-// or the next item might not fit, or the gap's items end, lane 0 reserves
-// the list's pair slots with one atomic and the lanes convert it one photon
-// each.  The keys of the wave's next item of the same gap are requested
-// before the current item is tested.  No workgroup barrier.
+// first listed item's slot).  Once the list holds two rounds of the wave
+// (kDueFlush), or the gap's items end, lane 0 reserves the list's pair slots
+// with one atomic and the lanes convert it one photon each; the list has
+// room for kDueFlush - 1 photons and a whole item.  The keys of the wave's
+// next item of the same gap are requested before the current item is
+// tested.  No workgroup barrier.
 template <typename T>
 __device__ void convert_role(GapDev* __restrict__ gaps, const long long* __restrict__ pwi, int B,
                              int vb, int nvb, uint32_t* s_due) {
@@ -1414,7 +1418,7 @@ __device__ void convert_role(GapDev* __restrict__ gaps, const long long* __restr
   const int lane = lane_id();
   // the wave's index, uniform
   const int v = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
-  uint32_t* due = s_due + v * kPhChunk;
+  uint32_t* due = s_due + v * kDueList;
   const long long total = pwi[B];
   long long x0, x1;
   xcd_range(total, x0, x1, vb, nvb);
@@ -1464,6 +1468,7 @@ __device__ void convert_role(GapDev* __restrict__ gaps, const long long* __restr
       unsigned long long base = 0;
       if (lane == 0) base = reserve_pairs(G, pending);
       base = __shfl(base, 0, 64);
+#pragma unroll 1
       for (uint32_t q = (uint32_t)lane; q < pending; q += 64) {
         const long long i = lb + (long long)due[q];
         const u64x2 pr = get_photon(phr, i);
@@ -1504,8 +1509,7 @@ __device__ void convert_role(GapDev* __restrict__ gaps, const long long* __restr
       const uint32_t c = (uint32_t)__popc(m);
       const uint32_t incl = (uint32_t)wave_incl_scan_dpp((int)c);
       const uint32_t cnt = (uint32_t)__builtin_amdgcn_readfirstlane(__shfl((int)incl, 63, 64));
-      if (cnt > 0) {  // uniform
-        if (pending + cnt > (uint32_t)kPhChunk) convert_list();  // the list holds kPhChunk
+      if (cnt > 0) {  // uniform (the list holds it: pending < kDueFlush, cnt <= kPhChunk)
         if (pending == 0) lb = ib;
         uint32_t pos = pending + incl - c;
         const uint32_t off = (uint32_t)(ib - lb);
@@ -1518,7 +1522,7 @@ __device__ void convert_role(GapDev* __restrict__ gaps, const long long* __restr
       }
       // convert once the list holds two rounds of the wave, and at the end
       // of the gap's items
-      if (pending >= 128u || (pending > 0u && x + 1 == wend)) convert_list();
+      if (pending >= (uint32_t)kDueFlush || (pending > 0u && x + 1 == wend)) convert_list();
     }
     w = wend;
   }
@@ -1880,7 +1884,7 @@ __global__ __launch_bounds__(kBlock) void k_post(GapDev* __restrict__ gaps,
   __shared__ int s_tmp[kBlock / 64];
   // the emission role's prefix of the push workgroups' emitters, or the
   // conversion role's lists of due photons, one per wave (a block takes one role)
-  __shared__ uint32_t s_buf[kPushGrid > kConvGroup * kPhChunk ? kPushGrid : kConvGroup * kPhChunk];
+  __shared__ uint32_t s_buf[kPushGrid > kConvGroup * kDueList ? kPushGrid : kConvGroup * kDueList];
   const int b = blockIdx.x;
   if (b < n_field) field_role(gaps, cwi, B, b, s_red);
   else if (b < n_field + n_conv)
