@@ -628,6 +628,35 @@ def test_emission_in_push_and_in_kernel_match_oracle(case, split):
     assert m.push_emissions == (emitted if split == SPLIT_PUSH else 0)
 
 
+@pytest.mark.parametrize("split", [SPLIT_KERNEL, SPLIT_PUSH])
+@pytest.mark.parametrize("case", ["c1", "c3"])
+def test_dense_emission_matches_oracle(case, split):
+    """About 14 photons per lepton and step (gamma_thr = 10, gamma_pair = 2,
+    E0 dt = 36): a chunk of 1024 leptons emits more photons than the push's
+    photon-to-emitter map holds (8192), so the rest find their emitter by
+    searching the prefixes.  Six steps against the oracle: history, leptons
+    and the photon store."""
+    cfg = workloads.config("c3_mixed_single_gap" if case == "c3" else "c1_fp64_reference_gap")
+    cfg.update(gamma_thr=10.0, f=0.2, e0=80.0, photon_capacity=2_000_000, capacity=400_000)
+    steps = 6
+    cfg["history_rows"] = steps + 8
+    print(f"[case] dense emission {case} split={split}", flush=True)
+    go = pc.make_oracle(cfg)
+    assert go.step(steps) == 0
+    gg = pc.make_gpu(cfg)
+    gg.emission_split(split)
+    gg.step_n(steps)
+    _check_all(gg, go, cfg["precision"])
+    a, b = gg.read_photons(), go.photons()
+    key = lambda d: np.lexsort((d["child"], d["dir"], d["conv_step"], d["xq"]))  # noqa: E731
+    ka, kb = key(a), key(b)
+    assert len(ka) == len(kb) > 500000
+    for k in ("xq", "conv_step", "dir", "child"):
+        assert np.array_equal(np.asarray(a[k])[ka], np.asarray(b[k])[kb]), k
+    first = int(go.history()["photons_emitted"][0])
+    assert first > 2 * 8192  # both species' first chunks pass the map on step 1
+
+
 # ------------------------------------------------------------------- batch
 @pytest.mark.parametrize("split", [SPLIT_KERNEL, None])
 def test_batch_matches_oracle_per_gap(split):
