@@ -384,6 +384,9 @@ pic_status pic_batch_prepare(pic_batch* b);
 pic_status pic_batch_tuning(pic_batch* b, int32_t* sort_every, int32_t* autotuned,
                             int64_t* replays, int32_t* switches);
 /* The same for a single gap. */
+pic_status pic_tuning(pic_gap* g, int32_t* sort_every, int32_t* autotuned, int64_t* replays,
+                      int32_t* switches);
+
 /* Where a step's emissions are drawn (section 2's emission: the photons, or
  * the pairs made in place, of the leptons that reached the threshold).  Not
  * part of the method: both kernels draw the same photons; only the cost
@@ -396,8 +399,6 @@ pic_status pic_batch_tuning(pic_batch* b, int32_t* sort_every, int32_t* autotune
  * PIC_ERR_DEVICE. */
 pic_status pic_batch_emission_split(pic_batch* b, int64_t max_push_chunks);
 pic_status pic_emission_split(pic_gap* g, int64_t max_push_chunks);
-pic_status pic_tuning(pic_gap* g, int32_t* sort_every, int32_t* autotuned, int64_t* replays,
-                      int32_t* switches);
 
 #ifdef __cplusplus
 }
