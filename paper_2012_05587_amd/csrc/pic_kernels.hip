@@ -2284,9 +2284,11 @@ __global__ __launch_bounds__(kBlock) void k_ph_zero(GapDev* __restrict__ gaps, i
 
 // Counting sort of the photon store by conversion step (key = step - now),
 // dropping photons that converted or escaped (key < 0).  A workgroup takes a
-// contiguous range of one gap's store; with at most kPhBins keys it counts in
-// an LDS histogram and touches each global bucket once per range, otherwise
-// it uses one global atomic per run of equal keys.
+// contiguous range of one gap's store and counts the keys below kPhBins in
+// an LDS histogram, touching each of those global buckets once per range;
+// the rare keys beyond (conversion tables longer than kPhBins steps, whose
+// far entries hold a vanishing share of the photons) take one global
+// atomic per run of equal keys.
 template <int PASS>
 __global__ __launch_bounds__(kBlock) void k_ph_pass(GapDev* __restrict__ gaps,
                                                     const long long* __restrict__ qwi, int B) {
@@ -2307,91 +2309,79 @@ __global__ __launch_bounds__(kBlock) void k_ph_pass(GapDev* __restrict__ gaps,
     const int pb = G->phbuf;
     const long long stepn = G->step;
     const int L = G->table_len;
+    const int nh = L < kPhBins ? L : kPhBins;  // keys counted in LDS
     gptr<int32_t> bucket = glb(G->ph_bucket);
     gptr<const int32_t> sin = glb<const int32_t>((void*)G->ph_step[pb]);
-    if (L <= kPhBins) {
-      for (int k = threadIdx.x; k < L; k += kBlock) s_hist[k] = 0;
+    for (int k = threadIdx.x; k < nh; k += kBlock) s_hist[k] = 0;
+    __syncthreads();
+    // one LDS atomic per run of equal keys in a wave (the sorted body of
+    // the store holds long runs); far keys count in the global buckets
+    for (long long r = p0; r < p1; r += kPhUnroll * kBlock) {
+      int key[kPhUnroll];
+#pragma unroll
+      for (int k = 0; k < kPhUnroll; ++k) {
+        const long long i = r + threadIdx.x + (long long)k * kBlock;
+        const long long cs = i < p1 ? (long long)sin[i] : (long long)INT32_MIN;
+        key[k] = cs >= stepn ? (int)(cs - stepn) : -1;
+      }
+#pragma unroll
+      for (int k = 0; k < kPhUnroll; ++k) {
+        int head_lane, run_len;
+        wave_runs(key[k], head_lane, run_len);
+        if (run_len > 0 && key[k] >= 0) {
+          if (key[k] < nh) atomicAdd(&s_hist[key[k]], run_len);
+          else if (PASS == 0)
+            __hip_atomic_fetch_add(bucket + key[k], run_len, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < nh; k += kBlock) {
+      const int c = s_hist[k];
+      if (c == 0) continue;
+      if (PASS == 0)
+        __hip_atomic_fetch_add(bucket + k, c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      else
+        s_hist[k] = __hip_atomic_fetch_add(bucket + k, c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (PASS == 1) {
       __syncthreads();
-      // one LDS atomic per run of equal keys in a wave (the sorted body of
-      // the store holds long runs)
       for (long long r = p0; r < p1; r += kPhUnroll * kBlock) {
         int key[kPhUnroll];
+        u64x2 rv[kPhUnroll];
 #pragma unroll
         for (int k = 0; k < kPhUnroll; ++k) {
           const long long i = r + threadIdx.x + (long long)k * kBlock;
           const long long cs = i < p1 ? (long long)sin[i] : (long long)INT32_MIN;
           key[k] = cs >= stepn ? (int)(cs - stepn) : -1;
         }
+        // the kept photons' state is requested before the ranks are taken
+#pragma unroll
+        for (int k = 0; k < kPhUnroll; ++k) {
+          const long long i = r + threadIdx.x + (long long)k * kBlock;
+          rv[k] = u64x2{0ull, 0ull};
+          if (key[k] >= 0) rv[k] = get_photon(glb<const PhotonRec>((void*)G->ph_rec[pb]), i);
+        }
 #pragma unroll
         for (int k = 0; k < kPhUnroll; ++k) {
           int head_lane, run_len;
           wave_runs(key[k], head_lane, run_len);
-          if (run_len > 0 && key[k] >= 0) atomicAdd(&s_hist[key[k]], run_len);
-        }
-      }
-      __syncthreads();
-      for (int k = threadIdx.x; k < L; k += kBlock) {
-        const int c = s_hist[k];
-        if (c == 0) continue;
-        if (PASS == 0)
-          __hip_atomic_fetch_add(bucket + k, c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        else
-          s_hist[k] = __hip_atomic_fetch_add(bucket + k, c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
-      if (PASS == 1) {
-        __syncthreads();
-        for (long long r = p0; r < p1; r += kPhUnroll * kBlock) {
-          int key[kPhUnroll];
-          u64x2 rv[kPhUnroll];
-#pragma unroll
-          for (int k = 0; k < kPhUnroll; ++k) {
-            const long long i = r + threadIdx.x + (long long)k * kBlock;
-            const long long cs = i < p1 ? (long long)sin[i] : (long long)INT32_MIN;
-            key[k] = cs >= stepn ? (int)(cs - stepn) : -1;
+          int b = 0;
+          if (run_len > 0 && key[k] >= 0) {
+            if (key[k] < nh) b = atomicAdd(&s_hist[key[k]], run_len);
+            else
+              b = __hip_atomic_fetch_add(bucket + key[k], run_len, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
           }
-          // the kept photons' state is requested before the ranks are taken
-#pragma unroll
-          for (int k = 0; k < kPhUnroll; ++k) {
-            const long long i = r + threadIdx.x + (long long)k * kBlock;
-            rv[k] = u64x2{0ull, 0ull};
-            if (key[k] >= 0) rv[k] = get_photon(glb<const PhotonRec>((void*)G->ph_rec[pb]), i);
-          }
-#pragma unroll
-          for (int k = 0; k < kPhUnroll; ++k) {
-            int head_lane, run_len;
-            wave_runs(key[k], head_lane, run_len);
-            int b = 0;
-            if (run_len > 0 && key[k] >= 0) b = atomicAdd(&s_hist[key[k]], run_len);
-            b = __shfl(b, head_lane, 64);
-            if (key[k] < 0) continue;
-            const long long dst = (long long)b + (lane - head_lane);
-            *(gptr<u64x2>)(glb(G->ph_rec[pb ^ 1]) + dst) = rv[k];
-            G->ph_step[pb ^ 1][dst] = (int32_t)(stepn + key[k]);
-          }
-        }
-      }
-      __syncthreads();  // s_hist is zeroed for the next range
-    } else {
-      for (long long r = p0; r < p1; r += kBlock) {
-        const long long i = r + threadIdx.x;
-        const long long cs = i < p1 ? (long long)sin[i] : (long long)INT32_MIN;
-        const int key = cs >= stepn ? (int)(cs - stepn) : -1;
-        int head_lane, run_len;
-        wave_runs(key, head_lane, run_len);
-        int b = 0;
-        if (run_len > 0 && key >= 0)
-          b = __hip_atomic_fetch_add(bucket + key, run_len, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (PASS == 1) {
           b = __shfl(b, head_lane, 64);
-          if (key >= 0) {
-            const long long dst = (long long)b + (lane - head_lane);
-            *(gptr<u64x2>)(glb(G->ph_rec[pb ^ 1]) + dst) =
-                get_photon(glb<const PhotonRec>((void*)G->ph_rec[pb]), i);
-            G->ph_step[pb ^ 1][dst] = (int32_t)cs;
-          }
+          if (key[k] < 0) continue;
+          const long long dst = (long long)b + (lane - head_lane);
+          *(gptr<u64x2>)(glb(G->ph_rec[pb ^ 1]) + dst) = rv[k];
+          G->ph_step[pb ^ 1][dst] = (int32_t)(stepn + key[k]);
         }
       }
     }
+    __syncthreads();  // s_hist is read before the next range clears it
   }
 }
 

@@ -657,6 +657,36 @@ def test_dense_emission_matches_oracle(case, split):
     assert first > 2 * 8192  # both species' first chunks pass the map on step 1
 
 
+@pytest.mark.parametrize("case", ["c1", "c3"])
+def test_long_photon_path_matches_oracle(case):
+    """A mean photon path of 2000 cells in a periodic gap: the conversion
+    table runs to about 9.9e4 steps, past the photon sort's LDS histogram
+    (8192 keys), so the re-sorts of the store count and place the far keys
+    through global atomics.  300 steps at a fixed re-sort cadence of 20
+    against the oracle: history, leptons and the photon store (about 1e5
+    photons, a sixth of them due more than 8192 steps later)."""
+    cfg = workloads.config("c3_mixed_single_gap" if case == "c3" else "c1_fp64_reference_gap")
+    # periodic, so that long paths wrap instead of leaving the domain
+    cfg.update(l_gamma=2000.0, photon_capacity=400_000, sort_every=20,
+               boundary=workloads.PERIODIC, e0=150.0)
+    steps = 300
+    cfg["history_rows"] = steps + 8
+    print(f"[case] long photon path {case}", flush=True)
+    go = pc.make_oracle(cfg)
+    assert go.step(steps) == 0
+    gg = pc.make_gpu(cfg)
+    gg.step_n(steps)
+    _check_all(gg, go, cfg["precision"])
+    a, b = gg.read_photons(), go.photons()
+    key = lambda d: np.lexsort((d["child"], d["dir"], d["conv_step"], d["xq"]))  # noqa: E731
+    ka, kb = key(a), key(b)
+    assert len(ka) == len(kb) > 50000
+    for k in ("xq", "conv_step", "dir", "child"):
+        assert np.array_equal(np.asarray(a[k])[ka], np.asarray(b[k])[kb]), k
+    far = np.asarray(b["conv_step"]) - steps
+    assert (far >= 8192).sum() > 1000  # the store holds keys past the histogram
+
+
 # ------------------------------------------------------------------- batch
 @pytest.mark.parametrize("split", [SPLIT_KERNEL, None])
 def test_batch_matches_oracle_per_gap(split):
