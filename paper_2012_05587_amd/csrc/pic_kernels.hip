@@ -1372,6 +1372,7 @@ __device__ __forceinline__ uint32_t key_matches(u32x4 kv, uint32_t key) {
 
 constexpr int kConvGroup = kBlock / 64;  // waves of a conversion workgroup, each with its own list
 constexpr int kDueFlush = 128;           // listed due photons that start a conversion round
+constexpr int kConvPerGroup = 32;        // conversion items a workgroup takes at least
 constexpr int kDueList = 2 * kPhChunk;   // a wave's list: below kDueFlush, plus one item
 static_assert(kDueList >= kDueFlush - 1 + kPhChunk, "a wave's list holds a flush's worth and an item");
 
@@ -1420,8 +1421,16 @@ __device__ void convert_role(GapDev* __restrict__ gaps, const long long* __restr
   const int v = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
   uint32_t* due = s_due + v * kDueList;
   const long long total = pwi[B];
+  // only as many workgroups as hold kConvPerGroup items each (a multiple of
+  // the 8 XCDs, at most the role's blocks) take part: in small steps the
+  // others' start-up (finding their gap, its descriptor and due ranges)
+  // would cost more than the items they would take
+  long long nact = (total + kConvPerGroup - 1) / kConvPerGroup;
+  nact = (nact + 7) / 8 * 8;
+  if (nact > nvb) nact = nvb;
+  if (vb >= nact) return;
   long long x0, x1;
-  xcd_range(total, x0, x1, vb, nvb);
+  xcd_range(total, x0, x1, vb, (int)nact);
   const long long per = (x1 - x0 + kConvGroup - 1) / kConvGroup;
   long long w = x0 + (long long)v * per;
   w = w < x1 ? w : x1;
